@@ -1,0 +1,1136 @@
+/*
+ * oracle.c -- plain FP64 CPU reference for amplitude-aware lossy compressed
+ * state-vector simulation.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Written for obviousness, not for
+ * speed: bits are packed one at a time, every ladder level is compressed in
+ * full exactly as the AALC loop states, and sums follow the perfect binary
+ * tree that defines them.
+ *
+ * Paper sections followed:
+ *   Sec. II   amplitude vector, pair update of a single-qubit gate, controlled
+ *             two-qubit gate, pure-state fidelity.
+ *   Sec. III  stride partition (Alg. 1), error-bounded lossy compression with
+ *             normalisation before the gate, lossless compression, AALC error
+ *             bound ladder and ratio threshold (Alg. 2).
+ * Where the paper leaves a choice open (codec internals, stride size,
+ * gates spanning strides, normalisation scope, fidelity square) this file
+ * follows the readings listed in the design notes of the repository and in
+ * the block-stream format definition; each such place says which reading.
+ *
+ * Build: cc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAGIC 0x31424141u /* "AAB1" little-endian */
+#define HDR_BYTES 32u
+#define PLANE_HDR_BYTES 16u
+#define OUTLIER_BYTES 16u
+#define CHUNK 64u
+#define QMAX 1073741824.0 /* 2^30: largest |y| accepted by the quantiser */
+
+/* ------------------------------------------------------------------------ */
+/* growable byte buffer                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint8_t *p;
+    size_t len, cap;
+} obuf;
+
+static int ob_put(obuf *o, const void *src, size_t n)
+{
+    if (o->len + n > o->cap) {
+        size_t nc = o->cap ? o->cap : 256;
+        while (nc < o->len + n)
+            nc *= 2;
+        uint8_t *np = (uint8_t *)realloc(o->p, nc);
+        if (!np)
+            return OR_ENOMEM;
+        o->p = np;
+        o->cap = nc;
+    }
+    memcpy(o->p + o->len, src, n);
+    o->len += n;
+    return OR_OK;
+}
+static int ob_u32(obuf *o, uint32_t v) { return ob_put(o, &v, 4); }
+static int ob_u64(obuf *o, uint64_t v) { return ob_put(o, &v, 8); }
+static int ob_zero(obuf *o, size_t n)
+{
+    static const uint8_t z[64] = {0};
+    while (n) {
+        size_t k = n < 64 ? n : 64;
+        if (ob_put(o, z, k))
+            return OR_ENOMEM;
+        n -= k;
+    }
+    return OR_OK;
+}
+
+static uint64_t rd_u64(const uint8_t *p) { uint64_t v; memcpy(&v, p, 8); return v; }
+static uint32_t rd_u32(const uint8_t *p) { uint32_t v; memcpy(&v, p, 4); return v; }
+static double rd_f64(const uint8_t *p) { double v; memcpy(&v, p, 8); return v; }
+static uint64_t dbits(double x) { uint64_t v; memcpy(&v, &x, 8); return v; }
+static double bitsd(uint64_t v) { double x; memcpy(&x, &v, 8); return x; }
+
+/* ------------------------------------------------------------------------ */
+/* sums                                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Perfect binary tree: sum(v[0:m]) = sum(v[0:m/2]) + sum(v[m/2:m]).  This is
+ * the summation order fixed for every norm, mean and inner product. */
+double or_pairwise(const double *v, size_t m)
+{
+    if (m == 1)
+        return v[0];
+    return or_pairwise(v, m / 2) + or_pairwise(v + m / 2, m / 2);
+}
+
+/* ------------------------------------------------------------------------ */
+/* codec: error-bounded quantiser, integer Lorenzo predictor, fixed-length  */
+/* chunk packing (Sec. III: SZ-style prediction + quantisation under an     */
+/* absolute bound delta; delta = 0 is the lossless level)                   */
+/* ------------------------------------------------------------------------ */
+
+static int bitlen64(uint64_t z)
+{
+    int n = 0;
+    while (z) {
+        n++;
+        z >>= 1;
+    }
+    return n;
+}
+
+/* zigzag of a two's-complement 64-bit difference: 0,-1,1,-2,... -> 0,1,2,3 */
+static uint64_t zigzag(uint64_t c)
+{
+    uint64_t sign = (c >> 63) ? ~(uint64_t)0 : 0;
+    return (c << 1) ^ sign;
+}
+static uint64_t unzigzag(uint64_t z) { return (z >> 1) ^ (0 - (z & 1)); }
+
+/* Quantise one plane of m scalars at error bound delta.
+ * Lossy (delta > 0), reading of Sec. III's bound D_i - delta <= D'_i <=
+ * D_i + delta, applied per real component:
+ *   e = 2 delta, r = fl(1/e), y = fl(x r)
+ *   if |y| < 2^30:  q = round-half-even(y), xhat = fl(q e),
+ *                   outlier iff not (|fl(x - xhat)| < delta)
+ *   else (also NaN): q = 0, outlier.
+ * Lossless (delta == 0, the zstd role of Sec. III): q = the 64 bits of x.
+ * q is returned as a 64-bit two's-complement pattern. */
+static void quantize_plane(const double *v, size_t m, double delta,
+                           uint64_t *q, uint8_t *outl)
+{
+    if (delta == 0.0) {
+        for (size_t i = 0; i < m; i++) {
+            q[i] = dbits(v[i]);
+            outl[i] = 0;
+        }
+        return;
+    }
+    double e = 2.0 * delta;
+    double r = 1.0 / e;
+    for (size_t i = 0; i < m; i++) {
+        double y = v[i] * r;
+        if (fabs(y) < QMAX) {
+            double qr = nearbyint(y); /* default mode: ties to even */
+            int64_t qi = (int64_t)qr;
+            double xh = (double)qi * e;
+            q[i] = (uint64_t)qi;
+            outl[i] = !(fabs(v[i] - xh) < delta);
+        } else {
+            q[i] = 0;
+            outl[i] = 1;
+        }
+    }
+}
+
+/* Set bit `pos` of a little-endian word array. */
+static void setbit(uint64_t *w, uint64_t pos) { w[pos >> 6] |= (uint64_t)1 << (pos & 63); }
+static int getbit(const uint64_t *w, uint64_t pos) { return (int)((w[pos >> 6] >> (pos & 63)) & 1); }
+
+/* Encode one plane (m = 2^s scalars) as a plane record of the block stream:
+ *   i64 anchor (q_0) | u32 payload_words | u32 n_outliers |
+ *   [width byte per chunk, zero-padded to 8 bytes, only if payload_words>0] |
+ *   payload words | outliers (u32 index, u32 0, f64 value) ascending index. */
+static int encode_plane(obuf *o, const double *v, size_t m, double delta,
+                        uint32_t *nout_ret)
+{
+    size_t nch = m / CHUNK;
+    uint64_t *q = (uint64_t *)malloc(m * 8);
+    uint64_t *z = (uint64_t *)malloc(m * 8);
+    uint8_t *outl = (uint8_t *)malloc(m);
+    uint8_t *wid = (uint8_t *)malloc(nch);
+    int rc = OR_ENOMEM;
+    if (!q || !z || !outl || !wid)
+        goto done;
+
+    quantize_plane(v, m, delta, q, outl);
+
+    /* Lorenzo on the integer codes: c_0 = 0, c_i = q_i - q_{i-1}. */
+    z[0] = 0;
+    for (size_t i = 1; i < m; i++)
+        z[i] = zigzag(q[i] - q[i - 1]);
+
+    uint32_t pw = 0, nout = 0;
+    for (size_t c = 0; c < nch; c++) {
+        int w = 0;
+        for (size_t l = 0; l < CHUNK; l++) {
+            int bl = bitlen64(z[c * CHUNK + l]);
+            if (bl > w)
+                w = bl;
+        }
+        wid[c] = (uint8_t)w;
+        pw += (uint32_t)w;
+    }
+    for (size_t i = 0; i < m; i++)
+        nout += outl[i];
+
+    rc = OR_ENOMEM;
+    if (ob_u64(o, q[0]) || ob_u32(o, pw) || ob_u32(o, nout))
+        goto done;
+    if (pw > 0) {
+        size_t padded = (nch + 7) / 8 * 8;
+        if (ob_put(o, wid, nch) || ob_zero(o, padded - nch))
+            goto done;
+    }
+    for (size_t c = 0; c < nch; c++) {
+        int w = wid[c];
+        if (w == 0)
+            continue;
+        uint64_t words[64];
+        memset(words, 0, sizeof words);
+        /* field l occupies chunk-stream bits [l*w, l*w + w), LSB first */
+        for (size_t l = 0; l < CHUNK; l++)
+            for (int bit = 0; bit < w; bit++)
+                if ((z[c * CHUNK + l] >> bit) & 1)
+                    setbit(words, (uint64_t)l * (uint64_t)w + (uint64_t)bit);
+        if (ob_put(o, words, (size_t)w * 8))
+            goto done;
+    }
+    for (size_t i = 0; i < m; i++) {
+        if (!outl[i])
+            continue;
+        if (ob_u32(o, (uint32_t)i) || ob_u32(o, 0) || ob_u64(o, dbits(v[i])))
+            goto done;
+    }
+    *nout_ret = nout;
+    rc = OR_OK;
+done:
+    free(q);
+    free(z);
+    free(outl);
+    free(wid);
+    return rc;
+}
+
+/* Decode one plane record starting at p (bounded by end).  Writes m values
+ * to v with stride `stride` doubles.  Returns bytes consumed or 0 on error. */
+static size_t decode_plane(const uint8_t *p, const uint8_t *end, size_t m,
+                           double delta, double *v, size_t stride,
+                           uint32_t *nout_ret)
+{
+    size_t nch = m / CHUNK;
+    if ((size_t)(end - p) < PLANE_HDR_BYTES)
+        return 0;
+    uint64_t anchor = rd_u64(p);
+    uint32_t pw = rd_u32(p + 8);
+    uint32_t nout = rd_u32(p + 12);
+    const uint8_t *cur = p + PLANE_HDR_BYTES;
+    uint8_t wid[CHUNK * 4]; /* nch <= 2^(s-6) <= 256 for s <= 14 */
+    if (nch > sizeof wid)
+        return 0;
+    memset(wid, 0, nch);
+    if (pw > 0) {
+        size_t padded = (nch + 7) / 8 * 8;
+        if ((size_t)(end - cur) < padded)
+            return 0;
+        memcpy(wid, cur, nch);
+        cur += padded;
+        uint32_t sum = 0;
+        for (size_t c = 0; c < nch; c++) {
+            if (wid[c] > 64)
+                return 0;
+            sum += wid[c];
+        }
+        if (sum != pw)
+            return 0;
+    }
+    if ((size_t)(end - cur) < (size_t)pw * 8)
+        return 0;
+    const uint8_t *payload = cur;
+    cur += (size_t)pw * 8;
+
+    /* unpack + unzigzag + running sum from the anchor */
+    uint64_t qprev = anchor;
+    size_t woff = 0;
+    for (size_t c = 0; c < nch; c++) {
+        int w = wid[c];
+        uint64_t words[64];
+        memcpy(words, payload + woff * 8, (size_t)w * 8);
+        for (size_t l = 0; l < CHUNK; l++) {
+            size_t i = c * CHUNK + l;
+            uint64_t zz = 0;
+            for (int bit = 0; bit < w; bit++)
+                if (getbit(words, (uint64_t)l * (uint64_t)w + (uint64_t)bit))
+                    zz |= (uint64_t)1 << bit;
+            if (i == 0 && zz != 0)
+                return 0; /* c_0 is 0 by definition */
+            uint64_t q = (i == 0) ? anchor : qprev + unzigzag(zz);
+            qprev = q;
+            if (delta == 0.0)
+                v[i * stride] = bitsd(q);
+            else
+                v[i * stride] = (double)(int64_t)q * (2.0 * delta);
+        }
+        woff += (size_t)w;
+    }
+    /* outliers replace the dequantised value with the stored one */
+    if ((size_t)(end - cur) < (size_t)nout * OUTLIER_BYTES)
+        return 0;
+    uint32_t last = 0;
+    for (uint32_t k = 0; k < nout; k++) {
+        uint32_t idx = rd_u32(cur);
+        if (idx >= m || (k > 0 && idx <= last) || delta == 0.0)
+            return 0;
+        last = idx;
+        v[idx * stride] = rd_f64(cur + 8);
+        cur += OUTLIER_BYTES;
+    }
+    *nout_ret = nout;
+    return (size_t)(cur - p);
+}
+
+int or_decode_block(const uint8_t *stream, size_t len, double *x)
+{
+    if (len < HDR_BYTES || rd_u32(stream) != OR_MAGIC)
+        return OR_EINVAL;
+    int s = stream[6], b = stream[7];
+    if (s < 6 || s > 14 || b < s || b > 40)
+        return OR_EINVAL;
+    if (rd_u32(stream + 12) != len)
+        return OR_EINVAL;
+    double delta = rd_f64(stream + 16);
+    if (!(delta >= 0.0))
+        return OR_EINVAL;
+    const uint8_t *p = stream + HDR_BYTES, *end = stream + len;
+    size_t m = (size_t)1 << s;
+    size_t nseg = (size_t)1 << (b - s);
+    uint32_t nout = 0;
+    for (size_t g = 0; g < nseg; g++) {
+        for (int pl = 0; pl < 2; pl++) {
+            uint32_t no = 0;
+            size_t used = decode_plane(p, end, m, delta, x + 2 * g * m + pl, 2, &no);
+            if (!used)
+                return OR_EINVAL;
+            nout += no;
+            p += used;
+        }
+    }
+    if (p != end || nout != rd_u32(stream + 8))
+        return OR_EINVAL;
+    return OR_OK;
+}
+
+/* normsq of the stored block: pairwise sum over amplitude index of
+ * fl(fl(re*re) + fl(im*im)). */
+static double block_normsq(const double *xh, size_t namp)
+{
+    double *leaf = (double *)malloc(namp * sizeof(double));
+    if (!leaf)
+        return NAN;
+    for (size_t i = 0; i < namp; i++) {
+        double rr = xh[2 * i] * xh[2 * i];
+        double ii = xh[2 * i + 1] * xh[2 * i + 1];
+        leaf[i] = rr + ii;
+    }
+    double r = or_pairwise(leaf, namp);
+    free(leaf);
+    return r;
+}
+
+/* Compress one stride at one error bound: the compress(delta_k, s_j) step of
+ * Alg. 2.  Block stream v1:
+ *   header 32 B: u32 magic | u8 level | u8 0 | u8 s | u8 b | u32 n_outliers |
+ *                u32 total_bytes | f64 delta | f64 normsq
+ *   then for each segment, re plane record then im plane record. */
+static int encode_block_obuf(obuf *o, const double *x, int b, int s,
+                             double delta, int level)
+{
+    size_t m = (size_t)1 << s;
+    size_t nseg = (size_t)1 << (b - s);
+    uint8_t hdr[HDR_BYTES];
+    memset(hdr, 0, sizeof hdr);
+    if (ob_put(o, hdr, HDR_BYTES))
+        return OR_ENOMEM;
+    double *v = (double *)malloc(m * sizeof(double));
+    if (!v)
+        return OR_ENOMEM;
+    uint32_t nout_total = 0;
+    for (size_t g = 0; g < nseg; g++) {
+        for (int pl = 0; pl < 2; pl++) {
+            for (size_t i = 0; i < m; i++)
+                v[i] = x[2 * (g * m + i) + pl];
+            uint32_t no = 0;
+            if (encode_plane(o, v, m, delta, &no)) {
+                free(v);
+                return OR_ENOMEM;
+            }
+            nout_total += no;
+        }
+    }
+    free(v);
+    uint32_t magic = OR_MAGIC, total = (uint32_t)o->len;
+    memcpy(hdr, &magic, 4);
+    hdr[4] = (uint8_t)level;
+    hdr[6] = (uint8_t)s;
+    hdr[7] = (uint8_t)b;
+    memcpy(hdr + 8, &nout_total, 4);
+    memcpy(hdr + 12, &total, 4);
+    memcpy(hdr + 16, &delta, 8);
+    memcpy(o->p, hdr, HDR_BYTES);
+
+    /* normsq from the values a decoder reconstructs from these bytes */
+    size_t namp = (size_t)1 << b;
+    double *xh = (double *)malloc(2 * namp * sizeof(double));
+    if (!xh)
+        return OR_ENOMEM;
+    if (or_decode_block(o->p, o->len, xh)) {
+        free(xh);
+        return OR_EINVAL;
+    }
+    double ns = block_normsq(xh, namp);
+    free(xh);
+    memcpy(o->p + 24, &ns, 8);
+    return OR_OK;
+}
+
+int or_encode_block(const double *x, int b, int s, double delta, int level,
+                    uint8_t *out, size_t cap, size_t *len)
+{
+    if (s < 6 || b < s || b > 30 || !(delta >= 0.0) || level < 0 || level > 255)
+        return OR_EINVAL;
+    obuf o = {0};
+    int rc = encode_block_obuf(&o, x, b, s, delta, level);
+    if (rc) {
+        free(o.p);
+        return rc;
+    }
+    *len = o.len;
+    if (o.len > cap) {
+        free(o.p);
+        return OR_ENOMEM;
+    }
+    memcpy(out, o.p, o.len);
+    free(o.p);
+    return OR_OK;
+}
+
+/* Alg. 2, inner loop for one stride: for delta_k in delta_0..delta_n,
+ * ratio = compress(delta_k, s_j); stop at the first ratio >= theta.  The
+ * ratio is the raw stride size 16*2^b over the stream size, compared as
+ * raw >= theta * size in FP64.  If no level qualifies the loop runs out and
+ * the last level's stream is kept. */
+static int aalc_encode_obuf(obuf *out, const double *x, int b, int s,
+                            const double *ladder, int L, double theta,
+                            uint64_t *sizes)
+{
+    double raw = (double)((uint64_t)16 << b);
+    for (int k = 0; k < L; k++)
+        if (sizes)
+            sizes[k] = 0;
+    for (int k = 0; k < L; k++) {
+        obuf o = {0};
+        int rc = encode_block_obuf(&o, x, b, s, ladder[k], k);
+        if (rc) {
+            free(o.p);
+            return rc;
+        }
+        if (sizes)
+            sizes[k] = o.len;
+        if (raw >= theta * (double)o.len || k == L - 1) {
+            *out = o;
+            return k;
+        }
+        free(o.p);
+    }
+    return OR_EINVAL;
+}
+
+static int ladder_ok(const double *ladder, int L, double theta)
+{
+    if (L < 1 || L > 8 || !(theta >= 1.0) || !isfinite(theta))
+        return 0;
+    for (int k = 0; k < L; k++) {
+        double d = ladder[k];
+        if (!isfinite(d) || d < 0.0)
+            return 0;
+        if (d == 0.0 && k != 0)
+            return 0;
+        if (d > 0.0 && d < 0x1p-30)
+            return 0;
+        if (k > 0 && !(d > ladder[k - 1]))
+            return 0;
+    }
+    return 1;
+}
+
+int or_aalc_encode(const double *x, int b, int s, const double *ladder, int L,
+                   double theta, uint8_t *out, size_t cap, size_t *len,
+                   uint64_t *sizes)
+{
+    if (s < 6 || b < s || b > 30 || !ladder_ok(ladder, L, theta))
+        return OR_EINVAL;
+    obuf o = {0};
+    int k = aalc_encode_obuf(&o, x, b, s, ladder, L, theta, sizes);
+    if (k < 0) {
+        free(o.p);
+        return k;
+    }
+    *len = o.len;
+    if (o.len > cap) {
+        free(o.p);
+        return OR_ENOMEM;
+    }
+    memcpy(out, o.p, o.len);
+    free(o.p);
+    return k;
+}
+
+/* ------------------------------------------------------------------------ */
+/* gates (Sec. II)                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* complex product u*a with one rounding per operation:
+ * re = fl(fl(ur ar) - fl(ui ai)), im = fl(fl(ur ai) + fl(ui ar)) */
+static void cmul(const double *u, const double *a, double *out)
+{
+    double rr = u[0] * a[0];
+    double ii = u[1] * a[1];
+    double ri = u[0] * a[1];
+    double ir = u[1] * a[0];
+    out[0] = rr - ii;
+    out[1] = ri + ir;
+}
+
+/* Coupling mask: amplitude i interacts with i ^ mask (0 = diagonal). */
+static uint64_t gate_mask(const or_gate *g)
+{
+    switch (g->kind) {
+    case OR_G_U:
+    case OR_G_X:
+        return (uint64_t)1 << g->q0;
+    case OR_G_CU:
+        return (uint64_t)1 << g->q1;
+    case OR_G_SWAP:
+        return ((uint64_t)1 << g->q0) | ((uint64_t)1 << g->q1);
+    default:
+        return 0;
+    }
+}
+
+static int gate_valid(const or_gate *g, int n)
+{
+    switch (g->kind) {
+    case OR_G_U:
+    case OR_G_DIAG1:
+    case OR_G_X:
+        return g->q0 >= 0 && g->q0 < n;
+    case OR_G_CU:
+    case OR_G_CPHASE:
+    case OR_G_CZ:
+    case OR_G_SWAP:
+        return g->q0 >= 0 && g->q0 < n && g->q1 >= 0 && g->q1 < n && g->q0 != g->q1;
+    case OR_G_PHASE_FLIP:
+        return g->index < ((uint64_t)1 << n);
+    case OR_G_DIFFUSE:
+        return 1;
+    default:
+        return 0;
+    }
+}
+
+/* A view of up to two blocks of the state by global amplitude index. */
+typedef struct {
+    double *base[2];
+    uint64_t blk[2];
+    int nb;
+    int b;
+} gview;
+
+static double *at(const gview *v, uint64_t i)
+{
+    uint64_t j = i >> v->b;
+    int k = (v->nb == 2 && j == v->blk[1]) ? 1 : 0;
+    return v->base[k] + 2 * (i & (((uint64_t)1 << v->b) - 1));
+}
+
+static int bit(uint64_t i, int q) { return (int)((i >> q) & 1); }
+
+/* Apply gate g to every amplitude of the view.  Pair gates follow the
+ * Sec. II update [a0'; a1'] = U [a0; a1] on indices that differ only in the
+ * target bit; the controlled form acts where the control bit is 1. */
+static void gate_apply(const or_gate *g, const gview *v, const double *tdiff)
+{
+    uint64_t mask = gate_mask(g);
+    uint64_t per = (uint64_t)1 << v->b;
+    const double *u00 = g->u, *u01 = g->u + 2, *u10 = g->u + 4, *u11 = g->u + 6;
+    for (int k = 0; k < v->nb; k++) {
+        for (uint64_t li = 0; li < per; li++) {
+            uint64_t i = (v->blk[k] << v->b) | li;
+            if (mask) {
+                uint64_t j = i ^ mask;
+                if (!(i < j))
+                    continue;
+                double *a = at(v, i), *bb = at(v, j);
+                switch (g->kind) {
+                case OR_G_CU: /* U on the control = 1 subspace */
+                    if (!bit(i, g->q0))
+                        break;
+                    /* fall through */
+                case OR_G_U: {
+                    double p[2], q[2], r[2], t[2];
+                    cmul(u00, a, p);
+                    cmul(u01, bb, q);
+                    cmul(u10, a, r);
+                    cmul(u11, bb, t);
+                    a[0] = p[0] + q[0];
+                    a[1] = p[1] + q[1];
+                    bb[0] = r[0] + t[0];
+                    bb[1] = r[1] + t[1];
+                    break;
+                }
+                case OR_G_X:
+                case OR_G_SWAP:
+                    if (g->kind == OR_G_SWAP && bit(i, g->q0) == bit(i, g->q1))
+                        break;
+                    {
+                        double t0 = a[0], t1 = a[1];
+                        a[0] = bb[0];
+                        a[1] = bb[1];
+                        bb[0] = t0;
+                        bb[1] = t1;
+                    }
+                    break;
+                default:
+                    break;
+                }
+            } else {
+                double *a = at(v, i);
+                switch (g->kind) {
+                case OR_G_DIAG1:
+                    if (bit(i, g->q0)) {
+                        double r[2];
+                        cmul(u11, a, r);
+                        a[0] = r[0];
+                        a[1] = r[1];
+                    }
+                    break;
+                case OR_G_CPHASE:
+                    if (bit(i, g->q0) && bit(i, g->q1)) {
+                        double r[2];
+                        cmul(u11, a, r);
+                        a[0] = r[0];
+                        a[1] = r[1];
+                    }
+                    break;
+                case OR_G_CZ:
+                    if (bit(i, g->q0) && bit(i, g->q1)) {
+                        a[0] = -a[0];
+                        a[1] = -a[1];
+                    }
+                    break;
+                case OR_G_PHASE_FLIP:
+                    if (i == g->index) {
+                        a[0] = -a[0];
+                        a[1] = -a[1];
+                    }
+                    break;
+                case OR_G_DIFFUSE:
+                    /* (2|s><s| - I) psi = 2 mean(psi) - psi, per component */
+                    a[0] = tdiff[0] - a[0];
+                    a[1] = tdiff[1] - a[1];
+                    break;
+                default:
+                    break;
+                }
+            }
+        }
+    }
+}
+
+/* Pairwise mean-doubling for DIFFUSE over a plain array:
+ * t = 2 * (pairwise sum) / 2^n, the division being an exact power-of-two
+ * scaling. */
+static int diffuse_t_plain(const double *amp, int n, double *t)
+{
+    size_t N = (size_t)1 << n;
+    double *tmp = (double *)malloc(N * sizeof(double));
+    if (!tmp)
+        return OR_ENOMEM;
+    for (int c = 0; c < 2; c++) {
+        for (size_t i = 0; i < N; i++)
+            tmp[i] = amp[2 * i + c];
+        t[c] = or_pairwise(tmp, N) * ldexp(1.0, 1 - n);
+    }
+    free(tmp);
+    return OR_OK;
+}
+
+int or_sv_apply_gate(double *amp, int n, const or_gate *g)
+{
+    if (n < 1 || n > 34 || !g || !gate_valid(g, n))
+        return OR_EINVAL;
+    double t[2] = {0.0, 0.0};
+    if (g->kind == OR_G_DIFFUSE && diffuse_t_plain(amp, n, t))
+        return OR_ENOMEM;
+    gview v = {{amp, amp}, {0, 0}, 1, n};
+    gate_apply(g, &v, t);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 2 driver                                                            */
+/* ------------------------------------------------------------------------ */
+
+struct or_sim {
+    int n, b, s, L, normalize;
+    double ladder[8];
+    double theta;
+    uint64_t nblocks;
+    uint8_t **streams;
+    size_t *lens;
+    double normsq, scale;
+    int collapsed;
+    double min_ratio, last_ratio;
+    uint64_t passes;
+    uint64_t level_hist[8];
+};
+
+static void normalize_block(double *x, size_t nscalar, double scale)
+{
+    if (scale == 1.0)
+        return; /* multiplying by 1 is the identity; skipping keeps NaN bits */
+    for (size_t i = 0; i < nscalar; i++)
+        x[i] = x[i] * scale;
+}
+
+/* Decompress, normalise, gateComputation and AALC-compress one group: the
+ * body of Alg. 2 for the stride(s) a gate touches together.  A gate whose
+ * pairs span two strides processes both strides of each coupled pair as one
+ * group (reading of Alg. 1 for high qubits). */
+static int group_run(int n, int b, int s, const double *ladder, int L,
+                     double theta, double scale, const double *tdiff,
+                     const or_gate *g, uint64_t j0, const uint8_t *const *in,
+                     const size_t *inlen, obuf *out, int *levels)
+{
+    (void)n;
+    uint64_t mb = gate_mask(g) >> b;
+    int nb = mb ? 2 : 1;
+    size_t namp = (size_t)1 << b;
+    double *x[2] = {NULL, NULL};
+    int rc = OR_OK;
+    for (int k = 0; k < nb; k++) {
+        x[k] = (double *)malloc(2 * namp * sizeof(double));
+        if (!x[k]) {
+            rc = OR_ENOMEM;
+            goto done;
+        }
+        if (or_decode_block(in[k], inlen[k], x[k])) {
+            rc = OR_EINVAL;
+            goto done;
+        }
+        normalize_block(x[k], 2 * namp, scale);
+    }
+    {
+        gview v = {{x[0], x[1]}, {j0, j0 ^ mb}, nb, b};
+        gate_apply(g, &v, tdiff);
+    }
+    for (int k = 0; k < nb; k++) {
+        int lev = aalc_encode_obuf(&out[k], x[k], b, s, ladder, L, theta, NULL);
+        if (lev < 0) {
+            rc = lev;
+            goto done;
+        }
+        levels[k] = lev;
+    }
+done:
+    free(x[0]);
+    free(x[1]);
+    return rc;
+}
+
+int or_process_group(int n, int b, int s, const double *ladder, int L,
+                     double theta, double scale, const double *tdiff,
+                     const or_gate *g, uint64_t j0, const uint8_t *in0,
+                     size_t len0, const uint8_t *in1, size_t len1,
+                     uint8_t *out0, size_t cap0, size_t *olen0, uint8_t *out1,
+                     size_t cap1, size_t *olen1)
+{
+    if (s < 6 || b < s || b > n || n > 48 || !ladder_ok(ladder, L, theta) ||
+        !g || !gate_valid(g, n) || j0 >= ((uint64_t)1 << (n - b)))
+        return OR_EINVAL;
+    uint64_t mb = gate_mask(g) >> b;
+    if (mb && (j0 ^ mb) < j0)
+        return OR_EINVAL; /* the group is named by its lower block */
+    double t0[2] = {0.0, 0.0};
+    const uint8_t *in[2] = {in0, in1};
+    size_t inl[2] = {len0, len1};
+    obuf out[2] = {{0}, {0}};
+    int lev[2];
+    int rc = group_run(n, b, s, ladder, L, theta, scale, tdiff ? tdiff : t0, g,
+                       j0, in, inl, out, lev);
+    if (rc == OR_OK) {
+        *olen0 = out[0].len;
+        if (out[0].len > cap0)
+            rc = OR_ENOMEM;
+        else
+            memcpy(out0, out[0].p, out[0].len);
+        if (mb) {
+            *olen1 = out[1].len;
+            if (out[1].len > cap1)
+                rc = OR_ENOMEM;
+            else
+                memcpy(out1, out[1].p, out[1].len);
+        }
+    }
+    free(out[0].p);
+    free(out[1].p);
+    return rc;
+}
+
+static double stream_normsq(const uint8_t *p) { return rd_f64(p + 24); }
+
+/* N^2 = pairwise over blocks of the per-block normsq (the block sums are the
+ * aligned subtrees of the tree over all 2^n amplitudes); s = 1/sqrt(N^2),
+ * applied before the next gate (Sec. III: the state vector is normalised
+ * before the gate computation). */
+static void update_norm(or_sim *sim)
+{
+    double *v = (double *)malloc(sim->nblocks * sizeof(double));
+    uint64_t total = 0;
+    for (uint64_t j = 0; j < sim->nblocks; j++) {
+        v[j] = stream_normsq(sim->streams[j]);
+        total += sim->lens[j];
+    }
+    sim->normsq = or_pairwise(v, sim->nblocks);
+    free(v);
+    double N2 = sim->normsq;
+    if (N2 > 0.0 && isfinite(N2)) {
+        if (sim->normalize)
+            sim->scale = 1.0 / sqrt(N2);
+    } else {
+        sim->collapsed = 1;
+        sim->scale = 1.0;
+    }
+    double raw = (double)((uint64_t)16 << sim->n);
+    sim->last_ratio = raw / (double)total;
+    if (sim->passes == 0 || sim->last_ratio < sim->min_ratio)
+        sim->min_ratio = sim->last_ratio;
+}
+
+or_sim *or_create(int n, int b, int s, const double *ladder, int L,
+                  double theta, int normalize)
+{
+    if (n < 6 || n > 40 || b < 6 || b > n || b > 30 || s < 6 || s > 14 || s > b ||
+        !ladder_ok(ladder, L, theta))
+        return NULL;
+    or_sim *sim = (or_sim *)calloc(1, sizeof *sim);
+    if (!sim)
+        return NULL;
+    sim->n = n;
+    sim->b = b;
+    sim->s = s;
+    sim->L = L;
+    sim->normalize = normalize ? 1 : 0;
+    memcpy(sim->ladder, ladder, (size_t)L * sizeof(double));
+    sim->theta = theta;
+    sim->nblocks = (uint64_t)1 << (n - b);
+    sim->streams = (uint8_t **)calloc(sim->nblocks, sizeof(uint8_t *));
+    sim->lens = (size_t *)calloc(sim->nblocks, sizeof(size_t));
+    if (!sim->streams || !sim->lens || or_set_basis(sim, 0)) {
+        or_destroy(sim);
+        return NULL;
+    }
+    return sim;
+}
+
+void or_destroy(or_sim *sim)
+{
+    if (!sim)
+        return;
+    if (sim->streams)
+        for (uint64_t j = 0; j < sim->nblocks; j++)
+            free(sim->streams[j]);
+    free(sim->streams);
+    free(sim->lens);
+    free(sim);
+}
+
+int or_set_basis(or_sim *sim, uint64_t x)
+{
+    if (!sim || x >= ((uint64_t)1 << sim->n))
+        return OR_EINVAL;
+    size_t namp = (size_t)1 << sim->b;
+    double *blk = (double *)calloc(2 * namp, sizeof(double));
+    if (!blk)
+        return OR_ENOMEM;
+    for (uint64_t j = 0; j < sim->nblocks; j++) {
+        int has = (x >> sim->b) == j;
+        if (has)
+            blk[2 * (x & (namp - 1))] = 1.0;
+        obuf o = {0};
+        int lev = aalc_encode_obuf(&o, blk, sim->b, sim->s, sim->ladder, sim->L,
+                                   sim->theta, NULL);
+        if (has)
+            blk[2 * (x & (namp - 1))] = 0.0;
+        if (lev < 0) {
+            free(blk);
+            free(o.p);
+            return lev;
+        }
+        free(sim->streams[j]);
+        sim->streams[j] = o.p;
+        sim->lens[j] = o.len;
+    }
+    free(blk);
+    sim->collapsed = 0;
+    sim->scale = 1.0;
+    sim->passes = 0;
+    memset(sim->level_hist, 0, sizeof sim->level_hist);
+    update_norm(sim);
+    return OR_OK;
+}
+
+/* S = pairwise over all amplitudes of the normalised decoded values (per
+ * component), t = 2 S / 2^n.  Block sums are aligned subtrees. */
+static int diffuse_t_sim(const or_sim *sim, double *t)
+{
+    size_t namp = (size_t)1 << sim->b;
+    double *x = (double *)malloc(2 * namp * sizeof(double));
+    double *tmp = (double *)malloc(namp * sizeof(double));
+    double *bs[2];
+    bs[0] = (double *)malloc(sim->nblocks * sizeof(double));
+    bs[1] = (double *)malloc(sim->nblocks * sizeof(double));
+    int rc = OR_ENOMEM;
+    if (!x || !tmp || !bs[0] || !bs[1])
+        goto done;
+    for (uint64_t j = 0; j < sim->nblocks; j++) {
+        rc = or_decode_block(sim->streams[j], sim->lens[j], x);
+        if (rc)
+            goto done;
+        normalize_block(x, 2 * namp, sim->scale);
+        for (int c = 0; c < 2; c++) {
+            for (size_t i = 0; i < namp; i++)
+                tmp[i] = x[2 * i + c];
+            bs[c][j] = or_pairwise(tmp, namp);
+        }
+    }
+    for (int c = 0; c < 2; c++)
+        t[c] = or_pairwise(bs[c], sim->nblocks) * ldexp(1.0, 1 - sim->n);
+    rc = OR_OK;
+done:
+    free(x);
+    free(tmp);
+    free(bs[0]);
+    free(bs[1]);
+    return rc;
+}
+
+/* Alg. 2: for each gate, for each stride (group): decompress, normalize,
+ * gateComputation, AALC compress.  Every block is re-encoded on every gate,
+ * including blocks the gate leaves unchanged, as Alg. 1 states. */
+int or_apply_gate(or_sim *sim, const or_gate *g)
+{
+    if (!sim || !g || !gate_valid(g, sim->n))
+        return OR_EINVAL;
+    double t[2] = {0.0, 0.0};
+    if (g->kind == OR_G_DIFFUSE) {
+        int rc = diffuse_t_sim(sim, t);
+        if (rc)
+            return rc;
+    }
+    uint64_t mb = gate_mask(g) >> sim->b;
+    uint8_t **ns = (uint8_t **)calloc(sim->nblocks, sizeof(uint8_t *));
+    size_t *nl = (size_t *)calloc(sim->nblocks, sizeof(size_t));
+    int hist[8] = {0};
+    int rc = OR_OK;
+    if (!ns || !nl) {
+        rc = OR_ENOMEM;
+        goto fail;
+    }
+    for (uint64_t j = 0; j < sim->nblocks; j++) {
+        if (mb && (j ^ mb) < j)
+            continue;
+        const uint8_t *in[2] = {sim->streams[j], mb ? sim->streams[j ^ mb] : NULL};
+        size_t inl[2] = {sim->lens[j], mb ? sim->lens[j ^ mb] : 0};
+        obuf out[2] = {{0}, {0}};
+        int lev[2] = {0, 0};
+        rc = group_run(sim->n, sim->b, sim->s, sim->ladder, sim->L, sim->theta,
+                       sim->scale, t, g, j, in, inl, out, lev);
+        if (rc) {
+            free(out[0].p);
+            free(out[1].p);
+            goto fail;
+        }
+        ns[j] = out[0].p;
+        nl[j] = out[0].len;
+        hist[lev[0]]++;
+        if (mb) {
+            ns[j ^ mb] = out[1].p;
+            nl[j ^ mb] = out[1].len;
+            hist[lev[1]]++;
+        }
+    }
+    for (uint64_t j = 0; j < sim->nblocks; j++) {
+        free(sim->streams[j]);
+        sim->streams[j] = ns[j];
+        sim->lens[j] = nl[j];
+    }
+    free(ns);
+    free(nl);
+    for (int k = 0; k < 8; k++)
+        sim->level_hist[k] += (uint64_t)hist[k];
+    sim->passes++;
+    update_norm(sim);
+    return sim->collapsed ? OR_ECOLLAPSED : OR_OK;
+fail:
+    if (ns)
+        for (uint64_t j = 0; j < sim->nblocks; j++)
+            free(ns[j]);
+    free(ns);
+    free(nl);
+    return rc;
+}
+
+int or_get_amplitudes(const or_sim *sim, uint64_t first, uint64_t count,
+                      double *out)
+{
+    if (!sim || first + count > ((uint64_t)1 << sim->n) || first + count < first)
+        return OR_EINVAL;
+    size_t namp = (size_t)1 << sim->b;
+    double *x = (double *)malloc(2 * namp * sizeof(double));
+    if (!x)
+        return OR_ENOMEM;
+    uint64_t cur = ~(uint64_t)0;
+    for (uint64_t k = 0; k < count; k++) {
+        uint64_t i = first + k, j = i >> sim->b;
+        if (j != cur) {
+            if (or_decode_block(sim->streams[j], sim->lens[j], x)) {
+                free(x);
+                return OR_EINVAL;
+            }
+            normalize_block(x, 2 * namp, sim->scale);
+            cur = j;
+        }
+        out[2 * k] = x[2 * (i & (namp - 1))];
+        out[2 * k + 1] = x[2 * (i & (namp - 1)) + 1];
+    }
+    free(x);
+    return OR_OK;
+}
+
+int or_export_block(const or_sim *sim, uint64_t j, uint8_t *buf, size_t cap,
+                    size_t *len)
+{
+    if (!sim || j >= sim->nblocks)
+        return OR_EINVAL;
+    *len = sim->lens[j];
+    if (cap < sim->lens[j])
+        return OR_ENOMEM;
+    memcpy(buf, sim->streams[j], sim->lens[j]);
+    return OR_OK;
+}
+
+int or_get_stats(const or_sim *sim, or_stats *st)
+{
+    if (!sim || !st)
+        return OR_EINVAL;
+    memset(st, 0, sizeof *st);
+    st->normsq = sim->normsq;
+    st->scale = sim->scale;
+    st->collapsed = sim->collapsed;
+    for (uint64_t j = 0; j < sim->nblocks; j++)
+        st->resident_bytes += sim->lens[j];
+    st->min_ratio = sim->min_ratio;
+    st->last_ratio = sim->last_ratio;
+    st->passes = sim->passes;
+    memcpy(st->level_hist, sim->level_hist, sizeof st->level_hist);
+    return OR_OK;
+}
+
+/* Outcome probabilities of the listed qubits: P(o) = sum over indices whose
+ * listed bits spell o of |a_i|^2, a = normalised amplitudes, ascending i. */
+int or_measure_probs(const or_sim *sim, const int *qubits, int nq,
+                     double *probs)
+{
+    if (!sim || nq < 1 || nq > 24)
+        return OR_EINVAL;
+    for (int k = 0; k < nq; k++) {
+        if (qubits[k] < 0 || qubits[k] >= sim->n)
+            return OR_EINVAL;
+        for (int m = 0; m < k; m++)
+            if (qubits[m] == qubits[k])
+                return OR_EINVAL;
+    }
+    memset(probs, 0, ((size_t)1 << nq) * sizeof(double));
+    size_t namp = (size_t)1 << sim->b;
+    double *x = (double *)malloc(2 * namp * sizeof(double));
+    if (!x)
+        return OR_ENOMEM;
+    for (uint64_t j = 0; j < sim->nblocks; j++) {
+        if (or_decode_block(sim->streams[j], sim->lens[j], x)) {
+            free(x);
+            return OR_EINVAL;
+        }
+        normalize_block(x, 2 * namp, sim->scale);
+        for (size_t li = 0; li < namp; li++) {
+            uint64_t i = (j << sim->b) | li;
+            uint64_t o = 0;
+            for (int k = 0; k < nq; k++)
+                o |= (uint64_t)bit(i, qubits[k]) << k;
+            double rr = x[2 * li] * x[2 * li];
+            double ii = x[2 * li + 1] * x[2 * li + 1];
+            probs[o] += rr + ii;
+        }
+    }
+    free(x);
+    return OR_OK;
+}
+
+/* Pure-state fidelity (Sec. II) with the modulus squared and both norms
+ * divided out, so that it lies in [0, 1] for any two non-zero vectors. */
+double or_fidelity(const double *a, const double *b, int n)
+{
+    size_t N = (size_t)1 << n;
+    double *re = (double *)malloc(N * sizeof(double));
+    double *im = (double *)malloc(N * sizeof(double));
+    double *na = (double *)malloc(N * sizeof(double));
+    double *nb = (double *)malloc(N * sizeof(double));
+    double F = NAN;
+    if (re && im && na && nb) {
+        for (size_t i = 0; i < N; i++) {
+            double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
+            double p1 = ar * br, p2 = ai * bi, p3 = ar * bi, p4 = ai * br;
+            re[i] = p1 + p2; /* conj(a) b */
+            im[i] = p3 - p4;
+            double q1 = ar * ar, q2 = ai * ai, q3 = br * br, q4 = bi * bi;
+            na[i] = q1 + q2;
+            nb[i] = q3 + q4;
+        }
+        double R = or_pairwise(re, N), I = or_pairwise(im, N);
+        double A = or_pairwise(na, N), B = or_pairwise(nb, N);
+        double num = R * R + I * I;
+        F = num / (A * B);
+    }
+    free(re);
+    free(im);
+    free(na);
+    free(nb);
+    return F;
+}

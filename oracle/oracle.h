@@ -1,0 +1,141 @@
+/*
+ * oracle.h -- plain FP64 CPU reference for amplitude-aware lossy compressed
+ * state-vector simulation (Wu, Di, Cappello, Finkel, Alexeev, Chong,
+ * "Amplitude-Aware Lossy Compression for Quantum Circuit Simulation").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source with the GPU path: both are
+ * written from the paper and from the block-stream format definition.
+ *
+ * Conventions
+ *   - Qubit q is bit q of the amplitude index (little-endian).
+ *   - A state of n qubits is 2^n complex doubles, stored interleaved (re, im).
+ *   - A block (the paper's "stride", Sec. III) is 2^b consecutive amplitudes.
+ *   - A segment is 2^s consecutive amplitudes inside a block (6 <= s <= b).
+ *   - Every floating-point operation is one IEEE binary64 operation; the file
+ *     is compiled with -ffp-contract=off so no fused multiply-add appears.
+ */
+#ifndef AALC_ORACLE_H
+#define AALC_ORACLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    OR_OK = 0,
+    OR_EINVAL = -1,
+    OR_ENOMEM = -2,
+    OR_ECOLLAPSED = -5
+};
+
+/* Gate kinds (same numbering as the product header, defined independently). */
+enum {
+    OR_G_U = 1,          /* 2x2 unitary u on qubit q0 (Sec. II pair update) */
+    OR_G_DIAG1 = 2,      /* diag(1, u11) on qubit q0 */
+    OR_G_CU = 3,         /* u on target q1 where control q0 is 1 (Sec. II) */
+    OR_G_CPHASE = 4,     /* amplitude with bits q0 and q1 set times u11 */
+    OR_G_CZ = 5,         /* amplitude with bits q0 and q1 set negated */
+    OR_G_SWAP = 6,       /* exchange qubits q0 and q1 */
+    OR_G_X = 7,          /* exchange the pair on qubit q0 */
+    OR_G_PHASE_FLIP = 8, /* amplitude at index `index` negated */
+    OR_G_DIFFUSE = 9     /* 2|s><s| - I over all n qubits */
+};
+
+/* u holds a 2x2 complex matrix row-major: u00=(u[0],u[1]) u01=(u[2],u[3])
+ * u10=(u[4],u[5]) u11=(u[6],u[7]). */
+typedef struct {
+    uint32_t kind;
+    int32_t q0, q1;
+    uint32_t pad;
+    uint64_t index;
+    double u[8];
+} or_gate;
+
+/* ---- building blocks, exposed so tests can pin each one ---------------- */
+
+/* Perfect-binary-tree sum of m = 2^k values (m >= 1). */
+double or_pairwise(const double *v, size_t m);
+
+/* Encode one block (2^b interleaved complex values) at error bound `delta`
+ * (0 = lossless) into the block stream v1.  `level` is recorded in the
+ * header.  Writes up to cap bytes, sets *len to the stream length (also when
+ * cap is too small, in which case OR_ENOMEM is returned and nothing useful is
+ * written).  The header's normsq field is filled from the decoded values. */
+int or_encode_block(const double *x, int b, int s, double delta, int level,
+                    uint8_t *out, size_t cap, size_t *len);
+
+/* Decode a block stream into 2^b interleaved complex values (the stored,
+ * unnormalised x-hat).  Returns OR_EINVAL on a malformed stream. */
+int or_decode_block(const uint8_t *stream, size_t len, double *x);
+
+/* Alg. 2 inner loop on one block: compress at ladder levels 0,1,... in order
+ * and stop at the first whose ratio 16*2^b / size reaches theta; otherwise the
+ * last level.  sizes[k] receives the stream size of every level tried (the
+ * untried ones are set to 0).  Returns the chosen level or a negative code. */
+int or_aalc_encode(const double *x, int b, int s, const double *ladder, int L,
+                   double theta, uint8_t *out, size_t cap, size_t *len,
+                   uint64_t *sizes);
+
+/* Plain state-vector gate on a full 2^n complex array (no compression, no
+ * normalisation).  DIFFUSE uses the mean of the array itself. */
+int or_sv_apply_gate(double *amp, int n, const or_gate *g);
+
+/* ---- compressed simulator (Alg. 2 driver) ------------------------------ */
+
+typedef struct or_sim or_sim;
+
+/* ladder: L strictly increasing error bounds, ladder[0] may be 0 (lossless),
+ * 1 <= L <= 8, theta >= 1.  The state starts as |0...0>. */
+or_sim *or_create(int n, int b, int s, const double *ladder, int L,
+                  double theta, int normalize);
+void or_destroy(or_sim *sim);
+int or_set_basis(or_sim *sim, uint64_t x);
+int or_apply_gate(or_sim *sim, const or_gate *g);
+
+/* Normalised amplitudes fl(xhat * scale) for indices [first, first+count). */
+int or_get_amplitudes(const or_sim *sim, uint64_t first, uint64_t count,
+                      double *out);
+int or_export_block(const or_sim *sim, uint64_t j, uint8_t *buf, size_t cap,
+                    size_t *len);
+
+typedef struct {
+    double normsq;           /* N^2 of the stored state after the last pass */
+    double scale;            /* s applied at the next decode */
+    int32_t collapsed;       /* N^2 was 0 or not finite */
+    int32_t pad;
+    uint64_t resident_bytes; /* sum of stream lengths */
+    double min_ratio;        /* min over passes (and the initial encode) */
+    double last_ratio;
+    uint64_t passes;
+    uint64_t level_hist[8];  /* blocks encoded at each level, all passes */
+} or_stats;
+int or_get_stats(const or_sim *sim, or_stats *st);
+
+/* Probability of every outcome of the listed qubits (2^nq doubles). */
+int or_measure_probs(const or_sim *sim, const int *qubits, int nq,
+                     double *probs);
+
+/* One group of Alg. 2 on its own: decode the input streams of the group
+ * (block j0, and block j0 ^ (mask >> b) when the gate couples two blocks),
+ * normalise with `scale`, apply the gate, re-encode each block with the
+ * ladder.  tdiff holds 2*mean (re, im) for DIFFUSE.  Used for sampled parity
+ * at sizes where the whole state does not fit in host memory. */
+int or_process_group(int n, int b, int s, const double *ladder, int L,
+                     double theta, double scale, const double *tdiff,
+                     const or_gate *g, uint64_t j0, const uint8_t *in0,
+                     size_t len0, const uint8_t *in1, size_t len1,
+                     uint8_t *out0, size_t cap0, size_t *olen0, uint8_t *out1,
+                     size_t cap1, size_t *olen1);
+
+/* Fidelity |<a|b>|^2 / (<a|a><b|b>) of two 2^n complex arrays. */
+double or_fidelity(const double *a, const double *b, int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
