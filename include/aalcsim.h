@@ -1,0 +1,176 @@
+/*
+ * aalcsim.h -- C ABI of libaalcsim.so: amplitude-aware lossy-compressed
+ * state-vector simulation on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Wu, Di, Cappello, Finkel, Alexeev, Chong, "Amplitude-Aware Lossy
+ * Compression for Quantum Circuit Simulation".  The state vector of n qubits
+ * (2^n complex doubles, Sec. II) is never held uncompressed: it is split into
+ * blocks ("strides", Sec. III) of 2^b amplitudes, each stored as a compressed
+ * block stream in device memory.  Every gate runs the loop of Alg. 2 on every
+ * block: decompress, normalise, apply the gate, compress at the error bounds
+ * delta_0 < delta_1 < ... of the ladder until the ratio reaches theta.
+ *
+ * Conventions for every entry point
+ *   - Qubit q is bit q of the amplitude index.
+ *   - Pointers named host_* or documented as host are host memory, borrowed
+ *     for the duration of the call only.  Device memory is owned by the sim
+ *     unless it came from sim_context_create.
+ *   - Calls on one sim are ordered on that sim's HIP stream.  sim_apply_gate
+ *     is asynchronous; every call that returns data to the host synchronises
+ *     the stream first.  A sim is not thread-safe; different sims are
+ *     independent.
+ *   - Return codes are SIM_OK (0) or a negative SIM_E* code.  Validation
+ *     failures leave the state unchanged.  sim_last_error() gives a
+ *     thread-local text for the last failure.
+ *   - Errors found on the device during an asynchronous pass (arena
+ *     overflow) are reported by the next synchronising call: the state is
+ *     rolled back to the input of the failing gate and that gate and the ones
+ *     queued after it are dropped; the call returns SIM_ENOMEM.
+ */
+#ifndef AALCSIM_H
+#define AALCSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sim sim_t;
+
+enum {
+    SIM_OK = 0,
+    SIM_EINVAL = -1,        /* bad argument */
+    SIM_ENOMEM = -2,        /* device allocation or arena capacity exhausted */
+    SIM_EBUDGET = -3,       /* reserved for budgeted contexts */
+    SIM_EDEVICE = -4,       /* HIP runtime error */
+    SIM_ECOLLAPSED = -5,    /* N^2 of the stored state was 0 or not finite */
+    SIM_EUNSUPPORTED = -6   /* valid request this build does not implement */
+};
+
+/* Gate kinds.  u is a 2x2 complex matrix, row-major, (re, im) pairs:
+ * u00=(u[0],u[1]) u01=(u[2],u[3]) u10=(u[4],u[5]) u11=(u[6],u[7]).
+ * Matrices and phases are computed by the caller; the library applies them
+ * with one IEEE binary64 rounding per multiply and add (no fused
+ * multiply-add), so results are reproducible bit for bit. */
+enum {
+    G_U = 1,          /* u on qubit q0: pair update of Sec. II */
+    G_DIAG1 = 2,      /* diag(1, u11) on qubit q0 (T, S, Z, phase) */
+    G_CU = 3,         /* u on target q1 where control q0 is 1 (Sec. II) */
+    G_CPHASE = 4,     /* amplitude with bits q0 and q1 set times u11 */
+    G_CZ = 5,         /* amplitude with bits q0 and q1 set negated */
+    G_SWAP = 6,       /* exchange qubits q0 and q1 */
+    G_X = 7,          /* exchange the two amplitudes of each pair on q0 */
+    G_PHASE_FLIP = 8, /* amplitude at `index` negated (Grover oracle, Sec. IV) */
+    G_DIFFUSE = 9     /* 2|s><s| - I on all qubits (Grover diffusion) */
+};
+
+typedef struct {
+    uint32_t kind;
+    int32_t q0, q1;
+    uint32_t pad;     /* must be 0 */
+    uint64_t index;   /* G_PHASE_FLIP only */
+    double u[8];
+} sim_gate_t;
+
+typedef struct {
+    double normsq;             /* N^2 of the stored state after the last pass */
+    double scale;              /* s = 1/sqrt(N^2), applied at the next decode */
+    int32_t collapsed;         /* N^2 was 0 or not finite at some pass */
+    int32_t compressed;        /* 0 for the uncompressed path */
+    uint64_t resident_bytes;   /* bytes of block streams now (compressed) */
+    uint64_t peak_resident;    /* max over passes of resident_bytes */
+    double min_ratio;          /* min over passes of 16*2^n / resident_bytes */
+    double last_ratio;
+    uint64_t passes;           /* gates applied since the last set_basis */
+    uint64_t level_hist[8];    /* blocks encoded at each ladder level */
+    uint64_t arena_bytes;      /* capacity of each of the two arenas */
+    uint64_t device_bytes;     /* all device memory held by the sim */
+} sim_stats_t;
+
+/* Create an n-qubit state |0...0> with blocks of 2^block_log2 amplitudes
+ * (the AALC decision unit; clamped to n; 6 <= block_log2; 6 <= n <= 40).
+ *   error_bound > 0 : AALC ladder (0, eb/1000, eb/100, eb/10, eb), theta 4
+ *                     (Alg. 2: lossless first, then growing bounds).
+ *   error_bound == 0: lossless only.
+ *   error_bound < 0 : uncompressed FP64 state vector (n <= 34), the
+ *                     "no compression" comparator of Sec. IV.
+ * Two arenas of compressed streams are allocated (ping-pong between
+ * passes); their size is min(1.05 * 16 * 2^n + 1 MiB, 8 GiB) each unless
+ * sim_create_ex gives one.  Returns NULL on failure (sim_last_error()). */
+sim_t *sim_create(int n_qubits, int block_log2, double error_bound);
+
+/* As sim_create, with an explicit capacity per arena (0 = default) and a
+ * HIP stream (NULL = a stream created and owned by the sim). */
+sim_t *sim_create_ex(int n_qubits, int block_log2, double error_bound,
+                     uint64_t arena_bytes, void *hip_stream);
+
+void sim_destroy(sim_t *sim);
+
+/* Apply one gate (Alg. 2 for every block).  Asynchronous on the sim stream;
+ * the gate record is copied.  Returns SIM_EINVAL for an invalid gate (qubit
+ * out of range, equal qubits, index >= 2^n, unknown kind, pad != 0). */
+int sim_apply_gate(sim_t *sim, const sim_gate_t *gate);
+
+/* Apply `count` gates in order (same contract as sim_apply_gate; stops at
+ * the first invalid gate, whose position is in sim_last_error()). */
+int sim_apply_gates(sim_t *sim, const sim_gate_t *gates, size_t count);
+
+/* Probabilities of every outcome of `qubits` (nq distinct qubits, 1..24):
+ * probs[o] = sum over indices whose listed bits spell o (bit k of o is
+ * qubit qubits[k]) of |a_i|^2 for the normalised amplitudes a = s * xhat.
+ * probs is host memory of 2^nq doubles.  Synchronises. */
+int sim_measure_probs(sim_t *sim, const int *qubits, int nq, double *probs);
+
+/* Fidelity of two states with the same n (Sec. II, with the modulus squared
+ * and both norms divided out): F = |<a|b>|^2 / (<a|a><b|b>).  Either sim may
+ * be compressed or uncompressed.  Synchronises. */
+int sim_fidelity(sim_t *a, sim_t *b, double *F);
+
+/* Replace the state by the basis state |x> (x < 2^n); resets stats. */
+int sim_set_basis(sim_t *sim, uint64_t x);
+
+/* Set the AALC ladder: L (1..8) strictly increasing error bounds, ladder[0]
+ * may be 0 (lossless), every lossy bound >= 2^-30, theta >= 1.  Takes effect
+ * for the next pass.  SIM_EINVAL otherwise, SIM_EUNSUPPORTED on the
+ * uncompressed path. */
+int sim_set_aalc(sim_t *sim, const double *ladder, int L, double theta);
+
+/* Turn the normalisation before each gate (Sec. III) on (default) or off. */
+int sim_set_normalize(sim_t *sim, int on);
+
+/* Copy normalised amplitudes s * xhat for indices [first, first+count) to
+ * host memory `out` as interleaved (re, im) doubles.  Synchronises. */
+int sim_get_amplitudes(sim_t *sim, uint64_t first, uint64_t count,
+                       double *out);
+
+/* Copy the canonical block stream v1 of block j to host memory buf (cap
+ * bytes); *len receives its length (also when cap is too small, in which
+ * case SIM_ENOMEM is returned).  Synchronises. */
+int sim_export_block(sim_t *sim, uint64_t j, void *buf, size_t cap,
+                     size_t *len);
+
+/* Statistics of the stored state.  Synchronises. */
+int sim_stats(sim_t *sim, sim_stats_t *st);
+
+/* Wait for all queued work of the sim; reports device-side errors. */
+int sim_sync(sim_t *sim);
+
+/* Use `hip_stream` (a hipStream_t, e.g. a torch stream's handle) for all
+ * later work of the sim.  The previous work is synchronised first. */
+int sim_set_stream(sim_t *sim, void *hip_stream);
+
+/* Self-test hook for the normalisation scalar: out[i] = 1/sqrt(in[i])
+ * computed on the device by the same code that derives s from N^2 (one
+ * correctly rounded sqrt, one correctly rounded division).  in and out are
+ * host arrays of count doubles.  Uses the default device. */
+int sim_debug_rsqrt(const double *in, double *out, size_t count);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char *sim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

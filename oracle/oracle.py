@@ -194,6 +194,8 @@ def sv_run(n, gates, basis=0):
 def fidelity(a, b, n):
     ai = _as_complex_interleaved(a)
     bi = _as_complex_interleaved(b)
+    if ai.size != 2 << n or bi.size != 2 << n:
+        raise ValueError("fidelity needs two arrays of 2^n complex values")
     return lib().or_fidelity(_dp(ai), _dp(bi), n)
 
 

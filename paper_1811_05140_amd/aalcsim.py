@@ -1,0 +1,257 @@
+"""ctypes binding of libaalcsim.so (include/aalcsim.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of the library.  The library must have been built (see build.py);
+importing this module on a machine without it raises ImportError instead of
+falling back to anything else.
+
+Gates are tuples (kind, q0, q1, index, u) as produced by `inputs`.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaalcsim.so")
+
+SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EBUDGET, SIM_EDEVICE, SIM_ECOLLAPSED, \
+    SIM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+
+EXPORTS = [
+    "sim_create", "sim_create_ex", "sim_destroy", "sim_apply_gate",
+    "sim_apply_gates", "sim_measure_probs", "sim_fidelity", "sim_set_basis",
+    "sim_set_aalc", "sim_set_normalize", "sim_get_amplitudes",
+    "sim_export_block", "sim_stats", "sim_sync", "sim_set_stream",
+    "sim_debug_rsqrt", "sim_last_error",
+]
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+class CollapsedError(SimError):
+    pass
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("q0", ctypes.c_int32),
+                ("q1", ctypes.c_int32), ("pad", ctypes.c_uint32),
+                ("index", ctypes.c_uint64), ("u", ctypes.c_double * 8)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("normsq", ctypes.c_double), ("scale", ctypes.c_double),
+                ("collapsed", ctypes.c_int32), ("compressed", ctypes.c_int32),
+                ("resident_bytes", ctypes.c_uint64),
+                ("peak_resident", ctypes.c_uint64),
+                ("min_ratio", ctypes.c_double), ("last_ratio", ctypes.c_double),
+                ("passes", ctypes.c_uint64),
+                ("level_hist", ctypes.c_uint64 * 8),
+                ("arena_bytes", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            "libaalcsim.so is not built (run `python -c 'import __graft_entry__ as g; "
+            "g.build()'` or python paper_1811_05140_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    dp = P(ctypes.c_double)
+    L.sim_create.restype = vp
+    L.sim_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double]
+    L.sim_create_ex.restype = vp
+    L.sim_create_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                ctypes.c_uint64, vp]
+    L.sim_destroy.argtypes = [vp]
+    L.sim_destroy.restype = None
+    L.sim_apply_gate.argtypes = [vp, P(Gate)]
+    L.sim_apply_gates.argtypes = [vp, P(Gate), ctypes.c_size_t]
+    L.sim_measure_probs.argtypes = [vp, P(ctypes.c_int), ctypes.c_int, dp]
+    L.sim_fidelity.argtypes = [vp, vp, dp]
+    L.sim_set_basis.argtypes = [vp, ctypes.c_uint64]
+    L.sim_set_aalc.argtypes = [vp, dp, ctypes.c_int, ctypes.c_double]
+    L.sim_set_normalize.argtypes = [vp, ctypes.c_int]
+    L.sim_get_amplitudes.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, dp]
+    L.sim_export_block.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t,
+                                   P(ctypes.c_size_t)]
+    L.sim_stats.argtypes = [vp, P(Stats)]
+    L.sim_sync.argtypes = [vp]
+    L.sim_set_stream.argtypes = [vp, vp]
+    L.sim_debug_rsqrt.argtypes = [dp, dp, ctypes.c_size_t]
+    L.sim_last_error.restype = ctypes.c_char_p
+    L.sim_last_error.argtypes = []
+    return L
+
+
+lib = _load()
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def last_error():
+    return lib.sim_last_error().decode(errors="replace")
+
+
+def check(rc, allow_collapsed=False):
+    if rc == SIM_OK:
+        return rc
+    if rc == SIM_ECOLLAPSED:
+        if allow_collapsed:
+            return rc
+        raise CollapsedError(rc, last_error())
+    raise SimError(rc, last_error())
+
+
+def make_gate(g):
+    kind, q0, q1, index, u = g
+    out = Gate()
+    out.kind, out.q0, out.q1, out.pad, out.index = kind, q0, q1, 0, index
+    for k in range(8):
+        out.u[k] = float(u[k])
+    return out
+
+
+def gate_array(gates):
+    arr = (Gate * len(gates))()
+    for k, g in enumerate(gates):
+        arr[k] = make_gate(g)
+    return arr
+
+
+def _stream_handle(stream):
+    """Accept None, an int handle or a torch.cuda.Stream."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Sim:
+    """One simulated state on the GPU.
+
+    error_bound > 0: default AALC ladder (0, eb/1000, eb/100, eb/10, eb), theta 4;
+    error_bound == 0: lossless only; error_bound < 0: uncompressed FP64.
+    """
+
+    def __init__(self, n, block_log2, error_bound, arena_bytes=0, stream=None,
+                 ladder=None, theta=None, normalize=True):
+        self._stream_obj = stream  # keep a torch stream alive
+        self.h = lib.sim_create_ex(n, block_log2, float(error_bound),
+                                   int(arena_bytes), _stream_handle(stream))
+        if not self.h:
+            raise SimError(SIM_EINVAL, last_error())
+        self.n = n
+        self.b = min(block_log2, n)
+        self.compressed = not error_bound < 0
+        if ladder is not None:
+            self.set_aalc(ladder, 4.0 if theta is None else theta)
+        if not normalize:
+            self.set_normalize(False)
+        if ladder is not None or not normalize:
+            self.set_basis(0)  # encode the initial state under these settings
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- state --------------------------------------------------------------
+    def set_basis(self, x):
+        check(lib.sim_set_basis(self.h, int(x)))
+
+    def set_aalc(self, ladder, theta):
+        lad = np.ascontiguousarray(ladder, dtype=np.float64)
+        check(lib.sim_set_aalc(self.h, _dp(lad), lad.size, float(theta)))
+
+    def set_normalize(self, on):
+        check(lib.sim_set_normalize(self.h, 1 if on else 0))
+
+    def set_stream(self, stream):
+        self._stream_obj = stream
+        check(lib.sim_set_stream(self.h, _stream_handle(stream)))
+
+    def apply(self, gate):
+        g = make_gate(gate)
+        check(lib.sim_apply_gate(self.h, ctypes.byref(g)))
+
+    def run(self, gates):
+        arr = gate_array(gates)
+        check(lib.sim_apply_gates(self.h, arr, len(gates)))
+
+    def sync(self, allow_collapsed=True):
+        return check(lib.sim_sync(self.h), allow_collapsed)
+
+    # -- queries ------------------------------------------------------------
+    def amplitudes(self, first=0, count=None):
+        if count is None:
+            count = (1 << self.n) - first
+        out = np.zeros(2 * count, dtype=np.float64)
+        check(lib.sim_get_amplitudes(self.h, first, count, _dp(out)), True)
+        return out[0::2] + 1j * out[1::2]
+
+    def probs(self, qubits):
+        q = (ctypes.c_int * len(qubits))(*qubits)
+        out = np.zeros(1 << len(qubits), dtype=np.float64)
+        check(lib.sim_measure_probs(self.h, q, len(qubits), _dp(out)), True)
+        return out
+
+    def fidelity(self, other):
+        F = ctypes.c_double(0.0)
+        check(lib.sim_fidelity(self.h, other.h, ctypes.byref(F)), True)
+        return F.value
+
+    def export_block(self, j):
+        ln = ctypes.c_size_t(0)
+        rc = lib.sim_export_block(self.h, j, None, 0, ctypes.byref(ln))
+        if rc not in (SIM_OK, SIM_ENOMEM, SIM_ECOLLAPSED):
+            check(rc)
+        buf = ctypes.create_string_buffer(max(ln.value, 1))
+        check(lib.sim_export_block(self.h, j, buf, ln.value, ctypes.byref(ln)), True)
+        return buf.raw[:ln.value]
+
+    def stats(self):
+        st = Stats()
+        check(lib.sim_stats(self.h, ctypes.byref(st)), True)
+        return {"normsq": st.normsq, "scale": st.scale,
+                "collapsed": st.collapsed, "compressed": st.compressed,
+                "resident_bytes": st.resident_bytes,
+                "peak_resident": st.peak_resident,
+                "min_ratio": st.min_ratio, "last_ratio": st.last_ratio,
+                "passes": st.passes,
+                "level_hist": [int(st.level_hist[k]) for k in range(8)],
+                "arena_bytes": st.arena_bytes,
+                "device_bytes": st.device_bytes}
+
+
+def debug_rsqrt(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    check(lib.sim_debug_rsqrt(_dp(x), _dp(out), x.size))
+    return out
+
+
+def state_bytes(n):
+    """Uncompressed complex-double state of n qubits: 2^(n+4) bytes."""
+    return 1 << (n + 4)

@@ -1,0 +1,127 @@
+// device.h -- types shared by the host runtime and the gfx950 kernels of
+// libaalcsim.so (internal; the public ABI is include/aalcsim.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aalc {
+
+// Block stream v1 constants (format of the compressed stride, Sec. III).
+constexpr uint32_t kMagic = 0x31424141u;  // "AAB1"
+constexpr uint32_t kHdrBytes = 32;
+constexpr uint32_t kPlaneHdrBytes = 16;
+constexpr uint32_t kOutlierBytes = 16;
+constexpr int kChunk = 64;     // scalars per chunk: one wavefront
+constexpr int kWG = 256;       // threads per workgroup: four wavefronts
+constexpr int kMaxL = 8;       // ladder levels
+constexpr int kMinS = 6;       // segment log2 range supported by the kernels
+constexpr int kMaxS = 10;
+constexpr double kQMax = 1073741824.0;  // 2^30
+
+// Gate kinds (numbering of the public header).
+enum : uint32_t {
+    kNone = 0, kU = 1, kDiag1 = 2, kCU = 3, kCPhase = 4, kCZ = 5, kSwap = 6,
+    kX = 7, kPhaseFlip = 8, kDiffuse = 9
+};
+
+struct GateArg {
+    uint32_t kind;
+    int32_t q0, q1;
+    uint32_t pad;
+    uint64_t index;
+    uint64_t mask;  // amplitude i couples with i ^ mask (0: diagonal)
+    double u[8];
+};
+
+struct Ladder {
+    int32_t L;
+    int32_t pad;
+    double theta;
+    double delta[kMaxL];  // 0 = lossless
+    double e[kMaxL];      // 2 * delta (exact)
+    double r[kMaxL];      // fl(1 / e), rounded on the host
+};
+
+// One descriptor set: where each block stream and plane record lives.
+struct Desc {
+    uint64_t *blk_off;    // [nblocks] byte offset of the block stream in its arena
+    uint32_t *blk_len;    // [nblocks] stream bytes
+    uint8_t *blk_level;   // [nblocks] ladder level of the stream
+    uint32_t *plane_rel;  // [2*nseg] plane record offset from the block start
+};
+
+// Device-resident scalars of one sim, read and written only by kernels.
+struct DevState {
+    double normsq;          // N^2 of the stored state
+    double scale;           // s applied at the next decode
+    double tdiff[2];        // 2 * mean for DIFFUSE
+    uint64_t arena_used[2]; // bump pointers of the two arenas
+    uint64_t resident;      // bytes of the current state
+    uint64_t peak_resident;
+    double min_ratio;
+    double last_ratio;
+    uint64_t level_hist[kMaxL];
+    uint64_t passes;
+    uint32_t err;           // sticky error bits (kErr*)
+    uint32_t err_pass;      // pass index of the first error
+    int32_t collapsed;
+    int32_t normalize;
+};
+
+enum : uint32_t { kErrArena = 1u, kErrSize = 2u };
+
+struct Geo {
+    int32_t n, b, s, pad;
+    uint64_t nblocks;  // 2^(n-b)
+    uint64_t nseg;     // 2^(n-s)
+    uint64_t nunits;   // workgroup work items of a pass
+};
+
+// Everything a pass kernel needs.
+struct PassArgs {
+    Geo geo;
+    Ladder lad;
+    GateArg gate;
+    Desc din, dout;
+    const uint8_t *arena_in;
+    uint8_t *arena_out;
+    uint64_t arena_cap;
+    int32_t out_arena;   // index of arena_out (bump pointer)
+    int32_t in_arena;
+    uint64_t pass;       // pass counter (for error reporting)
+    uint64_t basis;      // source state |basis> when src_basis != 0
+    int32_t src_basis;
+    int32_t pad;
+    uint32_t *psz;       // [L][2*nseg]: payload words | n_outliers << 16
+    double *segnorm;     // [nseg]
+    double *blknorm;     // [nblocks]
+    double *segsum;      // [2][nseg] DIFFUSE pre-pass
+    double *blksum;      // [2][nblocks]
+    DevState *dev;
+};
+
+// Launchers (kernels.hip).
+void launch_mean(const PassArgs &a, hipStream_t st);
+void launch_pass(const PassArgs &a, hipStream_t st);
+void launch_encode_basis(const PassArgs &a, hipStream_t st);
+void launch_decode_range(const PassArgs &a, uint64_t first, uint64_t count,
+                         double *out, hipStream_t st);
+void launch_probs(const PassArgs &a, const int *qubits_dev, int nq,
+                  double *probs_dev, hipStream_t st);
+void launch_inner(const PassArgs &a, const PassArgs &b, const double *amp_a,
+                  const double *amp_b, double *part, double *result,
+                  hipStream_t st);
+void launch_rsqrt(const double *in, double *out, uint64_t count,
+                  hipStream_t st);
+
+// Uncompressed path (sv.hip).
+void sv_set_basis(double *amp, int n, uint64_t x, hipStream_t st);
+void sv_apply(double *amp, int n, const GateArg &g, double *scratch,
+              double *tdiff_dev, hipStream_t st);
+void sv_probs(const double *amp, int n, const int *qubits_dev, int nq,
+              double *probs_dev, hipStream_t st);
+void sv_normsq(const double *amp, int n, double *scratch, double *out_dev,
+               hipStream_t st);
+
+}  // namespace aalc

@@ -1,0 +1,978 @@
+// kernels.hip -- gfx950 kernels of the compressed path.
+//
+// One pass of a gate (Alg. 2 of the paper for every stride) is five kernels
+// on the sim stream:
+//   k_pass<false>  decode + normalise + gate, then the size of every plane
+//                  record at every ladder level (no output written)
+//   k_decide       per block: the first ladder level whose ratio reaches
+//                  theta (else the last), the block's place in the output
+//                  arena, the plane record offsets and the stream header
+//   k_pass<true>   decode + normalise + gate again, encode each plane at its
+//                  block's level, pack, write; per-segment normsq
+//   k_blocknorm    per block: pairwise normsq into the stream header
+//   k_reduce       N^2 over blocks, s = 1/sqrt(N^2), statistics
+// DIFFUSE adds a read-only mean pre-pass (k_mean + k_segtree + k_mean_final).
+//
+// Work decomposition: a workgroup of four wave64s takes one unit of two
+// segments (2 x 2^s amplitudes); wave w decodes / encodes plane (w & 1) of
+// segment (w >> 1), one 64-scalar chunk per wave instruction.  The decoded
+// unit sits in LDS (32 KiB at s = 10) for the gate butterflies, so four
+// workgroups share a CU.  Units are segment pairs (g, g ^ (mask >> s)) when
+// a gate couples segments, so every pair update of Sec. II finds both
+// amplitudes in LDS.
+//
+// Arithmetic: every floating-point operation is one IEEE binary64 rounding
+// (contraction off), in the order the block-stream format and the gate
+// definitions fix, so codes and streams match the CPU reference bit for bit.
+#pragma clang fp contract(off)
+
+#include "device.h"
+#include "gates.h"
+
+namespace aalc {
+
+// ------------------------------------------------------------- helpers ----
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
+{
+    uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d)
+{
+    return (uint64_t)__shfl_up((unsigned long long)v, (unsigned int)d, 64);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_xor(v, d, 64);
+        v = v > o ? v : o;
+    }
+    return v;
+}
+
+// Inclusive prefix sum over the 64 lanes (two's complement, wraps).
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t t = shfl_up64(v, d);
+        if (lane >= d)
+            v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t bitlen64(uint64_t z)
+{
+    return z ? 64u - (uint32_t)__builtin_clzll(z) : 0u;
+}
+
+__device__ __forceinline__ uint64_t zigzag64(uint64_t c)
+{
+    return (c << 1) ^ (uint64_t)((int64_t)c >> 63);
+}
+
+__device__ __forceinline__ uint64_t unzigzag64(uint64_t z)
+{
+    return (z >> 1) ^ (0 - (z & 1));
+}
+
+__device__ __forceinline__ uint32_t pad8(uint32_t v) { return (v + 7u) & ~7u; }
+
+// Bytes of a plane record from its (payload words, outliers) pair.
+__device__ __forceinline__ uint64_t rec_bytes(uint32_t v, uint32_t padC)
+{
+    uint32_t pw = v & 0xFFFFu, no = v >> 16;
+    return kPlaneHdrBytes + (pw ? padC : 0u) + 8ull * pw + (uint64_t)kOutlierBytes * no;
+}
+
+// s = 1/sqrt(N^2): one correctly rounded square root, one correctly
+// rounded division.
+__device__ __forceinline__ double inv_sqrt_exact(double x)
+{
+    double r = __builtin_sqrt(x);
+    return 1.0 / r;
+}
+
+// Quantiser of one ladder level (format: q = rint(x r) under |x r| < 2^30,
+// outlier unless |x - q e| < delta; delta == 0: q = the bits of x).
+__device__ __forceinline__ void quantize(double x, double delta, double e,
+                                         double r, uint64_t &q, bool &out)
+{
+    if (delta == 0.0) {
+        q = (uint64_t)__double_as_longlong(x);
+        out = false;
+        return;
+    }
+    double y = x * r;
+    if (fabs(y) < kQMax) {
+        double qr = __builtin_rint(y);
+        int32_t qi = (int32_t)qr;
+        double xh = (double)qi * e;
+        q = (uint64_t)(int64_t)qi;
+        out = !(fabs(x - xh) < delta);
+    } else {
+        q = 0;
+        out = true;
+    }
+}
+
+// ------------------------------------------------------------ units -------
+
+struct Unit {
+    uint64_t g[2];  // segments (g[0] < g[1] when coupled)
+    int nsu;        // segments in the unit (1 only when the state has one)
+};
+
+__device__ __forceinline__ Unit unit_of(uint64_t u, uint64_t nseg, uint64_t Ms)
+{
+    Unit r;
+    if (nseg == 1) {
+        r.g[0] = 0;
+        r.g[1] = 0;
+        r.nsu = 1;
+        return r;
+    }
+    r.nsu = 2;
+    if (Ms == 0) {
+        r.g[0] = 2 * u;
+        r.g[1] = 2 * u + 1;
+    } else {
+        int hb = 63 - __builtin_clzll(Ms);
+        uint64_t lo = u & ((1ull << hb) - 1);
+        uint64_t g0 = ((u >> hb) << (hb + 1)) | lo;
+        r.g[0] = g0;
+        r.g[1] = g0 ^ Ms;
+    }
+    return r;
+}
+
+typedef double Planes[2][2][1 << kMaxS];
+
+// Decode one plane record into dst[0 .. 2^s) (one wavefront), scaling each
+// value by `scale` when do_scale (normalisation before the gate).
+__device__ void decode_plane(const uint8_t *rec, int s, double delta,
+                             double scale, bool do_scale, double *dst)
+{
+    const int lane = lane_id();
+    const int C = 1 << (s - 6);
+    const uint64_t anchor = *(const uint64_t *)rec;
+    const uint32_t pw = *(const uint32_t *)(rec + 8);
+    const uint32_t nout = *(const uint32_t *)(rec + 12);
+    const uint8_t *widths = rec + kPlaneHdrBytes;
+    const uint64_t *payload =
+        (const uint64_t *)(rec + kPlaneHdrBytes + (pw ? pad8((uint32_t)C) : 0u));
+    const double e = 2.0 * delta;
+    uint64_t carry = anchor;
+    uint32_t woff = 0;
+    for (int c = 0; c < C; ++c) {
+        const uint32_t w = pw ? (uint32_t)widths[c] : 0u;
+        uint64_t z = 0;
+        if (w) {
+            const uint32_t bp = (uint32_t)lane * w;
+            const uint32_t wi = bp >> 6, sh = bp & 63u;
+            uint64_t v = payload[woff + wi] >> sh;
+            if (sh + w > 64u)
+                v |= payload[woff + wi + 1] << (64u - sh);
+            if (w < 64u)
+                v &= (1ull << w) - 1ull;
+            z = v;
+        }
+        const uint64_t q = carry + wave_incl_scan64(unzigzag64(z));
+        carry = readlane64(q, 63);
+        double x = (delta == 0.0) ? __longlong_as_double((long long)q)
+                                  : (double)(int64_t)q * e;
+        if (do_scale)
+            x = x * scale;
+        dst[c * kChunk + lane] = x;
+        woff += w;
+    }
+    const uint8_t *outl = (const uint8_t *)(payload + pw);
+    for (uint32_t k = (uint32_t)lane; k < nout; k += 64u) {
+        const uint32_t idx = *(const uint32_t *)(outl + (uint64_t)kOutlierBytes * k);
+        double v = *(const double *)(outl + (uint64_t)kOutlierBytes * k + 8);
+        if (do_scale)
+            v = v * scale;
+        dst[idx] = v;
+    }
+}
+
+// Decode (or synthesise, for the basis-state source) the planes of a unit
+// into LDS; wave w owns plane (w & 1) of segment (w >> 1).
+__device__ void load_unit(const PassArgs &a, const Unit &uc, Planes &X,
+                          double scale, bool do_scale)
+{
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int us = wave >> 1, p = wave & 1;
+    const int s = a.geo.s;
+    if (us >= uc.nsu)
+        return;
+    const uint64_t g = uc.g[us];
+    double *dst = &X[us][p][0];
+    if (a.src_basis) {
+        for (int o = lane; o < (1 << s); o += 64)
+            dst[o] = (p == 0 && ((g << s) | (uint64_t)o) == a.basis) ? 1.0 : 0.0;
+        return;
+    }
+    const uint64_t j = g >> (a.geo.b - s);
+    const uint8_t *blk = a.arena_in + a.din.blk_off[j];
+    const double delta = *(const double *)(blk + 16);
+    decode_plane(blk + a.din.plane_rel[2 * g + p], s, delta, scale, do_scale, dst);
+}
+
+__device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
+                          const double *tdiff)
+{
+    const int tid = threadIdx.x;
+    if (G.kind == kNone)
+        return;
+    const uint64_t M = G.mask;
+    const uint64_t Ms = M >> s;
+    const uint32_t S = 1u << s;
+    const uint32_t Ml = (uint32_t)(M & (S - 1));
+    if (M == 0) {
+        const uint32_t total = (uint32_t)uc.nsu << s;
+        for (uint32_t t = tid; t < total; t += kWG) {
+            const int us = (int)(t >> s);
+            const uint32_t o = t & (S - 1);
+            const uint64_t i = (uc.g[us] << s) | o;
+            double ar = X[us][0][o], ai = X[us][1][o];
+            gate_diag(G, i, ar, ai, tdiff);
+            X[us][0][o] = ar;
+            X[us][1][o] = ai;
+        }
+    } else if (Ms) {
+        for (uint32_t o = tid; o < S; o += kWG) {
+            const uint32_t o2 = o ^ Ml;
+            const uint64_t i = (uc.g[0] << s) | o;
+            double ar = X[0][0][o], ai = X[0][1][o];
+            double br = X[1][0][o2], bi = X[1][1][o2];
+            gate_pair(G, i, ar, ai, br, bi);
+            X[0][0][o] = ar;
+            X[0][1][o] = ai;
+            X[1][0][o2] = br;
+            X[1][1][o2] = bi;
+        }
+    } else {
+        const int hb = 31 - __builtin_clz(Ml);
+        const uint32_t half = S >> 1;
+        const uint32_t total = (uint32_t)uc.nsu * half;
+        for (uint32_t t = tid; t < total; t += kWG) {
+            const int us = (int)(t >> (s - 1));
+            const uint32_t r = t & (half - 1);
+            const uint32_t o = ((r >> hb) << (hb + 1)) | (r & ((1u << hb) - 1));
+            const uint32_t o2 = o ^ Ml;
+            const uint64_t i = (uc.g[us] << s) | o;
+            double ar = X[us][0][o], ai = X[us][1][o];
+            double br = X[us][0][o2], bi = X[us][1][o2];
+            gate_pair(G, i, ar, ai, br, bi);
+            X[us][0][o] = ar;
+            X[us][1][o] = ai;
+            X[us][0][o2] = br;
+            X[us][1][o2] = bi;
+        }
+    }
+}
+
+// Sizes of one plane at every ladder level (one wavefront).
+__device__ void size_plane(const double *x, int s, const Ladder &lad,
+                           uint32_t *psz, uint64_t plane, uint64_t nplanes)
+{
+    const int lane = lane_id();
+    const int C = 1 << (s - 6);
+    uint64_t carry[kMaxL];
+    uint32_t pw[kMaxL], no[kMaxL];
+#pragma unroll
+    for (int k = 0; k < kMaxL; ++k) {
+        carry[k] = 0;
+        pw[k] = 0;
+        no[k] = 0;
+    }
+    for (int c = 0; c < C; ++c) {
+        const double v = x[c * kChunk + lane];
+#pragma unroll
+        for (int k = 0; k < kMaxL; ++k) {
+            if (k < lad.L) {
+                uint64_t q;
+                bool out;
+                quantize(v, lad.delta[k], lad.e[k], lad.r[k], q, out);
+                uint64_t prev = shfl_up64(q, 1);
+                if (lane == 0)
+                    prev = (c == 0) ? q : carry[k];
+                const uint32_t w = wave_max_u32(bitlen64(zigzag64(q - prev)));
+                pw[k] += w;
+                no[k] += (uint32_t)__popcll(__ballot(out));
+                carry[k] = readlane64(q, 63);
+            }
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kMaxL; ++k)
+            if (k < lad.L)
+                psz[(uint64_t)k * nplanes + plane] = pw[k] | (no[k] << 16);
+    }
+}
+
+// Encode one plane at one level into its record (one wavefront).  x is
+// overwritten with the decoded values x-hat for the normsq.
+__device__ void encode_plane(double *x, int s, double delta, double e,
+                             double r, uint32_t pszv, uint8_t *rec,
+                             uint64_t *pb, uint32_t *err)
+{
+    const int lane = lane_id();
+    const int C = 1 << (s - 6);
+    const uint32_t pw_total = pszv & 0xFFFFu, nout_total = pszv >> 16;
+    uint8_t *widths = rec + kPlaneHdrBytes;
+    uint64_t *payload =
+        (uint64_t *)(rec + kPlaneHdrBytes + (pw_total ? pad8((uint32_t)C) : 0u));
+    uint8_t *outl = (uint8_t *)(payload + pw_total);
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+    uint64_t carry = 0;
+    uint32_t woff = 0, nout = 0;
+    for (int c = 0; c < C; ++c) {
+        const double v = x[c * kChunk + lane];
+        uint64_t q;
+        bool out;
+        quantize(v, delta, e, r, q, out);
+        uint64_t prev = shfl_up64(q, 1);
+        if (lane == 0)
+            prev = (c == 0) ? q : carry;
+        const uint64_t z = zigzag64(q - prev);
+        const uint32_t w = wave_max_u32(bitlen64(z));
+        if (c == 0 && lane == 0) {
+            *(uint64_t *)rec = q;
+            *(uint32_t *)(rec + 8) = pw_total;
+            *(uint32_t *)(rec + 12) = nout_total;
+        }
+        if (pw_total && lane == 0)
+            widths[c] = (uint8_t)w;
+        // Record sizes come from the sizing kernel; the bounds below keep a
+        // disagreement (reported through kErrSize) inside the record.
+        const bool fits = woff + w <= pw_total;
+        if (!fits) {
+            // nothing is written for this chunk
+        } else if (w == 64u) {
+            payload[woff + lane] = z;
+        } else if (w) {
+            if ((uint32_t)lane < w)
+                pb[lane] = 0;
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t bp = (uint32_t)lane * w;
+            const uint32_t wi = bp >> 6, sh = bp & 63u;
+            atomicOr((unsigned long long *)&pb[wi], (unsigned long long)(z << sh));
+            if (sh + w > 64u)
+                atomicOr((unsigned long long *)&pb[wi + 1],
+                         (unsigned long long)(z >> (64u - sh)));
+            __builtin_amdgcn_wave_barrier();
+            if ((uint32_t)lane < w)
+                payload[woff + lane] = pb[lane];
+            __builtin_amdgcn_wave_barrier();
+        }
+        const uint64_t bal = __ballot(out);
+        if (out && nout + (uint32_t)__popcll(bal & lt_mask) < nout_total) {
+            const uint32_t rank = nout + (uint32_t)__popcll(bal & lt_mask);
+            uint8_t *ent = outl + (uint64_t)kOutlierBytes * rank;
+            *(uint32_t *)ent = (uint32_t)(c * kChunk + lane);
+            *(uint32_t *)(ent + 4) = 0u;
+            *(uint64_t *)(ent + 8) = (uint64_t)__double_as_longlong(v);
+        }
+        nout += (uint32_t)__popcll(bal);
+        double xh = v;
+        if (!out && delta != 0.0)
+            xh = (double)(int64_t)q * e;
+        x[c * kChunk + lane] = xh;
+        carry = readlane64(q, 63);
+        woff += w;
+    }
+    if (pw_total && lane == 0)
+        for (int i = C; i < (int)pad8((uint32_t)C); ++i)
+            widths[i] = 0;
+    if (lane == 0 && (woff != pw_total || nout != nout_total))
+        atomicOr(err, kErrSize);
+}
+
+// Pairwise sums of a unit's segments: leaf(o) for the amplitudes of segment
+// us, tree over o; the two waves of a segment each reduce one half.
+template <class Leaf>
+__device__ double segment_tree(const Unit &uc, int s, double *red, Leaf leaf)
+{
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int us = wave >> 1, half = wave & 1;
+    const int halfn = 1 << (s - 1);
+    const int per = halfn >= 64 ? halfn / 64 : 1;
+    const int active = halfn >= 64 ? 64 : halfn;
+    double v = 0.0;
+    if (us < uc.nsu) {
+        if (lane < active) {
+            const int base = half * halfn + lane * per;
+            double t[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                t[i] = (i < per) ? leaf(us, base + i) : 0.0;
+#pragma unroll
+            for (int st = 1; st < 8; st <<= 1)
+                if (st < per) {
+#pragma unroll
+                    for (int i = 0; i < 8; i += 2 * st)
+                        t[i] = t[i] + t[i + st];
+                }
+            v = t[0];
+        }
+        for (int d = 1; d < active; d <<= 1)
+            v = v + __shfl_xor(v, d, 64);
+    }
+    if (lane == 0)
+        red[wave] = v;
+    __syncthreads();
+    double out = 0.0;
+    if (threadIdx.x < (unsigned)uc.nsu)
+        out = red[2 * threadIdx.x] + red[2 * threadIdx.x + 1];
+    __syncthreads();
+    return out;
+}
+
+// --------------------------------------------------------- the pass -------
+
+template <bool ENC>
+__global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
+{
+    if (a.dev->err)
+        return;
+    __shared__ Planes X;
+    __shared__ uint64_t pack[4][64];
+    __shared__ double red[8];
+    const int s = a.geo.s;
+    const int wave = threadIdx.x >> 6;
+    const double scale = a.dev->scale;
+    const bool do_scale = !a.src_basis && scale != 1.0;
+    const double *tdiff = a.dev->tdiff;
+    const uint64_t Ms = a.gate.mask >> s;
+    const uint64_t nplanes = 2 * a.geo.nseg;
+    for (uint64_t u = blockIdx.x; u < a.geo.nunits; u += gridDim.x) {
+        const Unit uc = unit_of(u, a.geo.nseg, Ms);
+        load_unit(a, uc, X, scale, do_scale);
+        __syncthreads();
+        gate_unit(a.gate, uc, s, X, tdiff);
+        __syncthreads();
+        const int us = wave >> 1, p = wave & 1;
+        if (us < uc.nsu) {
+            const uint64_t g = uc.g[us];
+            const uint64_t plane = 2 * g + p;
+            if (!ENC) {
+                size_plane(&X[us][p][0], s, a.lad, a.psz, plane, nplanes);
+            } else {
+                const uint64_t j = g >> (a.geo.b - s);
+                const int k = a.dout.blk_level[j];
+                uint8_t *rec = a.arena_out + a.dout.blk_off[j] + a.dout.plane_rel[plane];
+                encode_plane(&X[us][p][0], s, a.lad.delta[k], a.lad.e[k], a.lad.r[k],
+                             a.psz[(uint64_t)k * nplanes + plane], rec, &pack[wave][0],
+                             &a.dev->err);
+            }
+        }
+        if (ENC) {
+            __syncthreads();
+            const double ns = segment_tree(uc, s, red, [&](int su, int o) {
+                const double re = X[su][0][o], im = X[su][1][o];
+                const double rr = re * re;
+                const double ii = im * im;
+                return rr + ii;
+            });
+            if (threadIdx.x < (unsigned)uc.nsu)
+                a.segnorm[uc.g[threadIdx.x]] = ns;
+        }
+        __syncthreads();
+    }
+}
+
+// Read-only DIFFUSE pre-pass: per-segment pairwise sums of the normalised
+// re and im parts.
+__global__ __launch_bounds__(kWG) void k_mean(PassArgs a)
+{
+    if (a.dev->err)
+        return;
+    __shared__ Planes X;
+    __shared__ double red[8];
+    const int s = a.geo.s;
+    const double scale = a.dev->scale;
+    const bool do_scale = scale != 1.0;
+    for (uint64_t u = blockIdx.x; u < a.geo.nunits; u += gridDim.x) {
+        const Unit uc = unit_of(u, a.geo.nseg, 0);
+        load_unit(a, uc, X, scale, do_scale);
+        __syncthreads();
+        for (int c = 0; c < 2; ++c) {
+            const double sm = segment_tree(uc, s, red,
+                                           [&](int su, int o) { return X[su][c][o]; });
+            if (threadIdx.x < (unsigned)uc.nsu)
+                a.segsum[(uint64_t)c * a.geo.nseg + uc.g[threadIdx.x]] = sm;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------ reductions --------
+
+// Pairwise sum of m = 2^k values load(0..m) by one workgroup.
+template <class Load>
+__device__ double wg_tree(Load load, uint64_t m, double *lds)
+{
+    const int t = threadIdx.x;
+    uint64_t nact;
+    if (m >= kWG) {
+        const uint64_t per = m / kWG;
+        double stack[40];
+        int sp = 0;
+        for (uint64_t i = 0; i < per; ++i) {
+            double v = load(t * per + i);
+            for (uint64_t k = i; k & 1; k >>= 1)
+                v = stack[--sp] + v;
+            stack[sp++] = v;
+        }
+        lds[t] = stack[0];
+        nact = kWG;
+    } else {
+        lds[t] = (t < (int)m) ? load((uint64_t)t) : 0.0;
+        nact = m;
+    }
+    __syncthreads();
+    for (uint64_t st = 1; st < nact; st <<= 1) {
+        if ((t & (2 * st - 1)) == 0 && (uint64_t)t + st < nact)
+            lds[t] = lds[t] + lds[t + st];
+        __syncthreads();
+    }
+    const double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// dst[j] = pairwise(src[j*per .. (j+1)*per)) for j < nout.
+__global__ __launch_bounds__(kWG) void k_segtree(PassArgs a, const double *src,
+                                                 double *dst, uint64_t per,
+                                                 uint64_t nout, int write_hdr)
+{
+    if (a.dev->err)
+        return;
+    __shared__ double lds[kWG];
+    for (uint64_t j = blockIdx.x; j < nout; j += gridDim.x) {
+        const double *p = src + j * per;
+        const double v = wg_tree([&](uint64_t i) { return p[i]; }, per, lds);
+        if (threadIdx.x == 0) {
+            dst[j] = v;
+            if (write_hdr)
+                *(double *)(a.arena_out + a.dout.blk_off[j] + 24) = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_mean_final(PassArgs a, double pow2)
+{
+    if (a.dev->err)
+        return;
+    __shared__ double lds[kWG];
+    for (int c = 0; c < 2; ++c) {
+        const double *p = a.blksum + (uint64_t)c * a.geo.nblocks;
+        const double S = wg_tree([&](uint64_t i) { return p[i]; }, a.geo.nblocks, lds);
+        if (threadIdx.x == 0)
+            a.dev->tdiff[c] = S * pow2;
+    }
+}
+
+// Alg. 2 level choice per block + output placement + stream header.
+__global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
+{
+    if (a.dev->err)
+        return;
+    __shared__ uint64_t red[kWG];
+    __shared__ uint64_t tot[kMaxL];
+    __shared__ uint64_t nout[kMaxL];
+    __shared__ int kstar;
+    const int t = threadIdx.x;
+    const int s = a.geo.s, b = a.geo.b;
+    const uint32_t padC = pad8(1u << (s - 6));
+    const uint64_t npb = 2ull << (b - s);
+    const uint64_t nplanes = 2 * a.geo.nseg;
+    const int L = a.lad.L;
+    const double raw = (double)(16ull << b);
+    for (uint64_t j = blockIdx.x; j < a.geo.nblocks; j += gridDim.x) {
+        const uint64_t base = j * npb;
+        for (int k = 0; k < L; ++k) {
+            uint64_t by = 0, no = 0;
+            for (uint64_t p = t; p < npb; p += kWG) {
+                const uint32_t v = a.psz[(uint64_t)k * nplanes + base + p];
+                by += rec_bytes(v, padC);
+                no += v >> 16;
+            }
+            for (int part = 0; part < 2; ++part) {
+                red[t] = part ? no : by;
+                __syncthreads();
+                for (int st = kWG / 2; st > 0; st >>= 1) {
+                    if (t < st)
+                        red[t] += red[t + st];
+                    __syncthreads();
+                }
+                if (t == 0) {
+                    if (part)
+                        nout[k] = red[0];
+                    else
+                        tot[k] = red[0] + kHdrBytes;
+                }
+                __syncthreads();
+            }
+        }
+        if (t == 0) {
+            int ks = L - 1;
+            for (int k = 0; k < L; ++k)
+                if (raw >= a.lad.theta * (double)tot[k]) {
+                    ks = k;
+                    break;
+                }
+            kstar = ks;
+        }
+        __syncthreads();
+        const int ks = kstar;
+        // plane record offsets at the chosen level, canonical order
+        const uint64_t per = (npb + kWG - 1) / kWG;
+        const uint64_t p0 = (uint64_t)t * per;
+        uint64_t local = 0;
+        for (uint64_t p = p0; p < p0 + per && p < npb; ++p)
+            local += rec_bytes(a.psz[(uint64_t)ks * nplanes + base + p], padC);
+        red[t] = local;
+        __syncthreads();
+        // exclusive scan of thread totals (Hillis-Steele on a copy)
+        for (int st = 1; st < kWG; st <<= 1) {
+            const uint64_t add = (t >= st) ? red[t - st] : 0;
+            __syncthreads();
+            red[t] += add;
+            __syncthreads();
+        }
+        uint64_t run = kHdrBytes + red[t] - local;
+        for (uint64_t p = p0; p < p0 + per && p < npb; ++p) {
+            a.dout.plane_rel[base + p] = (uint32_t)run;
+            run += rec_bytes(a.psz[(uint64_t)ks * nplanes + base + p], padC);
+        }
+        if (t == 0) {
+            const uint64_t len = tot[ks];
+            const uint64_t off = atomicAdd(
+                (unsigned long long *)&a.dev->arena_used[a.out_arena],
+                (unsigned long long)len);
+            if (off + len > a.arena_cap) {
+                if (atomicOr(&a.dev->err, kErrArena) == 0)
+                    a.dev->err_pass = (uint32_t)a.pass;
+                a.dout.blk_len[j] = 0;
+            } else {
+                a.dout.blk_off[j] = off;
+                a.dout.blk_len[j] = (uint32_t)len;
+                a.dout.blk_level[j] = (uint8_t)ks;
+                uint64_t *h = (uint64_t *)(a.arena_out + off);
+                h[0] = (uint64_t)kMagic | ((uint64_t)ks << 32) | ((uint64_t)s << 48) |
+                       ((uint64_t)b << 56);
+                h[1] = (uint64_t)(uint32_t)nout[ks] | (len << 32);
+                h[2] = (uint64_t)__double_as_longlong(a.lad.delta[ks]);
+                h[3] = 0;
+                if (!a.src_basis)
+                    atomicAdd((unsigned long long *)&a.dev->level_hist[ks], 1ull);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// N^2, s, statistics; frees the input arena for the next pass.
+__global__ __launch_bounds__(kWG) void k_reduce(PassArgs a)
+{
+    if (a.dev->err)
+        return;
+    __shared__ double lds[kWG];
+    __shared__ uint64_t ures[kWG];
+    const int t = threadIdx.x;
+    const double N2 = wg_tree([&](uint64_t i) { return a.blknorm[i]; }, a.geo.nblocks, lds);
+    uint64_t by = 0;
+    for (uint64_t j = t; j < a.geo.nblocks; j += kWG)
+        by += a.dout.blk_len[j];
+    ures[t] = by;
+    __syncthreads();
+    for (int st = kWG / 2; st > 0; st >>= 1) {
+        if (t < st)
+            ures[t] += ures[t + st];
+        __syncthreads();
+    }
+    if (t == 0) {
+        DevState *d = a.dev;
+        d->normsq = N2;
+        if (N2 > 0.0 && __builtin_isfinite(N2)) {
+            if (d->normalize)
+                d->scale = inv_sqrt_exact(N2);
+        } else {
+            d->collapsed = 1;
+            d->scale = 1.0;
+        }
+        const uint64_t res = ures[0];
+        d->resident = res;
+        if (res > d->peak_resident)
+            d->peak_resident = res;
+        const double ratio = (double)(16ull << a.geo.n) / (double)res;
+        d->last_ratio = ratio;
+        if (a.src_basis) {
+            d->min_ratio = ratio;
+        } else {
+            d->passes += 1;
+            if (ratio < d->min_ratio)
+                d->min_ratio = ratio;
+        }
+        d->arena_used[a.in_arena] = 0;
+    }
+}
+
+// ---------------------------------------------------- queries -------------
+
+__global__ __launch_bounds__(kWG) void k_decode_range(PassArgs a, uint64_t u0,
+                                                      uint64_t u1, uint64_t first,
+                                                      uint64_t count, double *out)
+{
+    __shared__ Planes X;
+    const int s = a.geo.s;
+    const double scale = a.dev->scale;
+    const bool do_scale = scale != 1.0;
+    for (uint64_t u = u0 + blockIdx.x; u < u1; u += gridDim.x) {
+        const Unit uc = unit_of(u, a.geo.nseg, 0);
+        load_unit(a, uc, X, scale, do_scale);
+        __syncthreads();
+        for (int us = 0; us < uc.nsu; ++us)
+            for (uint32_t o = threadIdx.x; o < (1u << s); o += kWG) {
+                const uint64_t i = (uc.g[us] << s) | o;
+                if (i >= first && i < first + count) {
+                    out[2 * (i - first)] = X[us][0][o];
+                    out[2 * (i - first) + 1] = X[us][1][o];
+                }
+            }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_probs(PassArgs a, const int *qubits, int nq,
+                                               double *probs)
+{
+    __shared__ Planes X;
+    __shared__ double bins[1024];
+    const int s = a.geo.s;
+    const double scale = a.dev->scale;
+    const bool do_scale = scale != 1.0;
+    const bool lds_bins = nq <= 10;
+    const uint32_t nb = 1u << nq;
+    if (lds_bins)
+        for (uint32_t k = threadIdx.x; k < nb; k += kWG)
+            bins[k] = 0.0;
+    __syncthreads();
+    for (uint64_t u = blockIdx.x; u < a.geo.nunits; u += gridDim.x) {
+        const Unit uc = unit_of(u, a.geo.nseg, 0);
+        load_unit(a, uc, X, scale, do_scale);
+        __syncthreads();
+        for (int us = 0; us < uc.nsu; ++us)
+            for (uint32_t o = threadIdx.x; o < (1u << s); o += kWG) {
+                const uint64_t i = (uc.g[us] << s) | o;
+                uint32_t oc = 0;
+                for (int k = 0; k < nq; ++k)
+                    oc |= (uint32_t)bit_of(i, qubits[k]) << k;
+                const double re = X[us][0][o], im = X[us][1][o];
+                const double rr = re * re;
+                const double ii = im * im;
+                const double pv = rr + ii;
+                if (lds_bins)
+                    atomicAdd(&bins[oc], pv);
+                else
+                    atomicAdd(&probs[oc], pv);
+            }
+        __syncthreads();
+    }
+    if (lds_bins)
+        for (uint32_t k = threadIdx.x; k < nb; k += kWG)
+            if (bins[k] != 0.0)
+                atomicAdd(&probs[k], bins[k]);
+}
+
+// Inner products of two states over ranges of 2^S amplitudes.  Planes of A
+// go to X[0], of B to X[1]; an uncompressed state is read from its array.
+__device__ void load_range(const PassArgs &a, const double *amp, uint64_t first,
+                           int S, double *dst, int p, double scale, bool do_scale)
+{
+    const int lane = lane_id();
+    const int cnt = 1 << S;
+    if (amp) {
+        for (int o = lane; o < cnt; o += 64)
+            dst[o] = amp[2 * (first + o) + p];
+        return;
+    }
+    const int s = a.geo.s;
+    for (int off = 0; off < cnt; off += (1 << s)) {
+        const uint64_t g = (first + off) >> s;
+        const uint64_t j = g >> (a.geo.b - s);
+        const uint8_t *blk = a.arena_in + a.din.blk_off[j];
+        const double delta = *(const double *)(blk + 16);
+        decode_plane(blk + a.din.plane_rel[2 * g + p], s, delta, scale, do_scale,
+                     dst + off);
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_inner(PassArgs A, PassArgs B,
+                                               const double *ampA,
+                                               const double *ampB, int S,
+                                               uint64_t nranges, double *part)
+{
+    __shared__ Planes X;
+    __shared__ double lds[kWG];
+    const int wave = threadIdx.x >> 6;
+    const double sa = ampA ? 1.0 : A.dev->scale;
+    const double sb = ampB ? 1.0 : B.dev->scale;
+    for (uint64_t u = blockIdx.x; u < nranges; u += gridDim.x) {
+        const uint64_t first = u << S;
+        if (wave < 2)
+            load_range(A, ampA, first, S, &X[0][wave][0], wave, sa, sa != 1.0);
+        else
+            load_range(B, ampB, first, S, &X[1][wave - 2][0], wave - 2, sb, sb != 1.0);
+        __syncthreads();
+        const uint64_t m = 1ull << S;
+        for (int c = 0; c < 4; ++c) {
+            const double v = wg_tree(
+                [&](uint64_t o) {
+                    const double ar = X[0][0][o], ai = X[0][1][o];
+                    const double br = X[1][0][o], bi = X[1][1][o];
+                    if (c == 0) {
+                        const double p1 = ar * br, p2 = ai * bi;
+                        return p1 + p2;
+                    } else if (c == 1) {
+                        const double p3 = ar * bi, p4 = ai * br;
+                        return p3 - p4;
+                    } else if (c == 2) {
+                        const double q1 = ar * ar, q2 = ai * ai;
+                        return q1 + q2;
+                    }
+                    const double q3 = br * br, q4 = bi * bi;
+                    return q3 + q4;
+                },
+                m, lds);
+            if (threadIdx.x == 0)
+                part[(uint64_t)c * nranges + u] = v;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_inner_final(const double *part,
+                                                     uint64_t nranges, double *res)
+{
+    __shared__ double lds[kWG];
+    double v[4];
+    for (int c = 0; c < 4; ++c) {
+        const double *p = part + (uint64_t)c * nranges;
+        v[c] = wg_tree([&](uint64_t i) { return p[i]; }, nranges, lds);
+    }
+    if (threadIdx.x == 0) {
+        const double num = v[0] * v[0] + v[1] * v[1];
+        res[0] = num / (v[2] * v[3]);
+        res[1] = v[0];
+        res[2] = v[1];
+        res[3] = v[2];
+        res[4] = v[3];
+    }
+}
+
+__global__ void k_rsqrt(const double *in, double *out, uint64_t count)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = inv_sqrt_exact(in[i]);
+}
+
+// ------------------------------------------------------- launchers --------
+
+static unsigned grid_for(uint64_t items)
+{
+    const uint64_t cap = 1ull << 20;
+    return (unsigned)(items < cap ? (items ? items : 1) : cap);
+}
+
+void launch_mean(const PassArgs &a, hipStream_t st)
+{
+    PassArgs m = a;
+    hipLaunchKernelGGL(k_mean, dim3(grid_for(a.geo.nunits)), dim3(kWG), 0, st, m);
+    const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
+    for (int c = 0; c < 2; ++c)
+        hipLaunchKernelGGL(k_segtree, dim3(grid_for(a.geo.nblocks)), dim3(kWG), 0, st, m,
+                           (const double *)(a.segsum + (uint64_t)c * a.geo.nseg),
+                           a.blksum + (uint64_t)c * a.geo.nblocks, spb, a.geo.nblocks, 0);
+    hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(kWG), 0, st, m,
+                       ldexp(1.0, 1 - a.geo.n));
+}
+
+static void launch_tail(const PassArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_decide, dim3(grid_for(a.geo.nblocks)), dim3(kWG), 0, st, a);
+    hipLaunchKernelGGL(k_pass<true>, dim3(grid_for(a.geo.nunits)), dim3(kWG), 0, st, a);
+    const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
+    hipLaunchKernelGGL(k_segtree, dim3(grid_for(a.geo.nblocks)), dim3(kWG), 0, st, a,
+                       (const double *)a.segnorm, a.blknorm, spb, a.geo.nblocks, 1);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, a);
+}
+
+void launch_pass(const PassArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pass<false>, dim3(grid_for(a.geo.nunits)), dim3(kWG), 0, st, a);
+    launch_tail(a, st);
+}
+
+void launch_encode_basis(const PassArgs &a, hipStream_t st) { launch_pass(a, st); }
+
+void launch_decode_range(const PassArgs &a, uint64_t first, uint64_t count,
+                         double *out, hipStream_t st)
+{
+    const int s = a.geo.s;
+    uint64_t u0, u1;
+    if (a.geo.nseg == 1) {
+        u0 = 0;
+        u1 = 1;
+    } else {
+        u0 = (first >> s) >> 1;
+        u1 = (((first + count - 1) >> s) >> 1) + 1;
+    }
+    hipLaunchKernelGGL(k_decode_range, dim3(grid_for(u1 - u0)), dim3(kWG), 0, st, a, u0,
+                       u1, first, count, out);
+}
+
+void launch_probs(const PassArgs &a, const int *qubits_dev, int nq, double *probs_dev,
+                  hipStream_t st)
+{
+    hipLaunchKernelGGL(k_probs, dim3(grid_for(a.geo.nunits)), dim3(kWG), 0, st, a,
+                       qubits_dev, nq, probs_dev);
+}
+
+void launch_inner(const PassArgs &a, const PassArgs &b, const double *amp_a,
+                  const double *amp_b, double *part, double *result, hipStream_t st)
+{
+    const int n = a.geo.n;
+    int S = kMaxS;
+    if (!amp_a && a.geo.s > S)
+        S = a.geo.s;
+    if (S > n)
+        S = n;
+    const uint64_t nr = 1ull << (n - S);
+    hipLaunchKernelGGL(k_inner, dim3(grid_for(nr)), dim3(kWG), 0, st, a, b, amp_a, amp_b,
+                       S, nr, part);
+    hipLaunchKernelGGL(k_inner_final, dim3(1), dim3(kWG), 0, st, (const double *)part, nr,
+                       result);
+}
+
+void launch_rsqrt(const double *in, double *out, uint64_t count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rsqrt, dim3(grid_for((count + kWG - 1) / kWG)), dim3(kWG), 0, st,
+                       in, out, count);
+}
+
+}  // namespace aalc

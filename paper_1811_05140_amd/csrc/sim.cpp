@@ -1,0 +1,758 @@
+// sim.cpp -- host runtime behind the C ABI of include/aalcsim.h.
+//
+// A compressed sim owns two arenas of block streams (ping-pong: a pass reads
+// one and writes the other), two descriptor sets locating every block stream
+// and plane record, per-plane size tables for the ladder, and a small
+// device-resident state (N^2, s, bump pointers, statistics, error bits).
+// Passes are queued on the sim's stream without host synchronisation; the
+// host learns about device-side errors at the next synchronising call and
+// rolls the state back to the input of the failing pass.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/aalcsim.h"
+#include "device.h"
+
+using namespace aalc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            return fail(SIM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr uint64_t kMiB = 1ull << 20;
+constexpr uint64_t kGiB = 1ull << 30;
+
+}  // namespace
+
+struct sim {
+    int n = 0, b = 0, s = 0;
+    bool compressed = true;
+    int normalize = 1;
+    Ladder lad{};
+    Geo geo{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // compressed path
+    uint8_t *arena[2] = {nullptr, nullptr};
+    uint64_t arena_cap = 0;
+    Desc desc[2]{};
+    uint32_t *psz = nullptr;
+    int psz_levels = 0;
+    double *segnorm = nullptr, *blknorm = nullptr, *segsum = nullptr, *blksum = nullptr;
+    DevState *dev = nullptr;
+    int cur = 0;
+    uint64_t passes = 0;
+    // uncompressed path
+    double *amp = nullptr;
+    double *sv_scratch = nullptr;
+    double *sv_tdiff = nullptr;
+    std::vector<void *> allocs;
+    uint64_t device_bytes = 0;
+};
+
+namespace {
+
+int dmalloc(sim *S, void **p, uint64_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0)
+        bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(SIM_ENOMEM, "hipMalloc(%llu bytes) failed: %s",
+                    (unsigned long long)bytes, hipGetErrorString(e));
+    }
+    S->allocs.push_back(*p);
+    S->device_bytes += bytes;
+    return SIM_OK;
+}
+
+void free_all(sim *S)
+{
+    for (void *p : S->allocs)
+        (void)hipFree(p);
+    S->allocs.clear();
+}
+
+bool ladder_ok(const double *ladder, int L, double theta)
+{
+    if (!ladder || L < 1 || L > kMaxL || !(theta >= 1.0) || !std::isfinite(theta))
+        return false;
+    for (int k = 0; k < L; ++k) {
+        const double d = ladder[k];
+        if (!std::isfinite(d) || d < 0.0)
+            return false;
+        if (d == 0.0 && k != 0)
+            return false;
+        if (d > 0.0 && d < 0x1p-30)
+            return false;
+        if (k > 0 && !(d > ladder[k - 1]))
+            return false;
+    }
+    return true;
+}
+
+void set_ladder(Ladder &lad, const double *ladder, int L, double theta)
+{
+    lad = Ladder{};
+    lad.L = L;
+    lad.theta = theta;
+    for (int k = 0; k < L; ++k) {
+        lad.delta[k] = ladder[k];
+        lad.e[k] = 2.0 * ladder[k];
+        lad.r[k] = ladder[k] > 0.0 ? 1.0 / lad.e[k] : 0.0;
+    }
+}
+
+int ensure_psz(sim *S, int L)
+{
+    if (S->psz_levels >= L)
+        return SIM_OK;
+    if (S->psz) {
+        HIPCHK(hipStreamSynchronize(S->stream));
+        for (auto it = S->allocs.begin(); it != S->allocs.end(); ++it)
+            if (*it == S->psz) {
+                S->allocs.erase(it);
+                break;
+            }
+        S->device_bytes -= (uint64_t)S->psz_levels * 2 * S->geo.nseg * 4;
+        (void)hipFree(S->psz);
+        S->psz = nullptr;
+    }
+    int rc = dmalloc(S, (void **)&S->psz, (uint64_t)L * 2 * S->geo.nseg * 4);
+    if (rc)
+        return rc;
+    S->psz_levels = L;
+    return SIM_OK;
+}
+
+uint64_t gate_mask(const sim_gate_t *g)
+{
+    switch (g->kind) {
+    case G_U:
+    case G_X:
+        return 1ull << g->q0;
+    case G_CU:
+        return 1ull << g->q1;
+    case G_SWAP:
+        return (1ull << g->q0) | (1ull << g->q1);
+    default:
+        return 0;
+    }
+}
+
+int check_gate(const sim *S, const sim_gate_t *g)
+{
+    if (!g)
+        return fail(SIM_EINVAL, "gate is NULL");
+    if (g->pad != 0)
+        return fail(SIM_EINVAL, "gate pad must be 0");
+    const int n = S->n;
+    auto qok = [n](int q) { return q >= 0 && q < n; };
+    switch (g->kind) {
+    case G_U:
+    case G_DIAG1:
+    case G_X:
+        if (!qok(g->q0))
+            return fail(SIM_EINVAL, "qubit %d out of range for n=%d", g->q0, n);
+        return SIM_OK;
+    case G_CU:
+    case G_CPHASE:
+    case G_CZ:
+    case G_SWAP:
+        if (!qok(g->q0) || !qok(g->q1) || g->q0 == g->q1)
+            return fail(SIM_EINVAL, "qubits (%d,%d) invalid for n=%d", g->q0, g->q1, n);
+        return SIM_OK;
+    case G_PHASE_FLIP:
+        if (g->index >= (1ull << n))
+            return fail(SIM_EINVAL, "index %llu >= 2^%d", (unsigned long long)g->index, n);
+        return SIM_OK;
+    case G_DIFFUSE:
+        return SIM_OK;
+    default:
+        return fail(SIM_EINVAL, "unknown gate kind %u", g->kind);
+    }
+}
+
+GateArg to_arg(const sim_gate_t *g)
+{
+    GateArg a{};
+    a.kind = g->kind;
+    a.q0 = g->q0;
+    a.q1 = g->q1;
+    a.index = g->index;
+    a.mask = gate_mask(g);
+    for (int k = 0; k < 8; ++k)
+        a.u[k] = g->u[k];
+    return a;
+}
+
+PassArgs make_args(const sim *S, int in, int out, const GateArg &g)
+{
+    PassArgs a{};
+    a.geo = S->geo;
+    a.lad = S->lad;
+    a.gate = g;
+    a.din = S->desc[in];
+    a.dout = S->desc[out];
+    a.arena_in = S->arena[in];
+    a.arena_out = S->arena[out];
+    a.arena_cap = S->arena_cap;
+    a.out_arena = out;
+    a.in_arena = in;
+    a.pass = S->passes;
+    a.psz = S->psz;
+    a.segnorm = S->segnorm;
+    a.blknorm = S->blknorm;
+    a.segsum = S->segsum;
+    a.blksum = S->blksum;
+    a.dev = S->dev;
+    return a;
+}
+
+int reset_devstate(sim *S)
+{
+    DevState d{};
+    d.scale = 1.0;
+    d.normalize = S->normalize;
+    HIPCHK(hipMemcpyAsync(S->dev, &d, sizeof d, hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipStreamSynchronize(S->stream));
+    return SIM_OK;
+}
+
+// Synchronise, then surface device-side errors (rolling back on overflow).
+int sync_check(sim *S)
+{
+    HIPCHK(hipStreamSynchronize(S->stream));
+    if (!S->compressed)
+        return SIM_OK;
+    DevState d;
+    HIPCHK(hipMemcpy(&d, S->dev, sizeof d, hipMemcpyDeviceToHost));
+    if (d.err) {
+        const uint64_t pe = d.err_pass;
+        const uint32_t bits = d.err;
+        S->passes = pe;
+        S->cur = (int)(pe & 1);
+        d.err = 0;
+        d.err_pass = 0;
+        d.passes = pe;
+        d.arena_used[1 - S->cur] = 0;
+        HIPCHK(hipMemcpy(S->dev, &d, sizeof d, hipMemcpyHostToDevice));
+        if (bits & kErrSize)
+            return fail(SIM_EDEVICE, "internal size mismatch at pass %llu",
+                        (unsigned long long)pe);
+        return fail(SIM_ENOMEM,
+                    "arena capacity %llu bytes exceeded at pass %llu; state rolled back "
+                    "to the input of that gate",
+                    (unsigned long long)S->arena_cap, (unsigned long long)pe);
+    }
+    if (d.collapsed)
+        return fail(SIM_ECOLLAPSED, "N^2 of the stored state was 0 or not finite");
+    return SIM_OK;
+}
+
+int run_basis(sim *S, uint64_t x)
+{
+    if (!S->compressed) {
+        sv_set_basis(S->amp, S->n, x, S->stream);
+        S->passes = 0;
+        HIPCHK(hipGetLastError());
+        return SIM_OK;
+    }
+    int rc = reset_devstate(S);
+    if (rc)
+        return rc;
+    GateArg none{};
+    none.kind = kNone;
+    PassArgs a = make_args(S, 1, 0, none);
+    a.src_basis = 1;
+    a.basis = x;
+    a.pass = 0;
+    launch_encode_basis(a, S->stream);
+    HIPCHK(hipGetLastError());
+    S->cur = 0;
+    S->passes = 0;
+    return SIM_OK;
+}
+
+sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream)
+{
+    g_err.clear();
+    const bool compressed = !(eb < 0.0);
+    if (std::isnan(eb)) {
+        fail(SIM_EINVAL, "error_bound is NaN");
+        return nullptr;
+    }
+    if (n < 6 || n > (compressed ? 40 : 34)) {
+        fail(SIM_EINVAL, "n_qubits %d out of range", n);
+        return nullptr;
+    }
+    if (block_log2 < 6) {
+        fail(SIM_EINVAL, "block_log2 %d < 6", block_log2);
+        return nullptr;
+    }
+    sim *S = new (std::nothrow) sim();
+    if (!S) {
+        fail(SIM_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    S->n = n;
+    S->compressed = compressed;
+    S->b = block_log2 > n ? n : block_log2;
+    S->s = S->b < kMaxS ? S->b : kMaxS;
+    if (stream) {
+        S->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+            fail(SIM_EDEVICE, "hipStreamCreate failed");
+            delete S;
+            return nullptr;
+        }
+        S->own_stream = true;
+    }
+    int rc = SIM_OK;
+    if (!compressed) {
+        const uint64_t N = 1ull << n;
+        rc = dmalloc(S, (void **)&S->amp, 16 * N);
+        if (!rc)
+            rc = dmalloc(S, (void **)&S->sv_scratch, 16 * ((N >> 16) + 1) + 64);
+        if (!rc)
+            rc = dmalloc(S, (void **)&S->sv_tdiff, 64);
+    } else {
+        S->geo.n = n;
+        S->geo.b = S->b;
+        S->geo.s = S->s;
+        S->geo.nblocks = 1ull << (n - S->b);
+        S->geo.nseg = 1ull << (n - S->s);
+        S->geo.nunits = S->geo.nseg == 1 ? 1 : S->geo.nseg / 2;
+        if (eb > 0.0) {
+            const double lad[5] = {0.0, eb / 1000.0, eb / 100.0, eb / 10.0, eb};
+            if (!ladder_ok(lad, 5, 4.0)) {
+                fail(SIM_EINVAL, "error_bound %g gives an invalid ladder (lossy bounds "
+                     "must be >= 2^-30)", eb);
+                delete S;
+                return nullptr;
+            }
+            set_ladder(S->lad, lad, 5, 4.0);
+        } else {
+            const double lad[1] = {0.0};
+            set_ladder(S->lad, lad, 1, 4.0);
+        }
+        uint64_t cap = arena_bytes;
+        if (cap == 0) {
+            const double want = 1.05 * 16.0 * std::ldexp(1.0, n) + (double)kMiB;
+            cap = want > (double)(8 * kGiB) ? 8 * kGiB : (uint64_t)want;
+        }
+        cap = (cap + 255) & ~255ull;
+        S->arena_cap = cap;
+        const uint64_t nb = S->geo.nblocks, ns = S->geo.nseg;
+        for (int k = 0; k < 2 && !rc; ++k) {
+            rc = dmalloc(S, (void **)&S->arena[k], cap + 64);
+            if (!rc)
+                rc = dmalloc(S, (void **)&S->desc[k].blk_off, 8 * nb);
+            if (!rc)
+                rc = dmalloc(S, (void **)&S->desc[k].blk_len, 4 * nb);
+            if (!rc)
+                rc = dmalloc(S, (void **)&S->desc[k].blk_level, nb);
+            if (!rc)
+                rc = dmalloc(S, (void **)&S->desc[k].plane_rel, 4 * 2 * ns);
+        }
+        if (!rc)
+            rc = ensure_psz(S, S->lad.L);
+        if (!rc)
+            rc = dmalloc(S, (void **)&S->segnorm, 8 * ns);
+        if (!rc)
+            rc = dmalloc(S, (void **)&S->blknorm, 8 * nb);
+        if (!rc)
+            rc = dmalloc(S, (void **)&S->segsum, 16 * ns);
+        if (!rc)
+            rc = dmalloc(S, (void **)&S->blksum, 16 * nb);
+        if (!rc)
+            rc = dmalloc(S, (void **)&S->dev, sizeof(DevState));
+    }
+    if (!rc)
+        rc = run_basis(S, 0);
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(S->stream);
+        if (e != hipSuccess)
+            rc = fail(SIM_EDEVICE, "initial encode: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        std::string keep = g_err;
+        free_all(S);
+        if (S->own_stream)
+            (void)hipStreamDestroy(S->stream);
+        delete S;
+        g_err = keep;
+        return nullptr;
+    }
+    return S;
+}
+
+}  // namespace
+
+extern "C" {
+
+sim_t *sim_create(int n_qubits, int block_log2, double error_bound)
+{
+    return create(n_qubits, block_log2, error_bound, 0, nullptr);
+}
+
+sim_t *sim_create_ex(int n_qubits, int block_log2, double error_bound,
+                     uint64_t arena_bytes, void *hip_stream)
+{
+    return create(n_qubits, block_log2, error_bound, arena_bytes, hip_stream);
+}
+
+void sim_destroy(sim_t *S)
+{
+    if (!S)
+        return;
+    (void)hipStreamSynchronize(S->stream);
+    free_all(S);
+    if (S->own_stream)
+        (void)hipStreamDestroy(S->stream);
+    delete S;
+}
+
+int sim_apply_gate(sim_t *S, const sim_gate_t *gate)
+{
+    if (!S)
+        return fail(SIM_EINVAL, "sim is NULL");
+    int rc = check_gate(S, gate);
+    if (rc)
+        return rc;
+    const GateArg g = to_arg(gate);
+    if (!S->compressed) {
+        sv_apply(S->amp, S->n, g, S->sv_scratch, S->sv_tdiff, S->stream);
+        HIPCHK(hipGetLastError());
+        S->passes++;
+        return SIM_OK;
+    }
+    const int in = S->cur, out = 1 - S->cur;
+    PassArgs a = make_args(S, in, out, g);
+    if (g.kind == kDiffuse)
+        launch_mean(a, S->stream);
+    launch_pass(a, S->stream);
+    HIPCHK(hipGetLastError());
+    S->cur = out;
+    S->passes++;
+    return SIM_OK;
+}
+
+int sim_apply_gates(sim_t *S, const sim_gate_t *gates, size_t count)
+{
+    if (!S || (!gates && count))
+        return fail(SIM_EINVAL, "NULL argument");
+    for (size_t k = 0; k < count; ++k) {
+        int rc = sim_apply_gate(S, &gates[k]);
+        if (rc) {
+            std::string m = g_err;
+            return fail(rc, "gate %zu: %s", k, m.c_str());
+        }
+    }
+    return SIM_OK;
+}
+
+int sim_set_basis(sim_t *S, uint64_t x)
+{
+    if (!S)
+        return fail(SIM_EINVAL, "sim is NULL");
+    if (x >= (1ull << S->n))
+        return fail(SIM_EINVAL, "basis index out of range");
+    HIPCHK(hipStreamSynchronize(S->stream));
+    return run_basis(S, x);
+}
+
+int sim_set_aalc(sim_t *S, const double *ladder, int L, double theta)
+{
+    if (!S)
+        return fail(SIM_EINVAL, "sim is NULL");
+    if (!S->compressed)
+        return fail(SIM_EUNSUPPORTED, "the uncompressed path has no ladder");
+    if (!ladder_ok(ladder, L, theta))
+        return fail(SIM_EINVAL, "invalid ladder or theta");
+    int rc = ensure_psz(S, L);
+    if (rc)
+        return rc;
+    set_ladder(S->lad, ladder, L, theta);
+    return SIM_OK;
+}
+
+int sim_set_normalize(sim_t *S, int on)
+{
+    if (!S)
+        return fail(SIM_EINVAL, "sim is NULL");
+    if (!S->compressed)
+        return fail(SIM_EUNSUPPORTED, "the uncompressed path does not normalise");
+    S->normalize = on ? 1 : 0;
+    const int32_t flag = S->normalize;
+    HIPCHK(hipMemcpyAsync(&S->dev->normalize, &flag, sizeof flag, hipMemcpyHostToDevice,
+                          S->stream));
+    if (!on) {
+        const double one = 1.0;
+        HIPCHK(hipMemcpyAsync(&S->dev->scale, &one, sizeof one, hipMemcpyHostToDevice,
+                              S->stream));
+    }
+    HIPCHK(hipStreamSynchronize(S->stream));
+    return SIM_OK;
+}
+
+int sim_get_amplitudes(sim_t *S, uint64_t first, uint64_t count, double *out)
+{
+    if (!S || (!out && count))
+        return fail(SIM_EINVAL, "NULL argument");
+    const uint64_t N = 1ull << S->n;
+    if (first > N || count > N - first)
+        return fail(SIM_EINVAL, "range out of bounds");
+    if (count == 0)
+        return SIM_OK;
+    if (!S->compressed) {
+        HIPCHK(hipMemcpyAsync(out, S->amp + 2 * first, 16 * count, hipMemcpyDeviceToHost,
+                              S->stream));
+        HIPCHK(hipStreamSynchronize(S->stream));
+        return SIM_OK;
+    }
+    int rc = sync_check(S);
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    const uint64_t step = 1ull << 24;
+    double *buf = nullptr;
+    const uint64_t bcount = count < step ? count : step;
+    HIPCHK(hipMalloc((void **)&buf, 16 * bcount));
+    PassArgs a = make_args(S, S->cur, 1 - S->cur, GateArg{});
+    for (uint64_t off = 0; off < count; off += step) {
+        const uint64_t c = count - off < step ? count - off : step;
+        launch_decode_range(a, first + off, c, buf, S->stream);
+        hipError_t e = hipMemcpyAsync(out + 2 * off, buf, 16 * c, hipMemcpyDeviceToHost,
+                                      S->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(S->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(buf);
+            return fail(SIM_EDEVICE, "decode range: %s", hipGetErrorString(e));
+        }
+    }
+    HIPCHK(hipFree(buf));
+    return rc;
+}
+
+int sim_export_block(sim_t *S, uint64_t j, void *buf, size_t cap, size_t *len)
+{
+    if (!S || !len)
+        return fail(SIM_EINVAL, "NULL argument");
+    if (!S->compressed)
+        return fail(SIM_EUNSUPPORTED, "the uncompressed path has no block streams");
+    if (j >= S->geo.nblocks)
+        return fail(SIM_EINVAL, "block index out of range");
+    int rc = sync_check(S);
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    uint64_t off = 0;
+    uint32_t l = 0;
+    HIPCHK(hipMemcpy(&off, S->desc[S->cur].blk_off + j, 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&l, S->desc[S->cur].blk_len + j, 4, hipMemcpyDeviceToHost));
+    *len = l;
+    if (cap < l || !buf)
+        return fail(SIM_ENOMEM, "buffer of %zu bytes too small for %u", cap, l);
+    HIPCHK(hipMemcpy(buf, S->arena[S->cur] + off, l, hipMemcpyDeviceToHost));
+    return rc;
+}
+
+int sim_stats(sim_t *S, sim_stats_t *st)
+{
+    if (!S || !st)
+        return fail(SIM_EINVAL, "NULL argument");
+    memset(st, 0, sizeof *st);
+    st->device_bytes = S->device_bytes;
+    st->passes = S->passes;
+    if (!S->compressed) {
+        double ns = 0.0;
+        sv_normsq(S->amp, S->n, S->sv_scratch, S->sv_tdiff + 4, S->stream);
+        HIPCHK(hipMemcpyAsync(&ns, S->sv_tdiff + 4, 8, hipMemcpyDeviceToHost, S->stream));
+        HIPCHK(hipStreamSynchronize(S->stream));
+        st->normsq = ns;
+        st->scale = 1.0;
+        st->compressed = 0;
+        st->resident_bytes = 16ull << S->n;
+        st->peak_resident = st->resident_bytes;
+        st->min_ratio = st->last_ratio = 1.0;
+        return SIM_OK;
+    }
+    int rc = sync_check(S);
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    DevState d;
+    HIPCHK(hipMemcpy(&d, S->dev, sizeof d, hipMemcpyDeviceToHost));
+    st->normsq = d.normsq;
+    st->scale = d.scale;
+    st->collapsed = d.collapsed;
+    st->compressed = 1;
+    st->resident_bytes = d.resident;
+    st->peak_resident = d.peak_resident;
+    st->min_ratio = d.min_ratio;
+    st->last_ratio = d.last_ratio;
+    st->passes = d.passes;
+    for (int k = 0; k < kMaxL; ++k)
+        st->level_hist[k] = d.level_hist[k];
+    st->arena_bytes = S->arena_cap;
+    return rc;
+}
+
+int sim_sync(sim_t *S)
+{
+    if (!S)
+        return fail(SIM_EINVAL, "sim is NULL");
+    return sync_check(S);
+}
+
+int sim_set_stream(sim_t *S, void *hip_stream)
+{
+    if (!S)
+        return fail(SIM_EINVAL, "sim is NULL");
+    HIPCHK(hipStreamSynchronize(S->stream));
+    if (S->own_stream)
+        (void)hipStreamDestroy(S->stream);
+    if (hip_stream) {
+        S->stream = (hipStream_t)hip_stream;
+        S->own_stream = false;
+    } else {
+        HIPCHK(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+        S->own_stream = true;
+    }
+    return SIM_OK;
+}
+
+int sim_measure_probs(sim_t *S, const int *qubits, int nq, double *probs)
+{
+    if (!S || !qubits || !probs)
+        return fail(SIM_EINVAL, "NULL argument");
+    if (nq < 1 || nq > 24)
+        return fail(SIM_EINVAL, "nq %d out of range", nq);
+    for (int k = 0; k < nq; ++k) {
+        if (qubits[k] < 0 || qubits[k] >= S->n)
+            return fail(SIM_EINVAL, "qubit %d out of range", qubits[k]);
+        for (int m = 0; m < k; ++m)
+            if (qubits[m] == qubits[k])
+                return fail(SIM_EINVAL, "qubit %d listed twice", qubits[k]);
+    }
+    int rc = S->compressed ? sync_check(S) : SIM_OK;
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    int *dq = nullptr;
+    double *dp = nullptr;
+    const size_t nb = (size_t)1 << nq;
+    HIPCHK(hipMalloc((void **)&dq, sizeof(int) * nq));
+    if (hipMalloc((void **)&dp, 8 * nb) != hipSuccess) {
+        (void)hipFree(dq);
+        return fail(SIM_ENOMEM, "probability buffer");
+    }
+    hipError_t e = hipMemcpyAsync(dq, qubits, sizeof(int) * nq, hipMemcpyHostToDevice,
+                                  S->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(dp, 0, 8 * nb, S->stream);
+    if (e == hipSuccess) {
+        if (S->compressed)
+            launch_probs(make_args(S, S->cur, 1 - S->cur, GateArg{}), dq, nq, dp, S->stream);
+        else
+            sv_probs(S->amp, S->n, dq, nq, dp, S->stream);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(probs, dp, 8 * nb, hipMemcpyDeviceToHost, S->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(S->stream);
+    (void)hipFree(dq);
+    (void)hipFree(dp);
+    if (e != hipSuccess)
+        return fail(SIM_EDEVICE, "measure: %s", hipGetErrorString(e));
+    return rc;
+}
+
+int sim_fidelity(sim_t *A, sim_t *B, double *F)
+{
+    if (!A || !B || !F)
+        return fail(SIM_EINVAL, "NULL argument");
+    if (A->n != B->n)
+        return fail(SIM_EINVAL, "qubit counts differ (%d vs %d)", A->n, B->n);
+    int ra = A->compressed ? sync_check(A) : SIM_OK;
+    if (ra && ra != SIM_ECOLLAPSED)
+        return ra;
+    int rb = B->compressed ? sync_check(B) : SIM_OK;
+    if (rb && rb != SIM_ECOLLAPSED)
+        return rb;
+    HIPCHK(hipStreamSynchronize(A->stream));
+    HIPCHK(hipStreamSynchronize(B->stream));
+    const int n = A->n;
+    const int S = n < kMaxS ? n : kMaxS;
+    const uint64_t nr = 1ull << (n - S);
+    double *part = nullptr;
+    HIPCHK(hipMalloc((void **)&part, 8 * (4 * nr + 8)));
+    PassArgs pa = A->compressed ? make_args(A, A->cur, 1 - A->cur, GateArg{}) : PassArgs{};
+    PassArgs pb = B->compressed ? make_args(B, B->cur, 1 - B->cur, GateArg{}) : PassArgs{};
+    pa.geo.n = n;
+    launch_inner(pa, pb, A->compressed ? nullptr : A->amp, B->compressed ? nullptr : B->amp,
+                 part, part + 4 * nr, A->stream);
+    double res[5];
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(res, part + 4 * nr, sizeof res, hipMemcpyDeviceToHost, A->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(A->stream);
+    (void)hipFree(part);
+    if (e != hipSuccess)
+        return fail(SIM_EDEVICE, "fidelity: %s", hipGetErrorString(e));
+    *F = res[0];
+    return ra ? ra : rb;
+}
+
+int sim_debug_rsqrt(const double *in, double *out, size_t count)
+{
+    if (!in || !out)
+        return fail(SIM_EINVAL, "NULL argument");
+    if (!count)
+        return SIM_OK;
+    double *d = nullptr;
+    HIPCHK(hipMalloc((void **)&d, 16 * count));
+    hipError_t e = hipMemcpy(d, in, 8 * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        launch_rsqrt(d, d + count, count, nullptr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(out, d + count, 8 * count, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess)
+        return fail(SIM_EDEVICE, "rsqrt: %s", hipGetErrorString(e));
+    return SIM_OK;
+}
+
+const char *sim_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

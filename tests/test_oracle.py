@@ -429,8 +429,8 @@ def test_fidelity_properties():
     assert abs(orc.fidelity(a, a * np.exp(0.7j) * 3.0, n) - 1.0) < 1e-14
     F = orc.fidelity(a, b, n)
     assert 0.0 <= F <= 1.0
-    e0 = np.zeros(1 << n)
-    e1 = np.zeros(1 << n)
+    e0 = np.zeros(1 << n, dtype=complex)
+    e1 = np.zeros(1 << n, dtype=complex)
     e0[0] = e1[1] = 1.0
     assert orc.fidelity(e0, e1, n) == 0.0
     # matches |<a|b>|^2 / (<a|a><b|b>) from numpy
