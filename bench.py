@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the compressed per-gate loop on one MI355X.
+
+Workload: the 24-qubit QFT (312 native gates: H, controlled phase, SWAP) on a
+seeded basis state, complex128 state of 2^24 amplitudes held as 256
+compressed blocks of 2^16, default AALC ladder (0, eb/1000, eb/100, eb/10,
+eb) with eb = 1e-4 and ratio threshold 4.  One step = encode the basis state
++ apply the 312 gates (every gate is one decompress-normalise-gate-compress
+pass over all blocks).  The state is resident in HBM before timing starts.
+
+Prints one JSON line: gates/s (value), amplitude-GB/s and its fraction of
+the 8 TB/s HBM peak, the dominant kernel's roofline entry (HIP events on the
+sim stream over the timed region), the fidelity against the uncompressed
+FP64 run of the same circuit, and the CPU oracle timed on a block sample.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("gates/s and amplitude-GB/s (% of HBM peak) at fidelity ≥0.999; "
+          "serving p50/p99")
+HBM_PEAK_GBS = 8000.0
+LOGICAL_BYTES_PER_AMP = 32  # one read + one write of a complex128 per pass
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "gates.h", "device.h"):
+        with open(os.path.join(ROOT, "paper_1811_05140_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, launches_bytes):
+    """HBM bytes per launch from the committed PMC summary, if it was taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_qft24.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(A, orc, inputs, w, eb, budget_s):
+    """The CPU oracle on a block sample of the same workload: at each gate
+    (until the budget is spent) one random block group is exported from the
+    GPU state, recomputed by the oracle, and its time scaled by the number of
+    groups of that gate."""
+    import numpy as np
+    n, b = w["n"], w["b"]
+    s = min(b, 10)
+    lad = inputs.default_ladder(eb)
+    nb = 1 << (n - b)
+    sim = A.Sim(n, b, eb)
+    sim.set_basis(w["basis"])
+    rng = np.random.default_rng(5)
+    spent = 0.0
+    est = 0.0
+    sampled = 0
+    for gate in w["gates"]:
+        if spent < budget_s:
+            kind = gate[0]
+            mask = 0
+            if kind in (inputs.G_U, inputs.G_X):
+                mask = 1 << gate[1]
+            elif kind == inputs.G_CU:
+                mask = 1 << gate[2]
+            elif kind == inputs.G_SWAP:
+                mask = (1 << gate[1]) | (1 << gate[2])
+            mb = mask >> b
+            j = int(rng.integers(0, nb))
+            j = min(j, j ^ mb) if mb else j
+            in0 = sim.export_block(j)
+            in1 = sim.export_block(j ^ mb) if mb else None
+            sc = sim.stats()["scale"]
+            t0 = time.perf_counter()
+            orc.process_group(n, b, s, lad, 4.0, sc, None, gate, j, in0, in1)
+            dt = time.perf_counter() - t0
+            spent += dt
+            est += dt * (nb // 2 if mb else nb)
+            sampled += 1
+        sim.apply(gate)
+    sim.close()
+    return {
+        "value": sampled / est,
+        "unit": "gates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": ("%d of %d QFT-24 gates, one random block group each (oracle "
+                   "time %.1f s), scaled by the groups per gate" %
+                   (sampled, len(w["gates"]), spent)),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def calibrate_copy(torch, nbytes, reps):
+    """A plain device copy of known size, for scaling HBM counters."""
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--error-bound", type=float, default=1e-4)
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of oracle time for the CPU baseline (0: skip)")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without per-kernel events (no roofline entry)")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="only run a device copy of this many bytes (counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this simulator runs on one GPU; --gpus %d is not "
+              "supported (multi-GPU sharding is a design note only)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.calibrate_copy:
+        calibrate_copy(torch, args.calibrate_copy, 10)
+        return
+    from paper_1811_05140_amd import aalcsim as A
+    from paper_1811_05140_amd import inputs
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    w = inputs.qft24_workload()
+    n, b, x, gates = w["n"], w["b"], w["basis"], w["gates"]
+    eb = args.error_bound
+    sim = A.Sim(n, b, eb, stream=stream)
+
+    def step():
+        sim.set_basis(x)
+        sim.run(gates)
+
+    for _ in range(args.warmup):
+        step()
+    sim.sync()
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        sim.profile(True)
+        sim.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {} if args.no_profile else sim.profile_read()
+    sim.profile(False)
+    elapsed = t1 - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    gates_per_s = len(gates) * args.steps / elapsed
+    amp_gbs = gates_per_s * LOGICAL_BYTES_PER_AMP * (1 << n) / 1e9
+    st = sim.stats()
+
+    # fidelity against the uncompressed FP64 run of the same circuit
+    ref = A.Sim(n, b, -1.0, stream=stream)
+    ref.set_basis(x)
+    ref.run(gates)
+    F = sim.fidelity(ref)
+    ref.close()
+
+    roofline = None
+    if prof:
+        name, (cnt, tot, mn, mx) = max(prof.items(), key=lambda kv: kv[1][1])
+        avg_s = tot / cnt / 1000.0
+        alg_bytes = LOGICAL_BYTES_PER_AMP * (1 << n)
+        achieved = alg_bytes / avg_s / 1e9
+        roofline = {
+            "bound": "hbm", "kernel": name,
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(name, alg_bytes),
+            "avg_launch_ms": round(tot / cnt, 4), "launches": cnt,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "kernels_ms_per_step": {k: round(v[1] / args.steps, 3)
+                                    for k, v in sorted(prof.items())},
+        }
+
+    cpu = None
+    if args.cpu_budget > 0:
+        from oracle import oracle as orc
+        cpu = cpu_baseline(A, orc, inputs, w, eb, args.cpu_budget)
+
+    out = {
+        "metric": METRIC,
+        "value": round(gates_per_s, 2),
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded basis state, generated circuit)",
+        "config": {
+            "workload": "qft24", "n_qubits": n, "block_log2": b,
+            "segment_log2": min(b, 10), "error_bound": eb,
+            "ladder": inputs.default_ladder(eb), "theta": 4.0,
+            "gates_per_step": len(gates), "basis": x,
+        },
+        "amplitude_gbs": round(amp_gbs, 1),
+        "hbm_frac": round(amp_gbs / HBM_PEAK_GBS, 4),
+        "fidelity": F,
+        "fidelity_ok": bool(F >= 0.999),
+        "min_ratio": st["min_ratio"],
+        "last_ratio": st["last_ratio"],
+        "peak_resident_bytes": st["peak_resident"],
+        "level_hist": st["level_hist"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

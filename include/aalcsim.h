@@ -13,8 +13,8 @@
  * Conventions for every entry point
  *   - Qubit q is bit q of the amplitude index.
  *   - Pointers named host_* or documented as host are host memory, borrowed
- *     for the duration of the call only.  Device memory is owned by the sim
- *     unless it came from sim_context_create.
+ *     for the duration of the call only.  Device memory is owned by the
+ *     sim and released by sim_destroy.
  *   - Calls on one sim are ordered on that sim's HIP stream.  sim_apply_gate
  *     is asynchronous; every call that returns data to the host synchronises
  *     the stream first.  A sim is not thread-safe; different sims are
@@ -160,6 +160,25 @@ int sim_sync(sim_t *sim);
 /* Use `hip_stream` (a hipStream_t, e.g. a torch stream's handle) for all
  * later work of the sim.  The previous work is synchronised first. */
 int sim_set_stream(sim_t *sim, void *hip_stream);
+
+/* Per-kernel device time of one sim's launches. */
+typedef struct {
+    char name[32];       /* kernel name, NUL-terminated */
+    uint64_t launches;
+    double total_ms;     /* sum over launches of (end event - begin event) */
+    double min_ms;
+    double max_ms;
+} sim_kernel_time_t;
+
+/* Turn on (1) or off (0) HIP-event timing of every kernel this sim launches:
+ * a begin and an end event are recorded on the sim stream around each
+ * launch.  Synchronises. */
+int sim_profile(sim_t *sim, int on);
+
+/* Per-kernel totals of the launches timed since the last read (then reset).
+ * Writes up to cap entries to host memory `out`, the number of kernels seen
+ * to *count.  Synchronises. */
+int sim_profile_read(sim_t *sim, sim_kernel_time_t *out, int cap, int *count);
 
 /* Self-test hook for the normalisation scalar: out[i] = 1/sqrt(in[i])
  * computed on the device by the same code that derives s from N^2 (one

@@ -23,7 +23,7 @@ EXPORTS = [
     "sim_apply_gates", "sim_measure_probs", "sim_fidelity", "sim_set_basis",
     "sim_set_aalc", "sim_set_normalize", "sim_get_amplitudes",
     "sim_export_block", "sim_stats", "sim_sync", "sim_set_stream",
-    "sim_debug_rsqrt", "sim_last_error",
+    "sim_debug_rsqrt", "sim_last_error", "sim_profile", "sim_profile_read",
 ]
 
 
@@ -41,6 +41,12 @@ class Gate(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_uint32), ("q0", ctypes.c_int32),
                 ("q1", ctypes.c_int32), ("pad", ctypes.c_uint32),
                 ("index", ctypes.c_uint64), ("u", ctypes.c_double * 8)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double), ("min_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -85,6 +91,9 @@ def _load():
     L.sim_sync.argtypes = [vp]
     L.sim_set_stream.argtypes = [vp, vp]
     L.sim_debug_rsqrt.argtypes = [dp, dp, ctypes.c_size_t]
+    L.sim_profile.argtypes = [vp, ctypes.c_int]
+    L.sim_profile_read.argtypes = [vp, P(KernelTime), ctypes.c_int,
+                                   P(ctypes.c_int)]
     L.sim_last_error.restype = ctypes.c_char_p
     L.sim_last_error.argtypes = []
     return L
@@ -230,6 +239,18 @@ class Sim:
         buf = ctypes.create_string_buffer(max(ln.value, 1))
         check(lib.sim_export_block(self.h, j, buf, ln.value, ctypes.byref(ln)), True)
         return buf.raw[:ln.value]
+
+    def profile(self, on=True):
+        check(lib.sim_profile(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        """{kernel: (launches, total_ms, min_ms, max_ms)} since the last read."""
+        arr = (KernelTime * 32)()
+        cnt = ctypes.c_int(0)
+        check(lib.sim_profile_read(self.h, arr, 32, ctypes.byref(cnt)))
+        return {arr[k].name.decode(): (int(arr[k].launches), arr[k].total_ms,
+                                       arr[k].min_ms, arr[k].max_ms)
+                for k in range(min(cnt.value, 32))}
 
     def stats(self):
         st = Stats()

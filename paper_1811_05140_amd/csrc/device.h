@@ -101,10 +101,27 @@ struct PassArgs {
     DevState *dev;
 };
 
+// Kernel identities for the optional per-launch event timer.
+enum KernelId : int {
+    kIdPassSize, kIdPassEncode, kIdDecide, kIdBlockNorm, kIdReduce, kIdMean,
+    kIdMeanTree, kIdMeanFinal, kIdInitState, kIdSvPair, kIdSvDiag, kIdSvPartial,
+    kIdSvFinal, kNumKernelIds
+};
+extern const char *const kKernelNames[kNumKernelIds];
+
+// Host-side timer hook: when non-null, launchers bracket each kernel launch
+// with begin/end on the launch stream.
+struct Prof {
+    virtual void begin(int id, hipStream_t st) = 0;
+    virtual void end(int id, hipStream_t st) = 0;
+    virtual ~Prof() {}
+};
+
 // Launchers (kernels.hip).
-void launch_mean(const PassArgs &a, hipStream_t st);
-void launch_pass(const PassArgs &a, hipStream_t st);
-void launch_encode_basis(const PassArgs &a, hipStream_t st);
+void launch_init_state(DevState *dev, int normalize, hipStream_t st, Prof *prof);
+void launch_mean(const PassArgs &a, hipStream_t st, Prof *prof);
+void launch_pass(const PassArgs &a, hipStream_t st, Prof *prof);
+void launch_encode_basis(const PassArgs &a, hipStream_t st, Prof *prof);
 void launch_decode_range(const PassArgs &a, uint64_t first, uint64_t count,
                          double *out, hipStream_t st);
 void launch_probs(const PassArgs &a, const int *qubits_dev, int nq,
@@ -118,7 +135,7 @@ void launch_rsqrt(const double *in, double *out, uint64_t count,
 // Uncompressed path (sv.hip).
 void sv_set_basis(double *amp, int n, uint64_t x, hipStream_t st);
 void sv_apply(double *amp, int n, const GateArg &g, double *scratch,
-              double *tdiff_dev, hipStream_t st);
+              double *tdiff_dev, hipStream_t st, Prof *prof);
 void sv_probs(const double *amp, int n, const int *qubits_dev, int nq,
               double *probs_dev, hipStream_t st);
 void sv_normsq(const double *amp, int n, double *scratch, double *out_dev,

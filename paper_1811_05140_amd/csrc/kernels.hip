@@ -35,39 +35,79 @@ namespace aalc {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// ---- DPP wave primitives (gfx9 DPP: row shifts, row broadcasts, wave shift).
+// update_dpp(old, v, ctrl, row_mask, bank_mask, bound_ctrl=false): lanes
+// whose source is invalid, or whose row is masked off, receive `old`.
+template <int CTRL, int ROWM = 0xF>
+__device__ __forceinline__ uint32_t dpp32(uint32_t old, uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWM, 0xF, false);
+}
+
+template <int CTRL, int ROWM = 0xF>
+__device__ __forceinline__ uint64_t dpp64(uint64_t old, uint64_t v)
+{
+    const uint32_t lo = dpp32<CTRL, ROWM>((uint32_t)old, (uint32_t)v);
+    const uint32_t hi = dpp32<CTRL, ROWM>((uint32_t)(old >> 32), (uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128;
+constexpr int kWaveShr1 = 0x138;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+constexpr int kQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+
+// Inclusive prefix sums over the 64 lanes: row-local Hillis-Steele, then
+// row 0 -> row 1 and row 2 -> row 3 (bcast 15), then rows 0-1 -> rows 2-3
+// (bcast 31).
+__device__ __forceinline__ uint32_t wave_scan32(uint32_t v)
+{
+    v += dpp32<kRowShr1>(0u, v);
+    v += dpp32<kRowShr2>(0u, v);
+    v += dpp32<kRowShr4>(0u, v);
+    v += dpp32<kRowShr8>(0u, v);
+    v += dpp32<kRowBcast15, 0xA>(0u, v);
+    v += dpp32<kRowBcast31, 0xC>(0u, v);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_scan64(uint64_t v)
+{
+    v += dpp64<kRowShr1>(0ull, v);
+    v += dpp64<kRowShr2>(0ull, v);
+    v += dpp64<kRowShr4>(0ull, v);
+    v += dpp64<kRowShr8>(0ull, v);
+    v += dpp64<kRowBcast15, 0xA>(0ull, v);
+    v += dpp64<kRowBcast31, 0xC>(0ull, v);
+    return v;
+}
+
+// Maximum over the 64 lanes, returned as a wave-uniform value.
+__device__ __forceinline__ uint32_t wave_max32(uint32_t v)
+{
+    uint32_t t;
+    t = dpp32<kQuadXor1>(0u, v);
+    v = v > t ? v : t;
+    t = dpp32<kQuadXor2>(0u, v);
+    v = v > t ? v : t;
+    t = dpp32<kRowRor4>(0u, v);
+    v = v > t ? v : t;
+    t = dpp32<kRowRor8>(0u, v);
+    v = v > t ? v : t;
+    t = dpp32<kRowBcast15, 0xA>(0u, v);
+    v = v > t ? v : t;
+    t = dpp32<kRowBcast31, 0xC>(0u, v);
+    v = v > t ? v : t;
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
 {
     uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
     uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
     return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d)
-{
-    return (uint64_t)__shfl_up((unsigned long long)v, (unsigned int)d, 64);
-}
-
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
-{
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t o = __shfl_xor(v, d, 64);
-        v = v > o ? v : o;
-    }
-    return v;
-}
-
-// Inclusive prefix sum over the 64 lanes (two's complement, wraps).
-__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v)
-{
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint64_t t = shfl_up64(v, d);
-        if (lane >= d)
-            v += t;
-    }
-    return v;
 }
 
 __device__ __forceinline__ uint32_t bitlen64(uint64_t z)
@@ -102,34 +142,12 @@ __device__ __forceinline__ double inv_sqrt_exact(double x)
     return 1.0 / r;
 }
 
-// Quantiser of one ladder level (format: q = rint(x r) under |x r| < 2^30,
-// outlier unless |x - q e| < delta; delta == 0: q = the bits of x).
-__device__ __forceinline__ void quantize(double x, double delta, double e,
-                                         double r, uint64_t &q, bool &out)
-{
-    if (delta == 0.0) {
-        q = (uint64_t)__double_as_longlong(x);
-        out = false;
-        return;
-    }
-    double y = x * r;
-    if (fabs(y) < kQMax) {
-        double qr = __builtin_rint(y);
-        int32_t qi = (int32_t)qr;
-        double xh = (double)qi * e;
-        q = (uint64_t)(int64_t)qi;
-        out = !(fabs(x - xh) < delta);
-    } else {
-        q = 0;
-        out = true;
-    }
-}
-
 // ------------------------------------------------------------ units -------
 
 struct Unit {
     uint64_t g[2];  // segments (g[0] < g[1] when coupled)
     int nsu;        // segments in the unit (1 only when the state has one)
+    __device__ __forceinline__ uint64_t seg(int k) const { return k ? g[1] : g[0]; }
 };
 
 __device__ __forceinline__ Unit unit_of(uint64_t u, uint64_t nseg, uint64_t Ms)
@@ -157,8 +175,11 @@ __device__ __forceinline__ Unit unit_of(uint64_t u, uint64_t nseg, uint64_t Ms)
 
 typedef double Planes[2][2][1 << kMaxS];
 
-// Decode one plane record into dst[0 .. 2^s) (one wavefront), scaling each
-// value by `scale` when do_scale (normalisation before the gate).
+// Decode one plane record into dst[0 .. 2^s) (one wavefront, one chunk of
+// 64 scalars per step), scaling each value by `scale` when do_scale
+// (normalisation before the gate).  Lossy planes run the prefix sum in 32
+// bits: within a chunk the partial sums are differences of two codes of
+// magnitude below 2^30, so they are exact.
 __device__ void decode_plane(const uint8_t *rec, int s, double delta,
                              double scale, bool do_scale, double *dst)
 {
@@ -186,10 +207,19 @@ __device__ void decode_plane(const uint8_t *rec, int s, double delta,
                 v &= (1ull << w) - 1ull;
             z = v;
         }
-        const uint64_t q = carry + wave_incl_scan64(unzigzag64(z));
-        carry = readlane64(q, 63);
-        double x = (delta == 0.0) ? __longlong_as_double((long long)q)
-                                  : (double)(int64_t)q * e;
+        double x;
+        if (delta == 0.0) {
+            const uint64_t q = carry + wave_scan64(unzigzag64(z));
+            carry = readlane64(q, 63);
+            x = __longlong_as_double((long long)q);
+        } else {
+            const uint32_t z32 = (uint32_t)z;
+            const uint32_t d = (z32 >> 1) ^ (0u - (z32 & 1u));
+            const int32_t part = (int32_t)wave_scan32(d);
+            const int64_t q = (int64_t)carry + (int64_t)part;
+            carry = (uint64_t)(int64_t)__builtin_amdgcn_readlane((int)(int32_t)q, 63);
+            x = (double)q * e;
+        }
         if (do_scale)
             x = x * scale;
         dst[c * kChunk + lane] = x;
@@ -215,7 +245,7 @@ __device__ void load_unit(const PassArgs &a, const Unit &uc, Planes &X,
     const int s = a.geo.s;
     if (us >= uc.nsu)
         return;
-    const uint64_t g = uc.g[us];
+    const uint64_t g = uc.seg(us);
     double *dst = &X[us][p][0];
     if (a.src_basis) {
         for (int o = lane; o < (1 << s); o += 64)
@@ -243,7 +273,7 @@ __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
         for (uint32_t t = tid; t < total; t += kWG) {
             const int us = (int)(t >> s);
             const uint32_t o = t & (S - 1);
-            const uint64_t i = (uc.g[us] << s) | o;
+            const uint64_t i = (uc.seg(us) << s) | o;
             double ar = X[us][0][o], ai = X[us][1][o];
             gate_diag(G, i, ar, ai, tdiff);
             X[us][0][o] = ar;
@@ -270,7 +300,7 @@ __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
             const uint32_t r = t & (half - 1);
             const uint32_t o = ((r >> hb) << (hb + 1)) | (r & ((1u << hb) - 1));
             const uint32_t o2 = o ^ Ml;
-            const uint64_t i = (uc.g[us] << s) | o;
+            const uint64_t i = (uc.seg(us) << s) | o;
             double ar = X[us][0][o], ai = X[us][1][o];
             double br = X[us][0][o2], bi = X[us][1][o2];
             gate_pair(G, i, ar, ai, br, bi);
@@ -282,44 +312,100 @@ __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
     }
 }
 
-// Sizes of one plane at every ladder level (one wavefront).
+// Codes of one chunk at one level.  Lossy: q is the int32 code, `out` the
+// outlier flag, xh the value a decoder reconstructs.  Lossless: q is the bit
+// pattern.  `zz` receives the zigzagged Lorenzo difference against the
+// previous scalar (lane 0 takes `prev0`).
+__device__ __forceinline__ void lossy_code(double x, double delta, double e, double r,
+                                           int32_t &q, bool &out, double &xh)
+{
+    const double y = x * r;
+    if (fabs(y) < kQMax) {
+        const double qr = __builtin_rint(y);
+        q = (int32_t)qr;
+        xh = qr * e;
+        out = !(fabs(x - xh) < delta);
+        if (out)
+            xh = x;
+    } else {
+        q = 0;
+        out = true;
+        xh = x;
+    }
+}
+
+__device__ __forceinline__ uint32_t zigzag32(int32_t d)
+{
+    return ((uint32_t)d << 1) ^ (uint32_t)(d >> 31);
+}
+
+__device__ __forceinline__ uint32_t bitlen32(uint32_t z)
+{
+    return z ? 32u - (uint32_t)__builtin_clz(z) : 0u;
+}
+
+// Sizes of one plane at every ladder level (one wavefront; levels outer so
+// that only one level's state is live).
 __device__ void size_plane(const double *x, int s, const Ladder &lad,
                            uint32_t *psz, uint64_t plane, uint64_t nplanes)
 {
     const int lane = lane_id();
     const int C = 1 << (s - 6);
-    uint64_t carry[kMaxL];
-    uint32_t pw[kMaxL], no[kMaxL];
-#pragma unroll
-    for (int k = 0; k < kMaxL; ++k) {
-        carry[k] = 0;
-        pw[k] = 0;
-        no[k] = 0;
-    }
-    for (int c = 0; c < C; ++c) {
-        const double v = x[c * kChunk + lane];
-#pragma unroll
-        for (int k = 0; k < kMaxL; ++k) {
-            if (k < lad.L) {
-                uint64_t q;
+    for (int k = 0; k < lad.L; ++k) {
+        const double delta = lad.delta[k];
+        uint32_t pw = 0, no = 0;
+        if (delta == 0.0) {
+            uint64_t carry = 0;
+            for (int c = 0; c < C; ++c) {
+                const uint64_t q = (uint64_t)__double_as_longlong(x[c * kChunk + lane]);
+                const uint64_t prev = dpp64<kWaveShr1>(c == 0 ? q : carry, q);
+                pw += wave_max32(bitlen64(zigzag64(q - prev)));
+                carry = readlane64(q, 63);
+            }
+        } else {
+            const double e = lad.e[k], r = lad.r[k];
+            int32_t carry = 0;
+            for (int c = 0; c < C; ++c) {
+                int32_t q;
                 bool out;
-                quantize(v, lad.delta[k], lad.e[k], lad.r[k], q, out);
-                uint64_t prev = shfl_up64(q, 1);
-                if (lane == 0)
-                    prev = (c == 0) ? q : carry[k];
-                const uint32_t w = wave_max_u32(bitlen64(zigzag64(q - prev)));
-                pw[k] += w;
-                no[k] += (uint32_t)__popcll(__ballot(out));
-                carry[k] = readlane64(q, 63);
+                double xh;
+                lossy_code(x[c * kChunk + lane], delta, e, r, q, out, xh);
+                const int32_t prev = (int32_t)dpp32<kWaveShr1>(
+                    (uint32_t)(c == 0 ? q : carry), (uint32_t)q);
+                pw += wave_max32(bitlen32(zigzag32(q - prev)));
+                no += (uint32_t)__popcll(__ballot(out));
+                carry = __builtin_amdgcn_readlane(q, 63);
             }
         }
+        if (lane == 0)
+            psz[(uint64_t)k * nplanes + plane] = pw | (no << 16);
     }
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < kMaxL; ++k)
-            if (k < lad.L)
-                psz[(uint64_t)k * nplanes + plane] = pw[k] | (no[k] << 16);
+}
+
+// Scatter one chunk's fields (z of width w, lane l at bits [l w, l w + w))
+// into w payload words through the wave's LDS word buffer.
+__device__ __forceinline__ void pack_chunk(uint64_t z, uint32_t w, uint64_t *pb,
+                                           uint64_t *dst)
+{
+    const int lane = lane_id();
+    if (w == 64u) {
+        dst[lane] = z;
+        return;
     }
+    if ((uint32_t)lane < w)
+        pb[lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t bp = (uint32_t)lane * w;
+    const uint32_t wi = bp >> 6, sh = bp & 63u;
+    if (z) {
+        atomicOr((unsigned long long *)&pb[wi], (unsigned long long)(z << sh));
+        if (sh + w > 64u)
+            atomicOr((unsigned long long *)&pb[wi + 1], (unsigned long long)(z >> (64u - sh)));
+    }
+    __builtin_amdgcn_wave_barrier();
+    if ((uint32_t)lane < w)
+        dst[lane] = pb[lane];
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Encode one plane at one level into its record (one wavefront).  x is
@@ -336,62 +422,62 @@ __device__ void encode_plane(double *x, int s, double delta, double e,
         (uint64_t *)(rec + kPlaneHdrBytes + (pw_total ? pad8((uint32_t)C) : 0u));
     uint8_t *outl = (uint8_t *)(payload + pw_total);
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    uint64_t carry = 0;
     uint32_t woff = 0, nout = 0;
-    for (int c = 0; c < C; ++c) {
-        const double v = x[c * kChunk + lane];
-        uint64_t q;
-        bool out;
-        quantize(v, delta, e, r, q, out);
-        uint64_t prev = shfl_up64(q, 1);
-        if (lane == 0)
-            prev = (c == 0) ? q : carry;
-        const uint64_t z = zigzag64(q - prev);
-        const uint32_t w = wave_max_u32(bitlen64(z));
-        if (c == 0 && lane == 0) {
-            *(uint64_t *)rec = q;
-            *(uint32_t *)(rec + 8) = pw_total;
-            *(uint32_t *)(rec + 12) = nout_total;
+    if (delta == 0.0) {
+        uint64_t carry = 0;
+        for (int c = 0; c < C; ++c) {
+            const uint64_t q = (uint64_t)__double_as_longlong(x[c * kChunk + lane]);
+            const uint64_t prev = dpp64<kWaveShr1>(c == 0 ? q : carry, q);
+            const uint64_t z = zigzag64(q - prev);
+            const uint32_t w = wave_max32(bitlen64(z));
+            if (c == 0 && lane == 0) {
+                *(uint64_t *)rec = q;
+                *(uint32_t *)(rec + 8) = pw_total;
+                *(uint32_t *)(rec + 12) = nout_total;
+            }
+            if (pw_total && lane == 0)
+                widths[c] = (uint8_t)w;
+            if (w && woff + w <= pw_total)
+                pack_chunk(z, w, pb, payload + woff);
+            carry = readlane64(q, 63);
+            woff += w;
         }
-        if (pw_total && lane == 0)
-            widths[c] = (uint8_t)w;
-        // Record sizes come from the sizing kernel; the bounds below keep a
-        // disagreement (reported through kErrSize) inside the record.
-        const bool fits = woff + w <= pw_total;
-        if (!fits) {
-            // nothing is written for this chunk
-        } else if (w == 64u) {
-            payload[woff + lane] = z;
-        } else if (w) {
-            if ((uint32_t)lane < w)
-                pb[lane] = 0;
-            __builtin_amdgcn_wave_barrier();
-            const uint32_t bp = (uint32_t)lane * w;
-            const uint32_t wi = bp >> 6, sh = bp & 63u;
-            atomicOr((unsigned long long *)&pb[wi], (unsigned long long)(z << sh));
-            if (sh + w > 64u)
-                atomicOr((unsigned long long *)&pb[wi + 1],
-                         (unsigned long long)(z >> (64u - sh)));
-            __builtin_amdgcn_wave_barrier();
-            if ((uint32_t)lane < w)
-                payload[woff + lane] = pb[lane];
-            __builtin_amdgcn_wave_barrier();
+    } else {
+        int32_t carry = 0;
+        for (int c = 0; c < C; ++c) {
+            const double v = x[c * kChunk + lane];
+            int32_t q;
+            bool out;
+            double xh;
+            lossy_code(v, delta, e, r, q, out, xh);
+            const int32_t prev =
+                (int32_t)dpp32<kWaveShr1>((uint32_t)(c == 0 ? q : carry), (uint32_t)q);
+            const uint32_t z = zigzag32(q - prev);
+            const uint32_t w = wave_max32(bitlen32(z));
+            if (c == 0 && lane == 0) {
+                *(int64_t *)rec = (int64_t)q;
+                *(uint32_t *)(rec + 8) = pw_total;
+                *(uint32_t *)(rec + 12) = nout_total;
+            }
+            if (pw_total && lane == 0)
+                widths[c] = (uint8_t)w;
+            if (w && woff + w <= pw_total)
+                pack_chunk((uint64_t)z, w, pb, payload + woff);
+            const uint64_t bal = __ballot(out);
+            if (out) {
+                const uint32_t rank = nout + (uint32_t)__popcll(bal & lt_mask);
+                if (rank < nout_total) {
+                    uint8_t *ent = outl + (uint64_t)kOutlierBytes * rank;
+                    *(uint32_t *)ent = (uint32_t)(c * kChunk + lane);
+                    *(uint32_t *)(ent + 4) = 0u;
+                    *(uint64_t *)(ent + 8) = (uint64_t)__double_as_longlong(v);
+                }
+            }
+            nout += (uint32_t)__popcll(bal);
+            x[c * kChunk + lane] = xh;
+            carry = __builtin_amdgcn_readlane(q, 63);
+            woff += w;
         }
-        const uint64_t bal = __ballot(out);
-        if (out && nout + (uint32_t)__popcll(bal & lt_mask) < nout_total) {
-            const uint32_t rank = nout + (uint32_t)__popcll(bal & lt_mask);
-            uint8_t *ent = outl + (uint64_t)kOutlierBytes * rank;
-            *(uint32_t *)ent = (uint32_t)(c * kChunk + lane);
-            *(uint32_t *)(ent + 4) = 0u;
-            *(uint64_t *)(ent + 8) = (uint64_t)__double_as_longlong(v);
-        }
-        nout += (uint32_t)__popcll(bal);
-        double xh = v;
-        if (!out && delta != 0.0)
-            xh = (double)(int64_t)q * e;
-        x[c * kChunk + lane] = xh;
-        carry = readlane64(q, 63);
-        woff += w;
     }
     if (pw_total && lane == 0)
         for (int i = C; i < (int)pad8((uint32_t)C); ++i)
@@ -465,7 +551,7 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
         __syncthreads();
         const int us = wave >> 1, p = wave & 1;
         if (us < uc.nsu) {
-            const uint64_t g = uc.g[us];
+            const uint64_t g = uc.seg(us);
             const uint64_t plane = 2 * g + p;
             if (!ENC) {
                 size_plane(&X[us][p][0], s, a.lad, a.psz, plane, nplanes);
@@ -487,7 +573,7 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
                 return rr + ii;
             });
             if (threadIdx.x < (unsigned)uc.nsu)
-                a.segnorm[uc.g[threadIdx.x]] = ns;
+                a.segnorm[uc.seg((int)threadIdx.x)] = ns;
         }
         __syncthreads();
     }
@@ -512,7 +598,7 @@ __global__ __launch_bounds__(kWG) void k_mean(PassArgs a)
             const double sm = segment_tree(uc, s, red,
                                            [&](int su, int o) { return X[su][c][o]; });
             if (threadIdx.x < (unsigned)uc.nsu)
-                a.segsum[(uint64_t)c * a.geo.nseg + uc.g[threadIdx.x]] = sm;
+                a.segsum[(uint64_t)c * a.geo.nseg + uc.seg((int)threadIdx.x)] = sm;
         }
         __syncthreads();
     }
@@ -747,7 +833,7 @@ __global__ __launch_bounds__(kWG) void k_decode_range(PassArgs a, uint64_t u0,
         __syncthreads();
         for (int us = 0; us < uc.nsu; ++us)
             for (uint32_t o = threadIdx.x; o < (1u << s); o += kWG) {
-                const uint64_t i = (uc.g[us] << s) | o;
+                const uint64_t i = (uc.seg(us) << s) | o;
                 if (i >= first && i < first + count) {
                     out[2 * (i - first)] = X[us][0][o];
                     out[2 * (i - first) + 1] = X[us][1][o];
@@ -777,7 +863,7 @@ __global__ __launch_bounds__(kWG) void k_probs(PassArgs a, const int *qubits, in
         __syncthreads();
         for (int us = 0; us < uc.nsu; ++us)
             for (uint32_t o = threadIdx.x; o < (1u << s); o += kWG) {
-                const uint64_t i = (uc.g[us] << s) | o;
+                const uint64_t i = (uc.seg(us) << s) | o;
                 uint32_t oc = 0;
                 for (int k = 0; k < nq; ++k)
                     oc |= (uint32_t)bit_of(i, qubits[k]) << k;
@@ -893,42 +979,80 @@ __global__ void k_rsqrt(const double *in, double *out, uint64_t count)
 
 // ------------------------------------------------------- launchers --------
 
+const char *const kKernelNames[kNumKernelIds] = {
+    "pass_size", "pass_encode", "decide", "block_norm", "reduce", "mean",
+    "mean_tree", "mean_final", "init_state", "sv_pair", "sv_diag", "sv_partial",
+    "sv_final"};
+
 static unsigned grid_for(uint64_t items)
 {
     const uint64_t cap = 1ull << 20;
     return (unsigned)(items < cap ? (items ? items : 1) : cap);
 }
 
-void launch_mean(const PassArgs &a, hipStream_t st)
+// Bracket one launch with the optional timer.
+#define TIMED(prof, id, st, launch)                                              \
+    do {                                                                         \
+        if (prof)                                                                \
+            (prof)->begin((id), (st));                                           \
+        launch;                                                                  \
+        if (prof)                                                                \
+            (prof)->end((id), (st));                                             \
+    } while (0)
+
+__global__ void k_init_state(DevState *dev, int normalize)
+{
+    if (threadIdx.x == 0) {
+        DevState d = {};
+        d.scale = 1.0;
+        d.normalize = normalize;
+        *dev = d;
+    }
+}
+
+void launch_init_state(DevState *dev, int normalize, hipStream_t st, Prof *prof)
+{
+    TIMED(prof, kIdInitState, st,
+          hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, st, dev, normalize));
+}
+
+void launch_mean(const PassArgs &a, hipStream_t st, Prof *prof)
 {
     PassArgs m = a;
-    hipLaunchKernelGGL(k_mean, dim3(grid_for(a.geo.nunits)), dim3(kWG), 0, st, m);
+    TIMED(prof, kIdMean, st,
+          hipLaunchKernelGGL(k_mean, dim3(grid_for(a.geo.nunits)), dim3(kWG), 0, st, m));
     const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
     for (int c = 0; c < 2; ++c)
-        hipLaunchKernelGGL(k_segtree, dim3(grid_for(a.geo.nblocks)), dim3(kWG), 0, st, m,
-                           (const double *)(a.segsum + (uint64_t)c * a.geo.nseg),
-                           a.blksum + (uint64_t)c * a.geo.nblocks, spb, a.geo.nblocks, 0);
-    hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(kWG), 0, st, m,
-                       ldexp(1.0, 1 - a.geo.n));
+        TIMED(prof, kIdMeanTree, st,
+              hipLaunchKernelGGL(k_segtree, dim3(grid_for(a.geo.nblocks)), dim3(kWG), 0,
+                                 st, m,
+                                 (const double *)(a.segsum + (uint64_t)c * a.geo.nseg),
+                                 a.blksum + (uint64_t)c * a.geo.nblocks, spb,
+                                 a.geo.nblocks, 0));
+    TIMED(prof, kIdMeanFinal, st,
+          hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(kWG), 0, st, m,
+                             ldexp(1.0, 1 - a.geo.n)));
 }
 
-static void launch_tail(const PassArgs &a, hipStream_t st)
+void launch_pass(const PassArgs &a, hipStream_t st, Prof *prof)
 {
-    hipLaunchKernelGGL(k_decide, dim3(grid_for(a.geo.nblocks)), dim3(kWG), 0, st, a);
-    hipLaunchKernelGGL(k_pass<true>, dim3(grid_for(a.geo.nunits)), dim3(kWG), 0, st, a);
+    const unsigned gu = grid_for(a.geo.nunits), gb = grid_for(a.geo.nblocks);
     const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
-    hipLaunchKernelGGL(k_segtree, dim3(grid_for(a.geo.nblocks)), dim3(kWG), 0, st, a,
-                       (const double *)a.segnorm, a.blknorm, spb, a.geo.nblocks, 1);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, a);
+    TIMED(prof, kIdPassSize, st,
+          hipLaunchKernelGGL(k_pass<false>, dim3(gu), dim3(kWG), 0, st, a));
+    TIMED(prof, kIdDecide, st, hipLaunchKernelGGL(k_decide, dim3(gb), dim3(kWG), 0, st, a));
+    TIMED(prof, kIdPassEncode, st,
+          hipLaunchKernelGGL(k_pass<true>, dim3(gu), dim3(kWG), 0, st, a));
+    TIMED(prof, kIdBlockNorm, st,
+          hipLaunchKernelGGL(k_segtree, dim3(gb), dim3(kWG), 0, st, a,
+                             (const double *)a.segnorm, a.blknorm, spb, a.geo.nblocks, 1));
+    TIMED(prof, kIdReduce, st, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, a));
 }
 
-void launch_pass(const PassArgs &a, hipStream_t st)
+void launch_encode_basis(const PassArgs &a, hipStream_t st, Prof *prof)
 {
-    hipLaunchKernelGGL(k_pass<false>, dim3(grid_for(a.geo.nunits)), dim3(kWG), 0, st, a);
-    launch_tail(a, st);
+    launch_pass(a, st, prof);
 }
-
-void launch_encode_basis(const PassArgs &a, hipStream_t st) { launch_pass(a, st); }
 
 void launch_decode_range(const PassArgs &a, uint64_t first, uint64_t count,
                          double *out, hipStream_t st)

@@ -46,6 +46,57 @@ int fail(int code, const char *fmt, ...)
 constexpr uint64_t kMiB = 1ull << 20;
 constexpr uint64_t kGiB = 1ull << 30;
 
+// Per-launch event timer: a begin and an end event around every kernel,
+// resolved into per-kernel totals when read.
+struct EventProf final : Prof {
+    struct Rec {
+        int id;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t pending = nullptr;
+    int pending_id = -1;
+
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        return e;
+    }
+    void begin(int id, hipStream_t st) override
+    {
+        pending = get();
+        pending_id = id;
+        if (pending)
+            (void)hipEventRecord(pending, st);
+    }
+    void end(int id, hipStream_t st) override
+    {
+        hipEvent_t e = get();
+        if (!e || !pending || id != pending_id)
+            return;
+        (void)hipEventRecord(e, st);
+        recs.push_back({id, pending, e});
+        pending = nullptr;
+    }
+    ~EventProf() override
+    {
+        for (auto &r : recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool)
+            (void)hipEventDestroy(e);
+    }
+};
+
 }  // namespace
 
 struct sim {
@@ -72,6 +123,7 @@ struct sim {
     double *sv_tdiff = nullptr;
     std::vector<void *> allocs;
     uint64_t device_bytes = 0;
+    EventProf *prof = nullptr;
 };
 
 namespace {
@@ -238,11 +290,8 @@ PassArgs make_args(const sim *S, int in, int out, const GateArg &g)
 
 int reset_devstate(sim *S)
 {
-    DevState d{};
-    d.scale = 1.0;
-    d.normalize = S->normalize;
-    HIPCHK(hipMemcpyAsync(S->dev, &d, sizeof d, hipMemcpyHostToDevice, S->stream));
-    HIPCHK(hipStreamSynchronize(S->stream));
+    launch_init_state(S->dev, S->normalize, S->stream, S->prof);
+    HIPCHK(hipGetLastError());
     return SIM_OK;
 }
 
@@ -294,7 +343,7 @@ int run_basis(sim *S, uint64_t x)
     a.src_basis = 1;
     a.basis = x;
     a.pass = 0;
-    launch_encode_basis(a, S->stream);
+    launch_encode_basis(a, S->stream, S->prof);
     HIPCHK(hipGetLastError());
     S->cur = 0;
     S->passes = 0;
@@ -435,6 +484,7 @@ void sim_destroy(sim_t *S)
     if (!S)
         return;
     (void)hipStreamSynchronize(S->stream);
+    delete S->prof;
     free_all(S);
     if (S->own_stream)
         (void)hipStreamDestroy(S->stream);
@@ -450,7 +500,7 @@ int sim_apply_gate(sim_t *S, const sim_gate_t *gate)
         return rc;
     const GateArg g = to_arg(gate);
     if (!S->compressed) {
-        sv_apply(S->amp, S->n, g, S->sv_scratch, S->sv_tdiff, S->stream);
+        sv_apply(S->amp, S->n, g, S->sv_scratch, S->sv_tdiff, S->stream, S->prof);
         HIPCHK(hipGetLastError());
         S->passes++;
         return SIM_OK;
@@ -458,8 +508,8 @@ int sim_apply_gate(sim_t *S, const sim_gate_t *gate)
     const int in = S->cur, out = 1 - S->cur;
     PassArgs a = make_args(S, in, out, g);
     if (g.kind == kDiffuse)
-        launch_mean(a, S->stream);
-    launch_pass(a, S->stream);
+        launch_mean(a, S->stream, S->prof);
+    launch_pass(a, S->stream, S->prof);
     HIPCHK(hipGetLastError());
     S->cur = out;
     S->passes++;
@@ -750,6 +800,61 @@ int sim_debug_rsqrt(const double *in, double *out, size_t count)
     (void)hipFree(d);
     if (e != hipSuccess)
         return fail(SIM_EDEVICE, "rsqrt: %s", hipGetErrorString(e));
+    return SIM_OK;
+}
+
+int sim_profile(sim_t *S, int on)
+{
+    if (!S)
+        return fail(SIM_EINVAL, "sim is NULL");
+    HIPCHK(hipStreamSynchronize(S->stream));
+    if (on && !S->prof)
+        S->prof = new (std::nothrow) EventProf();
+    if (on && !S->prof)
+        return fail(SIM_ENOMEM, "profiler allocation failed");
+    if (!on) {
+        delete S->prof;
+        S->prof = nullptr;
+    }
+    return SIM_OK;
+}
+
+int sim_profile_read(sim_t *S, sim_kernel_time_t *out, int cap, int *count)
+{
+    if (!S || !count || (cap > 0 && !out))
+        return fail(SIM_EINVAL, "NULL argument");
+    *count = 0;
+    if (!S->prof)
+        return SIM_OK;
+    HIPCHK(hipStreamSynchronize(S->stream));
+    sim_kernel_time_t acc[kNumKernelIds];
+    memset(acc, 0, sizeof acc);
+    for (auto &r : S->prof->recs) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            sim_kernel_time_t &k = acc[r.id];
+            if (k.launches == 0 || ms < k.min_ms)
+                k.min_ms = ms;
+            if (ms > k.max_ms)
+                k.max_ms = ms;
+            k.total_ms += ms;
+            k.launches += 1;
+        }
+        S->prof->pool.push_back(r.a);
+        S->prof->pool.push_back(r.b);
+    }
+    S->prof->recs.clear();
+    int m = 0;
+    for (int id = 0; id < kNumKernelIds; ++id) {
+        if (!acc[id].launches)
+            continue;
+        if (m < cap) {
+            out[m] = acc[id];
+            snprintf(out[m].name, sizeof out[m].name, "%s", kKernelNames[id]);
+        }
+        ++m;
+    }
+    *count = m;
     return SIM_OK;
 }
 

@@ -182,24 +182,38 @@ static void ranges_of(int n, uint64_t &per, uint64_t &nr)
     nr = 1ull << (n - k);
 }
 
+#define TIMED(prof, id, st, launch)                                              \
+    do {                                                                         \
+        if (prof)                                                                \
+            (prof)->begin((id), (st));                                           \
+        launch;                                                                  \
+        if (prof)                                                                \
+            (prof)->end((id), (st));                                             \
+    } while (0)
+
 void sv_apply(double *amp, int n, const GateArg &g, double *scratch, double *tdiff_dev,
-              hipStream_t st)
+              hipStream_t st, Prof *prof)
 {
     const uint64_t N = 1ull << n;
     if (g.kind == kDiffuse) {
         uint64_t per, nr;
         ranges_of(n, per, nr);
-        hipLaunchKernelGGL(k_sv_partial, dim3(sv_grid(nr * kSvWG)), dim3(kSvWG), 0, st,
-                           (const double *)amp, per, nr, 0, scratch);
-        hipLaunchKernelGGL(k_sv_final, dim3(1), dim3(kSvWG), 0, st, (const double *)scratch,
-                           nr, 2, ldexp(1.0, 1 - n), tdiff_dev);
+        TIMED(prof, kIdSvPartial, st,
+              hipLaunchKernelGGL(k_sv_partial, dim3(sv_grid(nr * kSvWG)), dim3(kSvWG), 0, st,
+                                 (const double *)amp, per, nr, 0, scratch));
+        TIMED(prof, kIdSvFinal, st,
+              hipLaunchKernelGGL(k_sv_final, dim3(1), dim3(kSvWG), 0, st,
+                                 (const double *)scratch, nr, 2, ldexp(1.0, 1 - n),
+                                 tdiff_dev));
     }
     if (g.mask) {
-        hipLaunchKernelGGL(k_sv_pair, dim3(sv_grid(N / 2)), dim3(kSvWG), 0, st, amp, g,
-                           N / 2);
+        TIMED(prof, kIdSvPair, st,
+              hipLaunchKernelGGL(k_sv_pair, dim3(sv_grid(N / 2)), dim3(kSvWG), 0, st, amp, g,
+                                 N / 2));
     } else {
-        hipLaunchKernelGGL(k_sv_diag, dim3(sv_grid(N)), dim3(kSvWG), 0, st, amp, g, N,
-                           (const double *)tdiff_dev);
+        TIMED(prof, kIdSvDiag, st,
+              hipLaunchKernelGGL(k_sv_diag, dim3(sv_grid(N)), dim3(kSvWG), 0, st, amp, g, N,
+                                 (const double *)tdiff_dev));
     }
 }
 
