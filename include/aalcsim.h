@@ -87,17 +87,23 @@ typedef struct {
     uint64_t level_hist[8];    /* blocks encoded at each ladder level */
     uint64_t arena_bytes;      /* capacity of each of the two arenas */
     uint64_t device_bytes;     /* all device memory held by the sim */
+    uint64_t replays;          /* blocks re-encoded because the level chosen
+                                  differed from the one speculated */
+    uint64_t escalations;      /* blocks whose first sized levels all missed
+                                  theta, so the rest of the ladder was sized */
+    uint64_t arena_peak;       /* largest arena fill of any pass (bytes) */
 } sim_stats_t;
 
 /* Create an n-qubit state |0...0> with blocks of 2^block_log2 amplitudes
- * (the AALC decision unit; clamped to n; 6 <= block_log2; 6 <= n <= 40).
+ * (the AALC decision unit; 6 <= block_log2 <= 20, clamped to n;
+ * 6 <= n <= 40).
  *   error_bound > 0 : AALC ladder (0, eb/1000, eb/100, eb/10, eb), theta 4
  *                     (Alg. 2: lossless first, then growing bounds).
  *   error_bound == 0: lossless only.
  *   error_bound < 0 : uncompressed FP64 state vector (n <= 34), the
  *                     "no compression" comparator of Sec. IV.
  * Two arenas of compressed streams are allocated (ping-pong between
- * passes); their size is min(1.05 * 16 * 2^n + 1 MiB, 8 GiB) each unless
+ * passes); their size is min(2.1 * 16 * 2^n + 1 MiB, 8 GiB) each unless
  * sim_create_ex gives one.  Returns NULL on failure (sim_last_error()). */
 sim_t *sim_create(int n_qubits, int block_log2, double error_bound);
 

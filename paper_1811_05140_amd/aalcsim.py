@@ -58,7 +58,10 @@ class Stats(ctypes.Structure):
                 ("passes", ctypes.c_uint64),
                 ("level_hist", ctypes.c_uint64 * 8),
                 ("arena_bytes", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64),
+                ("replays", ctypes.c_uint64),
+                ("escalations", ctypes.c_uint64),
+                ("arena_peak", ctypes.c_uint64)]
 
 
 def _load():
@@ -263,7 +266,9 @@ class Sim:
                 "passes": st.passes,
                 "level_hist": [int(st.level_hist[k]) for k in range(8)],
                 "arena_bytes": st.arena_bytes,
-                "device_bytes": st.device_bytes}
+                "device_bytes": st.device_bytes,
+                "replays": st.replays, "escalations": st.escalations,
+                "arena_peak": st.arena_peak}
 
 
 def debug_rsqrt(x):

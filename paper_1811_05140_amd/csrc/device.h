@@ -43,12 +43,14 @@ struct Ladder {
     double r[kMaxL];      // fl(1 / e), rounded on the host
 };
 
-// One descriptor set: where each block stream and plane record lives.
+// One descriptor set: the stream header of every block and where each plane
+// record lives in the arena.  A block's canonical stream is its header
+// followed by its plane records in plane order.
 struct Desc {
-    uint64_t *blk_off;    // [nblocks] byte offset of the block stream in its arena
-    uint32_t *blk_len;    // [nblocks] stream bytes
+    uint8_t *hdr;         // [nblocks][32] stream headers (block stream v1)
+    uint32_t *blk_len;    // [nblocks] canonical stream bytes
     uint8_t *blk_level;   // [nblocks] ladder level of the stream
-    uint32_t *plane_rel;  // [2*nseg] plane record offset from the block start
+    uint64_t *plane_off;  // [2*nseg] byte offset of each plane record
 };
 
 // Device-resident scalars of one sim, read and written only by kernels.
@@ -67,6 +69,11 @@ struct DevState {
     uint32_t err_pass;      // pass index of the first error
     int32_t collapsed;
     int32_t normalize;
+    uint32_t n_replay;      // blocks whose chosen level was not the speculated one
+    uint32_t n_esc;         // blocks whose computed levels all missed theta
+    uint64_t replays;       // cumulative count of replayed blocks
+    uint64_t escalations;   // cumulative count of escalated blocks
+    uint64_t arena_peak;    // largest bump pointer reached (incl. replay waste)
 };
 
 enum : uint32_t { kErrArena = 1u, kErrSize = 2u };
@@ -94,6 +101,8 @@ struct PassArgs {
     int32_t src_basis;
     int32_t pad;
     uint32_t *psz;       // [L][2*nseg]: payload words | n_outliers << 16
+    uint32_t *replay_list;  // [nblocks]
+    uint32_t *esc_list;     // [nblocks]
     double *segnorm;     // [nseg]
     double *blknorm;     // [nblocks]
     double *segsum;      // [2][nseg] DIFFUSE pre-pass
@@ -103,9 +112,9 @@ struct PassArgs {
 
 // Kernel identities for the optional per-launch event timer.
 enum KernelId : int {
-    kIdPassSize, kIdPassEncode, kIdDecide, kIdBlockNorm, kIdReduce, kIdMean,
-    kIdMeanTree, kIdMeanFinal, kIdInitState, kIdSvPair, kIdSvDiag, kIdSvPartial,
-    kIdSvFinal, kNumKernelIds
+    kIdPass, kIdDecide, kIdEscSize, kIdEscDecide, kIdReplay, kIdBlockNorm,
+    kIdReduce, kIdMean, kIdMeanTree, kIdMeanFinal, kIdInitState, kIdSvPair,
+    kIdSvDiag, kIdSvPartial, kIdSvFinal, kNumKernelIds
 };
 extern const char *const kKernelNames[kNumKernelIds];
 
@@ -131,6 +140,7 @@ void launch_inner(const PassArgs &a, const PassArgs &b, const double *amp_a,
                   hipStream_t st);
 void launch_rsqrt(const double *in, double *out, uint64_t count,
                   hipStream_t st);
+void launch_export(const PassArgs &a, uint64_t j, uint8_t *out, hipStream_t st);
 
 // Uncompressed path (sv.hip).
 void sv_set_basis(double *amp, int n, uint64_t x, hipStream_t st);

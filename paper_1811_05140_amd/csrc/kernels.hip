@@ -1,25 +1,37 @@
 // kernels.hip -- gfx950 kernels of the compressed path.
 //
-// One pass of a gate (Alg. 2 of the paper for every stride) is five kernels
-// on the sim stream:
-//   k_pass<false>  decode + normalise + gate, then the size of every plane
-//                  record at every ladder level (no output written)
-//   k_decide       per block: the first ladder level whose ratio reaches
-//                  theta (else the last), the block's place in the output
-//                  arena, the plane record offsets and the stream header
-//   k_pass<true>   decode + normalise + gate again, encode each plane at its
-//                  block's level, pack, write; per-segment normsq
-//   k_blocknorm    per block: pairwise normsq into the stream header
-//   k_reduce       N^2 over blocks, s = 1/sqrt(N^2), statistics
-// DIFFUSE adds a read-only mean pre-pass (k_mean + k_segtree + k_mean_final).
+// One pass of a gate runs Alg. 2 of the paper (decompress, normalise,
+// gateComputation, compress at delta_0, delta_1, ... until the ratio reaches
+// theta) for every stride, as these kernels on the sim stream:
+//   k_pass<kFused>   per unit of two segments: decode + normalise + gate in
+//                    LDS; the size of each plane record at the ladder levels
+//                    the block can plausibly take (0 .. previous level + 1);
+//                    encode at the block's previous level (the speculation),
+//                    write the records, per-segment normsq
+//   k_decide<false>  per block: the first computed level whose ratio reaches
+//                    theta; a block whose choice differs from the speculation
+//                    joins the replay list, one whose computed levels all
+//                    miss theta joins the escalation list
+//   k_pass<kEsc>     escalated blocks only: sizes of the remaining levels
+//   k_decide<true>   escalated blocks: the choice among the remaining levels
+//   k_pass<kReplay>  replayed blocks only: encode again at the chosen level
+//   k_segtree        per block: pairwise normsq into the stream header
+//   k_reduce         N^2 over blocks, s = 1/sqrt(N^2), statistics
+// The level chosen is always exactly the one of Alg. 2 (the first level
+// whose full-block ratio reaches theta, else the last); speculation only
+// decides which records have to be written twice.  DIFFUSE adds a read-only
+// mean pre-pass (k_mean + k_segtree + k_mean_final).
 //
 // Work decomposition: a workgroup of four wave64s takes one unit of two
 // segments (2 x 2^s amplitudes); wave w decodes / encodes plane (w & 1) of
-// segment (w >> 1), one 64-scalar chunk per wave instruction.  The decoded
+// segment (w >> 1), one 64-scalar chunk per wave instruction, with DPP row
+// and wave operations for prefix sums, neighbours and widths.  The decoded
 // unit sits in LDS (32 KiB at s = 10) for the gate butterflies, so four
 // workgroups share a CU.  Units are segment pairs (g, g ^ (mask >> s)) when
 // a gate couples segments, so every pair update of Sec. II finds both
-// amplitudes in LDS.
+// amplitudes in LDS.  Plane records are bump-allocated per unit in the
+// output arena; a block's canonical stream is its header plus its records
+// in plane order.
 //
 // Arithmetic: every floating-point operation is one IEEE binary64 rounding
 // (contraction off), in the order the block-stream format and the gate
@@ -150,27 +162,36 @@ struct Unit {
     __device__ __forceinline__ uint64_t seg(int k) const { return k ? g[1] : g[0]; }
 };
 
-__device__ __forceinline__ Unit unit_of(uint64_t u, uint64_t nseg, uint64_t Ms)
+// The unit holding segment g: {g, g ^ Ms} for coupled segments, else the
+// aligned pair {g & ~1, g | 1}.
+__device__ __forceinline__ Unit unit_of_seg(uint64_t g, uint64_t nseg, uint64_t Ms)
 {
     Unit r;
     if (nseg == 1) {
-        r.g[0] = 0;
-        r.g[1] = 0;
+        r.g[0] = r.g[1] = 0;
         r.nsu = 1;
         return r;
     }
     r.nsu = 2;
-    if (Ms == 0) {
-        r.g[0] = 2 * u;
-        r.g[1] = 2 * u + 1;
-    } else {
-        int hb = 63 - __builtin_clzll(Ms);
-        uint64_t lo = u & ((1ull << hb) - 1);
-        uint64_t g0 = ((u >> hb) << (hb + 1)) | lo;
+    if (Ms) {
+        const uint64_t g0 = (g ^ Ms) < g ? (g ^ Ms) : g;
         r.g[0] = g0;
         r.g[1] = g0 ^ Ms;
+    } else {
+        r.g[0] = g & ~1ull;
+        r.g[1] = g | 1ull;
     }
     return r;
+}
+
+// The u-th unit of a pass.
+__device__ __forceinline__ Unit unit_of(uint64_t u, uint64_t nseg, uint64_t Ms)
+{
+    if (nseg == 1 || Ms == 0)
+        return unit_of_seg(2 * u, nseg, Ms);
+    const int hb = 63 - __builtin_clzll(Ms);
+    const uint64_t g0 = ((u >> hb) << (hb + 1)) | (u & ((1ull << hb) - 1));
+    return unit_of_seg(g0, nseg, Ms);
 }
 
 typedef double Planes[2][2][1 << kMaxS];
@@ -253,9 +274,8 @@ __device__ void load_unit(const PassArgs &a, const Unit &uc, Planes &X,
         return;
     }
     const uint64_t j = g >> (a.geo.b - s);
-    const uint8_t *blk = a.arena_in + a.din.blk_off[j];
-    const double delta = *(const double *)(blk + 16);
-    decode_plane(blk + a.din.plane_rel[2 * g + p], s, delta, scale, do_scale, dst);
+    const double delta = *(const double *)(a.din.hdr + 32 * j + 16);
+    decode_plane(a.arena_in + a.din.plane_off[2 * g + p], s, delta, scale, do_scale, dst);
 }
 
 __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
@@ -312,10 +332,8 @@ __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
     }
 }
 
-// Codes of one chunk at one level.  Lossy: q is the int32 code, `out` the
-// outlier flag, xh the value a decoder reconstructs.  Lossless: q is the bit
-// pattern.  `zz` receives the zigzagged Lorenzo difference against the
-// previous scalar (lane 0 takes `prev0`).
+// Lossy code of one scalar at one level: q the int32 code, `out` the outlier
+// flag, xh the value a decoder reconstructs (the scalar itself for outliers).
 __device__ __forceinline__ void lossy_code(double x, double delta, double e, double r,
                                            int32_t &q, bool &out, double &xh)
 {
@@ -344,14 +362,16 @@ __device__ __forceinline__ uint32_t bitlen32(uint32_t z)
     return z ? 32u - (uint32_t)__builtin_clz(z) : 0u;
 }
 
-// Sizes of one plane at every ladder level (one wavefront; levels outer so
-// that only one level's state is live).
-__device__ void size_plane(const double *x, int s, const Ladder &lad,
-                           uint32_t *psz, uint64_t plane, uint64_t nplanes)
+// Sizes of one plane at ladder levels k0 .. k1 (one wavefront; levels outer
+// so that only one level's state is live).  Returns the (payload words,
+// outliers) word of level `want` when it lies in the range.
+__device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k0, int k1,
+                                int want, uint32_t *psz, uint64_t plane, uint64_t nplanes)
 {
     const int lane = lane_id();
     const int C = 1 << (s - 6);
-    for (int k = 0; k < lad.L; ++k) {
+    uint32_t wanted = 0;
+    for (int k = k0; k <= k1; ++k) {
         const double delta = lad.delta[k];
         uint32_t pw = 0, no = 0;
         if (delta == 0.0) {
@@ -377,9 +397,13 @@ __device__ void size_plane(const double *x, int s, const Ladder &lad,
                 carry = __builtin_amdgcn_readlane(q, 63);
             }
         }
+        const uint32_t v = pw | (no << 16);
         if (lane == 0)
-            psz[(uint64_t)k * nplanes + plane] = pw | (no << 16);
+            psz[(uint64_t)k * nplanes + plane] = v;
+        if (k == want)
+            wanted = v;
     }
+    return wanted;
 }
 
 // Scatter one chunk's fields (z of width w, lane l at bits [l w, l w + w))
@@ -528,7 +552,18 @@ __device__ double segment_tree(const Unit &uc, int s, double *red, Leaf leaf)
 
 // --------------------------------------------------------- the pass -------
 
-template <bool ENC>
+enum : int { kFused = 0, kEsc = 1, kReplay = 2 };
+
+// Ladder level the block's previous stream used (0 for the basis source).
+__device__ __forceinline__ int hint_level(const PassArgs &a, uint64_t j)
+{
+    if (a.src_basis)
+        return 0;
+    const int h = a.din.blk_level[j];
+    return h < a.lad.L ? h : a.lad.L - 1;
+}
+
+template <int MODE>
 __global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
 {
     if (a.dev->err)
@@ -536,35 +571,100 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
     __shared__ Planes X;
     __shared__ uint64_t pack[4][64];
     __shared__ double red[8];
+    __shared__ uint64_t rbytes[4];
+    __shared__ uint64_t rbase;
     const int s = a.geo.s;
-    const int wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int us = wave >> 1, p = wave & 1;
+    const int L = a.lad.L;
     const double scale = a.dev->scale;
     const bool do_scale = !a.src_basis && scale != 1.0;
     const double *tdiff = a.dev->tdiff;
     const uint64_t Ms = a.gate.mask >> s;
     const uint64_t nplanes = 2 * a.geo.nseg;
-    for (uint64_t u = blockIdx.x; u < a.geo.nunits; u += gridDim.x) {
-        const Unit uc = unit_of(u, a.geo.nseg, Ms);
+    const int bs = a.geo.b - s;
+    const uint64_t spb = 1ull << bs;
+    const uint32_t padC = pad8(1u << (s - 6));
+    uint64_t nitems;
+    const uint32_t *list = nullptr;
+    if (MODE == kFused) {
+        nitems = a.geo.nunits;
+    } else {
+        const uint32_t cnt = MODE == kEsc ? a.dev->n_esc : a.dev->n_replay;
+        list = MODE == kEsc ? a.esc_list : a.replay_list;
+        nitems = (uint64_t)cnt << bs;
+    }
+    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        Unit uc;
+        uint64_t jsel = ~0ull;  // the block this item works for (kEsc, kReplay)
+        if (MODE == kFused) {
+            uc = unit_of(it, a.geo.nseg, Ms);
+        } else {
+            jsel = list[it >> bs];
+            const uint64_t g = (jsel << bs) | (it & (spb - 1));
+            uc = unit_of_seg(g, a.geo.nseg, Ms);
+            // one item per (unit, block): skip when the unit's other segment
+            // lies in the same block and comes first
+            const uint64_t other = uc.nsu == 2 ? (uc.g[0] == g ? uc.g[1] : uc.g[0]) : g;
+            if ((other >> bs) == jsel && other < g)
+                continue;
+        }
         load_unit(a, uc, X, scale, do_scale);
         __syncthreads();
         gate_unit(a.gate, uc, s, X, tdiff);
         __syncthreads();
-        const int us = wave >> 1, p = wave & 1;
-        if (us < uc.nsu) {
-            const uint64_t g = uc.seg(us);
-            const uint64_t plane = 2 * g + p;
-            if (!ENC) {
-                size_plane(&X[us][p][0], s, a.lad, a.psz, plane, nplanes);
+        const bool active = us < uc.nsu;
+        const uint64_t g = active ? uc.seg(us) : 0;
+        const uint64_t j = g >> bs;
+        const uint64_t plane = 2 * g + p;
+        const bool mine = active && (MODE == kFused || j == jsel);
+        int lev = 0;
+        uint32_t pszv = 0;
+        if (mine) {
+            const int h = hint_level(a, j);
+            const int cm = h + 1 < L ? h + 1 : L - 1;
+            if (MODE == kFused) {
+                lev = h;
+                pszv = size_levels(&X[us][p][0], s, a.lad, 0, cm, h, a.psz, plane, nplanes);
+            } else if (MODE == kEsc) {
+                size_levels(&X[us][p][0], s, a.lad, cm + 1, L - 1, -1, a.psz, plane, nplanes);
             } else {
-                const uint64_t j = g >> (a.geo.b - s);
-                const int k = a.dout.blk_level[j];
-                uint8_t *rec = a.arena_out + a.dout.blk_off[j] + a.dout.plane_rel[plane];
-                encode_plane(&X[us][p][0], s, a.lad.delta[k], a.lad.e[k], a.lad.r[k],
-                             a.psz[(uint64_t)k * nplanes + plane], rec, &pack[wave][0],
-                             &a.dev->err);
+                lev = a.dout.blk_level[j];
+                pszv = a.psz[(uint64_t)lev * nplanes + plane];
             }
         }
-        if (ENC) {
+        if (MODE != kEsc) {
+            // bump-allocate this unit's records in the output arena
+            if (lane == 0)
+                rbytes[wave] = mine ? rec_bytes(pszv, padC) : 0;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const uint64_t tot = rbytes[0] + rbytes[1] + rbytes[2] + rbytes[3];
+                uint64_t base = 0;
+                if (tot) {
+                    base = atomicAdd((unsigned long long *)&a.dev->arena_used[a.out_arena],
+                                     (unsigned long long)tot);
+                    if (base + tot > a.arena_cap) {
+                        if (atomicOr(&a.dev->err, kErrArena) == 0)
+                            a.dev->err_pass = (uint32_t)a.pass;
+                        base = ~0ull;
+                    } else {
+                        atomicMax((unsigned long long *)&a.dev->arena_peak,
+                                  (unsigned long long)(base + tot));
+                    }
+                }
+                rbase = base;
+            }
+            __syncthreads();
+            if (mine && rbase != ~0ull) {
+                uint64_t off = rbase;
+                for (int w2 = 0; w2 < wave; ++w2)
+                    off += rbytes[w2];
+                if (lane == 0)
+                    a.dout.plane_off[plane] = off;
+                encode_plane(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev], a.lad.r[lev],
+                             pszv, a.arena_out + off, &pack[wave][0], &a.dev->err);
+            }
             __syncthreads();
             const double ns = segment_tree(uc, s, red, [&](int su, int o) {
                 const double re = X[su][0][o], im = X[su][1][o];
@@ -572,8 +672,11 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
                 const double ii = im * im;
                 return rr + ii;
             });
-            if (threadIdx.x < (unsigned)uc.nsu)
-                a.segnorm[uc.seg((int)threadIdx.x)] = ns;
+            if (threadIdx.x < (unsigned)uc.nsu) {
+                const uint64_t gs = uc.seg((int)threadIdx.x);
+                if (MODE == kFused || (gs >> bs) == jsel)
+                    a.segnorm[gs] = ns;
+            }
         }
         __syncthreads();
     }
@@ -639,7 +742,8 @@ __device__ double wg_tree(Load load, uint64_t m, double *lds)
     return r;
 }
 
-// dst[j] = pairwise(src[j*per .. (j+1)*per)) for j < nout.
+// dst[j] = pairwise(src[j*per .. (j+1)*per)) for j < nout; with write_hdr,
+// also the normsq field of block j's output header.
 __global__ __launch_bounds__(kWG) void k_segtree(PassArgs a, const double *src,
                                                  double *dst, uint64_t per,
                                                  uint64_t nout, int write_hdr)
@@ -653,7 +757,7 @@ __global__ __launch_bounds__(kWG) void k_segtree(PassArgs a, const double *src,
         if (threadIdx.x == 0) {
             dst[j] = v;
             if (write_hdr)
-                *(double *)(a.arena_out + a.dout.blk_off[j] + 24) = v;
+                *(double *)(a.dout.hdr + 32 * j + 24) = v;
         }
     }
 }
@@ -671,7 +775,63 @@ __global__ __launch_bounds__(kWG) void k_mean_final(PassArgs a, double pow2)
     }
 }
 
-// Alg. 2 level choice per block + output placement + stream header.
+// ------------------------------------------------------ decisions --------
+
+// Per-level block totals over levels k0..k1 into tot[]/nout[] (workgroup).
+__device__ void block_totals(const PassArgs &a, uint64_t j, int k0, int k1, uint64_t *red,
+                             uint64_t *tot, uint64_t *nout)
+{
+    const int t = threadIdx.x;
+    const uint64_t npb = 2ull << (a.geo.b - a.geo.s);
+    const uint64_t nplanes = 2 * a.geo.nseg;
+    const uint32_t padC = pad8(1u << (a.geo.s - 6));
+    const uint64_t base = j * npb;
+    for (int k = k0; k <= k1; ++k) {
+        uint64_t by = 0, no = 0;
+        for (uint64_t q = t; q < npb; q += kWG) {
+            const uint32_t v = a.psz[(uint64_t)k * nplanes + base + q];
+            by += rec_bytes(v, padC);
+            no += v >> 16;
+        }
+        for (int part = 0; part < 2; ++part) {
+            red[t] = part ? no : by;
+            __syncthreads();
+            for (int st = kWG / 2; st > 0; st >>= 1) {
+                if (t < st)
+                    red[t] += red[t + st];
+                __syncthreads();
+            }
+            if (t == 0) {
+                if (part)
+                    nout[k] = red[0];
+                else
+                    tot[k] = red[0] + kHdrBytes;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Header, length and level of block j's output stream.
+__device__ void finalize_block(const PassArgs &a, uint64_t j, int d, uint64_t len,
+                               uint64_t nout)
+{
+    uint64_t *h = (uint64_t *)(a.dout.hdr + 32 * j);
+    h[0] = (uint64_t)kMagic | ((uint64_t)d << 32) | ((uint64_t)a.geo.s << 48) |
+           ((uint64_t)a.geo.b << 56);
+    h[1] = (uint64_t)(uint32_t)nout | (len << 32);
+    h[2] = (uint64_t)__double_as_longlong(a.lad.delta[d]);
+    h[3] = 0;
+    a.dout.blk_len[j] = (uint32_t)len;
+    a.dout.blk_level[j] = (uint8_t)d;
+    if (!a.src_basis)
+        atomicAdd((unsigned long long *)&a.dev->level_hist[d], 1ull);
+}
+
+// Alg. 2's choice for each block.  ESC = false: over the levels computed by
+// the fused pass (0 .. previous level + 1).  ESC = true: over the remaining
+// levels of escalated blocks.
+template <bool ESC>
 __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
 {
     if (a.dev->err)
@@ -679,92 +839,36 @@ __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
     __shared__ uint64_t red[kWG];
     __shared__ uint64_t tot[kMaxL];
     __shared__ uint64_t nout[kMaxL];
-    __shared__ int kstar;
-    const int t = threadIdx.x;
-    const int s = a.geo.s, b = a.geo.b;
-    const uint32_t padC = pad8(1u << (s - 6));
-    const uint64_t npb = 2ull << (b - s);
-    const uint64_t nplanes = 2 * a.geo.nseg;
     const int L = a.lad.L;
-    const double raw = (double)(16ull << b);
-    for (uint64_t j = blockIdx.x; j < a.geo.nblocks; j += gridDim.x) {
-        const uint64_t base = j * npb;
-        for (int k = 0; k < L; ++k) {
-            uint64_t by = 0, no = 0;
-            for (uint64_t p = t; p < npb; p += kWG) {
-                const uint32_t v = a.psz[(uint64_t)k * nplanes + base + p];
-                by += rec_bytes(v, padC);
-                no += v >> 16;
-            }
-            for (int part = 0; part < 2; ++part) {
-                red[t] = part ? no : by;
-                __syncthreads();
-                for (int st = kWG / 2; st > 0; st >>= 1) {
-                    if (t < st)
-                        red[t] += red[t + st];
-                    __syncthreads();
-                }
-                if (t == 0) {
-                    if (part)
-                        nout[k] = red[0];
-                    else
-                        tot[k] = red[0] + kHdrBytes;
-                }
-                __syncthreads();
-            }
-        }
-        if (t == 0) {
-            int ks = L - 1;
-            for (int k = 0; k < L; ++k)
+    const double raw = (double)(16ull << a.geo.b);
+    const uint64_t count = ESC ? a.dev->n_esc : a.geo.nblocks;
+    for (uint64_t r = blockIdx.x; r < count; r += gridDim.x) {
+        const uint64_t j = ESC ? a.esc_list[r] : r;
+        const int h = hint_level(a, j);
+        const int cm = h + 1 < L ? h + 1 : L - 1;
+        const int k0 = ESC ? cm + 1 : 0;
+        const int k1 = ESC ? L - 1 : cm;
+        block_totals(a, j, k0, k1, red, tot, nout);
+        if (threadIdx.x == 0) {
+            int d = -1;
+            for (int k = k0; k <= k1; ++k)
                 if (raw >= a.lad.theta * (double)tot[k]) {
-                    ks = k;
+                    d = k;
                     break;
                 }
-            kstar = ks;
-        }
-        __syncthreads();
-        const int ks = kstar;
-        // plane record offsets at the chosen level, canonical order
-        const uint64_t per = (npb + kWG - 1) / kWG;
-        const uint64_t p0 = (uint64_t)t * per;
-        uint64_t local = 0;
-        for (uint64_t p = p0; p < p0 + per && p < npb; ++p)
-            local += rec_bytes(a.psz[(uint64_t)ks * nplanes + base + p], padC);
-        red[t] = local;
-        __syncthreads();
-        // exclusive scan of thread totals (Hillis-Steele on a copy)
-        for (int st = 1; st < kWG; st <<= 1) {
-            const uint64_t add = (t >= st) ? red[t - st] : 0;
-            __syncthreads();
-            red[t] += add;
-            __syncthreads();
-        }
-        uint64_t run = kHdrBytes + red[t] - local;
-        for (uint64_t p = p0; p < p0 + per && p < npb; ++p) {
-            a.dout.plane_rel[base + p] = (uint32_t)run;
-            run += rec_bytes(a.psz[(uint64_t)ks * nplanes + base + p], padC);
-        }
-        if (t == 0) {
-            const uint64_t len = tot[ks];
-            const uint64_t off = atomicAdd(
-                (unsigned long long *)&a.dev->arena_used[a.out_arena],
-                (unsigned long long)len);
-            if (off + len > a.arena_cap) {
-                if (atomicOr(&a.dev->err, kErrArena) == 0)
-                    a.dev->err_pass = (uint32_t)a.pass;
-                a.dout.blk_len[j] = 0;
+            if (d < 0 && k1 == L - 1)
+                d = L - 1;
+            if (d < 0) {
+                const uint32_t slot = atomicAdd(&a.dev->n_esc, 1u);
+                a.esc_list[slot] = (uint32_t)j;
+                atomicAdd((unsigned long long *)&a.dev->escalations, 1ull);
             } else {
-                a.dout.blk_off[j] = off;
-                a.dout.blk_len[j] = (uint32_t)len;
-                a.dout.blk_level[j] = (uint8_t)ks;
-                uint64_t *h = (uint64_t *)(a.arena_out + off);
-                h[0] = (uint64_t)kMagic | ((uint64_t)ks << 32) | ((uint64_t)s << 48) |
-                       ((uint64_t)b << 56);
-                h[1] = (uint64_t)(uint32_t)nout[ks] | (len << 32);
-                h[2] = (uint64_t)__double_as_longlong(a.lad.delta[ks]);
-                h[3] = 0;
-                if (!a.src_basis)
-                    atomicAdd((unsigned long long *)&a.dev->level_hist[ks], 1ull);
+                finalize_block(a, j, d, tot[d], nout[d]);
+                if (d != h) {
+                    const uint32_t slot = atomicAdd(&a.dev->n_replay, 1u);
+                    a.replay_list[slot] = (uint32_t)j;
+                    atomicAdd((unsigned long long *)&a.dev->replays, 1ull);
+                }
             }
         }
         __syncthreads();
@@ -814,6 +918,8 @@ __global__ __launch_bounds__(kWG) void k_reduce(PassArgs a)
                 d->min_ratio = ratio;
         }
         d->arena_used[a.in_arena] = 0;
+        d->n_replay = 0;
+        d->n_esc = 0;
     }
 }
 
@@ -900,9 +1006,8 @@ __device__ void load_range(const PassArgs &a, const double *amp, uint64_t first,
     for (int off = 0; off < cnt; off += (1 << s)) {
         const uint64_t g = (first + off) >> s;
         const uint64_t j = g >> (a.geo.b - s);
-        const uint8_t *blk = a.arena_in + a.din.blk_off[j];
-        const double delta = *(const double *)(blk + 16);
-        decode_plane(blk + a.din.plane_rel[2 * g + p], s, delta, scale, do_scale,
+        const double delta = *(const double *)(a.din.hdr + 32 * j + 16);
+        decode_plane(a.arena_in + a.din.plane_off[2 * g + p], s, delta, scale, do_scale,
                      dst + off);
     }
 }
@@ -977,12 +1082,64 @@ __global__ void k_rsqrt(const double *in, double *out, uint64_t count)
         out[i] = inv_sqrt_exact(in[i]);
 }
 
+// Canonical stream of block j (header + plane records in plane order) into
+// `out` (one workgroup).
+__global__ __launch_bounds__(kWG) void k_export(PassArgs a, uint64_t j, uint8_t *out)
+{
+    __shared__ uint64_t offs[2 << 10];  // planes per block: at most 2^(1 + 20 - 10)
+    __shared__ uint64_t red[kWG];
+    const int t = threadIdx.x;
+    const int s = a.geo.s;
+    const uint64_t npb = 2ull << (a.geo.b - s);
+    const uint32_t padC = pad8(1u << (s - 6));
+    const uint64_t base = j * npb;
+    const uint64_t per = (npb + kWG - 1) / kWG;
+    // sizes of this thread's planes, from their record headers
+    uint64_t local = 0;
+    for (uint64_t q = t * per; q < (t + 1) * per && q < npb; ++q) {
+        const uint8_t *rec = a.arena_in + a.din.plane_off[base + q];
+        const uint32_t pw = *(const uint32_t *)(rec + 8);
+        const uint32_t no = *(const uint32_t *)(rec + 12);
+        const uint64_t sz = kPlaneHdrBytes + (pw ? padC : 0u) + 8ull * pw +
+                            (uint64_t)kOutlierBytes * no;
+        offs[q] = sz;
+        local += sz;
+    }
+    red[t] = local;
+    __syncthreads();
+    for (int st = 1; st < kWG; st <<= 1) {
+        const uint64_t add = t >= st ? red[t - st] : 0;
+        __syncthreads();
+        red[t] += add;
+        __syncthreads();
+    }
+    uint64_t run = kHdrBytes + red[t] - local;
+    for (uint64_t q = t * per; q < (t + 1) * per && q < npb; ++q) {
+        const uint64_t sz = offs[q];
+        offs[q] = run;
+        run += sz;
+    }
+    if (t < 4)
+        ((uint64_t *)out)[t] = ((const uint64_t *)(a.din.hdr + 32 * j))[t];
+    __syncthreads();
+    // copy records: wave w takes planes w, w+4, ...
+    const int wave = t >> 6, lane = lane_id();
+    for (uint64_t q = wave; q < npb; q += 4) {
+        const uint64_t *src = (const uint64_t *)(a.arena_in + a.din.plane_off[base + q]);
+        const uint64_t end = (q + 1 < npb) ? offs[q + 1] : (uint64_t)a.din.blk_len[j];
+        const uint64_t nw = (end - offs[q]) / 8;
+        uint64_t *dst = (uint64_t *)(out + offs[q]);
+        for (uint64_t k = lane; k < nw; k += 64)
+            dst[k] = src[k];
+    }
+}
+
 // ------------------------------------------------------- launchers --------
 
 const char *const kKernelNames[kNumKernelIds] = {
-    "pass_size", "pass_encode", "decide", "block_norm", "reduce", "mean",
-    "mean_tree", "mean_final", "init_state", "sv_pair", "sv_diag", "sv_partial",
-    "sv_final"};
+    "pass", "decide", "esc_size", "esc_decide", "replay", "block_norm", "reduce",
+    "mean", "mean_tree", "mean_final", "init_state", "sv_pair", "sv_diag",
+    "sv_partial", "sv_final"};
 
 static unsigned grid_for(uint64_t items)
 {
@@ -1037,12 +1194,21 @@ void launch_mean(const PassArgs &a, hipStream_t st, Prof *prof)
 void launch_pass(const PassArgs &a, hipStream_t st, Prof *prof)
 {
     const unsigned gu = grid_for(a.geo.nunits), gb = grid_for(a.geo.nblocks);
+    const unsigned gside = grid_for(a.geo.nunits < 2048 ? a.geo.nunits : 2048);
+    const unsigned gdec = grid_for(a.geo.nblocks < 1024 ? a.geo.nblocks : 1024);
     const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
-    TIMED(prof, kIdPassSize, st,
-          hipLaunchKernelGGL(k_pass<false>, dim3(gu), dim3(kWG), 0, st, a));
-    TIMED(prof, kIdDecide, st, hipLaunchKernelGGL(k_decide, dim3(gb), dim3(kWG), 0, st, a));
-    TIMED(prof, kIdPassEncode, st,
-          hipLaunchKernelGGL(k_pass<true>, dim3(gu), dim3(kWG), 0, st, a));
+    TIMED(prof, kIdPass, st,
+          hipLaunchKernelGGL(k_pass<kFused>, dim3(gu), dim3(kWG), 0, st, a));
+    TIMED(prof, kIdDecide, st,
+          hipLaunchKernelGGL(k_decide<false>, dim3(gb), dim3(kWG), 0, st, a));
+    if (a.lad.L > 1) {
+        TIMED(prof, kIdEscSize, st,
+              hipLaunchKernelGGL(k_pass<kEsc>, dim3(gside), dim3(kWG), 0, st, a));
+        TIMED(prof, kIdEscDecide, st,
+              hipLaunchKernelGGL(k_decide<true>, dim3(gdec), dim3(kWG), 0, st, a));
+        TIMED(prof, kIdReplay, st,
+              hipLaunchKernelGGL(k_pass<kReplay>, dim3(gside), dim3(kWG), 0, st, a));
+    }
     TIMED(prof, kIdBlockNorm, st,
           hipLaunchKernelGGL(k_segtree, dim3(gb), dim3(kWG), 0, st, a,
                              (const double *)a.segnorm, a.blknorm, spb, a.geo.nblocks, 1));
@@ -1082,8 +1248,6 @@ void launch_inner(const PassArgs &a, const PassArgs &b, const double *amp_a,
 {
     const int n = a.geo.n;
     int S = kMaxS;
-    if (!amp_a && a.geo.s > S)
-        S = a.geo.s;
     if (S > n)
         S = n;
     const uint64_t nr = 1ull << (n - S);
@@ -1097,6 +1261,11 @@ void launch_rsqrt(const double *in, double *out, uint64_t count, hipStream_t st)
 {
     hipLaunchKernelGGL(k_rsqrt, dim3(grid_for((count + kWG - 1) / kWG)), dim3(kWG), 0, st,
                        in, out, count);
+}
+
+void launch_export(const PassArgs &a, uint64_t j, uint8_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_export, dim3(1), dim3(kWG), 0, st, a, j, out);
 }
 
 }  // namespace aalc

@@ -113,6 +113,7 @@ struct sim {
     Desc desc[2]{};
     uint32_t *psz = nullptr;
     int psz_levels = 0;
+    uint32_t *replay_list = nullptr, *esc_list = nullptr;
     double *segnorm = nullptr, *blknorm = nullptr, *segsum = nullptr, *blksum = nullptr;
     DevState *dev = nullptr;
     int cur = 0;
@@ -280,6 +281,8 @@ PassArgs make_args(const sim *S, int in, int out, const GateArg &g)
     a.in_arena = in;
     a.pass = S->passes;
     a.psz = S->psz;
+    a.replay_list = S->replay_list;
+    a.esc_list = S->esc_list;
     a.segnorm = S->segnorm;
     a.blknorm = S->blknorm;
     a.segsum = S->segsum;
@@ -362,8 +365,8 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
         fail(SIM_EINVAL, "n_qubits %d out of range", n);
         return nullptr;
     }
-    if (block_log2 < 6) {
-        fail(SIM_EINVAL, "block_log2 %d < 6", block_log2);
+    if (block_log2 < 6 || block_log2 > 20) {
+        fail(SIM_EINVAL, "block_log2 %d outside [6, 20]", block_log2);
         return nullptr;
     }
     sim *S = new (std::nothrow) sim();
@@ -415,7 +418,8 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
         }
         uint64_t cap = arena_bytes;
         if (cap == 0) {
-            const double want = 1.05 * 16.0 * std::ldexp(1.0, n) + (double)kMiB;
+            // a pass may write a block twice (speculated level, then the chosen one)
+            const double want = 2.1 * 16.0 * std::ldexp(1.0, n) + (double)kMiB;
             cap = want > (double)(8 * kGiB) ? 8 * kGiB : (uint64_t)want;
         }
         cap = (cap + 255) & ~255ull;
@@ -424,14 +428,18 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
         for (int k = 0; k < 2 && !rc; ++k) {
             rc = dmalloc(S, (void **)&S->arena[k], cap + 64);
             if (!rc)
-                rc = dmalloc(S, (void **)&S->desc[k].blk_off, 8 * nb);
+                rc = dmalloc(S, (void **)&S->desc[k].hdr, 32 * nb);
             if (!rc)
                 rc = dmalloc(S, (void **)&S->desc[k].blk_len, 4 * nb);
             if (!rc)
                 rc = dmalloc(S, (void **)&S->desc[k].blk_level, nb);
             if (!rc)
-                rc = dmalloc(S, (void **)&S->desc[k].plane_rel, 4 * 2 * ns);
+                rc = dmalloc(S, (void **)&S->desc[k].plane_off, 8 * 2 * ns);
         }
+        if (!rc)
+            rc = dmalloc(S, (void **)&S->replay_list, 4 * nb);
+        if (!rc)
+            rc = dmalloc(S, (void **)&S->esc_list, 4 * nb);
         if (!rc)
             rc = ensure_psz(S, S->lad.L);
         if (!rc)
@@ -624,14 +632,22 @@ int sim_export_block(sim_t *S, uint64_t j, void *buf, size_t cap, size_t *len)
     int rc = sync_check(S);
     if (rc && rc != SIM_ECOLLAPSED)
         return rc;
-    uint64_t off = 0;
     uint32_t l = 0;
-    HIPCHK(hipMemcpy(&off, S->desc[S->cur].blk_off + j, 8, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&l, S->desc[S->cur].blk_len + j, 4, hipMemcpyDeviceToHost));
     *len = l;
     if (cap < l || !buf)
         return fail(SIM_ENOMEM, "buffer of %zu bytes too small for %u", cap, l);
-    HIPCHK(hipMemcpy(buf, S->arena[S->cur] + off, l, hipMemcpyDeviceToHost));
+    uint8_t *stage = nullptr;
+    HIPCHK(hipMalloc((void **)&stage, l));
+    launch_export(make_args(S, S->cur, 1 - S->cur, GateArg{}), j, stage, S->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(buf, stage, l, hipMemcpyDeviceToHost, S->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(S->stream);
+    (void)hipFree(stage);
+    if (e != hipSuccess)
+        return fail(SIM_EDEVICE, "export: %s", hipGetErrorString(e));
     return rc;
 }
 
@@ -672,6 +688,9 @@ int sim_stats(sim_t *S, sim_stats_t *st)
     for (int k = 0; k < kMaxL; ++k)
         st->level_hist[k] = d.level_hist[k];
     st->arena_bytes = S->arena_cap;
+    st->replays = d.replays;
+    st->escalations = d.escalations;
+    st->arena_peak = d.arena_peak;
     return rc;
 }
 

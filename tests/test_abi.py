@@ -40,4 +40,4 @@ def test_binding_struct_layouts():
     assert ctypes.sizeof(aalcsim.Gate) == 88
     assert aalcsim.Gate.index.offset == 16 and aalcsim.Gate.u.offset == 24
     # sim_stats_t ends with arena_bytes, device_bytes
-    assert ctypes.sizeof(aalcsim.Stats) == 8 * 8 + 64 + 16
+    assert ctypes.sizeof(aalcsim.Stats) == 8 * 8 + 64 + 16 + 24
