@@ -115,6 +115,31 @@ __device__ __forceinline__ uint32_t wave_max32(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Maximum over each row of 16 lanes, held by every lane of the row.
+__device__ __forceinline__ uint32_t row_max32(uint32_t v)
+{
+    uint32_t t;
+    t = dpp32<kQuadXor1>(0u, v);
+    v = v > t ? v : t;
+    t = dpp32<kQuadXor2>(0u, v);
+    v = v > t ? v : t;
+    t = dpp32<kRowRor4>(0u, v);
+    v = v > t ? v : t;
+    t = dpp32<kRowRor8>(0u, v);
+    v = v > t ? v : t;
+    return v;
+}
+
+// Inclusive prefix sums within each row of 16 lanes.
+__device__ __forceinline__ uint32_t row_scan32(uint32_t v)
+{
+    v += dpp32<kRowShr1>(0u, v);
+    v += dpp32<kRowShr2>(0u, v);
+    v += dpp32<kRowShr4>(0u, v);
+    v += dpp32<kRowShr8>(0u, v);
+    return v;
+}
+
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
 {
     uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -196,57 +221,116 @@ __device__ __forceinline__ Unit unit_of(uint64_t u, uint64_t nseg, uint64_t Ms)
 
 typedef double Planes[2][2][1 << kMaxS];
 
-// Decode one plane record into dst[0 .. 2^s) (one wavefront, one chunk of
-// 64 scalars per step), scaling each value by `scale` when do_scale
-// (normalisation before the gate).  Lossy planes run the prefix sum in 32
-// bits: within a chunk the partial sums are differences of two codes of
-// magnitude below 2^30, so they are exact.
+// ---- codec layout: a wavefront works on four chunks at a time, row r
+// (lanes 16r .. 16r+15) on chunk 4t + r in step t, lane p of the row on the
+// four consecutive scalars 4p .. 4p+3 of that chunk.  Chunk widths are row
+// maxima, prefix sums run in-lane then over rows, and the neighbour of a
+// lane's first scalar is the previous lane's last one (wave shift by one).
+
+// Field of width w (<= 32) at bit b of a little-endian dword stream.
+__device__ __forceinline__ uint32_t field32(const uint32_t *P, uint32_t b, uint32_t w)
+{
+    const uint32_t k = b >> 5, sh = b & 31u;
+    const uint32_t v = __builtin_amdgcn_alignbit(P[k + 1], P[k], sh);
+    return w >= 32u ? v : (v & ((1u << w) - 1u));
+}
+
+// Field of width w (<= 64) at bit b.
+__device__ __forceinline__ uint64_t field64(const uint32_t *P, uint32_t b, uint32_t w)
+{
+    const uint32_t k = b >> 5, sh = b & 31u;
+    const uint32_t d0 = P[k], d1 = P[k + 1], d2 = P[k + 2];
+    uint32_t lo = __builtin_amdgcn_alignbit(d1, d0, sh);
+    uint32_t hi = __builtin_amdgcn_alignbit(d2, d1, sh);
+    if (w < 32u) {
+        lo &= (1u << w) - 1u;
+        hi = 0u;
+    } else if (w == 32u) {
+        hi = 0u;
+    } else if (w < 64u) {
+        hi &= (1u << (w - 32u)) - 1u;
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Chunk widths (lanes 0..C-1) and their exclusive prefix (payload word
+// offsets) from a plane record's width bytes.
+__device__ __forceinline__ void chunk_table(const uint8_t *widths, bool has, int C,
+                                            uint32_t &wl, uint32_t &ol)
+{
+    const int lane = lane_id();
+    wl = (has && lane < C) ? (uint32_t)widths[lane] : 0u;
+    ol = row_scan32(wl) - wl;  // lanes 0..15 of row 0 hold chunks 0..15
+}
+
+// Decode one plane record into dst[0 .. 2^s) (one wavefront), scaling each
+// value by `scale` when do_scale (normalisation before the gate).  Lossy
+// planes run the prefix sums in 32 bits: a partial sum is the difference of
+// two codes of magnitude below 2^30, so it is exact.
 __device__ void decode_plane(const uint8_t *rec, int s, double delta,
                              double scale, bool do_scale, double *dst)
 {
     const int lane = lane_id();
+    const int r = lane >> 4, p = lane & 15;
     const int C = 1 << (s - 6);
+    const int steps = (C + 3) >> 2;
     const uint64_t anchor = *(const uint64_t *)rec;
     const uint32_t pw = *(const uint32_t *)(rec + 8);
     const uint32_t nout = *(const uint32_t *)(rec + 12);
     const uint8_t *widths = rec + kPlaneHdrBytes;
-    const uint64_t *payload =
-        (const uint64_t *)(rec + kPlaneHdrBytes + (pw ? pad8((uint32_t)C) : 0u));
+    const uint32_t *payload =
+        (const uint32_t *)(rec + kPlaneHdrBytes + (pw ? pad8((uint32_t)C) : 0u));
+    uint32_t wl, ol;
+    chunk_table(widths, pw != 0, C, wl, ol);
     const double e = 2.0 * delta;
     uint64_t carry = anchor;
-    uint32_t woff = 0;
-    for (int c = 0; c < C; ++c) {
-        const uint32_t w = pw ? (uint32_t)widths[c] : 0u;
-        uint64_t z = 0;
-        if (w) {
-            const uint32_t bp = (uint32_t)lane * w;
-            const uint32_t wi = bp >> 6, sh = bp & 63u;
-            uint64_t v = payload[woff + wi] >> sh;
-            if (sh + w > 64u)
-                v |= payload[woff + wi + 1] << (64u - sh);
-            if (w < 64u)
-                v &= (1ull << w) - 1ull;
-            z = v;
-        }
-        double x;
+    for (int t = 0; t < steps; ++t) {
+        const int c = 4 * t + r;
+        const bool active = c < C;
+        const int cs = active ? c : 0;
+        const uint32_t w = active ? (uint32_t)__shfl((int)wl, cs, 64) : 0u;
+        const uint32_t woff = (uint32_t)__shfl((int)ol, cs, 64);
+        const uint32_t *P = payload + 2 * woff;
+        const uint32_t b0 = (uint32_t)(4 * p) * w;
+        double x[4];
         if (delta == 0.0) {
-            const uint64_t q = carry + wave_scan64(unzigzag64(z));
-            carry = readlane64(q, 63);
-            x = __longlong_as_double((long long)q);
+            uint64_t d[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                d[i] = w ? unzigzag64(field64(P, b0 + (uint32_t)i * w, w)) : 0ull;
+            const uint64_t s1 = d[0] + d[1], s2 = s1 + d[2], s3 = s2 + d[3];
+            const uint64_t incl = wave_scan64(s3);
+            const uint64_t base = carry + (incl - s3);
+            const uint64_t q0 = base + d[0], q1 = base + s1, q2 = base + s2, q3 = base + s3;
+            carry = carry + readlane64(incl, 63);
+            x[0] = __longlong_as_double((long long)q0);
+            x[1] = __longlong_as_double((long long)q1);
+            x[2] = __longlong_as_double((long long)q2);
+            x[3] = __longlong_as_double((long long)q3);
         } else {
-            const uint32_t z32 = (uint32_t)z;
-            const uint32_t d = (z32 >> 1) ^ (0u - (z32 & 1u));
-            const int32_t part = (int32_t)wave_scan32(d);
-            const int64_t q = (int64_t)carry + (int64_t)part;
-            carry = (uint64_t)(int64_t)__builtin_amdgcn_readlane((int)(int32_t)q, 63);
-            x = (double)q * e;
+            uint32_t d[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t z = w ? field32(P, b0 + (uint32_t)i * w, w) : 0u;
+                d[i] = (z >> 1) ^ (0u - (z & 1u));
+            }
+            const uint32_t s1 = d[0] + d[1], s2 = s1 + d[2], s3 = s2 + d[3];
+            const uint32_t incl = wave_scan32(s3);
+            const uint32_t ex = incl - s3;
+            const int32_t c32 = (int32_t)(uint32_t)carry;
+            x[0] = (double)(c32 + (int32_t)(ex + d[0])) * e;
+            x[1] = (double)(c32 + (int32_t)(ex + s1)) * e;
+            x[2] = (double)(c32 + (int32_t)(ex + s2)) * e;
+            x[3] = (double)(c32 + (int32_t)(ex + s3)) * e;
+            carry = (uint64_t)(int64_t)(c32 + (int32_t)__builtin_amdgcn_readlane((int)incl, 63));
         }
-        if (do_scale)
-            x = x * scale;
-        dst[c * kChunk + lane] = x;
-        woff += w;
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                dst[c * kChunk + 4 * p + i] = do_scale ? x[i] * scale : x[i];
+        }
     }
-    const uint8_t *outl = (const uint8_t *)(payload + pw);
+    const uint8_t *outl = (const uint8_t *)(payload + 2 * pw);
     for (uint32_t k = (uint32_t)lane; k < nout; k += 64u) {
         const uint32_t idx = *(const uint32_t *)(outl + (uint64_t)kOutlierBytes * k);
         double v = *(const double *)(outl + (uint64_t)kOutlierBytes * k + 8);
@@ -362,41 +446,94 @@ __device__ __forceinline__ uint32_t bitlen32(uint32_t z)
     return z ? 32u - (uint32_t)__builtin_clz(z) : 0u;
 }
 
-// Sizes of one plane at ladder levels k0 .. k1 (one wavefront; levels outer
-// so that only one level's state is live).  Returns the (payload words,
-// outliers) word of level `want` when it lies in the range.
-__device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k0, int k1,
-                                int want, uint32_t *psz, uint64_t plane, uint64_t nplanes)
+// Step t's chunk widths (row r holds chunk 4t + r) into lanes 4t .. 4t+3.
+__device__ __forceinline__ void gather_widths(uint32_t w, int t, uint32_t &wl)
 {
     const int lane = lane_id();
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)w, 0);
+    const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)w, 16);
+    const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)w, 32);
+    const uint32_t w3 = (uint32_t)__builtin_amdgcn_readlane((int)w, 48);
+    const int d = lane - 4 * t;
+    if (d == 0)
+        wl = w0;
+    else if (d == 1)
+        wl = w1;
+    else if (d == 2)
+        wl = w2;
+    else if (d == 3)
+        wl = w3;
+}
+
+// Sizes of one plane at ladder levels k0 .. k1 (one wavefront; levels outer
+// so that only one level's state is live).  Returns the (payload words,
+// outliers) word of level `want` when it lies in the range; lane c (< 16)
+// of `wl` then holds that level's width of chunk c.
+__device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k0, int k1,
+                                int want, uint32_t *psz, uint64_t plane, uint64_t nplanes,
+                                uint32_t &wl)
+{
+    const int lane = lane_id();
+    const int r = lane >> 4, p = lane & 15;
     const int C = 1 << (s - 6);
+    const int steps = (C + 3) >> 2;
     uint32_t wanted = 0;
+    wl = 0;
     for (int k = k0; k <= k1; ++k) {
         const double delta = lad.delta[k];
-        uint32_t pw = 0, no = 0;
+        uint32_t pw_acc = 0, no_acc = 0;
         if (delta == 0.0) {
             uint64_t carry = 0;
-            for (int c = 0; c < C; ++c) {
-                const uint64_t q = (uint64_t)__double_as_longlong(x[c * kChunk + lane]);
-                const uint64_t prev = dpp64<kWaveShr1>(c == 0 ? q : carry, q);
-                pw += wave_max32(bitlen64(zigzag64(q - prev)));
-                carry = readlane64(q, 63);
+            for (int t = 0; t < steps; ++t) {
+                const int c = 4 * t + r;
+                const bool active = c < C;
+                const double *xs = x + (active ? c : 0) * kChunk + 4 * p;
+                const uint64_t q0 = (uint64_t)__double_as_longlong(xs[0]);
+                const uint64_t q1 = (uint64_t)__double_as_longlong(xs[1]);
+                const uint64_t q2 = (uint64_t)__double_as_longlong(xs[2]);
+                const uint64_t q3 = (uint64_t)__double_as_longlong(xs[3]);
+                const uint64_t prev = dpp64<kWaveShr1>(t == 0 ? q0 : carry, q3);
+                const uint64_t o = zigzag64(q0 - prev) | zigzag64(q1 - q0) |
+                                   zigzag64(q2 - q1) | zigzag64(q3 - q2);
+                const uint32_t w = row_max32(active ? bitlen64(o) : 0u);
+                pw_acc += w;
+                if (k == want)
+                    gather_widths(w, t, wl);
+                carry = readlane64(q3, 63);
             }
         } else {
-            const double e = lad.e[k], r = lad.r[k];
+            const double e = lad.e[k], rr = lad.r[k];
             int32_t carry = 0;
-            for (int c = 0; c < C; ++c) {
-                int32_t q;
-                bool out;
-                double xh;
-                lossy_code(x[c * kChunk + lane], delta, e, r, q, out, xh);
+            for (int t = 0; t < steps; ++t) {
+                const int c = 4 * t + r;
+                const bool active = c < C;
+                const double *xs = x + (active ? c : 0) * kChunk + 4 * p;
+                int32_t q[4];
+                bool out[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    double xh;
+                    lossy_code(xs[i], delta, e, rr, q[i], out[i], xh);
+                }
                 const int32_t prev = (int32_t)dpp32<kWaveShr1>(
-                    (uint32_t)(c == 0 ? q : carry), (uint32_t)q);
-                pw += wave_max32(bitlen32(zigzag32(q - prev)));
-                no += (uint32_t)__popcll(__ballot(out));
-                carry = __builtin_amdgcn_readlane(q, 63);
+                    (uint32_t)(t == 0 ? q[0] : carry), (uint32_t)q[3]);
+                const uint32_t o = zigzag32(q[0] - prev) | zigzag32(q[1] - q[0]) |
+                                   zigzag32(q[2] - q[1]) | zigzag32(q[3] - q[2]);
+                const uint32_t w = row_max32(active ? bitlen32(o) : 0u);
+                pw_acc += w;
+                if (active)
+                    no_acc += (uint32_t)out[0] + (uint32_t)out[1] + (uint32_t)out[2] +
+                              (uint32_t)out[3];
+                if (k == want)
+                    gather_widths(w, t, wl);
+                carry = __builtin_amdgcn_readlane(q[3], 63);
             }
         }
+        const uint32_t pw = (uint32_t)__builtin_amdgcn_readlane((int)pw_acc, 0) +
+                            (uint32_t)__builtin_amdgcn_readlane((int)pw_acc, 16) +
+                            (uint32_t)__builtin_amdgcn_readlane((int)pw_acc, 32) +
+                            (uint32_t)__builtin_amdgcn_readlane((int)pw_acc, 48);
+        const uint32_t no = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan32(no_acc), 63);
         const uint32_t v = pw | (no << 16);
         if (lane == 0)
             psz[(uint64_t)k * nplanes + plane] = v;
@@ -406,107 +543,163 @@ __device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k
     return wanted;
 }
 
-// Scatter one chunk's fields (z of width w, lane l at bits [l w, l w + w))
-// into w payload words through the wave's LDS word buffer.
-__device__ __forceinline__ void pack_chunk(uint64_t z, uint32_t w, uint64_t *pb,
-                                           uint64_t *dst)
+// Dwords of one row of the packing buffer: a chunk of width w < 64 fills
+// bits below 64 w, so dwords 0 .. 2 w - 1 <= 125.
+constexpr int kPackRow = 126;
+
+// OR `v` into the dword stream of LDS buffer pb at bit b (v < 2^32 >> 0;
+// the bits above 32 - (b & 31) spill into the next dword).
+__device__ __forceinline__ void or_bits32(uint32_t *pb, uint32_t b, uint32_t v)
 {
-    const int lane = lane_id();
-    if (w == 64u) {
-        dst[lane] = z;
+    if (!v)
         return;
-    }
-    if ((uint32_t)lane < w)
-        pb[lane] = 0;
-    __builtin_amdgcn_wave_barrier();
-    const uint32_t bp = (uint32_t)lane * w;
-    const uint32_t wi = bp >> 6, sh = bp & 63u;
-    if (z) {
-        atomicOr((unsigned long long *)&pb[wi], (unsigned long long)(z << sh));
-        if (sh + w > 64u)
-            atomicOr((unsigned long long *)&pb[wi + 1], (unsigned long long)(z >> (64u - sh)));
-    }
-    __builtin_amdgcn_wave_barrier();
-    if ((uint32_t)lane < w)
-        dst[lane] = pb[lane];
-    __builtin_amdgcn_wave_barrier();
+    const uint32_t k = b >> 5, sh = b & 31u;
+    atomicOr(&pb[k], v << sh);
+    if (sh && (v >> (32u - sh)))
+        atomicOr(&pb[k + 1], v >> (32u - sh));
 }
 
-// Encode one plane at one level into its record (one wavefront).  x is
-// overwritten with the decoded values x-hat for the normsq.
-__device__ void encode_plane(double *x, int s, double delta, double e,
-                             double r, uint32_t pszv, uint8_t *rec,
-                             uint64_t *pb, uint32_t *err)
+// Encode one plane at one level into its record (one wavefront).  Lane c
+// (< 16) of wreg holds the level's width of chunk c from the sizing sweep.
+// x is overwritten with the decoded values x-hat for the normsq.  pb is the
+// wave's LDS packing buffer (4 rows of kPackRow dwords, zero on entry and on
+// exit).
+__device__ void encode_plane(double *x, int s, double delta, double e, double r,
+                             uint32_t pszv, uint32_t wreg, uint8_t *rec,
+                             uint32_t *pb, uint32_t *err)
 {
     const int lane = lane_id();
+    const int row = lane >> 4, p = lane & 15;
     const int C = 1 << (s - 6);
+    const int steps = (C + 3) >> 2;
     const uint32_t pw_total = pszv & 0xFFFFu, nout_total = pszv >> 16;
     uint8_t *widths = rec + kPlaneHdrBytes;
-    uint64_t *payload =
-        (uint64_t *)(rec + kPlaneHdrBytes + (pw_total ? pad8((uint32_t)C) : 0u));
-    uint8_t *outl = (uint8_t *)(payload + pw_total);
-    const uint64_t lt_mask = (1ull << lane) - 1ull;
-    uint32_t woff = 0, nout = 0;
-    if (delta == 0.0) {
-        uint64_t carry = 0;
-        for (int c = 0; c < C; ++c) {
-            const uint64_t q = (uint64_t)__double_as_longlong(x[c * kChunk + lane]);
-            const uint64_t prev = dpp64<kWaveShr1>(c == 0 ? q : carry, q);
-            const uint64_t z = zigzag64(q - prev);
-            const uint32_t w = wave_max32(bitlen64(z));
-            if (c == 0 && lane == 0) {
-                *(uint64_t *)rec = q;
-                *(uint32_t *)(rec + 8) = pw_total;
-                *(uint32_t *)(rec + 12) = nout_total;
-            }
-            if (pw_total && lane == 0)
-                widths[c] = (uint8_t)w;
-            if (w && woff + w <= pw_total)
-                pack_chunk(z, w, pb, payload + woff);
-            carry = readlane64(q, 63);
-            woff += w;
-        }
-    } else {
-        int32_t carry = 0;
-        for (int c = 0; c < C; ++c) {
-            const double v = x[c * kChunk + lane];
-            int32_t q;
-            bool out;
-            double xh;
-            lossy_code(v, delta, e, r, q, out, xh);
-            const int32_t prev =
-                (int32_t)dpp32<kWaveShr1>((uint32_t)(c == 0 ? q : carry), (uint32_t)q);
-            const uint32_t z = zigzag32(q - prev);
-            const uint32_t w = wave_max32(bitlen32(z));
-            if (c == 0 && lane == 0) {
-                *(int64_t *)rec = (int64_t)q;
-                *(uint32_t *)(rec + 8) = pw_total;
-                *(uint32_t *)(rec + 12) = nout_total;
-            }
-            if (pw_total && lane == 0)
-                widths[c] = (uint8_t)w;
-            if (w && woff + w <= pw_total)
-                pack_chunk((uint64_t)z, w, pb, payload + woff);
-            const uint64_t bal = __ballot(out);
-            if (out) {
-                const uint32_t rank = nout + (uint32_t)__popcll(bal & lt_mask);
-                if (rank < nout_total) {
-                    uint8_t *ent = outl + (uint64_t)kOutlierBytes * rank;
-                    *(uint32_t *)ent = (uint32_t)(c * kChunk + lane);
-                    *(uint32_t *)(ent + 4) = 0u;
-                    *(uint64_t *)(ent + 8) = (uint64_t)__double_as_longlong(v);
+    uint32_t *payload =
+        (uint32_t *)(rec + kPlaneHdrBytes + (pw_total ? pad8((uint32_t)C) : 0u));
+    uint8_t *outl = (uint8_t *)(payload + 2 * pw_total);
+    const uint32_t wl = lane < C ? wreg : 0u;
+    const uint32_t ol = row_scan32(wl) - wl;
+    const uint32_t wsum = (uint32_t)__builtin_amdgcn_readlane((int)(ol + wl), 15);
+    if (lane == 0) {
+        *(uint32_t *)(rec + 8) = pw_total;
+        *(uint32_t *)(rec + 12) = nout_total;
+    }
+    if (pw_total && lane < (int)pad8((uint32_t)C))
+        widths[lane] = lane < C ? (uint8_t)wl : (uint8_t)0;
+    uint32_t *prow = pb + kPackRow * row;
+    uint32_t nout = 0;
+    uint64_t carry = 0;
+    for (int t = 0; t < steps; ++t) {
+        const int c = 4 * t + row;
+        const bool active = c < C;
+        const int cs = active ? c : 0;
+        const uint32_t w = active ? (uint32_t)__shfl((int)wl, cs, 64) : 0u;
+        const uint32_t woff = (uint32_t)__shfl((int)ol, cs, 64);
+        const bool fits = woff + w <= pw_total;
+        double *xs = x + cs * kChunk + 4 * p;
+        const uint32_t b0 = (uint32_t)(4 * p) * w;
+        if (delta == 0.0) {
+            uint64_t q[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                q[i] = (uint64_t)__double_as_longlong(xs[i]);
+            const uint64_t prev = dpp64<kWaveShr1>(t == 0 ? q[0] : carry, q[3]);
+            if (t == 0 && lane == 0)
+                *(uint64_t *)rec = q[0];
+            uint64_t z[4];
+            z[0] = zigzag64(q[0] - prev);
+            z[1] = zigzag64(q[1] - q[0]);
+            z[2] = zigzag64(q[2] - q[1]);
+            z[3] = zigzag64(q[3] - q[2]);
+            carry = readlane64(q[3], 63);
+            if (active && fits && w == 64u) {
+                uint64_t *dst = (uint64_t *)payload + woff + 4 * p;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    dst[i] = z[i];
+            } else if (active && fits && w) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t bi = b0 + (uint32_t)i * w;
+                    const uint32_t sh = bi & 31u;
+                    const uint32_t lo = (uint32_t)z[i], hi = (uint32_t)(z[i] >> 32);
+                    or_bits32(prow, bi, lo);
+                    // bits 32.. of the field start at bit bi + 32
+                    if (hi) {
+                        const uint32_t k = (bi >> 5) + 1;
+                        atomicOr(&prow[k], hi << sh);
+                        if (sh && (hi >> (32u - sh)))
+                            atomicOr(&prow[k + 1], hi >> (32u - sh));
+                    }
                 }
             }
-            nout += (uint32_t)__popcll(bal);
-            x[c * kChunk + lane] = xh;
-            carry = __builtin_amdgcn_readlane(q, 63);
-            woff += w;
+        } else {
+            int32_t q[4];
+            bool out[4];
+            double xh[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                lossy_code(xs[i], delta, e, r, q[i], out[i], xh[i]);
+            const int32_t prev =
+                (int32_t)dpp32<kWaveShr1>((uint32_t)(t == 0 ? q[0] : (int32_t)carry),
+                                          (uint32_t)q[3]);
+            if (t == 0 && lane == 0)
+                *(int64_t *)rec = (int64_t)q[0];
+            uint32_t z[4];
+            z[0] = zigzag32(q[0] - prev);
+            z[1] = zigzag32(q[1] - q[0]);
+            z[2] = zigzag32(q[2] - q[1]);
+            z[3] = zigzag32(q[3] - q[2]);
+            carry = (uint64_t)(int64_t)__builtin_amdgcn_readlane(q[3], 63);
+            if (active && fits && w) {
+                if (4u * w <= 32u) {
+                    const uint32_t comb = z[0] | (z[1] << w) | (z[2] << (2u * w)) |
+                                          (z[3] << (3u * w));
+                    or_bits32(prow, b0, comb);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        or_bits32(prow, b0 + (uint32_t)i * w, z[i]);
+                }
+            }
+            // outliers, in plane index order
+            uint32_t nl = active ? (uint32_t)out[0] + (uint32_t)out[1] + (uint32_t)out[2] +
+                                       (uint32_t)out[3]
+                                 : 0u;
+            if (__ballot(nl != 0u)) {
+                const uint32_t incl = wave_scan32(nl);
+                uint32_t rank = nout + incl - nl;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (active && out[i]) {
+                        if (rank < nout_total) {
+                            uint8_t *ent = outl + (uint64_t)kOutlierBytes * rank;
+                            *(uint32_t *)ent = (uint32_t)(c * kChunk + 4 * p + i);
+                            *(uint32_t *)(ent + 4) = 0u;
+                            *(uint64_t *)(ent + 8) = (uint64_t)__double_as_longlong(xs[i]);
+                        }
+                        ++rank;
+                    }
+                }
+                nout += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            }
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    xs[i] = xh[i];
+            }
         }
+        __builtin_amdgcn_wave_barrier();
+        // copy each row's packed words out and clear the buffer
+        if (active && fits && w && w < 64u) {
+            for (uint32_t k = (uint32_t)p; k < 2u * w; k += 16u) {
+                payload[2 * woff + k] = prow[k];
+                prow[k] = 0u;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
-    if (pw_total && lane == 0)
-        for (int i = C; i < (int)pad8((uint32_t)C); ++i)
-            widths[i] = 0;
-    if (lane == 0 && (woff != pw_total || nout != nout_total))
+    if (lane == 0 && (wsum != pw_total || nout != nout_total))
         atomicOr(err, kErrSize);
 }
 
@@ -569,10 +762,13 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
     if (a.dev->err)
         return;
     __shared__ Planes X;
-    __shared__ uint64_t pack[4][64];
-    __shared__ double red[8];
-    __shared__ uint64_t rbytes[4];
-    __shared__ uint64_t rbase;
+    __shared__ uint32_t pack[4][4 * kPackRow];
+    __shared__ uint64_t misc[9];  // segment sums, then record bytes + base
+    double *red = (double *)misc;
+    uint64_t *rbytes = misc;
+    uint64_t &rbase = misc[8];
+    for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
+        (&pack[0][0])[k] = 0u;
     const int s = a.geo.s;
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int us = wave >> 1, p = wave & 1;
@@ -619,18 +815,21 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
         const uint64_t plane = 2 * g + p;
         const bool mine = active && (MODE == kFused || j == jsel);
         int lev = 0;
-        uint32_t pszv = 0;
+        uint32_t pszv = 0, wreg = 0;
         if (mine) {
             const int h = hint_level(a, j);
-            const int cm = h + 1 < L ? h + 1 : L - 1;
+            const int cm = h;
             if (MODE == kFused) {
                 lev = h;
-                pszv = size_levels(&X[us][p][0], s, a.lad, 0, cm, h, a.psz, plane, nplanes);
+                pszv = size_levels(&X[us][p][0], s, a.lad, 0, cm, h, a.psz, plane, nplanes,
+                                   wreg);
             } else if (MODE == kEsc) {
-                size_levels(&X[us][p][0], s, a.lad, cm + 1, L - 1, -1, a.psz, plane, nplanes);
+                size_levels(&X[us][p][0], s, a.lad, cm + 1, L - 1, -1, a.psz, plane, nplanes,
+                            wreg);
             } else {
                 lev = a.dout.blk_level[j];
-                pszv = a.psz[(uint64_t)lev * nplanes + plane];
+                pszv = size_levels(&X[us][p][0], s, a.lad, lev, lev, lev, a.psz, plane,
+                                   nplanes, wreg);
             }
         }
         if (MODE != kEsc) {
@@ -663,7 +862,7 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
                 if (lane == 0)
                     a.dout.plane_off[plane] = off;
                 encode_plane(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev], a.lad.r[lev],
-                             pszv, a.arena_out + off, &pack[wave][0], &a.dev->err);
+                             pszv, wreg, a.arena_out + off, &pack[wave][0], &a.dev->err);
             }
             __syncthreads();
             const double ns = segment_tree(uc, s, red, [&](int su, int o) {
@@ -845,7 +1044,7 @@ __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
     for (uint64_t r = blockIdx.x; r < count; r += gridDim.x) {
         const uint64_t j = ESC ? a.esc_list[r] : r;
         const int h = hint_level(a, j);
-        const int cm = h + 1 < L ? h + 1 : L - 1;
+        const int cm = h;
         const int k0 = ESC ? cm + 1 : 0;
         const int k1 = ESC ? L - 1 : cm;
         block_totals(a, j, k0, k1, red, tot, nout);
