@@ -176,9 +176,9 @@ typedef struct {
     double max_ms;
 } sim_kernel_time_t;
 
-/* Turn on (1) or off (0) HIP-event timing of every kernel this sim launches:
- * a begin and an end event are recorded on the sim stream around each
- * launch.  Synchronises. */
+/* HIP-event timing of this sim's kernels: 0 off, 1 every kernel, 2 only the
+ * fused per-gate pass kernel (fewest events).  A begin and an end event are
+ * recorded on the sim stream around each timed launch.  Synchronises. */
 int sim_profile(sim_t *sim, int on);
 
 /* Per-kernel totals of the launches timed since the last read (then reset).

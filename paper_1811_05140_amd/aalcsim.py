@@ -243,8 +243,8 @@ class Sim:
         check(lib.sim_export_block(self.h, j, buf, ln.value, ctypes.byref(ln)), True)
         return buf.raw[:ln.value]
 
-    def profile(self, on=True):
-        check(lib.sim_profile(self.h, 1 if on else 0))
+    def profile(self, on=True, pass_only=False):
+        check(lib.sim_profile(self.h, (2 if pass_only else 1) if on else 0))
 
     def profile_read(self):
         """{kernel: (launches, total_ms, min_ms, max_ms)} since the last read."""

@@ -51,32 +51,41 @@ struct Desc {
     uint32_t *blk_len;    // [nblocks] canonical stream bytes
     uint8_t *blk_level;   // [nblocks] ladder level of the stream
     uint64_t *plane_off;  // [2*nseg] byte offset of each plane record
+    double *segnorm;      // [nseg] pairwise normsq of each segment's x-hat
 };
 
 // Device-resident scalars of one sim, read and written only by kernels.
+// The counters that every workgroup of a pass updates atomically sit on
+// their own 128-byte lines, away from the read-mostly scalars.
 struct DevState {
     double normsq;          // N^2 of the stored state
     double scale;           // s applied at the next decode
     double tdiff[2];        // 2 * mean for DIFFUSE
-    uint64_t arena_used[2]; // bump pointers of the two arenas
     uint64_t resident;      // bytes of the current state
     uint64_t peak_resident;
     double min_ratio;
     double last_ratio;
-    uint64_t level_hist[kMaxL];
     uint64_t passes;
     uint32_t err;           // sticky error bits (kErr*)
     uint32_t err_pass;      // pass index of the first error
     int32_t collapsed;
     int32_t normalize;
+    uint8_t pad0[128 - 88];
+    uint64_t arena_used[2]; // bump pointers of the two arenas
+    uint64_t arena_peak;    // largest bump pointer reached (incl. replay waste)
+    uint8_t pad1[128 - 24];
     uint32_t n_replay;      // blocks whose chosen level was not the speculated one
     uint32_t n_esc;         // blocks whose computed levels all missed theta
     uint64_t replays;       // cumulative count of replayed blocks
     uint64_t escalations;   // cumulative count of escalated blocks
-    uint64_t arena_peak;    // largest bump pointer reached (incl. replay waste)
+    uint64_t level_hist[kMaxL];
 };
 
 enum : uint32_t { kErrArena = 1u, kErrSize = 2u };
+
+// Pass index recorded by the basis-state encode (set_basis), which has no
+// earlier state to fall back to.
+constexpr uint64_t kBasisPass = 0xFFFFFFFFull;
 
 struct Geo {
     int32_t n, b, s, pad;
@@ -96,14 +105,14 @@ struct PassArgs {
     uint64_t arena_cap;
     int32_t out_arena;   // index of arena_out (bump pointer)
     int32_t in_arena;
-    uint64_t pass;       // pass counter (for error reporting)
+    uint64_t pass;       // pass counter (for error reporting; kBasisPass for set_basis)
+    uint64_t chunk_bytes;  // arena space a workgroup takes per bump-pointer update
     uint64_t basis;      // source state |basis> when src_basis != 0
     int32_t src_basis;
     int32_t pad;
     uint32_t *psz;       // [L][2*nseg]: payload words | n_outliers << 16
     uint32_t *replay_list;  // [nblocks]
     uint32_t *esc_list;     // [nblocks]
-    double *segnorm;     // [nseg]
     double *blknorm;     // [nblocks]
     double *segsum;      // [2][nseg] DIFFUSE pre-pass
     double *blksum;      // [2][nblocks]

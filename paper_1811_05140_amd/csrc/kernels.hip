@@ -221,6 +221,15 @@ __device__ __forceinline__ Unit unit_of(uint64_t u, uint64_t nseg, uint64_t Ms)
 
 typedef double Planes[2][2][1 << kMaxS];
 
+// LDS position of in-plane scalar o.  Inside each 64-scalar chunk, o =
+// 4p + i (lane p of a row, its i-th scalar) is stored at 32 (i >> 1) + 2p +
+// (i & 1): the codec's 16-byte accesses of the 16 lanes of a row then sweep
+// 256 contiguous bytes (all banks once), instead of a 32-byte lane stride.
+__device__ __forceinline__ uint32_t sw(uint32_t o)
+{
+    return (o & ~63u) | ((o & 2u) << 4) | ((o >> 1) & 0x1Eu) | (o & 1u);
+}
+
 // ---- codec layout: a wavefront works on four chunks at a time, row r
 // (lanes 16r .. 16r+15) on chunk 4t + r in step t, lane p of the row on the
 // four consecutive scalars 4p .. 4p+3 of that chunk.  Chunk widths are row
@@ -327,7 +336,10 @@ __device__ void decode_plane(const uint8_t *rec, int s, double delta,
         if (active) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                dst[c * kChunk + 4 * p + i] = do_scale ? x[i] * scale : x[i];
+                x[i] = do_scale ? x[i] * scale : x[i];
+            double2 *pa = (double2 *)(dst + c * kChunk + 2 * p);
+            pa[0] = make_double2(x[0], x[1]);
+            pa[16] = make_double2(x[2], x[3]);
         }
     }
     const uint8_t *outl = (const uint8_t *)(payload + 2 * pw);
@@ -336,7 +348,7 @@ __device__ void decode_plane(const uint8_t *rec, int s, double delta,
         double v = *(const double *)(outl + (uint64_t)kOutlierBytes * k + 8);
         if (do_scale)
             v = v * scale;
-        dst[idx] = v;
+        dst[sw(idx)] = v;
     }
 }
 
@@ -354,7 +366,7 @@ __device__ void load_unit(const PassArgs &a, const Unit &uc, Planes &X,
     double *dst = &X[us][p][0];
     if (a.src_basis) {
         for (int o = lane; o < (1 << s); o += 64)
-            dst[o] = (p == 0 && ((g << s) | (uint64_t)o) == a.basis) ? 1.0 : 0.0;
+            dst[sw(o)] = (p == 0 && ((g << s) | (uint64_t)o) == a.basis) ? 1.0 : 0.0;
         return;
     }
     const uint64_t j = g >> (a.geo.b - s);
@@ -378,22 +390,24 @@ __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
             const int us = (int)(t >> s);
             const uint32_t o = t & (S - 1);
             const uint64_t i = (uc.seg(us) << s) | o;
-            double ar = X[us][0][o], ai = X[us][1][o];
+            const uint32_t so = sw(o);
+            double ar = X[us][0][so], ai = X[us][1][so];
             gate_diag(G, i, ar, ai, tdiff);
-            X[us][0][o] = ar;
-            X[us][1][o] = ai;
+            X[us][0][so] = ar;
+            X[us][1][so] = ai;
         }
     } else if (Ms) {
         for (uint32_t o = tid; o < S; o += kWG) {
             const uint32_t o2 = o ^ Ml;
             const uint64_t i = (uc.g[0] << s) | o;
-            double ar = X[0][0][o], ai = X[0][1][o];
-            double br = X[1][0][o2], bi = X[1][1][o2];
+            const uint32_t so = sw(o), so2 = sw(o2);
+            double ar = X[0][0][so], ai = X[0][1][so];
+            double br = X[1][0][so2], bi = X[1][1][so2];
             gate_pair(G, i, ar, ai, br, bi);
-            X[0][0][o] = ar;
-            X[0][1][o] = ai;
-            X[1][0][o2] = br;
-            X[1][1][o2] = bi;
+            X[0][0][so] = ar;
+            X[0][1][so] = ai;
+            X[1][0][so2] = br;
+            X[1][1][so2] = bi;
         }
     } else {
         const int hb = 31 - __builtin_clz(Ml);
@@ -405,13 +419,14 @@ __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
             const uint32_t o = ((r >> hb) << (hb + 1)) | (r & ((1u << hb) - 1));
             const uint32_t o2 = o ^ Ml;
             const uint64_t i = (uc.seg(us) << s) | o;
-            double ar = X[us][0][o], ai = X[us][1][o];
-            double br = X[us][0][o2], bi = X[us][1][o2];
+            const uint32_t so = sw(o), so2 = sw(o2);
+            double ar = X[us][0][so], ai = X[us][1][so];
+            double br = X[us][0][so2], bi = X[us][1][so2];
             gate_pair(G, i, ar, ai, br, bi);
-            X[us][0][o] = ar;
-            X[us][1][o] = ai;
-            X[us][0][o2] = br;
-            X[us][1][o2] = bi;
+            X[us][0][so] = ar;
+            X[us][1][so] = ai;
+            X[us][0][so2] = br;
+            X[us][1][so2] = bi;
         }
     }
 }
@@ -487,11 +502,12 @@ __device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k
             for (int t = 0; t < steps; ++t) {
                 const int c = 4 * t + r;
                 const bool active = c < C;
-                const double *xs = x + (active ? c : 0) * kChunk + 4 * p;
-                const uint64_t q0 = (uint64_t)__double_as_longlong(xs[0]);
-                const uint64_t q1 = (uint64_t)__double_as_longlong(xs[1]);
-                const uint64_t q2 = (uint64_t)__double_as_longlong(xs[2]);
-                const uint64_t q3 = (uint64_t)__double_as_longlong(xs[3]);
+                const double2 *pa = (const double2 *)(x + (active ? c : 0) * kChunk + 2 * p);
+                const double2 v01 = pa[0], v23 = pa[16];
+                const uint64_t q0 = (uint64_t)__double_as_longlong(v01.x);
+                const uint64_t q1 = (uint64_t)__double_as_longlong(v01.y);
+                const uint64_t q2 = (uint64_t)__double_as_longlong(v23.x);
+                const uint64_t q3 = (uint64_t)__double_as_longlong(v23.y);
                 const uint64_t prev = dpp64<kWaveShr1>(t == 0 ? q0 : carry, q3);
                 const uint64_t o = zigzag64(q0 - prev) | zigzag64(q1 - q0) |
                                    zigzag64(q2 - q1) | zigzag64(q3 - q2);
@@ -507,7 +523,9 @@ __device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k
             for (int t = 0; t < steps; ++t) {
                 const int c = 4 * t + r;
                 const bool active = c < C;
-                const double *xs = x + (active ? c : 0) * kChunk + 4 * p;
+                const double2 *pa = (const double2 *)(x + (active ? c : 0) * kChunk + 2 * p);
+                const double2 v01 = pa[0], v23 = pa[16];
+                const double xs[4] = {v01.x, v01.y, v23.x, v23.y};
                 int32_t q[4];
                 bool out[4];
 #pragma unroll
@@ -596,7 +614,9 @@ __device__ void encode_plane(double *x, int s, double delta, double e, double r,
         const uint32_t w = active ? (uint32_t)__shfl((int)wl, cs, 64) : 0u;
         const uint32_t woff = (uint32_t)__shfl((int)ol, cs, 64);
         const bool fits = woff + w <= pw_total;
-        double *xs = x + cs * kChunk + 4 * p;
+        double2 *pa = (double2 *)(x + cs * kChunk + 2 * p);
+        const double2 v01 = pa[0], v23 = pa[16];
+        const double xs[4] = {v01.x, v01.y, v23.x, v23.y};
         const uint32_t b0 = (uint32_t)(4 * p) * w;
         if (delta == 0.0) {
             uint64_t q[4];
@@ -684,9 +704,8 @@ __device__ void encode_plane(double *x, int s, double delta, double e, double r,
                 nout += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
             }
             if (active) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    xs[i] = xh[i];
+                pa[0] = make_double2(xh[0], xh[1]);
+                pa[16] = make_double2(xh[2], xh[3]);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -756,128 +775,197 @@ __device__ __forceinline__ int hint_level(const PassArgs &a, uint64_t j)
     return h < a.lad.L ? h : a.lad.L - 1;
 }
 
+// Workgroup-shared storage of the pass kernels (40.9 KiB: four workgroups
+// fit a CU).  After a unit's records are written, X doubles as scratch for
+// the block decisions and reductions.
+struct PassLds {
+    alignas(16) Planes X;
+    uint32_t pack[4][4 * kPackRow];
+    uint64_t misc[9];  // segment sums, then record bytes + base
+    uint64_t chunk[2]; // this workgroup's current arena chunk [cur, end)
+};
+
+// Arena space is taken from the shared bump pointer in chunks of
+// PassArgs::chunk_bytes (or one unit's need, if larger) and handed out unit by
+// unit, so a pass issues far fewer device-scope atomics than it has units.
+// The chunk is at most 32 KiB and at most 1/8 of the arena divided by the
+// workgroup count, which bounds the unused chunk tails.
+
+// One unit of a pass: decode + normalise + gate in LDS, then per plane
+//   kFused:  sizes at levels 0..h (h = the block's previous level), encode
+//            at h (the speculation);
+//   kEsc:    sizes at levels h+1 .. L-1 for the planes of block jsel;
+//   kReplay: encode the planes of block jsel at its chosen level;
+// records are bump-allocated per unit; per-segment normsq of what was
+// encoded.
 template <int MODE>
-__global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
+__device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, PassLds &S,
+                          double scale, const double *tdiff)
 {
-    if (a.dev->err)
-        return;
-    __shared__ Planes X;
-    __shared__ uint32_t pack[4][4 * kPackRow];
-    __shared__ uint64_t misc[9];  // segment sums, then record bytes + base
-    double *red = (double *)misc;
-    uint64_t *rbytes = misc;
-    uint64_t &rbase = misc[8];
-    for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
-        (&pack[0][0])[k] = 0u;
+    Planes &X = S.X;
+    double *red = (double *)S.misc;
+    uint64_t *rbytes = S.misc;
+    uint64_t &rbase = S.misc[8];
     const int s = a.geo.s;
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int us = wave >> 1, p = wave & 1;
     const int L = a.lad.L;
-    const double scale = a.dev->scale;
     const bool do_scale = !a.src_basis && scale != 1.0;
-    const double *tdiff = a.dev->tdiff;
-    const uint64_t Ms = a.gate.mask >> s;
     const uint64_t nplanes = 2 * a.geo.nseg;
     const int bs = a.geo.b - s;
-    const uint64_t spb = 1ull << bs;
     const uint32_t padC = pad8(1u << (s - 6));
-    uint64_t nitems;
-    const uint32_t *list = nullptr;
-    if (MODE == kFused) {
-        nitems = a.geo.nunits;
-    } else {
-        const uint32_t cnt = MODE == kEsc ? a.dev->n_esc : a.dev->n_replay;
-        list = MODE == kEsc ? a.esc_list : a.replay_list;
-        nitems = (uint64_t)cnt << bs;
-    }
-    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        Unit uc;
-        uint64_t jsel = ~0ull;  // the block this item works for (kEsc, kReplay)
+    load_unit(a, uc, X, scale, do_scale);
+    __syncthreads();
+    gate_unit(a.gate, uc, s, X, tdiff);
+    __syncthreads();
+    const bool active = us < uc.nsu;
+    const uint64_t g = active ? uc.seg(us) : 0;
+    const uint64_t j = g >> bs;
+    const uint64_t plane = 2 * g + p;
+    const bool mine = active && (MODE == kFused || j == jsel);
+    int lev = 0;
+    uint32_t pszv = 0, wreg = 0;
+    if (mine) {
+        const int h = hint_level(a, j);
         if (MODE == kFused) {
-            uc = unit_of(it, a.geo.nseg, Ms);
+            lev = h;
+            pszv = size_levels(&X[us][p][0], s, a.lad, 0, h, h, a.psz, plane, nplanes, wreg);
+        } else if (MODE == kEsc) {
+            size_levels(&X[us][p][0], s, a.lad, h + 1, L - 1, -1, a.psz, plane, nplanes, wreg);
         } else {
-            jsel = list[it >> bs];
+            lev = a.dout.blk_level[j];
+            pszv = size_levels(&X[us][p][0], s, a.lad, lev, lev, lev, a.psz, plane, nplanes,
+                               wreg);
+        }
+    }
+    if (MODE == kEsc)
+        return;
+    // bump-allocate this unit's records in the output arena
+    if (lane == 0)
+        rbytes[wave] = mine ? rec_bytes(pszv, padC) : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint64_t tot = rbytes[0] + rbytes[1] + rbytes[2] + rbytes[3];
+        uint64_t base = 0;
+        if (tot) {
+            if (S.chunk[0] + tot > S.chunk[1]) {
+                const uint64_t want = tot > a.chunk_bytes ? tot : a.chunk_bytes;
+                const uint64_t b0 = atomicAdd(
+                    (unsigned long long *)&a.dev->arena_used[a.out_arena],
+                    (unsigned long long)want);
+                S.chunk[0] = b0;
+                S.chunk[1] = b0 + want;
+            }
+            base = S.chunk[0];
+            S.chunk[0] += tot;
+            if (base + tot > a.arena_cap) {
+                if (atomicOr(&a.dev->err, kErrArena) == 0)
+                    a.dev->err_pass = (uint32_t)a.pass;
+                base = ~0ull;
+            }
+        }
+        rbase = base;
+    }
+    __syncthreads();
+    if (mine && rbase != ~0ull) {
+        uint64_t off = rbase;
+        for (int w2 = 0; w2 < wave; ++w2)
+            off += rbytes[w2];
+        if (lane == 0)
+            a.dout.plane_off[plane] = off;
+        encode_plane(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev], a.lad.r[lev], pszv,
+                     wreg, a.arena_out + off, &S.pack[wave][0], &a.dev->err);
+    }
+    __syncthreads();
+    const double ns = segment_tree(uc, s, red, [&](int su, int o) {
+        const double re = X[su][0][sw(o)], im = X[su][1][sw(o)];
+        const double rr = re * re;
+        const double ii = im * im;
+        return rr + ii;
+    });
+    if (threadIdx.x < (unsigned)uc.nsu) {
+        const uint64_t gs = uc.seg((int)threadIdx.x);
+        if (MODE == kFused || (gs >> bs) == jsel)
+            a.dout.segnorm[gs] = ns;
+    }
+}
+
+__device__ void decide_escalated(const PassArgs &a, uint64_t j, PassLds &S);
+
+// The fused pass over all units.
+__global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
+{
+    if (a.dev->err)
+        return;
+    __shared__ PassLds S;
+    for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
+        (&S.pack[0][0])[k] = 0u;
+    if (threadIdx.x == 0)
+        S.chunk[0] = S.chunk[1] = 0;
+    const uint64_t Ms = a.gate.mask >> a.geo.s;
+    // kernel-uniform device state, read once (its cache line also holds the
+    // bump pointers that every unit updates atomically)
+    const double scale = a.dev->scale;
+    const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
+    for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
+        const Unit uc = unit_of(it, a.geo.nseg, Ms);
+        unit_body<kFused>(a, uc, ~0ull, S, scale, tdiff);
+        __syncthreads();
+    }
+}
+
+// Replays and escalations left by k_decide.  Items: (replayed block,
+// segment) pairs, one unit each, encoded again at the chosen level; then
+// one item per escalated block, whose workgroup sizes the remaining levels
+// over all the block's units, decides, and re-encodes the block itself.
+__global__ __launch_bounds__(kWG) void k_fix(PassArgs a)
+{
+    if (a.dev->err)
+        return;
+    const uint32_t nrep = a.dev->n_replay, nesc = a.dev->n_esc;
+    if (nrep + nesc == 0)
+        return;
+    __shared__ PassLds S;
+    for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
+        (&S.pack[0][0])[k] = 0u;
+    if (threadIdx.x == 0)
+        S.chunk[0] = S.chunk[1] = 0;
+    const int bs = a.geo.b - a.geo.s;
+    const uint64_t spb = 1ull << bs;
+    const uint64_t Ms = a.gate.mask >> a.geo.s;
+    const uint64_t nrep_items = (uint64_t)nrep << bs;
+    const uint64_t nitems = nrep_items + nesc;
+    const double scale = a.dev->scale;
+    const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
+    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        if (it < nrep_items) {
+            const uint64_t jsel = a.replay_list[it >> bs];
             const uint64_t g = (jsel << bs) | (it & (spb - 1));
-            uc = unit_of_seg(g, a.geo.nseg, Ms);
-            // one item per (unit, block): skip when the unit's other segment
-            // lies in the same block and comes first
+            const Unit uc = unit_of_seg(g, a.geo.nseg, Ms);
             const uint64_t other = uc.nsu == 2 ? (uc.g[0] == g ? uc.g[1] : uc.g[0]) : g;
             if ((other >> bs) == jsel && other < g)
-                continue;
+                continue;  // the unit is handled with its first segment
+            unit_body<kReplay>(a, uc, jsel, S, scale, tdiff);
+            __syncthreads();
+            continue;
         }
-        load_unit(a, uc, X, scale, do_scale);
-        __syncthreads();
-        gate_unit(a.gate, uc, s, X, tdiff);
-        __syncthreads();
-        const bool active = us < uc.nsu;
-        const uint64_t g = active ? uc.seg(us) : 0;
-        const uint64_t j = g >> bs;
-        const uint64_t plane = 2 * g + p;
-        const bool mine = active && (MODE == kFused || j == jsel);
-        int lev = 0;
-        uint32_t pszv = 0, wreg = 0;
-        if (mine) {
-            const int h = hint_level(a, j);
-            const int cm = h;
-            if (MODE == kFused) {
-                lev = h;
-                pszv = size_levels(&X[us][p][0], s, a.lad, 0, cm, h, a.psz, plane, nplanes,
-                                   wreg);
-            } else if (MODE == kEsc) {
-                size_levels(&X[us][p][0], s, a.lad, cm + 1, L - 1, -1, a.psz, plane, nplanes,
-                            wreg);
-            } else {
-                lev = a.dout.blk_level[j];
-                pszv = size_levels(&X[us][p][0], s, a.lad, lev, lev, lev, a.psz, plane,
-                                   nplanes, wreg);
+        const uint64_t jsel = a.esc_list[it - nrep_items];
+        for (int phase = 0; phase < 2; ++phase) {
+            if (phase == 1)
+                decide_escalated(a, jsel, S);
+            for (uint64_t t = 0; t < spb; ++t) {
+                const uint64_t g = (jsel << bs) | t;
+                const Unit uc = unit_of_seg(g, a.geo.nseg, Ms);
+                const uint64_t other = uc.nsu == 2 ? (uc.g[0] == g ? uc.g[1] : uc.g[0]) : g;
+                if ((other >> bs) == jsel && other < g)
+                    continue;
+                if (phase == 0)
+                    unit_body<kEsc>(a, uc, jsel, S, scale, tdiff);
+                else
+                    unit_body<kReplay>(a, uc, jsel, S, scale, tdiff);
+                __syncthreads();
             }
         }
-        if (MODE != kEsc) {
-            // bump-allocate this unit's records in the output arena
-            if (lane == 0)
-                rbytes[wave] = mine ? rec_bytes(pszv, padC) : 0;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                const uint64_t tot = rbytes[0] + rbytes[1] + rbytes[2] + rbytes[3];
-                uint64_t base = 0;
-                if (tot) {
-                    base = atomicAdd((unsigned long long *)&a.dev->arena_used[a.out_arena],
-                                     (unsigned long long)tot);
-                    if (base + tot > a.arena_cap) {
-                        if (atomicOr(&a.dev->err, kErrArena) == 0)
-                            a.dev->err_pass = (uint32_t)a.pass;
-                        base = ~0ull;
-                    } else {
-                        atomicMax((unsigned long long *)&a.dev->arena_peak,
-                                  (unsigned long long)(base + tot));
-                    }
-                }
-                rbase = base;
-            }
-            __syncthreads();
-            if (mine && rbase != ~0ull) {
-                uint64_t off = rbase;
-                for (int w2 = 0; w2 < wave; ++w2)
-                    off += rbytes[w2];
-                if (lane == 0)
-                    a.dout.plane_off[plane] = off;
-                encode_plane(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev], a.lad.r[lev],
-                             pszv, wreg, a.arena_out + off, &pack[wave][0], &a.dev->err);
-            }
-            __syncthreads();
-            const double ns = segment_tree(uc, s, red, [&](int su, int o) {
-                const double re = X[su][0][o], im = X[su][1][o];
-                const double rr = re * re;
-                const double ii = im * im;
-                return rr + ii;
-            });
-            if (threadIdx.x < (unsigned)uc.nsu) {
-                const uint64_t gs = uc.seg((int)threadIdx.x);
-                if (MODE == kFused || (gs >> bs) == jsel)
-                    a.segnorm[gs] = ns;
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -887,7 +975,7 @@ __global__ __launch_bounds__(kWG) void k_mean(PassArgs a)
 {
     if (a.dev->err)
         return;
-    __shared__ Planes X;
+    __shared__ __attribute__((aligned(16))) Planes X;
     __shared__ double red[8];
     const int s = a.geo.s;
     const double scale = a.dev->scale;
@@ -898,7 +986,7 @@ __global__ __launch_bounds__(kWG) void k_mean(PassArgs a)
         __syncthreads();
         for (int c = 0; c < 2; ++c) {
             const double sm = segment_tree(uc, s, red,
-                                           [&](int su, int o) { return X[su][c][o]; });
+                                           [&](int su, int o) { return X[su][c][sw(o)]; });
             if (threadIdx.x < (unsigned)uc.nsu)
                 a.segsum[(uint64_t)c * a.geo.nseg + uc.seg((int)threadIdx.x)] = sm;
         }
@@ -908,7 +996,28 @@ __global__ __launch_bounds__(kWG) void k_mean(PassArgs a)
 
 // ------------------------------------------------------ reductions --------
 
-// Pairwise sum of m = 2^k values load(0..m) by one workgroup.
+// Largest segment count whose N^2 tree one workgroup forms directly.
+constexpr uint64_t kReduceDirect = 1ull << 13;
+
+// Pairwise sum of PER consecutive values, fully unrolled in registers.
+template <int PER, class Load>
+__device__ __forceinline__ double seq_tree(Load load, uint64_t base)
+{
+    double v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        v[i] = load(base + i);
+#pragma unroll
+    for (int st = 1; st < PER; st <<= 1) {
+#pragma unroll
+        for (int i = 0; i < PER; i += 2 * st)
+            v[i] = v[i] + v[i + st];
+    }
+    return v[0];
+}
+
+// Pairwise sum of m = 2^k values load(0..m) by one workgroup: each thread
+// sums m/256 consecutive values (an aligned subtree), then a tree in LDS.
 template <class Load>
 __device__ double wg_tree(Load load, uint64_t m, double *lds)
 {
@@ -916,15 +1025,29 @@ __device__ double wg_tree(Load load, uint64_t m, double *lds)
     uint64_t nact;
     if (m >= kWG) {
         const uint64_t per = m / kWG;
-        double stack[40];
-        int sp = 0;
-        for (uint64_t i = 0; i < per; ++i) {
-            double v = load(t * per + i);
-            for (uint64_t k = i; k & 1; k >>= 1)
-                v = stack[--sp] + v;
-            stack[sp++] = v;
+        const uint64_t base = t * per;
+        double v;
+        switch (per) {
+        case 1: v = seq_tree<1>(load, base); break;
+        case 2: v = seq_tree<2>(load, base); break;
+        case 4: v = seq_tree<4>(load, base); break;
+        case 8: v = seq_tree<8>(load, base); break;
+        case 16: v = seq_tree<16>(load, base); break;
+        case 32: v = seq_tree<32>(load, base); break;
+        default: {
+            // longer runs: subtrees of 32 combined through a binary counter
+            double stack[40];
+            int sp = 0;
+            for (uint64_t i = 0; i < per / 32; ++i) {
+                double x = seq_tree<32>(load, base + 32 * i);
+                for (uint64_t k = i; k & 1; k >>= 1)
+                    x = stack[--sp] + x;
+                stack[sp++] = x;
+            }
+            v = stack[0];
         }
-        lds[t] = stack[0];
+        }
+        lds[t] = v;
         nact = kWG;
     } else {
         lds[t] = (t < (int)m) ? load((uint64_t)t) : 0.0;
@@ -1027,10 +1150,11 @@ __device__ void finalize_block(const PassArgs &a, uint64_t j, int d, uint64_t le
         atomicAdd((unsigned long long *)&a.dev->level_hist[d], 1ull);
 }
 
-// Alg. 2's choice for each block.  ESC = false: over the levels computed by
-// the fused pass (0 .. previous level + 1).  ESC = true: over the remaining
-// levels of escalated blocks.
-template <bool ESC>
+// Alg. 2's choice for each block over the levels the fused pass sized
+// (0 .. h, h = the block's previous level): the first whose full-block ratio
+// reaches theta.  When that is the speculated level h the block is done;
+// another level sends the block to the replay list; when none qualifies and
+// levels above h remain, the block joins the escalation list.
 __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
 {
     if (a.dev->err)
@@ -1040,22 +1164,17 @@ __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
     __shared__ uint64_t nout[kMaxL];
     const int L = a.lad.L;
     const double raw = (double)(16ull << a.geo.b);
-    const uint64_t count = ESC ? a.dev->n_esc : a.geo.nblocks;
-    for (uint64_t r = blockIdx.x; r < count; r += gridDim.x) {
-        const uint64_t j = ESC ? a.esc_list[r] : r;
+    for (uint64_t j = blockIdx.x; j < a.geo.nblocks; j += gridDim.x) {
         const int h = hint_level(a, j);
-        const int cm = h;
-        const int k0 = ESC ? cm + 1 : 0;
-        const int k1 = ESC ? L - 1 : cm;
-        block_totals(a, j, k0, k1, red, tot, nout);
+        block_totals(a, j, 0, h, red, tot, nout);
         if (threadIdx.x == 0) {
             int d = -1;
-            for (int k = k0; k <= k1; ++k)
+            for (int k = 0; k <= h; ++k)
                 if (raw >= a.lad.theta * (double)tot[k]) {
                     d = k;
                     break;
                 }
-            if (d < 0 && k1 == L - 1)
+            if (d < 0 && h == L - 1)
                 d = L - 1;
             if (d < 0) {
                 const uint32_t slot = atomicAdd(&a.dev->n_esc, 1u);
@@ -1074,7 +1193,33 @@ __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
     }
 }
 
-// N^2, s, statistics; frees the input arena for the next pass.
+// Choice for an escalated block over levels h+1 .. L-1 (the first whose
+// ratio reaches theta, else the last) (workgroup).
+__device__ void decide_escalated(const PassArgs &a, uint64_t j, PassLds &S)
+{
+    uint64_t *red = (uint64_t *)&S.X[0][0][0];
+    uint64_t *tot = red + kWG;
+    uint64_t *nout = tot + kMaxL;
+    const int L = a.lad.L;
+    const int h = hint_level(a, j);
+    block_totals(a, j, h + 1, L - 1, red, tot, nout);
+    if (threadIdx.x == 0) {
+        const double raw = (double)(16ull << a.geo.b);
+        int d = L - 1;
+        for (int k = h + 1; k < L; ++k)
+            if (raw >= a.lad.theta * (double)tot[k]) {
+                d = k;
+                break;
+            }
+        finalize_block(a, j, d, tot[d], nout[d]);
+        atomicAdd((unsigned long long *)&a.dev->replays, 1ull);
+    }
+    __syncthreads();
+}
+
+// N^2 (pairwise over all amplitudes: block and segment sums are aligned
+// subtrees, so the tree runs over segment sums, or over block sums when
+// k_segtree has formed them), s, statistics; frees the input arena.
 __global__ __launch_bounds__(kWG) void k_reduce(PassArgs a)
 {
     if (a.dev->err)
@@ -1082,7 +1227,10 @@ __global__ __launch_bounds__(kWG) void k_reduce(PassArgs a)
     __shared__ double lds[kWG];
     __shared__ uint64_t ures[kWG];
     const int t = threadIdx.x;
-    const double N2 = wg_tree([&](uint64_t i) { return a.blknorm[i]; }, a.geo.nblocks, lds);
+    const bool by_block = a.geo.nseg > kReduceDirect;
+    const double N2 = by_block
+        ? wg_tree([&](uint64_t i) { return a.blknorm[i]; }, a.geo.nblocks, lds)
+        : wg_tree([&](uint64_t i) { return a.dout.segnorm[i]; }, a.geo.nseg, lds);
     uint64_t by = 0;
     for (uint64_t j = t; j < a.geo.nblocks; j += kWG)
         by += a.dout.blk_len[j];
@@ -1116,6 +1264,8 @@ __global__ __launch_bounds__(kWG) void k_reduce(PassArgs a)
             if (ratio < d->min_ratio)
                 d->min_ratio = ratio;
         }
+        if (d->arena_used[a.out_arena] > d->arena_peak)
+            d->arena_peak = d->arena_used[a.out_arena];
         d->arena_used[a.in_arena] = 0;
         d->n_replay = 0;
         d->n_esc = 0;
@@ -1128,7 +1278,7 @@ __global__ __launch_bounds__(kWG) void k_decode_range(PassArgs a, uint64_t u0,
                                                       uint64_t u1, uint64_t first,
                                                       uint64_t count, double *out)
 {
-    __shared__ Planes X;
+    __shared__ __attribute__((aligned(16))) Planes X;
     const int s = a.geo.s;
     const double scale = a.dev->scale;
     const bool do_scale = scale != 1.0;
@@ -1140,8 +1290,8 @@ __global__ __launch_bounds__(kWG) void k_decode_range(PassArgs a, uint64_t u0,
             for (uint32_t o = threadIdx.x; o < (1u << s); o += kWG) {
                 const uint64_t i = (uc.seg(us) << s) | o;
                 if (i >= first && i < first + count) {
-                    out[2 * (i - first)] = X[us][0][o];
-                    out[2 * (i - first) + 1] = X[us][1][o];
+                    out[2 * (i - first)] = X[us][0][sw(o)];
+                    out[2 * (i - first) + 1] = X[us][1][sw(o)];
                 }
             }
         __syncthreads();
@@ -1151,7 +1301,7 @@ __global__ __launch_bounds__(kWG) void k_decode_range(PassArgs a, uint64_t u0,
 __global__ __launch_bounds__(kWG) void k_probs(PassArgs a, const int *qubits, int nq,
                                                double *probs)
 {
-    __shared__ Planes X;
+    __shared__ __attribute__((aligned(16))) Planes X;
     __shared__ double bins[1024];
     const int s = a.geo.s;
     const double scale = a.dev->scale;
@@ -1172,7 +1322,7 @@ __global__ __launch_bounds__(kWG) void k_probs(PassArgs a, const int *qubits, in
                 uint32_t oc = 0;
                 for (int k = 0; k < nq; ++k)
                     oc |= (uint32_t)bit_of(i, qubits[k]) << k;
-                const double re = X[us][0][o], im = X[us][1][o];
+                const double re = X[us][0][sw(o)], im = X[us][1][sw(o)];
                 const double rr = re * re;
                 const double ii = im * im;
                 const double pv = rr + ii;
@@ -1198,7 +1348,7 @@ __device__ void load_range(const PassArgs &a, const double *amp, uint64_t first,
     const int cnt = 1 << S;
     if (amp) {
         for (int o = lane; o < cnt; o += 64)
-            dst[o] = amp[2 * (first + o) + p];
+            dst[sw(o)] = amp[2 * (first + o) + p];
         return;
     }
     const int s = a.geo.s;
@@ -1216,7 +1366,7 @@ __global__ __launch_bounds__(kWG) void k_inner(PassArgs A, PassArgs B,
                                                const double *ampB, int S,
                                                uint64_t nranges, double *part)
 {
-    __shared__ Planes X;
+    __shared__ __attribute__((aligned(16))) Planes X;
     __shared__ double lds[kWG];
     const int wave = threadIdx.x >> 6;
     const double sa = ampA ? 1.0 : A.dev->scale;
@@ -1232,8 +1382,9 @@ __global__ __launch_bounds__(kWG) void k_inner(PassArgs A, PassArgs B,
         for (int c = 0; c < 4; ++c) {
             const double v = wg_tree(
                 [&](uint64_t o) {
-                    const double ar = X[0][0][o], ai = X[0][1][o];
-                    const double br = X[1][0][o], bi = X[1][1][o];
+                    const uint32_t so = sw((uint32_t)o);
+                    const double ar = X[0][0][so], ai = X[0][1][so];
+                    const double br = X[1][0][so], bi = X[1][1][so];
                     if (c == 0) {
                         const double p1 = ar * br, p2 = ai * bi;
                         return p1 + p2;
@@ -1318,8 +1469,17 @@ __global__ __launch_bounds__(kWG) void k_export(PassArgs a, uint64_t j, uint8_t 
         offs[q] = run;
         run += sz;
     }
-    if (t < 4)
+    if (t < 3)
         ((uint64_t *)out)[t] = ((const uint64_t *)(a.din.hdr + 32 * j))[t];
+    {
+        // header normsq: pairwise over the block's segment sums
+        const uint64_t spb = 1ull << (a.geo.b - s);
+        const double *src = a.din.segnorm + j * spb;
+        __shared__ double lds[kWG];
+        const double ns = wg_tree([&](uint64_t i) { return src[i]; }, spb, lds);
+        if (t == 0)
+            *(double *)(out + 24) = ns;
+    }
     __syncthreads();
     // copy records: wave w takes planes w, w+4, ...
     const int wave = t >> 6, lane = lane_id();
@@ -1336,7 +1496,7 @@ __global__ __launch_bounds__(kWG) void k_export(PassArgs a, uint64_t j, uint8_t 
 // ------------------------------------------------------- launchers --------
 
 const char *const kKernelNames[kNumKernelIds] = {
-    "pass", "decide", "esc_size", "esc_decide", "replay", "block_norm", "reduce",
+    "pass", "decide", "esc_size", "esc_decide", "fix", "block_norm", "reduce",
     "mean", "mean_tree", "mean_final", "init_state", "sv_pair", "sv_diag",
     "sv_partial", "sv_final"};
 
@@ -1390,27 +1550,26 @@ void launch_mean(const PassArgs &a, hipStream_t st, Prof *prof)
                              ldexp(1.0, 1 - a.geo.n)));
 }
 
-void launch_pass(const PassArgs &a, hipStream_t st, Prof *prof)
+void launch_pass(const PassArgs &a0, hipStream_t st, Prof *prof)
 {
-    const unsigned gu = grid_for(a.geo.nunits), gb = grid_for(a.geo.nblocks);
-    const unsigned gside = grid_for(a.geo.nunits < 2048 ? a.geo.nunits : 2048);
-    const unsigned gdec = grid_for(a.geo.nblocks < 1024 ? a.geo.nblocks : 1024);
-    const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
-    TIMED(prof, kIdPass, st,
-          hipLaunchKernelGGL(k_pass<kFused>, dim3(gu), dim3(kWG), 0, st, a));
-    TIMED(prof, kIdDecide, st,
-          hipLaunchKernelGGL(k_decide<false>, dim3(gb), dim3(kWG), 0, st, a));
-    if (a.lad.L > 1) {
-        TIMED(prof, kIdEscSize, st,
-              hipLaunchKernelGGL(k_pass<kEsc>, dim3(gside), dim3(kWG), 0, st, a));
-        TIMED(prof, kIdEscDecide, st,
-              hipLaunchKernelGGL(k_decide<true>, dim3(gdec), dim3(kWG), 0, st, a));
-        TIMED(prof, kIdReplay, st,
-              hipLaunchKernelGGL(k_pass<kReplay>, dim3(gside), dim3(kWG), 0, st, a));
-    }
-    TIMED(prof, kIdBlockNorm, st,
-          hipLaunchKernelGGL(k_segtree, dim3(gb), dim3(kWG), 0, st, a,
-                             (const double *)a.segnorm, a.blknorm, spb, a.geo.nblocks, 1));
+    const uint64_t kMaxGrid = 2048;
+    const unsigned gu = grid_for(a0.geo.nunits < kMaxGrid ? a0.geo.nunits : kMaxGrid);
+    const unsigned gb = grid_for(a0.geo.nblocks);
+    const unsigned gfix = gu;
+    PassArgs a = a0;
+    uint64_t chunk = a.arena_cap / (8ull * gu);
+    chunk = chunk > 32768 ? 32768 : chunk;
+    chunk &= ~255ull;
+    a.chunk_bytes = chunk < 256 ? 256 : chunk;
+    TIMED(prof, kIdPass, st, hipLaunchKernelGGL(k_pass, dim3(gu), dim3(kWG), 0, st, a));
+    TIMED(prof, kIdDecide, st, hipLaunchKernelGGL(k_decide, dim3(gb), dim3(kWG), 0, st, a));
+    if (a.lad.L > 1)
+        TIMED(prof, kIdReplay, st, hipLaunchKernelGGL(k_fix, dim3(gfix), dim3(kWG), 0, st, a));
+    if (a.geo.nseg > kReduceDirect)
+        TIMED(prof, kIdBlockNorm, st,
+              hipLaunchKernelGGL(k_segtree, dim3(gb), dim3(kWG), 0, st, a,
+                                 (const double *)a.dout.segnorm, a.blknorm,
+                                 1ull << (a.geo.b - a.geo.s), a.geo.nblocks, 0));
     TIMED(prof, kIdReduce, st, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, a));
 }
 

@@ -57,6 +57,7 @@ struct EventProf final : Prof {
     std::vector<hipEvent_t> pool;
     hipEvent_t pending = nullptr;
     int pending_id = -1;
+    bool only_pass = false;  // time the fused pass kernel only
 
     hipEvent_t get()
     {
@@ -66,12 +67,15 @@ struct EventProf final : Prof {
             return e;
         }
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess)
+        // no system-scope fence on record: the events only time kernels
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
             return nullptr;
         return e;
     }
     void begin(int id, hipStream_t st) override
     {
+        if (only_pass && id != kIdPass)
+            return;
         pending = get();
         pending_id = id;
         if (pending)
@@ -79,6 +83,8 @@ struct EventProf final : Prof {
     }
     void end(int id, hipStream_t st) override
     {
+        if (only_pass && id != kIdPass)
+            return;
         hipEvent_t e = get();
         if (!e || !pending || id != pending_id)
             return;
@@ -114,10 +120,11 @@ struct sim {
     uint32_t *psz = nullptr;
     int psz_levels = 0;
     uint32_t *replay_list = nullptr, *esc_list = nullptr;
-    double *segnorm = nullptr, *blknorm = nullptr, *segsum = nullptr, *blksum = nullptr;
+    double *blknorm = nullptr, *segsum = nullptr, *blksum = nullptr;
     DevState *dev = nullptr;
     int cur = 0;
     uint64_t passes = 0;
+    bool valid = false;  // the current descriptor set holds a complete state
     // uncompressed path
     double *amp = nullptr;
     double *sv_scratch = nullptr;
@@ -283,7 +290,6 @@ PassArgs make_args(const sim *S, int in, int out, const GateArg &g)
     a.psz = S->psz;
     a.replay_list = S->replay_list;
     a.esc_list = S->esc_list;
-    a.segnorm = S->segnorm;
     a.blknorm = S->blknorm;
     a.segsum = S->segsum;
     a.blksum = S->blksum;
@@ -309,12 +315,29 @@ int sync_check(sim *S)
     if (d.err) {
         const uint64_t pe = d.err_pass;
         const uint32_t bits = d.err;
+        if (pe == kBasisPass) {
+            // the basis encode itself failed: there is no state to keep
+            S->valid = false;
+            S->passes = 0;
+            S->cur = 0;
+            d.err = 0;
+            d.err_pass = 0;
+            d.passes = 0;
+            d.arena_used[0] = d.arena_used[1] = 0;
+            d.n_replay = d.n_esc = 0;
+            HIPCHK(hipMemcpy(S->dev, &d, sizeof d, hipMemcpyHostToDevice));
+            return fail(bits & kErrSize ? SIM_EDEVICE : SIM_ENOMEM,
+                        "the basis state did not fit the %llu-byte arena; the sim holds "
+                        "no state until sim_set_basis succeeds",
+                        (unsigned long long)S->arena_cap);
+        }
         S->passes = pe;
         S->cur = (int)(pe & 1);
         d.err = 0;
         d.err_pass = 0;
         d.passes = pe;
         d.arena_used[1 - S->cur] = 0;
+        d.n_replay = d.n_esc = 0;
         HIPCHK(hipMemcpy(S->dev, &d, sizeof d, hipMemcpyHostToDevice));
         if (bits & kErrSize)
             return fail(SIM_EDEVICE, "internal size mismatch at pass %llu",
@@ -327,6 +350,18 @@ int sync_check(sim *S)
     if (d.collapsed)
         return fail(SIM_ECOLLAPSED, "N^2 of the stored state was 0 or not finite");
     return SIM_OK;
+}
+
+// Synchronise and require a complete state (for calls that read it).
+int sync_state(sim *S)
+{
+    int rc = sync_check(S);
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    if (S->compressed && !S->valid)
+        return fail(SIM_EINVAL, "the sim holds no state (a basis encode failed); call "
+                    "sim_set_basis");
+    return rc;
 }
 
 int run_basis(sim *S, uint64_t x)
@@ -345,11 +380,12 @@ int run_basis(sim *S, uint64_t x)
     PassArgs a = make_args(S, 1, 0, none);
     a.src_basis = 1;
     a.basis = x;
-    a.pass = 0;
+    a.pass = kBasisPass;
     launch_encode_basis(a, S->stream, S->prof);
     HIPCHK(hipGetLastError());
     S->cur = 0;
     S->passes = 0;
+    S->valid = true;  // until a synchronising call reports otherwise
     return SIM_OK;
 }
 
@@ -435,15 +471,16 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
                 rc = dmalloc(S, (void **)&S->desc[k].blk_level, nb);
             if (!rc)
                 rc = dmalloc(S, (void **)&S->desc[k].plane_off, 8 * 2 * ns);
+            if (!rc)
+                rc = dmalloc(S, (void **)&S->desc[k].segnorm, 8 * ns);
         }
         if (!rc)
             rc = dmalloc(S, (void **)&S->replay_list, 4 * nb);
         if (!rc)
             rc = dmalloc(S, (void **)&S->esc_list, 4 * nb);
+
         if (!rc)
             rc = ensure_psz(S, S->lad.L);
-        if (!rc)
-            rc = dmalloc(S, (void **)&S->segnorm, 8 * ns);
         if (!rc)
             rc = dmalloc(S, (void **)&S->blknorm, 8 * nb);
         if (!rc)
@@ -455,11 +492,8 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
     }
     if (!rc)
         rc = run_basis(S, 0);
-    if (!rc) {
-        hipError_t e = hipStreamSynchronize(S->stream);
-        if (e != hipSuccess)
-            rc = fail(SIM_EDEVICE, "initial encode: %s", hipGetErrorString(e));
-    }
+    if (!rc)
+        rc = sync_state(S);  // the initial encode must fit the arena
     if (rc) {
         std::string keep = g_err;
         free_all(S);
@@ -513,6 +547,9 @@ int sim_apply_gate(sim_t *S, const sim_gate_t *gate)
         S->passes++;
         return SIM_OK;
     }
+    if (!S->valid)
+        return fail(SIM_EINVAL, "the sim holds no state (a basis encode failed); call "
+                    "sim_set_basis");
     const int in = S->cur, out = 1 - S->cur;
     PassArgs a = make_args(S, in, out, g);
     if (g.kind == kDiffuse)
@@ -597,7 +634,7 @@ int sim_get_amplitudes(sim_t *S, uint64_t first, uint64_t count, double *out)
         HIPCHK(hipStreamSynchronize(S->stream));
         return SIM_OK;
     }
-    int rc = sync_check(S);
+    int rc = sync_state(S);
     if (rc && rc != SIM_ECOLLAPSED)
         return rc;
     const uint64_t step = 1ull << 24;
@@ -629,11 +666,14 @@ int sim_export_block(sim_t *S, uint64_t j, void *buf, size_t cap, size_t *len)
         return fail(SIM_EUNSUPPORTED, "the uncompressed path has no block streams");
     if (j >= S->geo.nblocks)
         return fail(SIM_EINVAL, "block index out of range");
-    int rc = sync_check(S);
+    int rc = sync_state(S);
     if (rc && rc != SIM_ECOLLAPSED)
         return rc;
     uint32_t l = 0;
     HIPCHK(hipMemcpy(&l, S->desc[S->cur].blk_len + j, 4, hipMemcpyDeviceToHost));
+    if (l < 32 || l > S->arena_cap)
+        return fail(SIM_EDEVICE, "block %llu has an implausible stream length %u",
+                    (unsigned long long)j, l);
     *len = l;
     if (cap < l || !buf)
         return fail(SIM_ENOMEM, "buffer of %zu bytes too small for %u", cap, l);
@@ -731,7 +771,7 @@ int sim_measure_probs(sim_t *S, const int *qubits, int nq, double *probs)
             if (qubits[m] == qubits[k])
                 return fail(SIM_EINVAL, "qubit %d listed twice", qubits[k]);
     }
-    int rc = S->compressed ? sync_check(S) : SIM_OK;
+    int rc = S->compressed ? sync_state(S) : SIM_OK;
     if (rc && rc != SIM_ECOLLAPSED)
         return rc;
     int *dq = nullptr;
@@ -770,10 +810,10 @@ int sim_fidelity(sim_t *A, sim_t *B, double *F)
         return fail(SIM_EINVAL, "NULL argument");
     if (A->n != B->n)
         return fail(SIM_EINVAL, "qubit counts differ (%d vs %d)", A->n, B->n);
-    int ra = A->compressed ? sync_check(A) : SIM_OK;
+    int ra = A->compressed ? sync_state(A) : SIM_OK;
     if (ra && ra != SIM_ECOLLAPSED)
         return ra;
-    int rb = B->compressed ? sync_check(B) : SIM_OK;
+    int rb = B->compressed ? sync_state(B) : SIM_OK;
     if (rb && rb != SIM_ECOLLAPSED)
         return rb;
     HIPCHK(hipStreamSynchronize(A->stream));
@@ -827,10 +867,14 @@ int sim_profile(sim_t *S, int on)
     if (!S)
         return fail(SIM_EINVAL, "sim is NULL");
     HIPCHK(hipStreamSynchronize(S->stream));
+    if (on < 0 || on > 2)
+        return fail(SIM_EINVAL, "profile mode %d", on);
     if (on && !S->prof)
         S->prof = new (std::nothrow) EventProf();
     if (on && !S->prof)
         return fail(SIM_ENOMEM, "profiler allocation failed");
+    if (on)
+        S->prof->only_pass = (on == 2);
     if (!on) {
         delete S->prof;
         S->prof = nullptr;

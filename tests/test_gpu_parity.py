@@ -271,6 +271,17 @@ def test_arena_overflow_rolls_back(A):
     assert_streams_equal(g, o, 1 << (n - b), "after rollback")
 
 
+def test_arena_too_small_for_the_basis_state(A):
+    say("arena too small for the basis state")
+    # 16 blocks of 2^8: the zero planes alone need 16 * 2 * 16 bytes
+    with pytest.raises(A.SimError) as e:
+        A.Sim(12, 8, 1e-4, arena_bytes=256)
+    assert "arena" in str(e.value)
+    g = A.Sim(12, 8, 1e-4)
+    g.set_basis(7)
+    assert abs(g.amplitudes(7, 1)[0] - 1.0) == 0.0
+
+
 def test_qft24_sampled_parity_and_fidelity(A):
     """The 24-qubit QFT workload (256 blocks of 2^16): every 24th gate the
     inputs of sampled groups are exported and the oracle recomputes those
