@@ -56,10 +56,11 @@ def measured_traffic(kernel, launches_bytes):
 
 
 def cpu_baseline(A, orc, inputs, w, eb, budget_s):
-    """The CPU oracle on a block sample of the same workload: at each gate
-    (until the budget is spent) one random block group is exported from the
-    GPU state, recomputed by the oracle, and its time scaled by the number of
-    groups of that gate."""
+    """The CPU oracle on a block sample of the same workload: at every gate
+    random block groups are exported from the GPU state and recomputed by the
+    oracle until that gate's share of the budget is spent (at least one
+    group); the mean time per group, times the number of groups of the gate,
+    estimates the oracle's time for the whole gate."""
     import numpy as np
     n, b = w["n"], w["b"]
     s = min(b, 10)
@@ -68,41 +69,46 @@ def cpu_baseline(A, orc, inputs, w, eb, budget_s):
     sim = A.Sim(n, b, eb)
     sim.set_basis(w["basis"])
     rng = np.random.default_rng(5)
+    per_gate = budget_s / len(w["gates"])
     spent = 0.0
     est = 0.0
-    sampled = 0
+    groups = 0
     for gate in w["gates"]:
-        if spent < budget_s:
-            kind = gate[0]
-            mask = 0
-            if kind in (inputs.G_U, inputs.G_X):
-                mask = 1 << gate[1]
-            elif kind == inputs.G_CU:
-                mask = 1 << gate[2]
-            elif kind == inputs.G_SWAP:
-                mask = (1 << gate[1]) | (1 << gate[2])
-            mb = mask >> b
+        kind = gate[0]
+        mask = 0
+        if kind in (inputs.G_U, inputs.G_X):
+            mask = 1 << gate[1]
+        elif kind == inputs.G_CU:
+            mask = 1 << gate[2]
+        elif kind == inputs.G_SWAP:
+            mask = (1 << gate[1]) | (1 << gate[2])
+        mb = mask >> b
+        ngroups = nb // 2 if mb else nb
+        sc = sim.stats()["scale"]
+        g_spent = 0.0
+        g_count = 0
+        while g_count == 0 or g_spent < per_gate:
             j = int(rng.integers(0, nb))
             j = min(j, j ^ mb) if mb else j
             in0 = sim.export_block(j)
             in1 = sim.export_block(j ^ mb) if mb else None
-            sc = sim.stats()["scale"]
             t0 = time.perf_counter()
             orc.process_group(n, b, s, lad, 4.0, sc, None, gate, j, in0, in1)
-            dt = time.perf_counter() - t0
-            spent += dt
-            est += dt * (nb // 2 if mb else nb)
-            sampled += 1
+            g_spent += time.perf_counter() - t0
+            g_count += 1
+        spent += g_spent
+        est += g_spent / g_count * ngroups
+        groups += g_count
         sim.apply(gate)
     sim.close()
     return {
-        "value": sampled / est,
+        "value": len(w["gates"]) / est,
         "unit": "gates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": ("%d of %d QFT-24 gates, one random block group each (oracle "
-                   "time %.1f s), scaled by the groups per gate" %
-                   (sampled, len(w["gates"]), spent)),
+        "sample": ("all %d QFT-24 gates, %d random block groups in total "
+                   "(oracle time %.1f s, single thread), each gate's mean group "
+                   "time scaled by its groups" % (len(w["gates"]), groups, spent)),
         "host_cpus": os.cpu_count(),
     }
 
