@@ -1,17 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the compressed per-gate loop on one MI355X.
 
-Workload: the 24-qubit QFT (312 native gates: H, controlled phase, SWAP) on a
-seeded basis state, complex128 state of 2^24 amplitudes held as 256
-compressed blocks of 2^16, default AALC ladder (0, eb/1000, eb/100, eb/10,
-eb) with eb = 1e-4 and ratio threshold 4.  One step = encode the basis state
-+ apply the 312 gates (every gate is one decompress-normalise-gate-compress
-pass over all blocks).  The state is resident in HBM before timing starts.
+Default workload (qft24): the 24-qubit QFT (312 native gates: H, controlled
+phase, SWAP) on a seeded basis state, complex128 state of 2^24 amplitudes
+held as 256 compressed blocks of 2^16, default AALC ladder (0, eb/1000,
+eb/100, eb/10, eb) with eb = 1e-4 and ratio threshold 4.  One step = encode
+the basis state + apply the 312 gates (every gate is one decompress-
+normalise-gate-compress pass over all blocks).
 
-Prints one JSON line: gates/s (value), amplitude-GB/s and its fraction of
-the 8 TB/s HBM peak, the dominant kernel's roofline entry (HIP events on the
-sim stream over the timed region), the fidelity against the uncompressed
-FP64 run of the same circuit, and the CPU oracle timed on a block sample.
+--workload grover36: Grover search on 36 qubits (2^36 amplitudes, 1 TiB as
+complex128, more than the 288 GB of HBM), 65536 blocks of 2^20, eb = 1e-5:
+H on every qubit, then 8 x (phase flip of a seeded index, diffusion).  One
+step = encode |0> + the 52 gates (each diffusion adds a read-only mean pass).
+
+The state is resident in HBM before timing starts.  Prints one JSON line:
+gates/s (value), amplitude-GB/s and its fraction of the 8 TB/s HBM peak, the
+dominant kernel's roofline entry (HIP events on the sim stream over the timed
+region), the fidelity (against the uncompressed FP64 run of the same circuit
+for qft24, against the closed-form Grover state for grover36), and the CPU
+oracle timed on a block sample.
 """
 import argparse
 import hashlib
@@ -39,10 +46,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, launches_bytes):
-    """HBM bytes per launch from the committed PMC summary, if it was taken
-    on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic_qft24.json")
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed PMC summary of this workload,
+    if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
     try:
@@ -55,7 +62,7 @@ def measured_traffic(kernel, launches_bytes):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(A, orc, inputs, w, eb, budget_s):
+def cpu_baseline(A, orc, inputs, w, eb, budget_s, name):
     """The CPU oracle on a block sample of the same workload: at every gate
     random block groups are exported from the GPU state and recomputed by the
     oracle until that gate's share of the budget is spent (at least one
@@ -69,6 +76,7 @@ def cpu_baseline(A, orc, inputs, w, eb, budget_s):
     sim = A.Sim(n, b, eb)
     sim.set_basis(w["basis"])
     rng = np.random.default_rng(5)
+    n_diffuse = 0
     per_gate = budget_s / len(w["gates"])
     spent = 0.0
     est = 0.0
@@ -85,6 +93,11 @@ def cpu_baseline(A, orc, inputs, w, eb, budget_s):
         mb = mask >> b
         ngroups = nb // 2 if mb else nb
         sc = sim.stats()["scale"]
+        tdiff = None
+        if kind == inputs.G_DIFFUSE:
+            S = sim.amplitude_sum()
+            tdiff = (S.real * 2.0 ** (1 - n), S.imag * 2.0 ** (1 - n))
+            n_diffuse += 1
         g_spent = 0.0
         g_count = 0
         while g_count == 0 or g_spent < per_gate:
@@ -93,7 +106,7 @@ def cpu_baseline(A, orc, inputs, w, eb, budget_s):
             in0 = sim.export_block(j)
             in1 = sim.export_block(j ^ mb) if mb else None
             t0 = time.perf_counter()
-            orc.process_group(n, b, s, lad, 4.0, sc, None, gate, j, in0, in1)
+            orc.process_group(n, b, s, lad, 4.0, sc, tdiff, gate, j, in0, in1)
             g_spent += time.perf_counter() - t0
             g_count += 1
         spent += g_spent
@@ -106,9 +119,12 @@ def cpu_baseline(A, orc, inputs, w, eb, budget_s):
         "unit": "gates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": ("all %d QFT-24 gates, %d random block groups in total "
+        "sample": ("all %d %s gates, %d random block groups in total "
                    "(oracle time %.1f s, single thread), each gate's mean group "
-                   "time scaled by its groups" % (len(w["gates"]), groups, spent)),
+                   "time scaled by its groups%s" %
+                   (len(w["gates"]), name, groups, spent,
+                    "; the oracle's whole-state mean pass of each of the %d "
+                    "diffusions is not included" % n_diffuse if n_diffuse else "")),
         "host_cpus": os.cpu_count(),
     }
 
@@ -125,12 +141,30 @@ def calibrate_copy(torch, nbytes, reps):
     print(json.dumps({"calibration_copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def grover_fidelity(sim, n, m, k):
+    """P(m) and F against the closed-form Grover state after k iterations:
+    sin((2k+1)t) on m and cos((2k+1)t)/sqrt(2^n - 1) elsewhere, sin t =
+    2^(-n/2).  The overlap needs only the amplitude sum and a_m."""
+    th = math.asin(2.0 ** (-n / 2.0))
+    alpha = math.sin((2 * k + 1) * th)
+    beta = math.cos((2 * k + 1) * th) / math.sqrt(float((1 << n) - 1))
+    am = complex(sim.amplitudes(m, 1)[0])
+    S = sim.amplitude_sum()
+    st = sim.stats()
+    F = abs(beta * S + (alpha - beta) * am) ** 2 / (st["normsq"] * st["scale"] ** 2)
+    return abs(am) ** 2, alpha ** 2, F
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--error-bound", type=float, default=1e-4)
+    ap.add_argument("--workload", choices=("qft24", "grover36"), default="qft24")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 5 for qft24, 1 for grover36)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps (default 1 for qft24, 0 for grover36)")
+    ap.add_argument("--error-bound", type=float, default=None,
+                    help="default 1e-4 for qft24, 1e-5 for grover36")
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle time for the CPU baseline (0: skip)")
     ap.add_argument("--no-profile", action="store_true",
@@ -138,6 +172,12 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a device copy of this many bytes (counters)")
     args = ap.parse_args()
+    grover = args.workload == "grover36"
+    if args.steps is None:
+        args.steps = 1 if grover else 5
+    if args.warmup is None:
+        args.warmup = 0 if grover else 1
+    eb = args.error_bound if args.error_bound is not None else (1e-5 if grover else 1e-4)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -155,9 +195,8 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    w = inputs.qft24_workload()
+    w = inputs.grover36_workload() if grover else inputs.qft24_workload()
     n, b, x, gates = w["n"], w["b"], w["basis"], w["gates"]
-    eb = args.error_bound
     sim = A.Sim(n, b, eb, stream=stream)
 
     def step():
@@ -182,7 +221,7 @@ def main():
     elapsed = t1 - t0
     # per-kernel split of one more step (all kernels timed), for the record
     split = {}
-    if not args.no_profile:
+    if not args.no_profile and not grover:
         sim.profile(True)
         sim.profile_read()
         step()
@@ -193,12 +232,20 @@ def main():
     amp_gbs = gates_per_s * LOGICAL_BYTES_PER_AMP * (1 << n) / 1e9
     st = sim.stats()
 
-    # fidelity against the uncompressed FP64 run of the same circuit
-    ref = A.Sim(n, b, -1.0, stream=stream)
-    ref.set_basis(x)
-    ref.run(gates)
-    F = sim.fidelity(ref)
-    ref.close()
+    extra = {}
+    if grover:
+        k = sum(1 for g in gates if g[0] == inputs.G_DIFFUSE)
+        P, P_closed, F = grover_fidelity(sim, n, w["marked"], k)
+        extra = {"p_marked": P, "p_marked_closed_form": P_closed,
+                 "fidelity_reference": "closed-form Grover state"}
+    else:
+        # fidelity against the uncompressed FP64 run of the same circuit
+        ref = A.Sim(n, b, -1.0, stream=stream)
+        ref.set_basis(x)
+        ref.run(gates)
+        F = sim.fidelity(ref)
+        ref.close()
+        extra = {"fidelity_reference": "uncompressed FP64 GPU run"}
 
     roofline = None
     if prof:
@@ -210,7 +257,7 @@ def main():
             "bound": "hbm", "kernel": name,
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(name, alg_bytes),
+            "traffic": measured_traffic(args.workload, name),
             "avg_launch_ms": round(tot / cnt, 4), "launches": cnt,
             "algorithmic_bytes_per_launch": alg_bytes,
             "kernels_ms_one_step": split,
@@ -219,8 +266,19 @@ def main():
     cpu = None
     if args.cpu_budget > 0:
         from oracle import oracle as orc
-        cpu = cpu_baseline(A, orc, inputs, w, eb, args.cpu_budget)
+        cpu = cpu_baseline(A, orc, inputs, w, eb, args.cpu_budget,
+                           "Grover-36" if grover else "QFT-24")
 
+    config = {
+        "workload": args.workload, "n_qubits": n, "block_log2": b,
+        "segment_log2": min(b, 10), "error_bound": eb,
+        "ladder": inputs.default_ladder(eb), "theta": 4.0,
+        "gates_per_step": len(gates),
+    }
+    if grover:
+        config.update({"marked": w["marked"], "iterations": k})
+    else:
+        config["basis"] = x
     out = {
         "metric": METRIC,
         "value": round(gates_per_s, 2),
@@ -234,12 +292,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded basis state, generated circuit)",
-        "config": {
-            "workload": "qft24", "n_qubits": n, "block_log2": b,
-            "segment_log2": min(b, 10), "error_bound": eb,
-            "ladder": inputs.default_ladder(eb), "theta": 4.0,
-            "gates_per_step": len(gates), "basis": x,
-        },
+        "config": config,
         "amplitude_gbs": round(amp_gbs, 1),
         "hbm_frac": round(amp_gbs / HBM_PEAK_GBS, 4),
         "fidelity": F,
@@ -247,10 +300,12 @@ def main():
         "min_ratio": st["min_ratio"],
         "last_ratio": st["last_ratio"],
         "peak_resident_bytes": st["peak_resident"],
+        "logical_state_bytes": 16 << n,
         "level_hist": st["level_hist"],
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    out.update(extra)
     sim.close()
     print(json.dumps(out), flush=True)
 

@@ -157,6 +157,19 @@ int sim_get_amplitudes(sim_t *sim, uint64_t first, uint64_t count,
 int sim_export_block(sim_t *sim, uint64_t j, void *buf, size_t cap,
                      size_t *len);
 
+/* Copy the 32-byte stream headers (block stream v1, normsq field filled) of
+ * blocks [first, first+count) to host memory buf (cap >= 32*count bytes).
+ * The N^2 of the state is the pairwise sum of the normsq fields over all
+ * blocks in index order (Sec. III normalisation).  Synchronises. */
+int sim_export_headers(sim_t *sim, uint64_t first, uint64_t count, void *buf,
+                       size_t cap);
+
+/* out[0], out[1] = sums of the real and imaginary parts of the normalised
+ * amplitudes s * xhat over all 2^n indices, as one perfect binary tree in
+ * index order: the sum that the Grover diffusion 2|s><s| - I takes its mean
+ * from (Sec. IV).  out is host memory of 2 doubles.  Synchronises. */
+int sim_amplitude_sum(sim_t *sim, double *out);
+
 /* Statistics of the stored state.  Synchronises. */
 int sim_stats(sim_t *sim, sim_stats_t *st);
 

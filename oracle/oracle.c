@@ -908,8 +908,8 @@ int or_set_basis(or_sim *sim, uint64_t x)
 }
 
 /* S = pairwise over all amplitudes of the normalised decoded values (per
- * component), t = 2 S / 2^n.  Block sums are aligned subtrees. */
-static int diffuse_t_sim(const or_sim *sim, double *t)
+ * component).  Block sums are aligned subtrees. */
+int or_amplitude_sum(const or_sim *sim, double *S)
 {
     size_t namp = (size_t)1 << sim->b;
     double *x = (double *)malloc(2 * namp * sizeof(double));
@@ -932,7 +932,7 @@ static int diffuse_t_sim(const or_sim *sim, double *t)
         }
     }
     for (int c = 0; c < 2; c++)
-        t[c] = or_pairwise(bs[c], sim->nblocks) * ldexp(1.0, 1 - sim->n);
+        S[c] = or_pairwise(bs[c], sim->nblocks);
     rc = OR_OK;
 done:
     free(x);
@@ -951,9 +951,12 @@ int or_apply_gate(or_sim *sim, const or_gate *g)
         return OR_EINVAL;
     double t[2] = {0.0, 0.0};
     if (g->kind == OR_G_DIFFUSE) {
-        int rc = diffuse_t_sim(sim, t);
+        /* (2|s><s| - I): t = 2 * mean = S * 2^(1-n) per component */
+        int rc = or_amplitude_sum(sim, t);
         if (rc)
             return rc;
+        for (int c = 0; c < 2; c++)
+            t[c] = t[c] * ldexp(1.0, 1 - sim->n);
     }
     uint64_t mb = gate_mask(g) >> sim->b;
     uint8_t **ns = (uint8_t **)calloc(sim->nblocks, sizeof(uint8_t *));

@@ -116,6 +116,11 @@ typedef struct {
 } or_stats;
 int or_get_stats(const or_sim *sim, or_stats *st);
 
+/* S[0], S[1] = pairwise sums of the re and im parts of the normalised
+ * amplitudes over the whole state (the sum the Grover diffusion's mean is
+ * taken from). */
+int or_amplitude_sum(const or_sim *sim, double *S);
+
 /* Probability of every outcome of the listed qubits (2^nq doubles). */
 int or_measure_probs(const or_sim *sim, const int *qubits, int nq,
                      double *probs);

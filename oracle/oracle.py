@@ -89,6 +89,7 @@ def lib():
             u8p, ctypes.c_size_t, szp, u8p, ctypes.c_size_t, szp]
         L.or_fidelity.restype = ctypes.c_double
         L.or_fidelity.argtypes = [dp, dp, ctypes.c_int]
+        L.or_amplitude_sum.argtypes = [ctypes.c_void_p, dp]
     return _lib
 
 
@@ -273,6 +274,14 @@ class OracleSim:
                 "min_ratio": st.min_ratio, "last_ratio": st.last_ratio,
                 "passes": st.passes,
                 "level_hist": [int(st.level_hist[k]) for k in range(8)]}
+
+    def amplitude_sum(self):
+        """Pairwise sums (re, im) of the normalised amplitudes."""
+        out = np.zeros(2)
+        rc = lib().or_amplitude_sum(self.h, _dp(out))
+        if rc:
+            raise RuntimeError("or_amplitude_sum failed (%d)" % rc)
+        return complex(out[0], out[1])
 
     def measure_probs(self, qubits):
         q = (ctypes.c_int * len(qubits))(*qubits)

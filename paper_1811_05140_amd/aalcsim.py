@@ -24,6 +24,7 @@ EXPORTS = [
     "sim_set_aalc", "sim_set_normalize", "sim_get_amplitudes",
     "sim_export_block", "sim_stats", "sim_sync", "sim_set_stream",
     "sim_debug_rsqrt", "sim_last_error", "sim_profile", "sim_profile_read",
+    "sim_export_headers", "sim_amplitude_sum",
 ]
 
 
@@ -90,6 +91,9 @@ def _load():
     L.sim_get_amplitudes.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, dp]
     L.sim_export_block.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t,
                                    P(ctypes.c_size_t)]
+    L.sim_export_headers.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, vp,
+                                     ctypes.c_size_t]
+    L.sim_amplitude_sum.argtypes = [vp, dp]
     L.sim_stats.argtypes = [vp, P(Stats)]
     L.sim_sync.argtypes = [vp]
     L.sim_set_stream.argtypes = [vp, vp]
@@ -242,6 +246,20 @@ class Sim:
         buf = ctypes.create_string_buffer(max(ln.value, 1))
         check(lib.sim_export_block(self.h, j, buf, ln.value, ctypes.byref(ln)), True)
         return buf.raw[:ln.value]
+
+    def export_headers(self, first=0, count=None):
+        """32-byte stream headers of blocks [first, first+count), normsq filled."""
+        if count is None:
+            count = (1 << (self.n - self.b)) - first
+        buf = ctypes.create_string_buffer(max(32 * count, 1))
+        check(lib.sim_export_headers(self.h, first, count, buf, 32 * count), True)
+        return buf.raw[:32 * count]
+
+    def amplitude_sum(self):
+        """Pairwise sums (re, im) of the normalised amplitudes over the state."""
+        out = np.zeros(2)
+        check(lib.sim_amplitude_sum(self.h, _dp(out)), True)
+        return complex(out[0], out[1])
 
     def profile(self, on=True, pass_only=False):
         check(lib.sim_profile(self.h, (2 if pass_only else 1) if on else 0))

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace aalc {
@@ -70,7 +71,8 @@ struct DevState {
     uint32_t err_pass;      // pass index of the first error
     int32_t collapsed;
     int32_t normalize;
-    uint8_t pad0[128 - 88];
+    double sum[2];          // amplitude sum query result
+    uint8_t pad0[128 - 104];
     uint64_t arena_used[2]; // bump pointers of the two arenas
     uint64_t arena_peak;    // largest bump pointer reached (incl. replay waste)
     uint8_t pad1[128 - 24];
@@ -80,6 +82,9 @@ struct DevState {
     uint64_t escalations;   // cumulative count of escalated blocks
     uint64_t level_hist[kMaxL];
 };
+
+static_assert(offsetof(DevState, arena_used) == 128 && offsetof(DevState, n_replay) == 256,
+              "DevState counters must start on their own 128-byte lines");
 
 enum : uint32_t { kErrArena = 1u, kErrSize = 2u };
 
@@ -137,7 +142,9 @@ struct Prof {
 
 // Launchers (kernels.hip).
 void launch_init_state(DevState *dev, int normalize, hipStream_t st, Prof *prof);
-void launch_mean(const PassArgs &a, hipStream_t st, Prof *prof);
+// Pairwise sums S (re, im) of the normalised amplitudes; out[c] = fl(S_c * mul)
+// (device pointer).
+void launch_mean(const PassArgs &a, double mul, double *out, hipStream_t st, Prof *prof);
 void launch_pass(const PassArgs &a, hipStream_t st, Prof *prof);
 void launch_encode_basis(const PassArgs &a, hipStream_t st, Prof *prof);
 void launch_decode_range(const PassArgs &a, uint64_t first, uint64_t count,
@@ -150,6 +157,8 @@ void launch_inner(const PassArgs &a, const PassArgs &b, const double *amp_a,
 void launch_rsqrt(const double *in, double *out, uint64_t count,
                   hipStream_t st);
 void launch_export(const PassArgs &a, uint64_t j, uint8_t *out, hipStream_t st);
+void launch_export_headers(const PassArgs &a, uint64_t first, uint64_t count, uint8_t *out,
+                           hipStream_t st);
 
 // Uncompressed path (sv.hip).
 void sv_set_basis(double *amp, int n, uint64_t x, hipStream_t st);
@@ -159,5 +168,6 @@ void sv_probs(const double *amp, int n, const int *qubits_dev, int nq,
               double *probs_dev, hipStream_t st);
 void sv_normsq(const double *amp, int n, double *scratch, double *out_dev,
                hipStream_t st);
+void sv_sum(const double *amp, int n, double *scratch, double *out_dev, hipStream_t st);
 
 }  // namespace aalc

@@ -1084,7 +1084,9 @@ __global__ __launch_bounds__(kWG) void k_segtree(PassArgs a, const double *src,
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_mean_final(PassArgs a, double pow2)
+// out[c] = fl(S_c * mul), S_c the pairwise sum over all amplitudes of
+// component c (block sums are aligned subtrees of the one tree).
+__global__ __launch_bounds__(kWG) void k_mean_final(PassArgs a, double mul, double *out)
 {
     if (a.dev->err)
         return;
@@ -1093,7 +1095,7 @@ __global__ __launch_bounds__(kWG) void k_mean_final(PassArgs a, double pow2)
         const double *p = a.blksum + (uint64_t)c * a.geo.nblocks;
         const double S = wg_tree([&](uint64_t i) { return p[i]; }, a.geo.nblocks, lds);
         if (threadIdx.x == 0)
-            a.dev->tdiff[c] = S * pow2;
+            out[c] = S * mul;
     }
 }
 
@@ -1493,6 +1495,25 @@ __global__ __launch_bounds__(kWG) void k_export(PassArgs a, uint64_t j, uint8_t 
     }
 }
 
+// Stream headers of blocks [first, first + count) into out[count][32], each
+// with its normsq field (pairwise over the block's segment sums).
+__global__ __launch_bounds__(kWG) void k_export_headers(PassArgs a, uint64_t first,
+                                                        uint64_t count, uint8_t *out)
+{
+    __shared__ double lds[kWG];
+    const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
+    for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
+        const uint64_t j = first + k;
+        const double *src = a.din.segnorm + j * spb;
+        const double ns = wg_tree([&](uint64_t i) { return src[i]; }, spb, lds);
+        if (threadIdx.x < 3)
+            ((uint64_t *)(out + 32 * k))[threadIdx.x] =
+                ((const uint64_t *)(a.din.hdr + 32 * j))[threadIdx.x];
+        if (threadIdx.x == 0)
+            *(double *)(out + 32 * k + 24) = ns;
+    }
+}
+
 // ------------------------------------------------------- launchers --------
 
 const char *const kKernelNames[kNumKernelIds] = {
@@ -1532,7 +1553,7 @@ void launch_init_state(DevState *dev, int normalize, hipStream_t st, Prof *prof)
           hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, st, dev, normalize));
 }
 
-void launch_mean(const PassArgs &a, hipStream_t st, Prof *prof)
+void launch_mean(const PassArgs &a, double mul, double *out, hipStream_t st, Prof *prof)
 {
     PassArgs m = a;
     TIMED(prof, kIdMean, st,
@@ -1546,8 +1567,7 @@ void launch_mean(const PassArgs &a, hipStream_t st, Prof *prof)
                                  a.blksum + (uint64_t)c * a.geo.nblocks, spb,
                                  a.geo.nblocks, 0));
     TIMED(prof, kIdMeanFinal, st,
-          hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(kWG), 0, st, m,
-                             ldexp(1.0, 1 - a.geo.n)));
+          hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(kWG), 0, st, m, mul, out));
 }
 
 void launch_pass(const PassArgs &a0, hipStream_t st, Prof *prof)
@@ -1624,6 +1644,13 @@ void launch_rsqrt(const double *in, double *out, uint64_t count, hipStream_t st)
 void launch_export(const PassArgs &a, uint64_t j, uint8_t *out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_export, dim3(1), dim3(kWG), 0, st, a, j, out);
+}
+
+void launch_export_headers(const PassArgs &a, uint64_t first, uint64_t count, uint8_t *out,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_export_headers, dim3(grid_for(count)), dim3(kWG), 0, st, a, first,
+                       count, out);
 }
 
 }  // namespace aalc

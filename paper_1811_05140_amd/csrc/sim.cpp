@@ -553,7 +553,7 @@ int sim_apply_gate(sim_t *S, const sim_gate_t *gate)
     const int in = S->cur, out = 1 - S->cur;
     PassArgs a = make_args(S, in, out, g);
     if (g.kind == kDiffuse)
-        launch_mean(a, S->stream, S->prof);
+        launch_mean(a, ldexp(1.0, 1 - S->n), &S->dev->tdiff[0], S->stream, S->prof);
     launch_pass(a, S->stream, S->prof);
     HIPCHK(hipGetLastError());
     S->cur = out;
@@ -688,6 +688,58 @@ int sim_export_block(sim_t *S, uint64_t j, void *buf, size_t cap, size_t *len)
     (void)hipFree(stage);
     if (e != hipSuccess)
         return fail(SIM_EDEVICE, "export: %s", hipGetErrorString(e));
+    return rc;
+}
+
+int sim_amplitude_sum(sim_t *S, double *out)
+{
+    if (!S || !out)
+        return fail(SIM_EINVAL, "NULL argument");
+    if (!S->compressed) {
+        sv_sum(S->amp, S->n, S->sv_scratch, S->sv_tdiff + 2, S->stream);
+        HIPCHK(hipMemcpyAsync(out, S->sv_tdiff + 2, 16, hipMemcpyDeviceToHost, S->stream));
+        HIPCHK(hipStreamSynchronize(S->stream));
+        return SIM_OK;
+    }
+    int rc = sync_state(S);
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    PassArgs a = make_args(S, S->cur, 1 - S->cur, GateArg{});
+    launch_mean(a, 1.0, &S->dev->sum[0], S->stream, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, &S->dev->sum[0], 16, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(hipStreamSynchronize(S->stream));
+    return rc;
+}
+
+int sim_export_headers(sim_t *S, uint64_t first, uint64_t count, void *buf, size_t cap)
+{
+    if (!S || (!buf && count))
+        return fail(SIM_EINVAL, "NULL argument");
+    if (!S->compressed)
+        return fail(SIM_EUNSUPPORTED, "the uncompressed path has no block streams");
+    if (first > S->geo.nblocks || count > S->geo.nblocks - first)
+        return fail(SIM_EINVAL, "block range out of bounds");
+    if (cap < 32 * count)
+        return fail(SIM_ENOMEM, "buffer of %zu bytes too small for %llu headers", cap,
+                    (unsigned long long)count);
+    if (count == 0)
+        return SIM_OK;
+    int rc = sync_state(S);
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    uint8_t *stage = nullptr;
+    HIPCHK(hipMalloc((void **)&stage, 32 * count));
+    launch_export_headers(make_args(S, S->cur, 1 - S->cur, GateArg{}), first, count, stage,
+                          S->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(buf, stage, 32 * count, hipMemcpyDeviceToHost, S->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(S->stream);
+    (void)hipFree(stage);
+    if (e != hipSuccess)
+        return fail(SIM_EDEVICE, "export headers: %s", hipGetErrorString(e));
     return rc;
 }
 

@@ -235,4 +235,15 @@ void sv_normsq(const double *amp, int n, double *scratch, double *out_dev, hipSt
                        1, 1.0, out_dev);
 }
 
+// out[0..1] = pairwise sums of the re and im parts over all amplitudes.
+void sv_sum(const double *amp, int n, double *scratch, double *out_dev, hipStream_t st)
+{
+    uint64_t per, nr;
+    ranges_of(n, per, nr);
+    hipLaunchKernelGGL(k_sv_partial, dim3(sv_grid(nr * kSvWG)), dim3(kSvWG), 0, st, amp, per,
+                       nr, 0, scratch);
+    hipLaunchKernelGGL(k_sv_final, dim3(1), dim3(kSvWG), 0, st, (const double *)scratch, nr,
+                       2, 1.0, out_dev);
+}
+
 }  // namespace aalc

@@ -237,6 +237,36 @@ def test_grover_n16_full_parity(A):
     assert abs(p - I.grover_success(n, k)) < 1e-6
 
 
+def test_amplitude_sum_and_headers_match_oracle(A):
+    for name, n, b, lad, x, gates in (
+            ("grover", 16, 12, I.default_ladder(1e-5), 0, I.grover(16, 0xBEEF, 3)),
+            ("qft12", 12, 8, I.default_ladder(1e-4), 0x5A3, I.qft(12)[:50])):
+        say("amplitude sum and headers", name)
+        g = A.Sim(n, b, lad[-1])
+        o = orc.OracleSim(n, b, lad, 4.0)
+        g.set_basis(x)
+        o.set_basis(x)
+        for k, gate in enumerate(gates):
+            g.apply(gate)
+            o.apply(gate)
+            if k % 7 == 0 or k == len(gates) - 1:
+                assert g.amplitude_sum() == o.amplitude_sum(), (name, k)
+                hg = g.export_headers()
+                ho = b"".join(o.export_block(j)[:32] for j in range(1 << (n - b)))
+                assert hg == ho, (name, k)
+                # a sub-range of headers
+                assert g.export_headers(1, 2) == hg[32:96]
+        g.close()
+    say("amplitude sum, uncompressed path")
+    u = A.Sim(12, 8, -1.0)
+    u.set_basis(0x5A3)
+    u.run(I.qft(12)[:50])
+    a = u.amplitudes()
+    S = u.amplitude_sum()
+    assert abs(S.real - math.fsum(a.real)) < 1e-12
+    assert abs(S.imag - math.fsum(a.imag)) < 1e-12
+
+
 def test_invalid_gates_rejected(A):
     say("invalid gates")
     g = A.Sim(8, 6, 1e-4)

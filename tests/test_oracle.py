@@ -461,6 +461,47 @@ def test_process_group_reproduces_driver_pass():
                 assert o1 == sim.export_block(j ^ mb)
 
 
+def test_amplitude_sum_pins():
+    # basis state: one amplitude 1, the rest 0
+    sim = orc.OracleSim(10, 7, I.default_ladder(1e-4), theta=4.0)
+    sim.set_basis(0x155)
+    assert sim.amplitude_sum() == 1.0 + 0.0j
+    # uniform superposition: 2^n equal leaves v sum to 2^n v exactly, so a
+    # dropped or doubled leaf anywhere in the tree shows
+    sim.set_basis(0)
+    sim.run([I.h(q) for q in range(10)])
+    a = sim.amplitudes()
+    assert np.all(a == a[0])
+    assert sim.amplitude_sum() == complex(1024 * a[0].real, 0.0)
+    # QFT of a basis state x: sum_k w^(xk) / 2^(n/2) is 2^(n/2) for x = 0 and
+    # 0 otherwise (geometric series)
+    for x, want in ((0, 32.0), (0x2A5, 0.0)):
+        sim = orc.OracleSim(10, 7, [0.0], theta=4.0)
+        sim.set_basis(x)
+        sim.run(I.qft(10))
+        assert abs(sim.amplitude_sum() - want) < 1e-12
+    # against an exactly rounded sum of the amplitudes (math.fsum), within
+    # the pairwise bound log2(N) * eps * sum |a|
+    sim = orc.OracleSim(11, 8, I.default_ladder(1e-4), theta=4.0)
+    sim.set_basis(0x3C1)
+    sim.run(I.qft(11)[:40])
+    a = sim.amplitudes()
+    S = sim.amplitude_sum()
+    tol = 11 * 2.0 ** -52 * np.abs(a).sum()
+    assert abs(S.real - math.fsum(a.real)) <= tol
+    assert abs(S.imag - math.fsum(a.imag)) <= tol
+    # Grover: before a diffusion the sum is -sin((2i-1)t) + sqrt(N-1) cos((2i-1)t)
+    n, m = 10, 0x2B7
+    sim = orc.OracleSim(n, 8, [0.0], theta=4.0)
+    sim.run([I.h(q) for q in range(n)])
+    th = math.asin(2.0 ** (-n / 2))
+    for i in range(1, 4):
+        sim.apply(I.phase_flip(m))
+        want = -math.sin((2 * i - 1) * th) + math.sqrt((1 << n) - 1) * math.cos((2 * i - 1) * th)
+        assert abs(sim.amplitude_sum() - want) < 1e-12
+        sim.apply(I.diffuse())
+
+
 def test_measure_probs_uniform_after_qft():
     n = 10
     sim = orc.OracleSim(n, 8, [0.0], theta=4.0)
