@@ -205,6 +205,45 @@ int sim_profile_read(sim_t *sim, sim_kernel_time_t *out, int cap, int *count);
  * host arrays of count doubles.  Uses the default device. */
 int sim_debug_rsqrt(const double *in, double *out, size_t count);
 
+/* ---- batches: many states advanced by the same kernels -----------------
+ *
+ * A batch applies one gate to each of several sims per pass with one set of
+ * kernel launches for all of them (the work items of every state share the
+ * grid), and optionally records the passes as a HIP graph that is replayed
+ * whenever the same shape comes again (the per-state arguments live in device
+ * memory and are rewritten before each launch, so the graph's topology stays
+ * fixed).  Every state computes exactly what sim_apply_gate computes for it:
+ * a state's streams are the same alone and in a batch.  Work of the batch is
+ * ordered after the work already queued on each sim's stream, and later work
+ * on those streams after the batch. */
+typedef struct sim_batch sim_batch_t;
+
+/* A batch for up to max_states sims per call and max_passes passes per call
+ * (each 1..4096), on `hip_stream` (NULL = a stream owned by the batch).
+ * Allocates device and pinned host memory for the per-pass arguments.
+ * Returns NULL on failure (sim_last_error()). */
+sim_batch_t *sim_batch_create(int max_states, int max_passes, void *hip_stream);
+
+void sim_batch_destroy(sim_batch_t *batch);
+
+/* Apply passes x count gates: gates[p * count + k] to sims[k] in pass p,
+ * passes in order.  A gate of kind 0 (all fields 0) leaves that sim alone in
+ * that pass.  sims must be distinct compressed sims holding a state.  With
+ * use_graph != 0 the passes are captured once per shape (count, passes,
+ * which passes hold a diffusion, launch grids) and replayed as one graph
+ * launch.  Asynchronous; validation failures (SIM_EINVAL, SIM_EUNSUPPORTED)
+ * queue nothing.  Device-side errors of a sim are reported by that sim's next
+ * synchronising call, as for sim_apply_gate. */
+int sim_batch_apply(sim_batch_t *batch, sim_t *const *sims, int count,
+                    const sim_gate_t *gates, int passes, int use_graph);
+
+/* Wait for all work of the batch. */
+int sim_batch_sync(sim_batch_t *batch);
+
+/* Number of graphs captured and graph launches so far (either may be NULL). */
+int sim_batch_info(sim_batch_t *batch, uint64_t *graph_builds,
+                   uint64_t *graph_launches);
+
 /* Thread-local message of the last failure on this thread ("" if none). */
 const char *sim_last_error(void);
 

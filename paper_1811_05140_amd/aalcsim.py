@@ -25,6 +25,8 @@ EXPORTS = [
     "sim_export_block", "sim_stats", "sim_sync", "sim_set_stream",
     "sim_debug_rsqrt", "sim_last_error", "sim_profile", "sim_profile_read",
     "sim_export_headers", "sim_amplitude_sum",
+    "sim_batch_create", "sim_batch_destroy", "sim_batch_apply", "sim_batch_sync",
+    "sim_batch_info",
 ]
 
 
@@ -101,6 +103,14 @@ def _load():
     L.sim_profile.argtypes = [vp, ctypes.c_int]
     L.sim_profile_read.argtypes = [vp, P(KernelTime), ctypes.c_int,
                                    P(ctypes.c_int)]
+    L.sim_batch_create.restype = vp
+    L.sim_batch_create.argtypes = [ctypes.c_int, ctypes.c_int, vp]
+    L.sim_batch_destroy.restype = None
+    L.sim_batch_destroy.argtypes = [vp]
+    L.sim_batch_apply.argtypes = [vp, P(vp), ctypes.c_int, P(Gate), ctypes.c_int,
+                                  ctypes.c_int]
+    L.sim_batch_sync.argtypes = [vp]
+    L.sim_batch_info.argtypes = [vp, P(ctypes.c_uint64), P(ctypes.c_uint64)]
     L.sim_last_error.restype = ctypes.c_char_p
     L.sim_last_error.argtypes = []
     return L
@@ -287,6 +297,52 @@ class Sim:
                 "device_bytes": st.device_bytes,
                 "replays": st.replays, "escalations": st.escalations,
                 "arena_peak": st.arena_peak}
+
+
+class Batch:
+    """Many sims advanced by shared kernel launches (optionally one HIP graph
+    launch per call)."""
+
+    def __init__(self, max_states, max_passes, stream=None):
+        self._stream_obj = stream
+        self.h = lib.sim_batch_create(max_states, max_passes, _stream_handle(stream))
+        if not self.h:
+            raise SimError(SIM_EINVAL, last_error())
+        self.max_states, self.max_passes = max_states, max_passes
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.sim_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, sims, passes, use_graph=False):
+        """passes: list of passes, each a list with one gate tuple (or None)
+        per sim."""
+        count = len(sims)
+        arr = (Gate * (count * len(passes)))()
+        for p, row in enumerate(passes):
+            if len(row) != count:
+                raise ValueError("pass %d has %d gates for %d sims" % (p, len(row), count))
+            for k, g in enumerate(row):
+                if g is not None:
+                    arr[p * count + k] = make_gate(g)
+        hs = (ctypes.c_void_p * count)(*[sm.h for sm in sims])
+        check(lib.sim_batch_apply(self.h, hs, count, arr, len(passes), 1 if use_graph else 0))
+
+    def sync(self):
+        check(lib.sim_batch_sync(self.h))
+
+    def info(self):
+        b = ctypes.c_uint64(0)
+        n = ctypes.c_uint64(0)
+        check(lib.sim_batch_info(self.h, ctypes.byref(b), ctypes.byref(n)))
+        return {"graph_builds": b.value, "graph_launches": n.value}
 
 
 def debug_rsqrt(x):

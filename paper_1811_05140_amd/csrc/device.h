@@ -160,6 +160,22 @@ void launch_export(const PassArgs &a, uint64_t j, uint8_t *out, hipStream_t st);
 void launch_export_headers(const PassArgs &a, uint64_t first, uint64_t count, uint8_t *out,
                            hipStream_t st);
 
+// One batched pass over nst states (device pointers; each prefix has nst + 1
+// entries).  upre/bpre count the units/blocks of the states with a gate in
+// this pass, mpre/mbpre those of the states whose gate is DIFFUSE.  Grids
+// depend only on the set of states, so a captured sequence stays valid when
+// the arrays are rewritten.
+struct BatchLaunch {
+    const PassArgs *args;
+    const uint64_t *upre, *bpre, *mpre, *mbpre;
+    uint32_t nst;
+    unsigned grid_units, grid_blocks;
+    bool any_mean, any_ladder, any_big;
+};
+void launch_batch_pass(const BatchLaunch &b, hipStream_t st, Prof *prof);
+// Arena chunk a workgroup takes per bump-pointer update.
+uint64_t batch_chunk_bytes(uint64_t arena_cap, unsigned grid);
+
 // Uncompressed path (sv.hip).
 void sv_set_basis(double *amp, int n, uint64_t x, hipStream_t st);
 void sv_apply(double *amp, int n, const GateArg &g, double *scratch,

@@ -918,16 +918,15 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
 // segment) pairs, one unit each, encoded again at the chosen level; then
 // one item per escalated block, whose workgroup sizes the remaining levels
 // over all the block's units, decides, and re-encodes the block itself.
-__global__ __launch_bounds__(kWG) void k_fix(PassArgs a)
+// Workgroup wg of nwg working on one state's replays and escalations (the
+// pack buffers of S must be zero).
+__device__ void fix_body(const PassArgs &a, uint64_t wg, uint64_t nwg, PassLds &S)
 {
     if (a.dev->err)
         return;
     const uint32_t nrep = a.dev->n_replay, nesc = a.dev->n_esc;
     if (nrep + nesc == 0)
         return;
-    __shared__ PassLds S;
-    for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
-        (&S.pack[0][0])[k] = 0u;
     if (threadIdx.x == 0)
         S.chunk[0] = S.chunk[1] = 0;
     const int bs = a.geo.b - a.geo.s;
@@ -937,7 +936,7 @@ __global__ __launch_bounds__(kWG) void k_fix(PassArgs a)
     const uint64_t nitems = nrep_items + nesc;
     const double scale = a.dev->scale;
     const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
-    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    for (uint64_t it = wg; it < nitems; it += nwg) {
         if (it < nrep_items) {
             const uint64_t jsel = a.replay_list[it >> bs];
             const uint64_t g = (jsel << bs) | (it & (spb - 1));
@@ -969,29 +968,40 @@ __global__ __launch_bounds__(kWG) void k_fix(PassArgs a)
     }
 }
 
+__global__ __launch_bounds__(kWG) void k_fix(PassArgs a)
+{
+    __shared__ PassLds S;
+    for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
+        (&S.pack[0][0])[k] = 0u;
+    fix_body(a, blockIdx.x, gridDim.x, S);
+}
+
 // Read-only DIFFUSE pre-pass: per-segment pairwise sums of the normalised
 // re and im parts.
+__device__ void mean_unit(const PassArgs &a, uint64_t u, Planes &X, double *red,
+                          double scale)
+{
+    const Unit uc = unit_of(u, a.geo.nseg, 0);
+    load_unit(a, uc, X, scale, scale != 1.0);
+    __syncthreads();
+    for (int c = 0; c < 2; ++c) {
+        const double sm = segment_tree(uc, a.geo.s, red,
+                                       [&](int su, int o) { return X[su][c][sw(o)]; });
+        if (threadIdx.x < (unsigned)uc.nsu)
+            a.segsum[(uint64_t)c * a.geo.nseg + uc.seg((int)threadIdx.x)] = sm;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kWG) void k_mean(PassArgs a)
 {
     if (a.dev->err)
         return;
     __shared__ __attribute__((aligned(16))) Planes X;
     __shared__ double red[8];
-    const int s = a.geo.s;
     const double scale = a.dev->scale;
-    const bool do_scale = scale != 1.0;
-    for (uint64_t u = blockIdx.x; u < a.geo.nunits; u += gridDim.x) {
-        const Unit uc = unit_of(u, a.geo.nseg, 0);
-        load_unit(a, uc, X, scale, do_scale);
-        __syncthreads();
-        for (int c = 0; c < 2; ++c) {
-            const double sm = segment_tree(uc, s, red,
-                                           [&](int su, int o) { return X[su][c][sw(o)]; });
-            if (threadIdx.x < (unsigned)uc.nsu)
-                a.segsum[(uint64_t)c * a.geo.nseg + uc.seg((int)threadIdx.x)] = sm;
-        }
-        __syncthreads();
-    }
+    for (uint64_t u = blockIdx.x; u < a.geo.nunits; u += gridDim.x)
+        mean_unit(a, u, X, red, scale);
 }
 
 // ------------------------------------------------------ reductions --------
@@ -1157,6 +1167,9 @@ __device__ void finalize_block(const PassArgs &a, uint64_t j, int d, uint64_t le
 // reaches theta.  When that is the speculated level h the block is done;
 // another level sends the block to the replay list; when none qualifies and
 // levels above h remain, the block joins the escalation list.
+__device__ void decide_block(const PassArgs &a, uint64_t j, uint64_t *red, uint64_t *tot,
+                             uint64_t *nout);
+
 __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
 {
     if (a.dev->err)
@@ -1164,9 +1177,16 @@ __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
     __shared__ uint64_t red[kWG];
     __shared__ uint64_t tot[kMaxL];
     __shared__ uint64_t nout[kMaxL];
+    for (uint64_t j = blockIdx.x; j < a.geo.nblocks; j += gridDim.x)
+        decide_block(a, j, red, tot, nout);
+}
+
+__device__ void decide_block(const PassArgs &a, uint64_t j, uint64_t *red, uint64_t *tot,
+                             uint64_t *nout)
+{
     const int L = a.lad.L;
     const double raw = (double)(16ull << a.geo.b);
-    for (uint64_t j = blockIdx.x; j < a.geo.nblocks; j += gridDim.x) {
+    {
         const int h = hint_level(a, j);
         block_totals(a, j, 0, h, red, tot, nout);
         if (threadIdx.x == 0) {
@@ -1222,12 +1242,19 @@ __device__ void decide_escalated(const PassArgs &a, uint64_t j, PassLds &S)
 // N^2 (pairwise over all amplitudes: block and segment sums are aligned
 // subtrees, so the tree runs over segment sums, or over block sums when
 // k_segtree has formed them), s, statistics; frees the input arena.
+__device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures);
+
 __global__ __launch_bounds__(kWG) void k_reduce(PassArgs a)
 {
     if (a.dev->err)
         return;
     __shared__ double lds[kWG];
     __shared__ uint64_t ures[kWG];
+    reduce_body(a, lds, ures);
+}
+
+__device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures)
+{
     const int t = threadIdx.x;
     const bool by_block = a.geo.nseg > kReduceDirect;
     const double N2 = by_block
@@ -1514,6 +1541,185 @@ __global__ __launch_bounds__(kWG) void k_export_headers(PassArgs a, uint64_t fir
     }
 }
 
+// ------------------------------------------------------ batched pass ------
+//
+// One pass over many states at once: each state s has its own PassArgs
+// (geometry, ladder, gate, buffers) in device memory and contributes
+// pre[s+1] - pre[s] work items to the kernel's item range (0 for a state
+// without a gate in this pass).  Items are handed out grid-stride; the state
+// of an item is found by binary search over the prefix.  Everything a state
+// computes is what the single-state kernels compute for it.
+
+__device__ __forceinline__ uint32_t state_of(const uint64_t *__restrict__ pre, uint32_t nst,
+                                             uint64_t it)
+{
+    uint32_t lo = 0, hi = nst;  // pre[lo] <= it < pre[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= it)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kWG) void k_bpass(const PassArgs *__restrict__ args,
+                                               const uint64_t *__restrict__ upre, uint32_t nst)
+{
+    __shared__ PassLds S;
+    for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
+        (&S.pack[0][0])[k] = 0u;
+    const uint64_t total = upre[nst];
+    uint32_t cur = ~0u;
+    bool skip = false;
+    double scale = 1.0, tdiff[2] = {0.0, 0.0};
+    uint64_t Ms = 0;
+    for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t st = state_of(upre, nst, it);
+        const PassArgs &a = args[st];
+        if (st != cur) {
+            cur = st;
+            if (threadIdx.x == 0)
+                S.chunk[0] = S.chunk[1] = 0;  // arena chunks belong to one state
+            skip = a.dev->err != 0;
+            scale = a.dev->scale;
+            tdiff[0] = a.dev->tdiff[0];
+            tdiff[1] = a.dev->tdiff[1];
+            Ms = a.gate.mask >> a.geo.s;
+        }
+        if (skip)
+            continue;
+        unit_body<kFused>(a, unit_of(it - upre[st], a.geo.nseg, Ms), ~0ull, S, scale, tdiff);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_bdecide(const PassArgs *__restrict__ args,
+                                                 const uint64_t *__restrict__ bpre,
+                                                 uint32_t nst)
+{
+    __shared__ uint64_t red[kWG];
+    __shared__ uint64_t tot[kMaxL];
+    __shared__ uint64_t nout[kMaxL];
+    const uint64_t total = bpre[nst];
+    for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t st = state_of(bpre, nst, it);
+        const PassArgs &a = args[st];
+        if (a.dev->err)
+            continue;
+        decide_block(a, it - bpre[st], red, tot, nout);
+    }
+}
+
+// Every workgroup visits every state with a gate and takes its share of
+// that state's replay and escalation items.
+__global__ __launch_bounds__(kWG) void k_bfix(const PassArgs *__restrict__ args,
+                                              const uint64_t *__restrict__ upre, uint32_t nst)
+{
+    __shared__ PassLds S;
+    for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
+        (&S.pack[0][0])[k] = 0u;
+    for (uint32_t st = 0; st < nst; ++st) {
+        if (upre[st + 1] == upre[st] || args[st].lad.L < 2)
+            continue;
+        fix_body(args[st], blockIdx.x, gridDim.x, S);
+        __syncthreads();
+    }
+}
+
+// Block normsq of the states with more than kReduceDirect segments.
+__global__ __launch_bounds__(kWG) void k_bblocknorm(const PassArgs *__restrict__ args,
+                                                    const uint64_t *__restrict__ bpre,
+                                                    uint32_t nst)
+{
+    __shared__ double lds[kWG];
+    const uint64_t total = bpre[nst];
+    for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t st = state_of(bpre, nst, it);
+        const PassArgs &a = args[st];
+        if (a.geo.nseg <= kReduceDirect || a.dev->err)
+            continue;
+        const uint64_t j = it - bpre[st];
+        const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
+        const double *src = a.dout.segnorm + j * spb;
+        const double v = wg_tree([&](uint64_t i) { return src[i]; }, spb, lds);
+        if (threadIdx.x == 0)
+            a.blknorm[j] = v;
+    }
+}
+
+// One workgroup per state with a gate.
+__global__ __launch_bounds__(kWG) void k_breduce(const PassArgs *__restrict__ args,
+                                                 const uint64_t *__restrict__ upre)
+{
+    __shared__ double lds[kWG];
+    __shared__ uint64_t ures[kWG];
+    const uint32_t st = blockIdx.x;
+    if (upre[st + 1] == upre[st] || args[st].dev->err)
+        return;
+    reduce_body(args[st], lds, ures);
+}
+
+// DIFFUSE pre-pass of the states whose gate is DIFFUSE (items: units).
+__global__ __launch_bounds__(kWG) void k_bmean(const PassArgs *__restrict__ args,
+                                               const uint64_t *__restrict__ mpre, uint32_t nst)
+{
+    __shared__ __attribute__((aligned(16))) Planes X;
+    __shared__ double red[8];
+    const uint64_t total = mpre[nst];
+    for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t st = state_of(mpre, nst, it);
+        const PassArgs &a = args[st];
+        if (a.dev->err)
+            continue;
+        mean_unit(a, it - mpre[st], X, red, a.dev->scale);
+    }
+}
+
+// Block sums of both components (items: blocks of those states).
+__global__ __launch_bounds__(kWG) void k_bmeantree(const PassArgs *__restrict__ args,
+                                                   const uint64_t *__restrict__ mbpre,
+                                                   uint32_t nst)
+{
+    __shared__ double lds[kWG];
+    const uint64_t total = mbpre[nst];
+    for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const uint32_t st = state_of(mbpre, nst, it);
+        const PassArgs &a = args[st];
+        if (a.dev->err)
+            continue;
+        const uint64_t j = it - mbpre[st];
+        const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
+        for (int c = 0; c < 2; ++c) {
+            const double *src = a.segsum + (uint64_t)c * a.geo.nseg + j * spb;
+            const double v = wg_tree([&](uint64_t i) { return src[i]; }, spb, lds);
+            if (threadIdx.x == 0)
+                a.blksum[(uint64_t)c * a.geo.nblocks + j] = v;
+        }
+    }
+}
+
+// 2 * mean of each DIFFUSE state (one workgroup per state).
+__global__ __launch_bounds__(kWG) void k_bmeanfinal(const PassArgs *__restrict__ args,
+                                                    const uint64_t *__restrict__ mpre)
+{
+    __shared__ double lds[kWG];
+    const uint32_t st = blockIdx.x;
+    if (mpre[st + 1] == mpre[st])
+        return;
+    const PassArgs &a = args[st];
+    if (a.dev->err)
+        return;
+    const double mul = ldexp(1.0, 1 - a.geo.n);
+    for (int c = 0; c < 2; ++c) {
+        const double *p = a.blksum + (uint64_t)c * a.geo.nblocks;
+        const double S = wg_tree([&](uint64_t i) { return p[i]; }, a.geo.nblocks, lds);
+        if (threadIdx.x == 0)
+            a.dev->tdiff[c] = S * mul;
+    }
+}
+
 // ------------------------------------------------------- launchers --------
 
 const char *const kKernelNames[kNumKernelIds] = {
@@ -1570,6 +1776,8 @@ void launch_mean(const PassArgs &a, double mul, double *out, hipStream_t st, Pro
           hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(kWG), 0, st, m, mul, out));
 }
 
+uint64_t batch_chunk_bytes(uint64_t arena_cap, unsigned grid);
+
 void launch_pass(const PassArgs &a0, hipStream_t st, Prof *prof)
 {
     const uint64_t kMaxGrid = 2048;
@@ -1577,10 +1785,7 @@ void launch_pass(const PassArgs &a0, hipStream_t st, Prof *prof)
     const unsigned gb = grid_for(a0.geo.nblocks);
     const unsigned gfix = gu;
     PassArgs a = a0;
-    uint64_t chunk = a.arena_cap / (8ull * gu);
-    chunk = chunk > 32768 ? 32768 : chunk;
-    chunk &= ~255ull;
-    a.chunk_bytes = chunk < 256 ? 256 : chunk;
+    a.chunk_bytes = batch_chunk_bytes(a.arena_cap, gu);
     TIMED(prof, kIdPass, st, hipLaunchKernelGGL(k_pass, dim3(gu), dim3(kWG), 0, st, a));
     TIMED(prof, kIdDecide, st, hipLaunchKernelGGL(k_decide, dim3(gb), dim3(kWG), 0, st, a));
     if (a.lad.L > 1)
@@ -1591,6 +1796,44 @@ void launch_pass(const PassArgs &a0, hipStream_t st, Prof *prof)
                                  (const double *)a.dout.segnorm, a.blknorm,
                                  1ull << (a.geo.b - a.geo.s), a.geo.nblocks, 0));
     TIMED(prof, kIdReduce, st, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, a));
+}
+
+void launch_batch_pass(const BatchLaunch &b, hipStream_t st, Prof *prof)
+{
+    if (b.any_mean) {
+        TIMED(prof, kIdMean, st,
+              hipLaunchKernelGGL(k_bmean, dim3(b.grid_units), dim3(kWG), 0, st, b.args, b.mpre,
+                                 b.nst));
+        TIMED(prof, kIdMeanTree, st,
+              hipLaunchKernelGGL(k_bmeantree, dim3(b.grid_blocks), dim3(kWG), 0, st, b.args,
+                                 b.mbpre, b.nst));
+        TIMED(prof, kIdMeanFinal, st,
+              hipLaunchKernelGGL(k_bmeanfinal, dim3(b.nst), dim3(kWG), 0, st, b.args, b.mpre));
+    }
+    TIMED(prof, kIdPass, st,
+          hipLaunchKernelGGL(k_bpass, dim3(b.grid_units), dim3(kWG), 0, st, b.args, b.upre,
+                             b.nst));
+    TIMED(prof, kIdDecide, st,
+          hipLaunchKernelGGL(k_bdecide, dim3(b.grid_blocks), dim3(kWG), 0, st, b.args, b.bpre,
+                             b.nst));
+    if (b.any_ladder)
+        TIMED(prof, kIdReplay, st,
+              hipLaunchKernelGGL(k_bfix, dim3(b.grid_units), dim3(kWG), 0, st, b.args, b.upre,
+                                 b.nst));
+    if (b.any_big)
+        TIMED(prof, kIdBlockNorm, st,
+              hipLaunchKernelGGL(k_bblocknorm, dim3(b.grid_blocks), dim3(kWG), 0, st, b.args,
+                                 b.bpre, b.nst));
+    TIMED(prof, kIdReduce, st,
+          hipLaunchKernelGGL(k_breduce, dim3(b.nst), dim3(kWG), 0, st, b.args, b.upre));
+}
+
+uint64_t batch_chunk_bytes(uint64_t arena_cap, unsigned grid)
+{
+    uint64_t chunk = arena_cap / (8ull * grid);
+    chunk = chunk > 32768 ? 32768 : chunk;
+    chunk &= ~255ull;
+    return chunk < 256 ? 256 : chunk;
 }
 
 void launch_encode_basis(const PassArgs &a, hipStream_t st, Prof *prof)

@@ -976,3 +976,299 @@ int sim_profile_read(sim_t *S, sim_kernel_time_t *out, int cap, int *count)
 const char *sim_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ batches -----
+
+struct sim_batch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int max_states = 0, max_passes = 0;
+    size_t slot_bytes = 0;     // one pass: PassArgs[max_states] + 4 prefixes
+    uint8_t *dslots = nullptr; // device [max_passes] slots
+    uint8_t *hslots = nullptr; // pinned host mirror
+    hipEvent_t uploaded = nullptr;  // the last upload from hslots has finished
+    hipEvent_t joined = nullptr;
+    std::vector<hipEvent_t> sim_ev;
+    struct Graph {
+        std::vector<uint8_t> key;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Graph> graphs;
+    uint64_t graph_launches = 0, graph_builds = 0;
+};
+
+namespace {
+
+constexpr size_t kMaxGraphs = 16;
+
+size_t slot_prefix_off(int max_states)
+{
+    return ((size_t)max_states * sizeof(PassArgs) + 255) & ~(size_t)255;
+}
+
+void destroy_graph(sim_batch::Graph &G)
+{
+    if (G.exec)
+        (void)hipGraphExecDestroy(G.exec);
+    if (G.g)
+        (void)hipGraphDestroy(G.g);
+    G.exec = nullptr;
+    G.g = nullptr;
+}
+
+BatchLaunch slot_launch(const sim_batch *B, int p, uint32_t nst, unsigned gu, unsigned gb,
+                        bool mean, bool ladder, bool big)
+{
+    const uint8_t *base = B->dslots + (size_t)p * B->slot_bytes;
+    const uint64_t *pre = (const uint64_t *)(base + slot_prefix_off(B->max_states));
+    const size_t stride = (size_t)B->max_states + 1;
+    BatchLaunch L{};
+    L.args = (const PassArgs *)base;
+    L.upre = pre;
+    L.bpre = pre + stride;
+    L.mpre = pre + 2 * stride;
+    L.mbpre = pre + 3 * stride;
+    L.nst = nst;
+    L.grid_units = gu;
+    L.grid_blocks = gb;
+    L.any_mean = mean;
+    L.any_ladder = ladder;
+    L.any_big = big;
+    return L;
+}
+
+void batch_free(sim_batch *B)
+{
+    if (B->stream)
+        (void)hipStreamSynchronize(B->stream);
+    for (auto &G : B->graphs)
+        destroy_graph(G);
+    for (auto e : B->sim_ev)
+        (void)hipEventDestroy(e);
+    if (B->uploaded)
+        (void)hipEventDestroy(B->uploaded);
+    if (B->joined)
+        (void)hipEventDestroy(B->joined);
+    if (B->dslots)
+        (void)hipFree(B->dslots);
+    if (B->hslots)
+        (void)hipHostFree(B->hslots);
+    if (B->own_stream && B->stream)
+        (void)hipStreamDestroy(B->stream);
+    delete B;
+}
+
+}  // namespace
+
+extern "C" {
+
+sim_batch_t *sim_batch_create(int max_states, int max_passes, void *hip_stream)
+{
+    g_err.clear();
+    if (max_states < 1 || max_states > 4096 || max_passes < 1 || max_passes > 4096) {
+        fail(SIM_EINVAL, "max_states %d / max_passes %d out of range [1, 4096]", max_states,
+             max_passes);
+        return nullptr;
+    }
+    sim_batch *B = new (std::nothrow) sim_batch();
+    if (!B) {
+        fail(SIM_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    B->max_states = max_states;
+    B->max_passes = max_passes;
+    B->slot_bytes = (slot_prefix_off(max_states) + 4 * 8 * ((size_t)max_states + 1) + 255) &
+                    ~(size_t)255;
+    const size_t total = B->slot_bytes * (size_t)max_passes;
+    bool ok = true;
+    if (hip_stream) {
+        B->stream = (hipStream_t)hip_stream;
+    } else {
+        ok = hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) == hipSuccess;
+        B->own_stream = ok;
+    }
+    ok = ok && hipMalloc((void **)&B->dslots, total) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&B->hslots, total, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&B->uploaded, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&B->joined, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        fail(SIM_ENOMEM, "batch allocation of %zu bytes failed", total);
+        batch_free(B);
+        return nullptr;
+    }
+    return B;
+}
+
+void sim_batch_destroy(sim_batch_t *B)
+{
+    if (B)
+        batch_free(B);
+}
+
+int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gate_t *gates,
+                    int passes, int use_graph)
+{
+    if (!B || !sims || !gates)
+        return fail(SIM_EINVAL, "NULL argument");
+    if (count < 1 || count > B->max_states || passes < 1 || passes > B->max_passes)
+        return fail(SIM_EINVAL, "count %d / passes %d outside the batch's limits (%d, %d)",
+                    count, passes, B->max_states, B->max_passes);
+    // validate everything before queuing anything
+    uint64_t units = 0, blocks = 0;
+    bool ladder = false, big = false;
+    for (int k = 0; k < count; ++k) {
+        sim *S = sims[k];
+        if (!S)
+            return fail(SIM_EINVAL, "sims[%d] is NULL", k);
+        if (!S->compressed)
+            return fail(SIM_EUNSUPPORTED, "sims[%d] is uncompressed", k);
+        for (int m = 0; m < k; ++m)
+            if (sims[m] == S)
+                return fail(SIM_EINVAL, "sims[%d] repeats sims[%d]", k, m);
+        if (!S->valid)
+            return fail(SIM_EINVAL, "sims[%d] holds no state", k);
+        units += S->geo.nunits;
+        blocks += S->geo.nblocks;
+        ladder = ladder || S->lad.L > 1;
+        big = big || S->geo.nseg > (1ull << 13);
+        for (int p = 0; p < passes; ++p) {
+            const sim_gate_t *g = &gates[(size_t)p * count + k];
+            if (g->kind == 0 && g->pad == 0)
+                continue;
+            const int rc = check_gate(S, g);
+            if (rc)
+                return fail(rc, "pass %d, sims[%d]: %s", p, k, std::string(g_err).c_str());
+        }
+    }
+    const unsigned gu = (unsigned)(units < 2048 ? units : 2048);
+    const unsigned gb = (unsigned)(blocks < (1u << 20) ? blocks : (1u << 20));
+    // the host mirror may still be the source of the previous upload
+    HIPCHK(hipEventSynchronize(B->uploaded));
+    const size_t poff = slot_prefix_off(B->max_states);
+    const size_t stride = (size_t)B->max_states + 1;
+    std::vector<uint8_t> key;
+    key.reserve(16 + passes);
+    auto put = [&key](uint64_t v) {
+        for (int i = 0; i < 8; ++i)
+            key.push_back((uint8_t)(v >> (8 * i)));
+    };
+    put((uint64_t)count);
+    put((uint64_t)passes);
+    put((uint64_t)gu | ((uint64_t)gb << 32));
+    put((uint64_t)ladder | ((uint64_t)big << 1));
+    std::vector<uint8_t> mean_of(passes, 0);
+    for (int p = 0; p < passes; ++p) {
+        uint8_t *slot = B->hslots + (size_t)p * B->slot_bytes;
+        PassArgs *args = (PassArgs *)slot;
+        uint64_t *pre = (uint64_t *)(slot + poff);
+        uint64_t *upre = pre, *bpre = pre + stride, *mpre = pre + 2 * stride,
+                 *mbpre = pre + 3 * stride;
+        upre[0] = bpre[0] = mpre[0] = mbpre[0] = 0;
+        for (int k = 0; k < count; ++k) {
+            sim *S = sims[k];
+            const sim_gate_t *g = &gates[(size_t)p * count + k];
+            const bool on = g->kind != 0;
+            const bool mean = on && g->kind == G_DIFFUSE;
+            if (on) {
+                args[k] = make_args(S, S->cur, 1 - S->cur, to_arg(g));
+                S->cur = 1 - S->cur;
+                S->passes++;
+            } else {
+                GateArg none{};
+                args[k] = make_args(S, S->cur, 1 - S->cur, none);
+            }
+            args[k].chunk_bytes = batch_chunk_bytes(S->arena_cap, gu);
+            upre[k + 1] = upre[k] + (on ? S->geo.nunits : 0);
+            bpre[k + 1] = bpre[k] + (on ? S->geo.nblocks : 0);
+            mpre[k + 1] = mpre[k] + (mean ? S->geo.nunits : 0);
+            mbpre[k + 1] = mbpre[k] + (mean ? S->geo.nblocks : 0);
+            mean_of[p] = mean_of[p] || mean;
+        }
+        key.push_back(mean_of[p]);
+    }
+    // order after the work already queued on each sim's stream
+    if (B->sim_ev.size() < (size_t)count) {
+        while (B->sim_ev.size() < (size_t)count) {
+            hipEvent_t e = nullptr;
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            B->sim_ev.push_back(e);
+        }
+    }
+    for (int k = 0; k < count; ++k) {
+        if (sims[k]->stream == B->stream)
+            continue;
+        HIPCHK(hipEventRecord(B->sim_ev[k], sims[k]->stream));
+        HIPCHK(hipStreamWaitEvent(B->stream, B->sim_ev[k], 0));
+    }
+    HIPCHK(hipMemcpyAsync(B->dslots, B->hslots, (size_t)passes * B->slot_bytes,
+                          hipMemcpyHostToDevice, B->stream));
+    HIPCHK(hipEventRecord(B->uploaded, B->stream));
+    if (use_graph) {
+        sim_batch::Graph *G = nullptr;
+        for (auto &c : B->graphs)
+            if (c.key == key) {
+                G = &c;
+                break;
+            }
+        if (!G) {
+            if (B->graphs.size() >= kMaxGraphs) {
+                destroy_graph(B->graphs.front());
+                B->graphs.erase(B->graphs.begin());
+            }
+            sim_batch::Graph fresh;
+            fresh.key = key;
+            HIPCHK(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+            for (int p = 0; p < passes; ++p)
+                launch_batch_pass(slot_launch(B, p, (uint32_t)count, gu, gb, mean_of[p] != 0,
+                                              ladder, big),
+                                  B->stream, nullptr);
+            hipError_t e = hipStreamEndCapture(B->stream, &fresh.g);
+            if (e == hipSuccess)
+                e = hipGraphInstantiate(&fresh.exec, fresh.g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                destroy_graph(fresh);
+                return fail(SIM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+            }
+            B->graphs.push_back(fresh);
+            G = &B->graphs.back();
+            B->graph_builds++;
+        }
+        HIPCHK(hipGraphLaunch(G->exec, B->stream));
+        B->graph_launches++;
+    } else {
+        for (int p = 0; p < passes; ++p)
+            launch_batch_pass(slot_launch(B, p, (uint32_t)count, gu, gb, mean_of[p] != 0,
+                                          ladder, big),
+                              B->stream, nullptr);
+        HIPCHK(hipGetLastError());
+    }
+    // later work on each sim's stream waits for the batch
+    HIPCHK(hipEventRecord(B->joined, B->stream));
+    for (int k = 0; k < count; ++k)
+        if (sims[k]->stream != B->stream)
+            HIPCHK(hipStreamWaitEvent(sims[k]->stream, B->joined, 0));
+    return SIM_OK;
+}
+
+int sim_batch_sync(sim_batch_t *B)
+{
+    if (!B)
+        return fail(SIM_EINVAL, "batch is NULL");
+    HIPCHK(hipStreamSynchronize(B->stream));
+    return SIM_OK;
+}
+
+int sim_batch_info(sim_batch_t *B, uint64_t *graph_builds, uint64_t *graph_launches)
+{
+    if (!B)
+        return fail(SIM_EINVAL, "batch is NULL");
+    if (graph_builds)
+        *graph_builds = B->graph_builds;
+    if (graph_launches)
+        *graph_launches = B->graph_launches;
+    return SIM_OK;
+}
+
+}  // extern "C"
