@@ -8,6 +8,11 @@ eb/100, eb/10, eb) with eb = 1e-4 and ratio threshold 4.  One step = encode
 the basis state + apply the 312 gates (every gate is one decompress-
 normalise-gate-compress pass over all blocks).
 
+--workload batch64: 64 seeded random brick circuits (n in [16, 28], depth
+20, eb = 1e-4) advanced together, one captured HIP graph launch per layer,
+block size and grid from the autotuner's table; also reports the same
+circuits run one at a time and checks that both give the same states.
+
 --workload grover36: Grover search on 36 qubits (2^36 amplitudes, 1 TiB as
 complex128, more than the 288 GB of HBM), 65536 blocks of 2^20, eb = 1e-5:
 H on every qubit, then 8 x (phase flip of a seeded index, diffusion).  One
@@ -141,6 +146,212 @@ def calibrate_copy(torch, nbytes, reps):
     print(json.dumps({"calibration_copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def coupled_block_mask(inputs, gate, b):
+    kind = gate[0]
+    if kind in (inputs.G_U, inputs.G_X):
+        mask = 1 << gate[1]
+    elif kind == inputs.G_CU:
+        mask = 1 << gate[2]
+    elif kind == inputs.G_SWAP:
+        mask = (1 << gate[1]) | (1 << gate[2])
+    else:
+        mask = 0
+    return mask >> b
+
+
+def cpu_baseline_batch(A, orc, inputs, insts, conf, eb, budget_s):
+    """The CPU oracle's cost per amplitude-pass on a block sample of the
+    batched workload (instances in a seeded order, every gate, one random
+    group per gate, until the budget is spent), times the workload's
+    amplitude-passes."""
+    import numpy as np
+    lad = inputs.default_ladder(eb)
+    rng = np.random.default_rng(6)
+    order = [int(v) for v in rng.permutation(len(insts))]
+    spent = 0.0
+    amps = 0
+    groups = 0
+    used = []
+    for k in order:
+        if spent >= budget_s:
+            break
+        n = insts[k]["n"]
+        b, _ = conf[k]
+        s = min(b, 10)
+        nb = 1 << (n - b)
+        sim = A.Sim(n, b, eb)
+        sim.set_basis(0)
+        used.append(n)
+        for layer in insts[k]["layers"]:
+            for gate in layer:
+                mb = coupled_block_mask(inputs, gate, b)
+                j = int(rng.integers(0, nb))
+                j = min(j, j ^ mb) if mb else j
+                in0 = sim.export_block(j)
+                in1 = sim.export_block(j ^ mb) if mb else None
+                sc = sim.stats()["scale"]
+                t0 = time.perf_counter()
+                orc.process_group(n, b, s, lad, 4.0, sc, None, gate, j, in0, in1)
+                spent += time.perf_counter() - t0
+                amps += (2 if mb else 1) << b
+                groups += 1
+                sim.apply(gate)
+        sim.close()
+    per_amp = spent / amps
+    total_gates = sum(len(g) for i in insts for g in i["layers"])
+    total_amps = sum(len(g) << i["n"] for i in insts for g in i["layers"])
+    return {
+        "value": total_gates / (per_amp * total_amps),
+        "unit": "gates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": ("%d block groups over every gate of %d instances (n = %s; oracle "
+                   "time %.1f s, single thread); oracle seconds per amplitude-pass "
+                   "times the workload's %.3e amplitude-passes"
+                   % (groups, len(used), used, spent, total_amps)),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def bench_batch64(args, A, inputs, stream):
+    """64 random brick circuits advanced together: one graph launch per
+    layer (each pass of a layer applies one gate to every instance that has
+    one)."""
+    from paper_1811_05140_amd import autotune
+    eb = args.error_bound if args.error_bound is not None else 1e-4
+    lad = inputs.default_ladder(eb)
+    insts = inputs.random_batch_workload()
+    table = autotune.load_table()
+    conf = []
+    for inst in insts:
+        t = autotune.lookup(table, inst["n"], lad, 4.0)
+        conf.append(t if t is not None else (min(16, inst["n"]), 2048))
+    tuned = all(autotune.lookup(table, i["n"], lad, 4.0) is not None for i in insts)
+    sims = []
+    for inst, (b, grid) in zip(insts, conf):
+        # default arenas (2.1 x raw): a pass's speculative encode at the
+        # previous level can take up to the raw size before a replay
+        sm = A.Sim(inst["n"], b, eb, stream=stream)
+        sm.set_grid(grid)
+        sims.append(sm)
+    depth = len(insts[0]["layers"])
+    layer_passes = []
+    for l in range(depth):
+        gl = [i["layers"][l] for i in insts]
+        P = max(len(g) for g in gl)
+        layer_passes.append([[g[p] if p < len(g) else None for g in gl] for p in range(P)])
+    batch = A.Batch(len(insts), max(len(lp) for lp in layer_passes), stream=stream)
+
+    def step(use_graph=True):
+        for sm in sims:
+            sm.set_basis(0)
+        for lp in layer_passes:
+            batch.apply(sims, lp, use_graph=use_graph)
+
+    for _ in range(args.warmup):
+        step()
+    batch.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    batch.sync()
+    for sm in sims:
+        sm.sync()
+    elapsed = time.perf_counter() - t0
+    gates_per_inst = [sum(len(g) for g in i["layers"]) for i in insts]
+    total_gates = sum(gates_per_inst)
+    amp_bytes = sum(g * 32 * (1 << i["n"]) for g, i in zip(gates_per_inst, insts))
+
+    def signature(k):
+        sm = sims[k]
+        st = sm.stats()
+        nb = 1 << (insts[k]["n"] - conf[k][0])
+        return (st["normsq"], st["resident_bytes"], tuple(st["level_hist"]),
+                sm.export_block(0), sm.export_block(nb - 1))
+
+    sig_batch = [signature(k) for k in range(len(insts))]
+    stats = [sm.stats() for sm in sims]
+    info = batch.info()
+    # the same circuits one at a time through sim_apply_gate
+    t0 = time.perf_counter()
+    for k, inst in enumerate(insts):
+        sims[k].set_basis(0)
+        for layer in inst["layers"]:
+            sims[k].run(layer)
+    for sm in sims:
+        sm.sync()
+    alone_s = time.perf_counter() - t0
+    same = all(signature(k) == sig_batch[k] for k in range(len(insts)))
+    # per-kernel times of one batched step launched directly (events)
+    batch.profile(True)
+    batch.profile_read()
+    step(use_graph=False)
+    prof = batch.profile_read()
+    batch.profile(False)
+    roofline = None
+    if "pass" in prof:
+        cnt, tot, mn, mx = prof["pass"]
+        # logical bytes of every pass of the step over the k_bpass time
+        achieved = amp_bytes / (tot / 1000.0) / 1e9
+        roofline = {
+            "bound": "hbm", "kernel": "pass (batched)", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("batch64", "bpass"),
+            "avg_launch_ms": round(tot / cnt, 4), "launches": cnt,
+            "algorithmic_bytes_per_launch": amp_bytes // cnt,
+            "kernels_ms_one_step": {k: round(v[1], 3) for k, v in sorted(prof.items())},
+        }
+    # fidelity of every instance against its uncompressed run
+    Fs = []
+    for k, inst in enumerate(insts):
+        ref = A.Sim(inst["n"], conf[k][0], -1.0, stream=stream)
+        ref.set_basis(0)
+        for layer in inst["layers"]:
+            ref.run(layer)
+        Fs.append(sims[k].fidelity(ref))
+        ref.close()
+    Fs_sorted = sorted(Fs)
+    cpu = None
+    if args.cpu_budget > 0:
+        from oracle import oracle as orc
+        cpu = cpu_baseline_batch(A, orc, inputs, insts, conf, eb, args.cpu_budget)
+    for sm in sims:
+        sm.close()
+    batch.close()
+    gps = total_gates * args.steps / elapsed
+    amp_gbs = amp_bytes * args.steps / elapsed / 1e9
+    b_by_n = {}
+    for inst, (b, grid) in zip(insts, conf):
+        b_by_n[str(inst["n"])] = [b, grid]
+    return {
+        "metric": METRIC, "value": round(gps, 2), "unit": "gates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * elapsed / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded random brick circuits)",
+        "config": {"workload": "batch64", "instances": len(insts),
+                   "n_qubits": [i["n"] for i in insts], "depth": depth,
+                   "error_bound": eb, "ladder": lad, "theta": 4.0,
+                   "gates_per_step": total_gates, "block_log2_and_grid_by_n": b_by_n,
+                   "autotuned": tuned, "graph_launch_per_layer": True},
+        "amplitude_gbs": round(amp_gbs, 1),
+        "hbm_frac": round(amp_gbs / HBM_PEAK_GBS, 4),
+        "one_at_a_time_gates_per_s": round(total_gates / alone_s, 2),
+        "batch_speedup": round((total_gates * args.steps / elapsed) / (total_gates / alone_s), 3),
+        "alone_equals_batch": same,
+        "fidelity": Fs_sorted[0], "fidelity_median": Fs_sorted[len(Fs) // 2],
+        "fidelity_ok_count": sum(1 for f in Fs if f >= 0.999),
+        "fidelity_ok": bool(Fs_sorted[0] >= 0.999),
+        "fidelity_reference": "uncompressed FP64 GPU run of each instance",
+        "min_ratio": min(st["min_ratio"] for st in stats),
+        "peak_resident_bytes": sum(st["peak_resident"] for st in stats),
+        "logical_state_bytes": sum(16 << i["n"] for i in insts),
+        "graph": info,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+
+
 def grover_fidelity(sim, n, m, k):
     """P(m) and F against the closed-form Grover state after k iterations:
     sin((2k+1)t) on m and cos((2k+1)t)/sqrt(2^n - 1) elsewhere, sin t =
@@ -158,7 +369,7 @@ def grover_fidelity(sim, n, m, k):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("qft24", "grover36"), default="qft24")
+    ap.add_argument("--workload", choices=("qft24", "grover36", "batch64"), default="qft24")
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default 5 for qft24, 1 for grover36)")
     ap.add_argument("--warmup", type=int, default=None,
@@ -174,9 +385,9 @@ def main():
     args = ap.parse_args()
     grover = args.workload == "grover36"
     if args.steps is None:
-        args.steps = 1 if grover else 5
+        args.steps = 5 if args.workload == "qft24" else 1
     if args.warmup is None:
-        args.warmup = 0 if grover else 1
+        args.warmup = 1 if args.workload != "grover36" else 0
     eb = args.error_bound if args.error_bound is not None else (1e-5 if grover else 1e-4)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -195,6 +406,9 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.workload == "batch64":
+        print(json.dumps(bench_batch64(args, A, inputs, stream)), flush=True)
+        return
     w = inputs.grover36_workload() if grover else inputs.qft24_workload()
     n, b, x, gates = w["n"], w["b"], w["basis"], w["gates"]
     sim = A.Sim(n, b, eb, stream=stream)

@@ -157,6 +157,11 @@ int sim_get_amplitudes(sim_t *sim, uint64_t first, uint64_t count,
 int sim_export_block(sim_t *sim, uint64_t j, void *buf, size_t cap,
                      size_t *len);
 
+/* Launch shape of the per-gate pass: at most max_workgroups workgroups
+ * (64..65536, default 2048) loop over the segment pairs of the state.  A
+ * tuning knob only: results do not depend on it. */
+int sim_set_grid(sim_t *sim, int max_workgroups);
+
 /* Copy the 32-byte stream headers (block stream v1, normsq field filled) of
  * blocks [first, first+count) to host memory buf (cap >= 32*count bytes).
  * The N^2 of the state is the pairwise sum of the normsq fields over all
@@ -199,6 +204,14 @@ int sim_profile(sim_t *sim, int on);
  * to *count.  Synchronises. */
 int sim_profile_read(sim_t *sim, sim_kernel_time_t *out, int cap, int *count);
 
+/* Overlap with the Fourier basis state QFT|x> (Sec. IV QFT workload):
+ * out[0] + i out[1] = sum over k of e^(-2 pi i x k / 2^n) a_k and out[2] =
+ * sum of |a_k|^2, for the normalised amplitudes a (each sum one pairwise
+ * tree in index order).  The fidelity to QFT|x> is
+ * (out[0]^2 + out[1]^2) / (2^n out[2]).  out is host memory of 3 doubles.
+ * Works on both paths.  Synchronises. */
+int sim_fourier_overlap(sim_t *sim, uint64_t x, double *out);
+
 /* Self-test hook for the normalisation scalar: out[i] = 1/sqrt(in[i])
  * computed on the device by the same code that derives s from N^2 (one
  * correctly rounded sqrt, one correctly rounded division).  in and out are
@@ -239,6 +252,13 @@ int sim_batch_apply(sim_batch_t *batch, sim_t *const *sims, int count,
 
 /* Wait for all work of the batch. */
 int sim_batch_sync(sim_batch_t *batch);
+
+/* HIP-event timing of the batch's kernels (modes as sim_profile).  While it
+ * is on, sim_batch_apply launches the passes directly instead of replaying a
+ * graph (events cannot time the kernels inside a graph launch). */
+int sim_batch_profile(sim_batch_t *batch, int on);
+int sim_batch_profile_read(sim_batch_t *batch, sim_kernel_time_t *out, int cap,
+                           int *count);
 
 /* Number of graphs captured and graph launches so far (either may be NULL). */
 int sim_batch_info(sim_batch_t *batch, uint64_t *graph_builds,

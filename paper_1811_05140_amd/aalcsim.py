@@ -26,7 +26,8 @@ EXPORTS = [
     "sim_debug_rsqrt", "sim_last_error", "sim_profile", "sim_profile_read",
     "sim_export_headers", "sim_amplitude_sum",
     "sim_batch_create", "sim_batch_destroy", "sim_batch_apply", "sim_batch_sync",
-    "sim_batch_info",
+    "sim_batch_info", "sim_set_grid", "sim_batch_profile", "sim_batch_profile_read",
+    "sim_fourier_overlap",
 ]
 
 
@@ -96,6 +97,8 @@ def _load():
     L.sim_export_headers.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, vp,
                                      ctypes.c_size_t]
     L.sim_amplitude_sum.argtypes = [vp, dp]
+    L.sim_set_grid.argtypes = [vp, ctypes.c_int]
+    L.sim_fourier_overlap.argtypes = [vp, ctypes.c_uint64, dp]
     L.sim_stats.argtypes = [vp, P(Stats)]
     L.sim_sync.argtypes = [vp]
     L.sim_set_stream.argtypes = [vp, vp]
@@ -111,6 +114,8 @@ def _load():
                                   ctypes.c_int]
     L.sim_batch_sync.argtypes = [vp]
     L.sim_batch_info.argtypes = [vp, P(ctypes.c_uint64), P(ctypes.c_uint64)]
+    L.sim_batch_profile.argtypes = [vp, ctypes.c_int]
+    L.sim_batch_profile_read.argtypes = [vp, P(KernelTime), ctypes.c_int, P(ctypes.c_int)]
     L.sim_last_error.restype = ctypes.c_char_p
     L.sim_last_error.argtypes = []
     return L
@@ -213,6 +218,15 @@ class Sim:
 
     def set_normalize(self, on):
         check(lib.sim_set_normalize(self.h, 1 if on else 0))
+
+    def fourier_fidelity(self, x):
+        """Fidelity to the closed-form QFT|x> (2^-n/2 e^(2 pi i x k / 2^n))."""
+        out = np.zeros(3)
+        check(lib.sim_fourier_overlap(self.h, int(x), _dp(out)), True)
+        return (out[0] ** 2 + out[1] ** 2) / (float(1 << self.n) * out[2])
+
+    def set_grid(self, max_workgroups):
+        check(lib.sim_set_grid(self.h, int(max_workgroups)))
 
     def set_stream(self, stream):
         self._stream_obj = stream
@@ -337,6 +351,17 @@ class Batch:
 
     def sync(self):
         check(lib.sim_batch_sync(self.h))
+
+    def profile(self, on=True, pass_only=False):
+        check(lib.sim_batch_profile(self.h, (2 if pass_only else 1) if on else 0))
+
+    def profile_read(self):
+        arr = (KernelTime * 32)()
+        cnt = ctypes.c_int(0)
+        check(lib.sim_batch_profile_read(self.h, arr, 32, ctypes.byref(cnt)))
+        return {arr[k].name.decode(): (int(arr[k].launches), arr[k].total_ms,
+                                       arr[k].min_ms, arr[k].max_ms)
+                for k in range(min(cnt.value, 32))}
 
     def info(self):
         b = ctypes.c_uint64(0)

@@ -145,8 +145,9 @@ void launch_init_state(DevState *dev, int normalize, hipStream_t st, Prof *prof)
 // Pairwise sums S (re, im) of the normalised amplitudes; out[c] = fl(S_c * mul)
 // (device pointer).
 void launch_mean(const PassArgs &a, double mul, double *out, hipStream_t st, Prof *prof);
-void launch_pass(const PassArgs &a, hipStream_t st, Prof *prof);
-void launch_encode_basis(const PassArgs &a, hipStream_t st, Prof *prof);
+// grid_cap: most workgroups of the unit kernels (they loop over units).
+void launch_pass(const PassArgs &a, unsigned grid_cap, hipStream_t st, Prof *prof);
+void launch_encode_basis(const PassArgs &a, unsigned grid_cap, hipStream_t st, Prof *prof);
 void launch_decode_range(const PassArgs &a, uint64_t first, uint64_t count,
                          double *out, hipStream_t st);
 void launch_probs(const PassArgs &a, const int *qubits_dev, int nq,
@@ -156,6 +157,9 @@ void launch_inner(const PassArgs &a, const PassArgs &b, const double *amp_a,
                   hipStream_t st);
 void launch_rsqrt(const double *in, double *out, uint64_t count,
                   hipStream_t st);
+// part: 3 * 2^(n - min(n, 10)) doubles; result: 3 doubles (device).
+void launch_fourier(const PassArgs &a, const double *amp, uint64_t x, double *part,
+                    double *result, hipStream_t st);
 void launch_export(const PassArgs &a, uint64_t j, uint8_t *out, hipStream_t st);
 void launch_export_headers(const PassArgs &a, uint64_t first, uint64_t count, uint8_t *out,
                            hipStream_t st);

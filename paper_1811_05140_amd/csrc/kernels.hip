@@ -1454,6 +1454,64 @@ __global__ __launch_bounds__(kWG) void k_inner_final(const double *part,
     }
 }
 
+// Overlap with a Fourier basis state: part[0..2][u] = pairwise over range u
+// of re and im of e^(-2 pi i x k / 2^n) a_k and of |a_k|^2 (a = s * xhat, or
+// amp when given).  The angle is formed from (x k) mod 2^n exactly.
+__global__ __launch_bounds__(kWG) void k_fourier(PassArgs A, const double *amp, uint64_t x,
+                                                 int S, uint64_t nranges, double *part)
+{
+    __shared__ __attribute__((aligned(16))) Planes X;
+    __shared__ double lds[kWG];
+    const int wave = threadIdx.x >> 6;
+    const double sa = amp ? 1.0 : A.dev->scale;
+    const int n = A.geo.n;
+    const uint64_t mask = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    const double inv = ldexp(1.0, 1 - n);
+    for (uint64_t u = blockIdx.x; u < nranges; u += gridDim.x) {
+        const uint64_t first = u << S;
+        if (wave < 2)
+            load_range(A, amp, first, S, &X[0][wave][0], wave, sa, sa != 1.0);
+        __syncthreads();
+        const uint64_t m = 1ull << S;
+        for (int c = 0; c < 3; ++c) {
+            const double v = wg_tree(
+                [&](uint64_t o) {
+                    const uint32_t so = sw((uint32_t)o);
+                    const double ar = X[0][0][so], ai = X[0][1][so];
+                    if (c == 2) {
+                        const double q1 = ar * ar, q2 = ai * ai;
+                        return q1 + q2;
+                    }
+                    const uint64_t r = (x * (first + o)) & mask;
+                    double sn, cs;
+                    sincospi((double)r * inv, &sn, &cs);
+                    if (c == 0) {
+                        const double p1 = cs * ar, p2 = sn * ai;
+                        return p1 + p2;
+                    }
+                    const double p3 = cs * ai, p4 = sn * ar;
+                    return p3 - p4;
+                },
+                m, lds);
+            if (threadIdx.x == 0)
+                part[(uint64_t)c * nranges + u] = v;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_fourier_final(const double *part, uint64_t nranges,
+                                                       double *res)
+{
+    __shared__ double lds[kWG];
+    for (int c = 0; c < 3; ++c) {
+        const double *p = part + (uint64_t)c * nranges;
+        const double v = wg_tree([&](uint64_t i) { return p[i]; }, nranges, lds);
+        if (threadIdx.x == 0)
+            res[c] = v;
+    }
+}
+
 __global__ void k_rsqrt(const double *in, double *out, uint64_t count)
 {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
@@ -1612,19 +1670,29 @@ __global__ __launch_bounds__(kWG) void k_bdecide(const PassArgs *__restrict__ ar
     }
 }
 
-// Every workgroup visits every state with a gate and takes its share of
-// that state's replay and escalation items.
+// Every workgroup takes its share of the replay and escalation items of
+// every state that has any.  The states are screened 64 at a time, one lane
+// each; the resulting mask is the same in every wave.
 __global__ __launch_bounds__(kWG) void k_bfix(const PassArgs *__restrict__ args,
                                               const uint64_t *__restrict__ upre, uint32_t nst)
 {
     __shared__ PassLds S;
     for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
         (&S.pack[0][0])[k] = 0u;
-    for (uint32_t st = 0; st < nst; ++st) {
-        if (upre[st + 1] == upre[st] || args[st].lad.L < 2)
-            continue;
-        fix_body(args[st], blockIdx.x, gridDim.x, S);
-        __syncthreads();
+    for (uint32_t base = 0; base < nst; base += 64) {
+        const uint32_t st = base + (uint32_t)lane_id();
+        bool work = false;
+        if (st < nst && upre[st + 1] != upre[st] && args[st].lad.L > 1) {
+            const DevState *d = args[st].dev;
+            work = d->err == 0 && d->n_replay + d->n_esc != 0;
+        }
+        uint64_t m = __ballot(work);
+        while (m) {
+            const int l = __builtin_ctzll(m);
+            m &= m - 1;
+            fix_body(args[base + l], blockIdx.x, gridDim.x, S);
+            __syncthreads();
+        }
     }
 }
 
@@ -1778,10 +1846,9 @@ void launch_mean(const PassArgs &a, double mul, double *out, hipStream_t st, Pro
 
 uint64_t batch_chunk_bytes(uint64_t arena_cap, unsigned grid);
 
-void launch_pass(const PassArgs &a0, hipStream_t st, Prof *prof)
+void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *prof)
 {
-    const uint64_t kMaxGrid = 2048;
-    const unsigned gu = grid_for(a0.geo.nunits < kMaxGrid ? a0.geo.nunits : kMaxGrid);
+    const unsigned gu = grid_for(a0.geo.nunits < grid_cap ? a0.geo.nunits : grid_cap);
     const unsigned gb = grid_for(a0.geo.nblocks);
     const unsigned gfix = gu;
     PassArgs a = a0;
@@ -1836,9 +1903,9 @@ uint64_t batch_chunk_bytes(uint64_t arena_cap, unsigned grid)
     return chunk < 256 ? 256 : chunk;
 }
 
-void launch_encode_basis(const PassArgs &a, hipStream_t st, Prof *prof)
+void launch_encode_basis(const PassArgs &a, unsigned grid_cap, hipStream_t st, Prof *prof)
 {
-    launch_pass(a, st, prof);
+    launch_pass(a, grid_cap, st, prof);
 }
 
 void launch_decode_range(const PassArgs &a, uint64_t first, uint64_t count,
@@ -1875,6 +1942,18 @@ void launch_inner(const PassArgs &a, const PassArgs &b, const double *amp_a,
     hipLaunchKernelGGL(k_inner, dim3(grid_for(nr)), dim3(kWG), 0, st, a, b, amp_a, amp_b,
                        S, nr, part);
     hipLaunchKernelGGL(k_inner_final, dim3(1), dim3(kWG), 0, st, (const double *)part, nr,
+                       result);
+}
+
+void launch_fourier(const PassArgs &a, const double *amp, uint64_t x, double *part,
+                    double *result, hipStream_t st)
+{
+    const int n = a.geo.n;
+    const int S = n < kMaxS ? n : kMaxS;
+    const uint64_t nr = 1ull << (n - S);
+    hipLaunchKernelGGL(k_fourier, dim3(grid_for(nr)), dim3(kWG), 0, st, a, amp, x, S, nr,
+                       part);
+    hipLaunchKernelGGL(k_fourier_final, dim3(1), dim3(kWG), 0, st, (const double *)part, nr,
                        result);
 }
 

@@ -125,6 +125,7 @@ struct sim {
     int cur = 0;
     uint64_t passes = 0;
     bool valid = false;  // the current descriptor set holds a complete state
+    unsigned grid_cap = 2048;  // workgroups of the per-gate unit kernels
     // uncompressed path
     double *amp = nullptr;
     double *sv_scratch = nullptr;
@@ -381,7 +382,7 @@ int run_basis(sim *S, uint64_t x)
     a.src_basis = 1;
     a.basis = x;
     a.pass = kBasisPass;
-    launch_encode_basis(a, S->stream, S->prof);
+    launch_encode_basis(a, S->grid_cap, S->stream, S->prof);
     HIPCHK(hipGetLastError());
     S->cur = 0;
     S->passes = 0;
@@ -554,7 +555,7 @@ int sim_apply_gate(sim_t *S, const sim_gate_t *gate)
     PassArgs a = make_args(S, in, out, g);
     if (g.kind == kDiffuse)
         launch_mean(a, ldexp(1.0, 1 - S->n), &S->dev->tdiff[0], S->stream, S->prof);
-    launch_pass(a, S->stream, S->prof);
+    launch_pass(a, S->grid_cap, S->stream, S->prof);
     HIPCHK(hipGetLastError());
     S->cur = out;
     S->passes++;
@@ -689,6 +690,16 @@ int sim_export_block(sim_t *S, uint64_t j, void *buf, size_t cap, size_t *len)
     if (e != hipSuccess)
         return fail(SIM_EDEVICE, "export: %s", hipGetErrorString(e));
     return rc;
+}
+
+int sim_set_grid(sim_t *S, int max_workgroups)
+{
+    if (!S)
+        return fail(SIM_EINVAL, "sim is NULL");
+    if (max_workgroups < 64 || max_workgroups > (1 << 16))
+        return fail(SIM_EINVAL, "max_workgroups %d outside [64, 65536]", max_workgroups);
+    S->grid_cap = (unsigned)max_workgroups;
+    return SIM_OK;
 }
 
 int sim_amplitude_sum(sim_t *S, double *out)
@@ -893,6 +904,36 @@ int sim_fidelity(sim_t *A, sim_t *B, double *F)
     return ra ? ra : rb;
 }
 
+int sim_fourier_overlap(sim_t *S, uint64_t x, double *out)
+{
+    if (!S || !out)
+        return fail(SIM_EINVAL, "NULL argument");
+    if (x >= (1ull << S->n))
+        return fail(SIM_EINVAL, "x out of range");
+    int rc = S->compressed ? sync_state(S) : SIM_OK;
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    HIPCHK(hipStreamSynchronize(S->stream));
+    const int n = S->n;
+    const int Sg = n < kMaxS ? n : kMaxS;
+    const uint64_t nr = 1ull << (n - Sg);
+    double *part = nullptr;
+    HIPCHK(hipMalloc((void **)&part, 8 * (3 * nr + 4)));
+    PassArgs pa = S->compressed ? make_args(S, S->cur, 1 - S->cur, GateArg{}) : PassArgs{};
+    pa.geo.n = n;
+    launch_fourier(pa, S->compressed ? nullptr : S->amp, x, part, part + 3 * nr, S->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, part + 3 * nr, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                           S->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(S->stream);
+    (void)hipFree(part);
+    if (e != hipSuccess)
+        return fail(SIM_EDEVICE, "fourier overlap: %s", hipGetErrorString(e));
+    return rc;
+}
+
 int sim_debug_rsqrt(const double *in, double *out, size_t count)
 {
     if (!in || !out)
@@ -914,37 +955,39 @@ int sim_debug_rsqrt(const double *in, double *out, size_t count)
     return SIM_OK;
 }
 
-int sim_profile(sim_t *S, int on)
+}  // extern "C"
+
+namespace {
+
+int prof_set(EventProf *&P, hipStream_t st, int on)
 {
-    if (!S)
-        return fail(SIM_EINVAL, "sim is NULL");
-    HIPCHK(hipStreamSynchronize(S->stream));
+    HIPCHK(hipStreamSynchronize(st));
     if (on < 0 || on > 2)
         return fail(SIM_EINVAL, "profile mode %d", on);
-    if (on && !S->prof)
-        S->prof = new (std::nothrow) EventProf();
-    if (on && !S->prof)
+    if (on && !P)
+        P = new (std::nothrow) EventProf();
+    if (on && !P)
         return fail(SIM_ENOMEM, "profiler allocation failed");
     if (on)
-        S->prof->only_pass = (on == 2);
+        P->only_pass = (on == 2);
     if (!on) {
-        delete S->prof;
-        S->prof = nullptr;
+        delete P;
+        P = nullptr;
     }
     return SIM_OK;
 }
 
-int sim_profile_read(sim_t *S, sim_kernel_time_t *out, int cap, int *count)
+int prof_read(EventProf *P, hipStream_t st, sim_kernel_time_t *out, int cap, int *count)
 {
-    if (!S || !count || (cap > 0 && !out))
+    if (!count || (cap > 0 && !out))
         return fail(SIM_EINVAL, "NULL argument");
     *count = 0;
-    if (!S->prof)
+    if (!P)
         return SIM_OK;
-    HIPCHK(hipStreamSynchronize(S->stream));
+    HIPCHK(hipStreamSynchronize(st));
     sim_kernel_time_t acc[kNumKernelIds];
     memset(acc, 0, sizeof acc);
-    for (auto &r : S->prof->recs) {
+    for (auto &r : P->recs) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
             sim_kernel_time_t &k = acc[r.id];
@@ -955,10 +998,10 @@ int sim_profile_read(sim_t *S, sim_kernel_time_t *out, int cap, int *count)
             k.total_ms += ms;
             k.launches += 1;
         }
-        S->prof->pool.push_back(r.a);
-        S->prof->pool.push_back(r.b);
+        P->pool.push_back(r.a);
+        P->pool.push_back(r.b);
     }
-    S->prof->recs.clear();
+    P->recs.clear();
     int m = 0;
     for (int id = 0; id < kNumKernelIds; ++id) {
         if (!acc[id].launches)
@@ -971,6 +1014,24 @@ int sim_profile_read(sim_t *S, sim_kernel_time_t *out, int cap, int *count)
     }
     *count = m;
     return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_profile(sim_t *S, int on)
+{
+    if (!S)
+        return fail(SIM_EINVAL, "sim is NULL");
+    return prof_set(S->prof, S->stream, on);
+}
+
+int sim_profile_read(sim_t *S, sim_kernel_time_t *out, int cap, int *count)
+{
+    if (!S)
+        return fail(SIM_EINVAL, "NULL argument");
+    return prof_read(S->prof, S->stream, out, cap, count);
 }
 
 const char *sim_last_error(void) { return g_err.c_str(); }
@@ -996,6 +1057,7 @@ struct sim_batch {
     };
     std::vector<Graph> graphs;
     uint64_t graph_launches = 0, graph_builds = 0;
+    EventProf *prof = nullptr;  // when set, passes are launched directly and timed
 };
 
 namespace {
@@ -1054,6 +1116,7 @@ void batch_free(sim_batch *B)
         (void)hipFree(B->dslots);
     if (B->hslots)
         (void)hipHostFree(B->hslots);
+    delete B->prof;
     if (B->own_stream && B->stream)
         (void)hipStreamDestroy(B->stream);
     delete B;
@@ -1205,7 +1268,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
     HIPCHK(hipMemcpyAsync(B->dslots, B->hslots, (size_t)passes * B->slot_bytes,
                           hipMemcpyHostToDevice, B->stream));
     HIPCHK(hipEventRecord(B->uploaded, B->stream));
-    if (use_graph) {
+    if (use_graph && !B->prof) {
         sim_batch::Graph *G = nullptr;
         for (auto &c : B->graphs)
             if (c.key == key) {
@@ -1241,7 +1304,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
         for (int p = 0; p < passes; ++p)
             launch_batch_pass(slot_launch(B, p, (uint32_t)count, gu, gb, mean_of[p] != 0,
                                           ladder, big),
-                              B->stream, nullptr);
+                              B->stream, B->prof);
         HIPCHK(hipGetLastError());
     }
     // later work on each sim's stream waits for the batch
@@ -1258,6 +1321,20 @@ int sim_batch_sync(sim_batch_t *B)
         return fail(SIM_EINVAL, "batch is NULL");
     HIPCHK(hipStreamSynchronize(B->stream));
     return SIM_OK;
+}
+
+int sim_batch_profile(sim_batch_t *B, int on)
+{
+    if (!B)
+        return fail(SIM_EINVAL, "batch is NULL");
+    return prof_set(B->prof, B->stream, on);
+}
+
+int sim_batch_profile_read(sim_batch_t *B, sim_kernel_time_t *out, int cap, int *count)
+{
+    if (!B)
+        return fail(SIM_EINVAL, "batch is NULL");
+    return prof_read(B->prof, B->stream, out, cap, count);
 }
 
 int sim_batch_info(sim_batch_t *B, uint64_t *graph_builds, uint64_t *graph_launches)

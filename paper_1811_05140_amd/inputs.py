@@ -213,3 +213,35 @@ def random_batch_workload(count=64, depth=20):
         inst.append({"n": n, "layers": random_brick_layers(n, depth, rng)})
     return inst
 
+
+
+def serving_workload(count=512, n_lo=10, n_hi=30, depth=20):
+    """Request stream for the serving loop, in arrival order.  Each request:
+    unit-rate arrival time `t1` (cumulative Exp(1) gaps; divide by the rate
+    lambda for arrivals at that rate), kind uniform over {qft, grover,
+    random}, n = n_lo + draw mod (n_hi - n_lo + 1), error bound uniform over
+    {1e-3, 1e-4, 1e-5}, then the kind's own draws (QFT: basis x; Grover:
+    marked index, iterations 1 + draw mod 6; random: depth-`depth` brick
+    circuit)."""
+    rng = rng_for(5)
+    reqs = []
+    t = 0.0
+    for i in range(count):
+        u = 1.0 - rng.uniform()  # (0, 1]
+        t += -math.log(u)
+        kind = ("qft", "grover", "random")[rng.next() % 3]
+        n = n_lo + rng.next() % (n_hi - n_lo + 1)
+        eb = (1e-3, 1e-4, 1e-5)[rng.next() % 3]
+        mask = (1 << n) - 1
+        r = {"id": i, "t1": t, "kind": kind, "n": n, "eb": eb, "basis": 0}
+        if kind == "qft":
+            r["basis"] = rng.next() & mask
+            r["gates"] = qft(n)
+        elif kind == "grover":
+            r["marked"] = rng.next() & mask
+            r["iterations"] = 1 + rng.next() % 6
+            r["gates"] = grover(n, r["marked"], r["iterations"])
+        else:
+            r["gates"] = random_brick(n, depth, rng)
+        reqs.append(r)
+    return reqs

@@ -1,0 +1,273 @@
+"""Serving loop: circuits arrive over time, their compressed states stay
+resident in HBM, and every step advances all admitted states together.
+
+Scheduling (continuous batching):
+  * requests are admitted in arrival order while a slot is free and their
+    memory reservation fits the budget still unreserved (a request that does
+    not fit waits, and so do the ones behind it);
+  * each step applies the next `gates_per_step` gates of every admitted
+    request in one batched launch sequence (one kernel set for all states);
+  * a request whose last gate went out in step k is retired after step k + 1
+    has been queued, so the device keeps working while the host reads its
+    result; retiring frees its reservation, and waiting requests are admitted
+    before the next step.
+The one-circuit-at-a-time baseline is the same loop with one slot and the
+whole circuit as one step, run through sim_apply_gate.
+
+A state whose arena overflows (the library reports SIM_ENOMEM and rolls the
+state back) is restarted with twice the arena once memory allows it.
+
+The executor is the only part that touches the GPU; the scheduler is plain
+Python and is tested on the CPU against a fake executor.
+"""
+import collections
+import math
+import time
+
+
+class Overflow(Exception):
+    """The state outgrew its arena (it is restarted with a larger one)."""
+
+
+class Request:
+    __slots__ = ("rid", "arrival", "kind", "n", "eb", "basis", "gates", "marked",
+                 "iterations", "arena_factor", "restarts", "admitted", "ready", "done",
+                 "result", "reserved", "handle", "pos")
+
+    def __init__(self, spec, rate):
+        self.rid = spec["id"]
+        self.arrival = spec["t1"] / rate if rate != math.inf else 0.0
+        self.kind = spec["kind"]
+        self.n = spec["n"]
+        self.eb = spec["eb"]
+        self.basis = spec.get("basis", 0)
+        self.gates = spec["gates"]
+        self.marked = spec.get("marked")
+        self.iterations = spec.get("iterations")
+        self.arena_factor = 1.0
+        self.restarts = 0
+        self.admitted = self.ready = self.done = None
+        self.result = None
+        self.reserved = 0
+        self.handle = None
+        self.pos = 0
+
+
+def percentile(values, q):
+    """Nearest-rank percentile (q in [0, 100]) of a non-empty list."""
+    v = sorted(values)
+    k = max(0, min(len(v) - 1, int(math.ceil(q / 100.0 * len(v))) - 1))
+    return v[k]
+
+
+def serve(specs, executor, budget_bytes, max_slots, gates_per_step=1, rate=math.inf,
+          clock=time.perf_counter, sleep=time.sleep):
+    """Run the request stream; returns (requests, summary)."""
+    reqs = [Request(s, rate) for s in specs]
+    pending = collections.deque(sorted(reqs, key=lambda r: (r.arrival, r.rid)))
+    active = []
+    retiring = []
+    reserved = 0
+    steps = 0
+    peak_active = 0
+    peak_reserved = 0
+    t0 = clock()
+    while pending or active or retiring:
+        now = clock() - t0
+        # admission: arrival order, slots and budget
+        while pending and pending[0].arrival <= now and len(active) < max_slots:
+            r = pending[0]
+            need = executor.reservation(r)
+            if need > budget_bytes:
+                raise ValueError("request %d needs %d bytes, more than the budget"
+                                 % (r.rid, need))
+            if reserved + need > budget_bytes:
+                break
+            pending.popleft()
+            r.reserved = need
+            reserved += need
+            r.handle = executor.open(r)
+            r.pos = 0
+            if r.admitted is None:
+                r.admitted = now
+            active.append(r)
+        peak_active = max(peak_active, len(active))
+        peak_reserved = max(peak_reserved, reserved)
+        if active:
+            items = []
+            for r in active:
+                g = r.gates[r.pos:r.pos + gates_per_step]
+                r.pos += len(g)
+                items.append((r.handle, g))
+            executor.step(items)
+            steps += 1
+        # retire what finished in the previous step
+        for r in retiring:
+            try:
+                r.result = executor.close(r.handle, r)
+                r.ready = r.result.pop("ready_at") - t0
+                r.done = clock() - t0
+            except Overflow:
+                r.restarts += 1
+                r.arena_factor *= 2.0
+                pending.appendleft(r)
+            r.handle = None
+            reserved -= r.reserved
+            r.reserved = 0
+        retiring = [r for r in active if r.pos >= len(r.gates)]
+        active = [r for r in active if r.pos < len(r.gates)]
+        if not active and not retiring and pending:
+            wait = pending[0].arrival - (clock() - t0)
+            if wait > 0:
+                sleep(wait)
+    lat = [r.ready - r.arrival for r in reqs]
+    makespan = max(r.ready for r in reqs) - min(r.arrival for r in reqs)
+    gates = sum(len(r.gates) for r in reqs)
+    summary = {
+        "requests": len(reqs),
+        "p50_latency_s": percentile(lat, 50),
+        "p99_latency_s": percentile(lat, 99),
+        "mean_latency_s": sum(lat) / len(lat),
+        "makespan_s": makespan,
+        "gates_per_s": gates / makespan if makespan > 0 else float("inf"),
+        "requests_per_s": len(reqs) / makespan if makespan > 0 else float("inf"),
+        "steps": steps,
+        "peak_active": peak_active,
+        "peak_reserved_bytes": peak_reserved,
+        "restarts": sum(r.restarts for r in reqs),
+    }
+    return reqs, summary
+
+
+# ------------------------------------------------------------- executor ----
+
+def reservation_bytes(n, b, arena_factor=1.0, levels=5):
+    """Device bytes a state of n qubits holds: two arenas of
+    ceil(1.3 * factor * 16 * 2^n) + 1 MiB (the pass's speculative encode at
+    the previous level can take up to the raw size before a replay, on top of
+    the kept streams), plus descriptors, size tables and reduction scratch."""
+    s = min(b, 10)
+    nseg = 1 << (n - s)
+    nblocks = 1 << (n - b)
+    arena = arena_bytes(n, arena_factor)
+    per_seg = 2 * (16 + 8) + 8 * levels + 16
+    per_block = 2 * (32 + 4 + 1) + 4 + 4 + 8 + 16
+    return 2 * arena + per_seg * nseg + per_block * nblocks + 4096
+
+
+def arena_bytes(n, arena_factor=1.0):
+    return int(math.ceil(1.3 * arena_factor * (16 << n))) + (1 << 20)
+
+
+class GpuExecutor:
+    """Opens one compressed sim per request (own stream), steps them with a
+    shared batch, and measures results at retirement."""
+
+    def __init__(self, A, max_slots, gates_per_step=1, sequential=False, tune=None,
+                 probs_qubits=4):
+        self.A = A
+        self.sequential = sequential
+        self.batch = None if sequential else A.Batch(max_slots, gates_per_step)
+        self.tune = tune or {}
+        self.probs_qubits = probs_qubits
+
+    def block_log2(self, r):
+        from paper_1811_05140_amd import autotune, inputs
+        t = autotune.lookup(self.tune, r.n, inputs.default_ladder(r.eb), 4.0)
+        if t is not None:
+            return t[0]
+        return min(r.n, 14)
+
+    def reservation(self, r):
+        return reservation_bytes(r.n, self.block_log2(r), r.arena_factor)
+
+    def open(self, r):
+        sim = self.A.Sim(r.n, self.block_log2(r), r.eb,
+                         arena_bytes=arena_bytes(r.n, r.arena_factor))
+        sim.set_basis(r.basis)
+        return sim
+
+    def step(self, items):
+        if self.sequential:
+            for sim, gates in items:
+                sim.run(gates)
+            return
+        sims = [sim for sim, g in items if g]
+        rows = [g for _, g in items if g]
+        if not sims:
+            return
+        P = max(len(g) for g in rows)
+        passes = [[g[p] if p < len(g) else None for g in rows] for p in range(P)]
+        self.batch.apply(sims, passes, use_graph=False)
+
+    def close(self, sim, r):
+        A = self.A
+        try:
+            nq = min(self.probs_qubits, r.n)
+            probs = sim.probs(list(range(nq)))
+        except A.SimError as e:
+            sim.close()
+            if e.code == A.SIM_ENOMEM:
+                raise Overflow(str(e))
+            raise
+        ready = time.perf_counter()
+        st = sim.stats()
+        out = {"ready_at": ready, "probs": probs.tolist(), "normsq": st["normsq"],
+               "resident_bytes": st["resident_bytes"], "min_ratio": st["min_ratio"],
+               "level_hist": st["level_hist"], "signature": signature(sim, r)}
+        if r.kind == "qft":
+            out["fidelity"] = sim.fourier_fidelity(r.basis)
+        elif r.kind == "grover":
+            P, Pc, F = grover_closed_form(sim, r.n, r.marked, r.iterations)
+            out.update({"fidelity": F, "p_marked": P, "p_marked_closed_form": Pc})
+        sim.close()
+        return out
+
+
+def signature(sim, r):
+    """Bytes that pin a final state: the first and last block streams plus the
+    statistics (compared between a request run in the mix and alone)."""
+    import hashlib
+    nb = 1 << (r.n - sim.b)
+    h = hashlib.sha256()
+    h.update(sim.export_block(0))
+    h.update(sim.export_block(nb - 1))
+    st = sim.stats()
+    h.update(repr((st["normsq"], st["resident_bytes"], st["level_hist"],
+                   st["replays"], st["escalations"])).encode())
+    return h.hexdigest()
+
+
+def grover_closed_form(sim, n, m, k):
+    """P(m) and the fidelity to the closed-form Grover state after k
+    iterations (sin((2k+1)t) on m, cos((2k+1)t)/sqrt(2^n - 1) elsewhere,
+    sin t = 2^(-n/2)), from the amplitude sum and a_m."""
+    th = math.asin(2.0 ** (-n / 2.0))
+    alpha = math.sin((2 * k + 1) * th)
+    beta = math.cos((2 * k + 1) * th) / math.sqrt(float((1 << n) - 1))
+    am = complex(sim.amplitudes(m, 1)[0])
+    S = sim.amplitude_sum()
+    st = sim.stats()
+    F = abs(beta * S + (alpha - beta) * am) ** 2 / (st["normsq"] * st["scale"] ** 2)
+    return abs(am) ** 2, alpha ** 2, F
+
+
+def random_fidelity(A, spec, b, arena_factor=1.0):
+    """Fidelity of a random-circuit request against its uncompressed run
+    (the request is run alone again, compressed, to have its final state;
+    its signature must equal the one recorded in the mix)."""
+    class R:
+        pass
+    r = R()
+    r.n, r.kind = spec["n"], spec["kind"]
+    sim = A.Sim(spec["n"], b, spec["eb"], arena_bytes=arena_bytes(spec["n"], arena_factor))
+    sim.set_basis(spec.get("basis", 0))
+    sim.run(spec["gates"])
+    sig = signature(sim, r)
+    ref = A.Sim(spec["n"], b, -1.0)
+    ref.set_basis(spec.get("basis", 0))
+    ref.run(spec["gates"])
+    F = sim.fidelity(ref)
+    ref.close()
+    sim.close()
+    return F, sig

@@ -1,0 +1,68 @@
+"""The serving loop on the GPU: a small request stream (QFT, Grover and
+random circuits of 8..14 qubits, three error bounds) served with continuous
+batching under a memory budget that forces queueing.  Every request's final
+state must be the same as when it runs alone (byte-identical first and last
+block streams and statistics) and, for the smallest ones, as the oracle's;
+the one-circuit-at-a-time path gives the same states; results carry
+fidelities against closed forms."""
+import math
+
+import pytest
+
+from oracle import oracle as orc
+from paper_1811_05140_amd import inputs as I
+from paper_1811_05140_amd import serve as SV
+
+pytestmark = pytest.mark.gpu
+
+
+def test_serving_mix_equals_alone_and_oracle():
+    from paper_1811_05140_amd import aalcsim as A
+    specs = I.serving_workload(count=24, n_lo=8, n_hi=14, depth=6)
+    print("serving %d requests" % len(specs), flush=True)
+    ex = SV.GpuExecutor(A, max_slots=6, gates_per_step=2)
+    budget = 3 * SV.reservation_bytes(14, 14)
+    reqs, summ = SV.serve(specs, ex, budget, 6, 2, rate=200.0)
+    print(summ, flush=True)
+    assert summ["peak_reserved_bytes"] <= budget and summ["restarts"] == 0
+    seq = SV.GpuExecutor(A, max_slots=1, sequential=True)
+    reqs1, summ1 = SV.serve(specs, seq, budget, 1, 10 ** 6, rate=200.0)
+    byid = {r.rid: r for r in reqs1}
+    for r in reqs:
+        s = specs[r.rid]
+        b = ex.block_log2(r)
+        sim = A.Sim(r.n, b, r.eb, arena_bytes=SV.arena_bytes(r.n))
+        assert sim.stats()["device_bytes"] <= SV.reservation_bytes(r.n, b)
+        sim.set_basis(r.basis)
+        sim.run(s["gates"])
+        assert SV.signature(sim, r) == r.result["signature"], r.rid
+        assert byid[r.rid].result["signature"] == r.result["signature"], r.rid
+        if r.n <= 9:
+            o = orc.OracleSim(r.n, b, I.default_ladder(r.eb), 4.0)
+            o.set_basis(r.basis)
+            o.run(s["gates"])
+            for j in range(1 << (r.n - b)):
+                assert sim.export_block(j) == o.export_block(j), (r.rid, j)
+        sim.close()
+        if r.kind == "qft":
+            assert r.result["fidelity"] > 0.99, (r.rid, r.result["fidelity"])
+        if r.kind == "grover":
+            assert abs(r.result["p_marked"] - r.result["p_marked_closed_form"]) < 1e-3
+        assert abs(sum(r.result["probs"]) - 1.0) < 1e-9
+    assert summ["gates_per_s"] > 0 and summ1["gates_per_s"] > 0
+
+
+def test_fourier_overlap_is_the_qft_fidelity():
+    from paper_1811_05140_amd import aalcsim as A
+    n, x = 12, 0x5A3
+    print("fourier overlap", flush=True)
+    g = A.Sim(n, 8, 1e-4)
+    u = A.Sim(n, 8, -1.0)
+    for s in (g, u):
+        s.set_basis(x)
+        s.run(I.qft(n))
+    Fu = u.fourier_fidelity(x)
+    assert abs(Fu - 1.0) < 1e-12
+    Fg = g.fourier_fidelity(x)
+    assert abs(Fg - g.fidelity(u)) < 1e-12
+    assert u.fourier_fidelity((x + 1) % (1 << n)) < 1e-20

@@ -1,0 +1,158 @@
+"""The serving loop's scheduling on the CPU, against a fake executor with a
+simulated clock: every gate applied once and in order, admission in arrival
+order within slots and budget, retirement one step late, restarts after an
+arena overflow, latency statistics."""
+import math
+
+import pytest
+
+from paper_1811_05140_amd import serve as SV
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += dt
+
+
+class Fake:
+    """Applies gates to lists; time advances with each step by the work of
+    its largest state; overflows the listed requests on their first run."""
+
+    def __init__(self, clock, budget, overflow_once=()):
+        self.clock = clock
+        self.budget = budget
+        self.applied = {}
+        self.reserved = 0
+        self.max_reserved = 0
+        self.open_order = []
+        self.steps = []
+        self.overflow = set(overflow_once)
+        self.live = 0
+        self.max_live = 0
+
+    def reservation(self, r):
+        return int((1 << r.n) * r.arena_factor)
+
+    def open(self, r):
+        assert r.arrival <= self.clock.t + 1e-12
+        self.reserved += self.reservation(r)
+        assert self.reserved <= self.budget
+        self.max_reserved = max(self.max_reserved, self.reserved)
+        self.live += 1
+        self.max_live = max(self.max_live, self.live)
+        self.open_order.append(r.rid)
+        h = {"rid": r.rid, "gates": [], "need": self.reservation(r)}
+        return h
+
+    def step(self, items):
+        self.steps.append([(h["rid"], len(g)) for h, g in items])
+        work = 0.0
+        for h, g in items:
+            h["gates"].extend(g)
+            work = max(work, len(g) * 1e-3)
+        self.clock.t += work
+
+    def close(self, h, r):
+        self.reserved -= h["need"]
+        self.live -= 1
+        if r.rid in self.overflow:
+            self.overflow.discard(r.rid)
+            raise SV.Overflow("arena")
+        self.applied[r.rid] = list(h["gates"])
+        return {"ready_at": self.clock.t, "ok": True}
+
+
+def specs(count, seed=0):
+    import random
+    rnd = random.Random(seed)
+    out = []
+    t = 0.0
+    for i in range(count):
+        t += rnd.expovariate(1.0)
+        n = rnd.randint(4, 9)
+        out.append({"id": i, "t1": t, "kind": "qft", "n": n, "eb": 1e-4,
+                    "gates": [(i, k) for k in range(rnd.randint(3, 30))]})
+    return out
+
+
+@pytest.mark.parametrize("slots,gps,rate", [(4, 1, 2.0), (16, 3, 50.0), (1, 10 ** 6, 5.0),
+                                            (64, 1, math.inf)])
+def test_every_gate_once_in_order_within_slots_and_budget(slots, gps, rate):
+    clk = Clock()
+    budget = 3 * (1 << 9)
+    ex = Fake(clk, budget)
+    sp = specs(60)
+    reqs, summ = SV.serve(sp, ex, budget, slots, gps, rate, clock=clk, sleep=clk.sleep)
+    for s in sp:
+        assert ex.applied[s["id"]] == s["gates"]
+    assert ex.max_live <= slots + 1  # one more may be retiring
+    assert ex.max_reserved <= budget
+    # admission in arrival order
+    assert ex.open_order == sorted(ex.open_order, key=lambda i: (sp[i]["t1"], i))
+    for r in reqs:
+        assert r.arrival <= r.admitted <= r.ready <= r.done
+    assert summ["requests"] == 60 and summ["p50_latency_s"] <= summ["p99_latency_s"]
+    assert summ["peak_reserved_bytes"] <= budget
+
+
+def test_step_gates_and_one_step_late_retirement():
+    clk = Clock()
+    ex = Fake(clk, 1 << 20)
+    sp = [{"id": 0, "t1": 0.0, "kind": "qft", "n": 4, "eb": 1e-4, "gates": list(range(5))},
+          {"id": 1, "t1": 0.0, "kind": "qft", "n": 4, "eb": 1e-4, "gates": list(range(2))}]
+    SV.serve(sp, ex, 1 << 20, 8, 2, math.inf, clock=clk, sleep=clk.sleep)
+    # step 1: both get 2 gates; step 2: request 0 gets 2, request 1 (done) is
+    # retired after it; step 3: request 0 gets its last gate
+    assert ex.steps == [[(0, 2), (1, 2)], [(0, 2)], [(0, 1)]]
+
+
+def test_overflow_restarts_with_a_larger_arena():
+    clk = Clock()
+    budget = 1 << 12
+    ex = Fake(clk, budget, overflow_once=(3,))
+    sp = specs(10, seed=3)
+    reqs, summ = SV.serve(sp, ex, budget, 4, 1, 10.0, clock=clk, sleep=clk.sleep)
+    r3 = [r for r in reqs if r.rid == 3][0]
+    assert r3.restarts == 1 and r3.arena_factor == 2.0 and summ["restarts"] == 1
+    for s in sp:
+        assert ex.applied[s["id"]] == s["gates"]
+
+
+def test_request_larger_than_the_budget_is_refused():
+    clk = Clock()
+    ex = Fake(clk, 100)
+    with pytest.raises(ValueError):
+        SV.serve(specs(3), ex, 100, 4, 1, 1.0, clock=clk, sleep=clk.sleep)
+
+
+def test_percentile_nearest_rank():
+    v = list(range(1, 101))
+    assert SV.percentile(v, 50) == 50 and SV.percentile(v, 99) == 99
+    assert SV.percentile(v, 100) == 100 and SV.percentile([7], 99) == 7
+
+
+def test_reservation_formula_covers_double_buffering():
+    # two arenas of 1.3 x raw + 1 MiB, plus metadata
+    n, b = 20, 14
+    res = SV.reservation_bytes(n, b)
+    assert res >= 2 * (1.3 * (16 << n))
+    assert SV.reservation_bytes(n, b, 2.0) > res
+
+
+def test_serving_workload_shape():
+    from paper_1811_05140_amd import inputs as I
+    reqs = I.serving_workload()
+    assert len(reqs) == 512
+    assert all(10 <= r["n"] <= 30 and r["eb"] in (1e-3, 1e-4, 1e-5) for r in reqs)
+    assert {r["kind"] for r in reqs} == {"qft", "grover", "random"}
+    assert all(1 <= r["iterations"] <= 6 for r in reqs if r["kind"] == "grover")
+    ts = [r["t1"] for r in reqs]
+    assert ts == sorted(ts) and ts[0] > 0
+    # unit-rate arrivals: mean gap close to 1
+    assert 0.8 < ts[-1] / len(ts) < 1.2
