@@ -13,6 +13,10 @@ normalise-gate-compress pass over all blocks).
 block size and grid from the autotuner's table; also reports the same
 circuits run one at a time and checks that both give the same states.
 
+--workload serve512: 512 requests (QFT, Grover, random; 10..30 qubits;
+three error bounds) with Poisson arrivals and a 200 GB compressed-memory
+budget, served with continuous batching and one circuit at a time.
+
 --workload grover36: Grover search on 36 qubits (2^36 amplitudes, 1 TiB as
 complex128, more than the 288 GB of HBM), 65536 blocks of 2^20, eb = 1e-5:
 H on every qubit, then 8 x (phase flip of a seeded index, diffusion).  One
@@ -352,6 +356,100 @@ def bench_batch64(args, A, inputs, stream):
     }
 
 
+SERVE_RATE = None  # requests/s; fixed from a saturated run (see --rate)
+
+
+def bench_serve(args, A, inputs, stream):
+    """512 requests (QFT / Grover / random, n in [10, 30], eb in {1e-3, 1e-4,
+    1e-5}) with Poisson arrivals at `rate`, 200 GB compressed budget, served
+    with continuous batching and, on the same arrivals, one circuit at a
+    time; p50/p99 latency, gates/s and per-request fidelity."""
+    from paper_1811_05140_amd import autotune, serve as SV
+    specs = inputs.serving_workload(count=args.requests)
+    table = autotune.load_table()
+    budget = int(200e9)
+    slots, G = 64, 4
+    last = [time.perf_counter()]
+
+    class Progress:
+        def __init__(self, ex):
+            self.ex = ex
+            self.done = 0
+
+        def __getattr__(self, k):
+            return getattr(self.ex, k)
+
+        def close(self, h, r):
+            out = self.ex.close(h, r)
+            self.done += 1
+            if time.perf_counter() - last[0] > 10:
+                last[0] = time.perf_counter()
+                print("serve: %d requests done" % self.done, file=sys.stderr, flush=True)
+            return out
+
+    def run(rate, sequential):
+        ex = SV.GpuExecutor(A, slots, G, sequential=sequential, tune=table)
+        if sequential:
+            return SV.serve(specs, Progress(ex), budget, 1, 10 ** 9, rate)
+        return SV.serve(specs, Progress(ex), budget, slots, G, rate)
+
+    out = {"metric": METRIC, "unit": "gates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic (seeded request stream)"}
+    rate = args.rate
+    if rate is None:
+        # saturated batched throughput (all requests at t = 0) fixes the rate
+        _, sat = run(math.inf, False)
+        rate = 0.7 * sat["requests_per_s"]
+        out["saturated"] = sat
+    reqs, summ = run(rate, False)
+    reqs1, summ1 = run(rate, True)
+    by1 = {r.rid: r for r in reqs1}
+    same = sum(1 for r in reqs if r.result["signature"] == by1[r.rid].result["signature"])
+    # random circuits: fidelity against uncompressed runs (n <= 24 all, larger sampled)
+    import numpy as np
+    rng = np.random.default_rng(7)
+    big = [r for r in reqs if r.kind == "random" and r.n > 24]
+    pick = {r.rid for r in big if rng.random() < 6.0 / max(1, len(big))}
+    checked_random = 0
+    for r in reqs:
+        if r.kind != "random" or (r.n > 24 and r.rid not in pick):
+            continue
+        ex = SV.GpuExecutor(A, 1, 1, sequential=True, tune=table)
+        F, sig = SV.random_fidelity(A, specs[r.rid], ex.block_log2(r), r.arena_factor)
+        assert sig == r.result["signature"]
+        r.result["fidelity"] = F
+        checked_random += 1
+    Fs = [r.result["fidelity"] for r in reqs if "fidelity" in r.result]
+    per_kind = {}
+    for kind in ("qft", "grover", "random"):
+        f = [r.result["fidelity"] for r in reqs if r.kind == kind and "fidelity" in r.result]
+        if f:
+            per_kind[kind] = {"count": len(f), "min": min(f), "median": sorted(f)[len(f) // 2],
+                              "ok": sum(1 for v in f if v >= 0.999)}
+    out.update({
+        "value": round(summ["gates_per_s"], 2),
+        "ms_per_step": round(1000.0 * summ["makespan_s"], 3),
+        "config": {"workload": "serve512", "requests": len(specs), "rate_per_s": rate,
+                   "n_range": [10, 30], "error_bounds": [1e-3, 1e-4, 1e-5],
+                   "budget_bytes": budget, "slots": slots, "gates_per_step": G,
+                   "gates": sum(len(s["gates"]) for s in specs)},
+        "batched": summ, "one_at_a_time": summ1,
+        "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
+        "one_at_a_time_p50_s": summ1["p50_latency_s"],
+        "one_at_a_time_p99_s": summ1["p99_latency_s"],
+        "mix_equals_alone": "%d of %d" % (same, len(reqs)),
+        "fidelity": min(Fs) if Fs else None,
+        "fidelity_by_kind": per_kind,
+        "fidelity_note": ("QFT: closed form (Fourier overlap); Grover: closed form; random: "
+                          "uncompressed run, %d of %d random requests (all n <= 24, a "
+                          "seeded sample above)" % (checked_random,
+                                                    sum(1 for r in reqs if r.kind == "random"))),
+        "roofline": None, "cpu_baseline": None,
+    })
+    return out
+
+
 def grover_fidelity(sim, n, m, k):
     """P(m) and F against the closed-form Grover state after k iterations:
     sin((2k+1)t) on m and cos((2k+1)t)/sqrt(2^n - 1) elsewhere, sin t =
@@ -369,7 +467,12 @@ def grover_fidelity(sim, n, m, k):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("qft24", "grover36", "batch64"), default="qft24")
+    ap.add_argument("--workload", choices=("qft24", "grover36", "batch64", "serve512"),
+                    default="qft24")
+    ap.add_argument("--rate", type=float, default=SERVE_RATE,
+                    help="serve512 arrival rate (requests/s); default: 0.7 x the "
+                         "saturated batched throughput, measured first")
+    ap.add_argument("--requests", type=int, default=512, help="serve512 request count")
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default 5 for qft24, 1 for grover36)")
     ap.add_argument("--warmup", type=int, default=None,
@@ -408,6 +511,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.workload == "batch64":
         print(json.dumps(bench_batch64(args, A, inputs, stream)), flush=True)
+        return
+    if args.workload == "serve512":
+        print(json.dumps(bench_serve(args, A, inputs, stream)), flush=True)
         return
     w = inputs.grover36_workload() if grover else inputs.qft24_workload()
     n, b, x, gates = w["n"], w["b"], w["basis"], w["gates"]
