@@ -174,7 +174,7 @@ struct BatchLaunch {
     const uint64_t *upre, *bpre, *mpre, *mbpre;
     uint32_t nst;
     unsigned grid_units, grid_blocks;
-    bool any_mean, any_ladder, any_big;
+    bool any_mean, any_ladder;
 };
 void launch_batch_pass(const BatchLaunch &b, hipStream_t st, Prof *prof);
 // Arena chunk a workgroup takes per bump-pointer update.

@@ -230,6 +230,20 @@ __device__ __forceinline__ uint32_t sw(uint32_t o)
     return (o & ~63u) | ((o & 2u) << 4) | ((o >> 1) & 0x1Eu) | (o & 1u);
 }
 
+// In-plane scalar stored at LDS position pos (inverse of sw).
+__device__ __forceinline__ uint32_t unsw(uint32_t pos)
+{
+    return (pos & ~63u) | (((pos >> 1) & 15u) << 2) | (((pos >> 5) & 1u) << 1) | (pos & 1u);
+}
+
+// sw is a permutation of the index bits (bit 0 stays, bit 1 -> 5, bits 2..5
+// -> 1..4, higher bits stay), so it maps an xor mask to an xor mask and bit k
+// of o to bit sw_bit(k) of the position.
+__device__ __forceinline__ int sw_bit(int k)
+{
+    return k == 0 ? 0 : (k == 1 ? 5 : (k < 6 ? k - 1 : k));
+}
+
 // ---- codec layout: a wavefront works on four chunks at a time, row r
 // (lanes 16r .. 16r+15) on chunk 4t + r in step t, lane p of the row on the
 // four consecutive scalars 4p .. 4p+3 of that chunk.  Chunk widths are row
@@ -377,6 +391,9 @@ __device__ void load_unit(const PassArgs &a, const Unit &uc, Planes &X,
 __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
                           const double *tdiff)
 {
+    // Loops run over LDS positions (consecutive lanes on consecutive
+    // positions, conflict-free); the amplitude index of a position comes
+    // from unsw, and a pair partner is an xor in position space too.
     const int tid = threadIdx.x;
     if (G.kind == kNone)
         return;
@@ -384,49 +401,49 @@ __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
     const uint64_t Ms = M >> s;
     const uint32_t S = 1u << s;
     const uint32_t Ml = (uint32_t)(M & (S - 1));
+    const uint32_t Pl = sw(Ml);
     if (M == 0) {
         const uint32_t total = (uint32_t)uc.nsu << s;
         for (uint32_t t = tid; t < total; t += kWG) {
             const int us = (int)(t >> s);
-            const uint32_t o = t & (S - 1);
-            const uint64_t i = (uc.seg(us) << s) | o;
-            const uint32_t so = sw(o);
-            double ar = X[us][0][so], ai = X[us][1][so];
+            const uint32_t pos = t & (S - 1);
+            const uint64_t i = (uc.seg(us) << s) | unsw(pos);
+            double ar = X[us][0][pos], ai = X[us][1][pos];
             gate_diag(G, i, ar, ai, tdiff);
-            X[us][0][so] = ar;
-            X[us][1][so] = ai;
+            X[us][0][pos] = ar;
+            X[us][1][pos] = ai;
         }
     } else if (Ms) {
-        for (uint32_t o = tid; o < S; o += kWG) {
-            const uint32_t o2 = o ^ Ml;
-            const uint64_t i = (uc.g[0] << s) | o;
-            const uint32_t so = sw(o), so2 = sw(o2);
-            double ar = X[0][0][so], ai = X[0][1][so];
-            double br = X[1][0][so2], bi = X[1][1][so2];
+        for (uint32_t pos = tid; pos < S; pos += kWG) {
+            const uint32_t pos2 = pos ^ Pl;
+            const uint64_t i = (uc.g[0] << s) | unsw(pos);
+            double ar = X[0][0][pos], ai = X[0][1][pos];
+            double br = X[1][0][pos2], bi = X[1][1][pos2];
             gate_pair(G, i, ar, ai, br, bi);
-            X[0][0][so] = ar;
-            X[0][1][so] = ai;
-            X[1][0][so2] = br;
-            X[1][1][so2] = bi;
+            X[0][0][pos] = ar;
+            X[0][1][pos] = ai;
+            X[1][0][pos2] = br;
+            X[1][1][pos2] = bi;
         }
     } else {
+        // pairs (o, o ^ Ml) with bit hb of o clear: in positions, bit pb clear
         const int hb = 31 - __builtin_clz(Ml);
+        const int pb = sw_bit(hb);
         const uint32_t half = S >> 1;
         const uint32_t total = (uint32_t)uc.nsu * half;
         for (uint32_t t = tid; t < total; t += kWG) {
             const int us = (int)(t >> (s - 1));
             const uint32_t r = t & (half - 1);
-            const uint32_t o = ((r >> hb) << (hb + 1)) | (r & ((1u << hb) - 1));
-            const uint32_t o2 = o ^ Ml;
-            const uint64_t i = (uc.seg(us) << s) | o;
-            const uint32_t so = sw(o), so2 = sw(o2);
-            double ar = X[us][0][so], ai = X[us][1][so];
-            double br = X[us][0][so2], bi = X[us][1][so2];
+            const uint32_t pos = ((r >> pb) << (pb + 1)) | (r & ((1u << pb) - 1));
+            const uint32_t pos2 = pos ^ Pl;
+            const uint64_t i = (uc.seg(us) << s) | unsw(pos);
+            double ar = X[us][0][pos], ai = X[us][1][pos];
+            double br = X[us][0][pos2], bi = X[us][1][pos2];
             gate_pair(G, i, ar, ai, br, bi);
-            X[us][0][so] = ar;
-            X[us][1][so] = ai;
-            X[us][0][so2] = br;
-            X[us][1][so2] = bi;
+            X[us][0][pos] = ar;
+            X[us][1][pos] = ai;
+            X[us][0][pos2] = br;
+            X[us][1][pos2] = bi;
         }
     }
 }
@@ -724,6 +741,58 @@ __device__ void encode_plane(double *x, int s, double delta, double e, double r,
 
 // Pairwise sums of a unit's segments: leaf(o) for the amplitudes of segment
 // us, tree over o; the two waves of a segment each reduce one half.
+constexpr int kRowMirror = 0x140, kRowHalfMirror = 0x141;
+
+// Perfect pairwise tree over the 64 lanes' values of a wave (exact order:
+// xor-1 and xor-2 partners by quad permutes, then the other half-row and
+// row by mirrors, each lane holding its aligned group's sum; rows combined
+// as (r0 + r1) + (r2 + r3)).  Valid in every lane.
+__device__ __forceinline__ double wave_tree_sum(double v)
+{
+    auto dv = [](uint64_t u) { return __longlong_as_double((long long)u); };
+    auto du = [](double d) { return (uint64_t)__double_as_longlong(d); };
+    v = v + dv(dpp64<kQuadXor1>(0ull, du(v)));
+    v = v + dv(dpp64<kQuadXor2>(0ull, du(v)));
+    v = v + dv(dpp64<kRowHalfMirror>(0ull, du(v)));
+    v = v + dv(dpp64<kRowMirror>(0ull, du(v)));
+    const double r0 = dv(readlane64(du(v), 0)), r1 = dv(readlane64(du(v), 16));
+    const double r2 = dv(readlane64(du(v), 32)), r3 = dv(readlane64(du(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+// segment_tree for s = 10 with a leaf f(re, im) of both planes: lane L of
+// a wave sums the 8 consecutive scalars 8L .. 8L+7 of its half segment, which
+// sit in two 4-double runs of the swizzled layout.
+template <class F>
+__device__ double segment_tree10(const Unit &uc, const Planes &X, double *red, F f)
+{
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int us = wave >> 1, half = wave & 1;
+    double v = 0.0;
+    if (us < uc.nsu) {
+        const int base = (half * 8 + (lane >> 3)) * kChunk + 4 * (lane & 7);
+        const double2 *ra = (const double2 *)&X[us][0][base];
+        const double2 *rb = (const double2 *)&X[us][0][base + 32];
+        const double2 *ia = (const double2 *)&X[us][1][base];
+        const double2 *ib = (const double2 *)&X[us][1][base + 32];
+        const double2 r01 = ra[0], r45 = ra[1], r23 = rb[0], r67 = rb[1];
+        const double2 i01 = ia[0], i45 = ia[1], i23 = ib[0], i67 = ib[1];
+        const double f0 = f(r01.x, i01.x), f1 = f(r01.y, i01.y);
+        const double f2 = f(r23.x, i23.x), f3 = f(r23.y, i23.y);
+        const double f4 = f(r45.x, i45.x), f5 = f(r45.y, i45.y);
+        const double f6 = f(r67.x, i67.x), f7 = f(r67.y, i67.y);
+        v = wave_tree_sum(((f0 + f1) + (f2 + f3)) + ((f4 + f5) + (f6 + f7)));
+    }
+    if (lane == 0)
+        red[wave] = v;
+    __syncthreads();
+    double out = 0.0;
+    if (threadIdx.x < (unsigned)uc.nsu)
+        out = red[2 * threadIdx.x] + red[2 * threadIdx.x + 1];
+    __syncthreads();
+    return out;
+}
+
 template <class Leaf>
 __device__ double segment_tree(const Unit &uc, int s, double *red, Leaf leaf)
 {
@@ -877,12 +946,18 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
                      wreg, a.arena_out + off, &S.pack[wave][0], &a.dev->err);
     }
     __syncthreads();
-    const double ns = segment_tree(uc, s, red, [&](int su, int o) {
-        const double re = X[su][0][sw(o)], im = X[su][1][sw(o)];
-        const double rr = re * re;
-        const double ii = im * im;
-        return rr + ii;
-    });
+    const double ns = s == kMaxS
+        ? segment_tree10(uc, X, red, [](double re, double im) {
+              const double rr = re * re;
+              const double ii = im * im;
+              return rr + ii;
+          })
+        : segment_tree(uc, s, red, [&](int su, int o) {
+              const double re = X[su][0][sw(o)], im = X[su][1][sw(o)];
+              const double rr = re * re;
+              const double ii = im * im;
+              return rr + ii;
+          });
     if (threadIdx.x < (unsigned)uc.nsu) {
         const uint64_t gs = uc.seg((int)threadIdx.x);
         if (MODE == kFused || (gs >> bs) == jsel)
@@ -985,8 +1060,9 @@ __device__ void mean_unit(const PassArgs &a, uint64_t u, Planes &X, double *red,
     load_unit(a, uc, X, scale, scale != 1.0);
     __syncthreads();
     for (int c = 0; c < 2; ++c) {
-        const double sm = segment_tree(uc, a.geo.s, red,
-                                       [&](int su, int o) { return X[su][c][sw(o)]; });
+        const double sm = a.geo.s == kMaxS
+            ? segment_tree10(uc, X, red, [c](double re, double im) { return c ? im : re; })
+            : segment_tree(uc, a.geo.s, red, [&](int su, int o) { return X[su][c][sw(o)]; });
         if (threadIdx.x < (unsigned)uc.nsu)
             a.segsum[(uint64_t)c * a.geo.nseg + uc.seg((int)threadIdx.x)] = sm;
     }
@@ -1005,9 +1081,6 @@ __global__ __launch_bounds__(kWG) void k_mean(PassArgs a)
 }
 
 // ------------------------------------------------------ reductions --------
-
-// Largest segment count whose N^2 tree one workgroup forms directly.
-constexpr uint64_t kReduceDirect = 1ull << 13;
 
 // Pairwise sum of PER consecutive values, fully unrolled in registers.
 template <int PER, class Load>
@@ -1072,6 +1145,42 @@ __device__ double wg_tree(Load load, uint64_t m, double *lds)
     const double r = lds[0];
     __syncthreads();
     return r;
+}
+
+// Pairwise sum of m = 2^k non-negative values src[0..m) by one wavefront
+// (lanes take aligned runs of m/64, or one value each with zero padding
+// when m < 64, which leaves every sum of real values unchanged).
+__device__ double wave_pairwise(const double *src, uint64_t m)
+{
+    const int lane = lane_id();
+    double v;
+    if (m >= 64) {
+        const uint64_t per = m / 64;
+        const uint64_t base = lane * per;
+        auto load = [&](uint64_t i) { return src[i]; };
+        switch (per) {
+        case 1: v = seq_tree<1>(load, base); break;
+        case 2: v = seq_tree<2>(load, base); break;
+        case 4: v = seq_tree<4>(load, base); break;
+        case 8: v = seq_tree<8>(load, base); break;
+        case 16: v = seq_tree<16>(load, base); break;
+        case 32: v = seq_tree<32>(load, base); break;
+        default: {
+            double stack[40];
+            int sp = 0;
+            for (uint64_t i = 0; i < per / 32; ++i) {
+                double x = seq_tree<32>(load, base + 32 * i);
+                for (uint64_t k = i; k & 1; k >>= 1)
+                    x = stack[--sp] + x;
+                stack[sp++] = x;
+            }
+            v = stack[0];
+        }
+        }
+    } else {
+        v = (uint64_t)lane < m ? src[lane] : 0.0;
+    }
+    return wave_tree_sum(v);
 }
 
 // dst[j] = pairwise(src[j*per .. (j+1)*per)) for j < nout; with write_hdr,
@@ -1167,51 +1276,82 @@ __device__ void finalize_block(const PassArgs &a, uint64_t j, int d, uint64_t le
 // reaches theta.  When that is the speculated level h the block is done;
 // another level sends the block to the replay list; when none qualifies and
 // levels above h remain, the block joins the escalation list.
-__device__ void decide_block(const PassArgs &a, uint64_t j, uint64_t *red, uint64_t *tot,
-                             uint64_t *nout);
+__device__ void decide_block(const PassArgs &a, uint64_t j);
 
+// One wavefront per block.
 __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
 {
     if (a.dev->err)
         return;
-    __shared__ uint64_t red[kWG];
-    __shared__ uint64_t tot[kMaxL];
-    __shared__ uint64_t nout[kMaxL];
-    for (uint64_t j = blockIdx.x; j < a.geo.nblocks; j += gridDim.x)
-        decide_block(a, j, red, tot, nout);
+    const uint64_t nw = (uint64_t)gridDim.x * (kWG / 64);
+    for (uint64_t j = (uint64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
+         j < a.geo.nblocks; j += nw)
+        decide_block(a, j);
 }
 
-__device__ void decide_block(const PassArgs &a, uint64_t j, uint64_t *red, uint64_t *tot,
-                             uint64_t *nout)
+__device__ void decide_block(const PassArgs &a, uint64_t j)
 {
+    // sizes of levels 0..h summed over the block's planes by one wavefront
+    const int lane = lane_id();
     const int L = a.lad.L;
-    const double raw = (double)(16ull << a.geo.b);
-    {
-        const int h = hint_level(a, j);
-        block_totals(a, j, 0, h, red, tot, nout);
-        if (threadIdx.x == 0) {
-            int d = -1;
-            for (int k = 0; k <= h; ++k)
-                if (raw >= a.lad.theta * (double)tot[k]) {
-                    d = k;
-                    break;
-                }
-            if (d < 0 && h == L - 1)
-                d = L - 1;
-            if (d < 0) {
-                const uint32_t slot = atomicAdd(&a.dev->n_esc, 1u);
-                a.esc_list[slot] = (uint32_t)j;
-                atomicAdd((unsigned long long *)&a.dev->escalations, 1ull);
-            } else {
-                finalize_block(a, j, d, tot[d], nout[d]);
-                if (d != h) {
-                    const uint32_t slot = atomicAdd(&a.dev->n_replay, 1u);
-                    a.replay_list[slot] = (uint32_t)j;
-                    atomicAdd((unsigned long long *)&a.dev->replays, 1ull);
-                }
+    const int h = hint_level(a, j);
+    const uint64_t npb = 2ull << (a.geo.b - a.geo.s);
+    const uint64_t nplanes = 2 * a.geo.nseg;
+    const uint32_t padC = pad8(1u << (a.geo.s - 6));
+    const uint64_t base = j * npb;
+    uint64_t by[kMaxL];
+    uint32_t no[kMaxL];
+#pragma unroll
+    for (int k = 0; k < kMaxL; ++k) {
+        by[k] = 0;
+        no[k] = 0;
+    }
+    for (uint64_t q = lane; q < npb; q += 64) {
+#pragma unroll
+        for (int k = 0; k < kMaxL; ++k) {
+            if (k <= h) {
+                const uint32_t v = a.psz[(uint64_t)k * nplanes + base + q];
+                by[k] += rec_bytes(v, padC);
+                no[k] += v >> 16;
             }
         }
-        __syncthreads();
+    }
+    const double raw = (double)(16ull << a.geo.b);
+    int d = -1;
+    uint64_t tot_d = 0, nout_d = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxL; ++k) {
+        if (k <= h && d < 0) {
+            const uint64_t tk = readlane64(wave_scan64(by[k]), 63) + kHdrBytes;
+            if (raw >= a.lad.theta * (double)tk || (k == h && h == L - 1)) {
+                d = k;
+                tot_d = tk;
+                nout_d = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan32(no[k]), 63);
+            }
+        }
+    }
+    if (d < 0) {
+        if (lane == 0) {
+            const uint32_t slot = atomicAdd(&a.dev->n_esc, 1u);
+            a.esc_list[slot] = (uint32_t)j;
+            atomicAdd((unsigned long long *)&a.dev->escalations, 1ull);
+        }
+        return;
+    }
+    if (lane == 0) {
+        finalize_block(a, j, d, tot_d, nout_d);
+        if (d != h) {
+            const uint32_t slot = atomicAdd(&a.dev->n_replay, 1u);
+            a.replay_list[slot] = (uint32_t)j;
+            atomicAdd((unsigned long long *)&a.dev->replays, 1ull);
+        }
+    }
+    if (d == h) {
+        // the block's streams are final: its normsq from its segment sums
+        const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
+        const double v = wave_pairwise(a.dout.segnorm + j * spb, spb);
+        if (lane == 0)
+            a.blknorm[j] = v;
     }
 }
 
@@ -1255,20 +1395,42 @@ __global__ __launch_bounds__(kWG) void k_reduce(PassArgs a)
 
 __device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures)
 {
-    const int t = threadIdx.x;
-    const bool by_block = a.geo.nseg > kReduceDirect;
-    const double N2 = by_block
-        ? wg_tree([&](uint64_t i) { return a.blknorm[i]; }, a.geo.nblocks, lds)
-        : wg_tree([&](uint64_t i) { return a.dout.segnorm[i]; }, a.geo.nseg, lds);
-    uint64_t by = 0;
-    for (uint64_t j = t; j < a.geo.nblocks; j += kWG)
-        by += a.dout.blk_len[j];
-    ures[t] = by;
+    const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
+    // normsq of the blocks that were re-encoded after k_decide
+    const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
+    const uint32_t nrep = a.dev->n_replay, nfix = nrep + a.dev->n_esc;
+    for (uint32_t k = (uint32_t)wave; k < nfix; k += kWG / 64) {
+        const uint64_t j = k < nrep ? a.replay_list[k] : a.esc_list[k - nrep];
+        const double v = wave_pairwise(a.dout.segnorm + j * spb, spb);
+        if (lane == 0)
+            a.blknorm[j] = v;
+    }
     __syncthreads();
-    for (int st = kWG / 2; st > 0; st >>= 1) {
-        if (t < st)
-            ures[t] += ures[t + st];
+    // N^2: one pairwise tree over the block norms (aligned subtrees)
+    const uint64_t nb = a.geo.nblocks;
+    double N2;
+    uint64_t res = 0;
+    if (nb <= 4096) {
+        N2 = wave == 0 ? wave_pairwise(a.blknorm, nb) : 0.0;
+        if (wave == 0) {
+            uint64_t by = 0;
+            for (uint64_t j = lane; j < nb; j += 64)
+                by += a.dout.blk_len[j];
+            res = readlane64(wave_scan64(by), 63);
+        }
+    } else {
+        N2 = wg_tree([&](uint64_t i) { return a.blknorm[i]; }, nb, lds);
+        uint64_t by = 0;
+        for (uint64_t j = t; j < nb; j += kWG)
+            by += a.dout.blk_len[j];
+        ures[t] = by;
         __syncthreads();
+        for (int st = kWG / 2; st > 0; st >>= 1) {
+            if (t < st)
+                ures[t] += ures[t + st];
+            __syncthreads();
+        }
+        res = ures[0];
     }
     if (t == 0) {
         DevState *d = a.dev;
@@ -1280,7 +1442,6 @@ __device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures)
             d->collapsed = 1;
             d->scale = 1.0;
         }
-        const uint64_t res = ures[0];
         d->resident = res;
         if (res > d->peak_resident)
             d->peak_resident = res;
@@ -1657,16 +1818,15 @@ __global__ __launch_bounds__(kWG) void k_bdecide(const PassArgs *__restrict__ ar
                                                  const uint64_t *__restrict__ bpre,
                                                  uint32_t nst)
 {
-    __shared__ uint64_t red[kWG];
-    __shared__ uint64_t tot[kMaxL];
-    __shared__ uint64_t nout[kMaxL];
     const uint64_t total = bpre[nst];
-    for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const uint64_t nw = (uint64_t)gridDim.x * (kWG / 64);
+    for (uint64_t it = (uint64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6); it < total;
+         it += nw) {
         const uint32_t st = state_of(bpre, nst, it);
         const PassArgs &a = args[st];
         if (a.dev->err)
             continue;
-        decide_block(a, it - bpre[st], red, tot, nout);
+        decide_block(a, it - bpre[st]);
     }
 }
 
@@ -1693,27 +1853,6 @@ __global__ __launch_bounds__(kWG) void k_bfix(const PassArgs *__restrict__ args,
             fix_body(args[base + l], blockIdx.x, gridDim.x, S);
             __syncthreads();
         }
-    }
-}
-
-// Block normsq of the states with more than kReduceDirect segments.
-__global__ __launch_bounds__(kWG) void k_bblocknorm(const PassArgs *__restrict__ args,
-                                                    const uint64_t *__restrict__ bpre,
-                                                    uint32_t nst)
-{
-    __shared__ double lds[kWG];
-    const uint64_t total = bpre[nst];
-    for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
-        const uint32_t st = state_of(bpre, nst, it);
-        const PassArgs &a = args[st];
-        if (a.geo.nseg <= kReduceDirect || a.dev->err)
-            continue;
-        const uint64_t j = it - bpre[st];
-        const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
-        const double *src = a.dout.segnorm + j * spb;
-        const double v = wg_tree([&](uint64_t i) { return src[i]; }, spb, lds);
-        if (threadIdx.x == 0)
-            a.blknorm[j] = v;
     }
 }
 
@@ -1849,7 +1988,7 @@ uint64_t batch_chunk_bytes(uint64_t arena_cap, unsigned grid);
 void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *prof)
 {
     const unsigned gu = grid_for(a0.geo.nunits < grid_cap ? a0.geo.nunits : grid_cap);
-    const unsigned gb = grid_for(a0.geo.nblocks);
+    const unsigned gb = grid_for((a0.geo.nblocks + 3) / 4);
     const unsigned gfix = gu;
     PassArgs a = a0;
     a.chunk_bytes = batch_chunk_bytes(a.arena_cap, gu);
@@ -1857,11 +1996,6 @@ void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *pr
     TIMED(prof, kIdDecide, st, hipLaunchKernelGGL(k_decide, dim3(gb), dim3(kWG), 0, st, a));
     if (a.lad.L > 1)
         TIMED(prof, kIdReplay, st, hipLaunchKernelGGL(k_fix, dim3(gfix), dim3(kWG), 0, st, a));
-    if (a.geo.nseg > kReduceDirect)
-        TIMED(prof, kIdBlockNorm, st,
-              hipLaunchKernelGGL(k_segtree, dim3(gb), dim3(kWG), 0, st, a,
-                                 (const double *)a.dout.segnorm, a.blknorm,
-                                 1ull << (a.geo.b - a.geo.s), a.geo.nblocks, 0));
     TIMED(prof, kIdReduce, st, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, a));
 }
 
@@ -1881,16 +2015,12 @@ void launch_batch_pass(const BatchLaunch &b, hipStream_t st, Prof *prof)
           hipLaunchKernelGGL(k_bpass, dim3(b.grid_units), dim3(kWG), 0, st, b.args, b.upre,
                              b.nst));
     TIMED(prof, kIdDecide, st,
-          hipLaunchKernelGGL(k_bdecide, dim3(b.grid_blocks), dim3(kWG), 0, st, b.args, b.bpre,
-                             b.nst));
+          hipLaunchKernelGGL(k_bdecide, dim3((b.grid_blocks + 3) / 4), dim3(kWG), 0, st,
+                             b.args, b.bpre, b.nst));
     if (b.any_ladder)
         TIMED(prof, kIdReplay, st,
               hipLaunchKernelGGL(k_bfix, dim3(b.grid_units), dim3(kWG), 0, st, b.args, b.upre,
                                  b.nst));
-    if (b.any_big)
-        TIMED(prof, kIdBlockNorm, st,
-              hipLaunchKernelGGL(k_bblocknorm, dim3(b.grid_blocks), dim3(kWG), 0, st, b.args,
-                                 b.bpre, b.nst));
     TIMED(prof, kIdReduce, st,
           hipLaunchKernelGGL(k_breduce, dim3(b.nst), dim3(kWG), 0, st, b.args, b.upre));
 }

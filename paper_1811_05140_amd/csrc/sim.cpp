@@ -1080,7 +1080,7 @@ void destroy_graph(sim_batch::Graph &G)
 }
 
 BatchLaunch slot_launch(const sim_batch *B, int p, uint32_t nst, unsigned gu, unsigned gb,
-                        bool mean, bool ladder, bool big)
+                        bool mean, bool ladder)
 {
     const uint8_t *base = B->dslots + (size_t)p * B->slot_bytes;
     const uint64_t *pre = (const uint64_t *)(base + slot_prefix_off(B->max_states));
@@ -1096,7 +1096,6 @@ BatchLaunch slot_launch(const sim_batch *B, int p, uint32_t nst, unsigned gu, un
     L.grid_blocks = gb;
     L.any_mean = mean;
     L.any_ladder = ladder;
-    L.any_big = big;
     return L;
 }
 
@@ -1180,7 +1179,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
                     count, passes, B->max_states, B->max_passes);
     // validate everything before queuing anything
     uint64_t units = 0, blocks = 0;
-    bool ladder = false, big = false;
+    bool ladder = false;
     for (int k = 0; k < count; ++k) {
         sim *S = sims[k];
         if (!S)
@@ -1195,7 +1194,6 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
         units += S->geo.nunits;
         blocks += S->geo.nblocks;
         ladder = ladder || S->lad.L > 1;
-        big = big || S->geo.nseg > (1ull << 13);
         for (int p = 0; p < passes; ++p) {
             const sim_gate_t *g = &gates[(size_t)p * count + k];
             if (g->kind == 0 && g->pad == 0)
@@ -1220,7 +1218,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
     put((uint64_t)count);
     put((uint64_t)passes);
     put((uint64_t)gu | ((uint64_t)gb << 32));
-    put((uint64_t)ladder | ((uint64_t)big << 1));
+    put((uint64_t)ladder);
     std::vector<uint8_t> mean_of(passes, 0);
     for (int p = 0; p < passes; ++p) {
         uint8_t *slot = B->hslots + (size_t)p * B->slot_bytes;
@@ -1285,7 +1283,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
             HIPCHK(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
             for (int p = 0; p < passes; ++p)
                 launch_batch_pass(slot_launch(B, p, (uint32_t)count, gu, gb, mean_of[p] != 0,
-                                              ladder, big),
+                                              ladder),
                                   B->stream, nullptr);
             hipError_t e = hipStreamEndCapture(B->stream, &fresh.g);
             if (e == hipSuccess)
@@ -1303,7 +1301,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
     } else {
         for (int p = 0; p < passes; ++p)
             launch_batch_pass(slot_launch(B, p, (uint32_t)count, gu, gb, mean_of[p] != 0,
-                                          ladder, big),
+                                          ladder),
                               B->stream, B->prof);
         HIPCHK(hipGetLastError());
     }
