@@ -1299,6 +1299,10 @@ __device__ void decide_block(const PassArgs &a, uint64_t j)
     const uint64_t nplanes = 2 * a.geo.nseg;
     const uint32_t padC = pad8(1u << (a.geo.s - 6));
     const uint64_t base = j * npb;
+    // the block's segment norms, loaded early (used when the block is final)
+    const uint64_t spb = npb >> 1;
+    const double *segn = a.dout.segnorm + j * spb;
+    const double sn0 = (spb <= 64 && (uint64_t)lane < spb) ? segn[lane] : 0.0;
     uint64_t by[kMaxL];
     uint32_t no[kMaxL];
 #pragma unroll
@@ -1348,8 +1352,8 @@ __device__ void decide_block(const PassArgs &a, uint64_t j)
     }
     if (d == h) {
         // the block's streams are final: its normsq from its segment sums
-        const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
-        const double v = wave_pairwise(a.dout.segnorm + j * spb, spb);
+        // (for up to 64 segments one per lane, zero-padded: norms are >= +0)
+        const double v = spb <= 64 ? wave_tree_sum(sn0) : wave_pairwise(segn, spb);
         if (lane == 0)
             a.blknorm[j] = v;
     }
@@ -1989,7 +1993,9 @@ void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *pr
 {
     const unsigned gu = grid_for(a0.geo.nunits < grid_cap ? a0.geo.nunits : grid_cap);
     const unsigned gb = grid_for((a0.geo.nblocks + 3) / 4);
-    const unsigned gfix = gu;
+    // replays are a few blocks per pass at most; a small grid launches and
+    // retires faster when there are none
+    const unsigned gfix = gu < 256 ? gu : 256;
     PassArgs a = a0;
     a.chunk_bytes = batch_chunk_bytes(a.arena_cap, gu);
     TIMED(prof, kIdPass, st, hipLaunchKernelGGL(k_pass, dim3(gu), dim3(kWG), 0, st, a));
