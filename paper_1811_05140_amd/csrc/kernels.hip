@@ -258,22 +258,16 @@ __device__ __forceinline__ uint32_t field32(const uint32_t *P, uint32_t b, uint3
     return w >= 32u ? v : (v & ((1u << w) - 1u));
 }
 
-// Field of width w (<= 64) at bit b.
+// Field of width w (<= 64) at bit b (branch-free, so that a lane's four
+// field loads can be issued together).
 __device__ __forceinline__ uint64_t field64(const uint32_t *P, uint32_t b, uint32_t w)
 {
     const uint32_t k = b >> 5, sh = b & 31u;
     const uint32_t d0 = P[k], d1 = P[k + 1], d2 = P[k + 2];
-    uint32_t lo = __builtin_amdgcn_alignbit(d1, d0, sh);
-    uint32_t hi = __builtin_amdgcn_alignbit(d2, d1, sh);
-    if (w < 32u) {
-        lo &= (1u << w) - 1u;
-        hi = 0u;
-    } else if (w == 32u) {
-        hi = 0u;
-    } else if (w < 64u) {
-        hi &= (1u << (w - 32u)) - 1u;
-    }
-    return ((uint64_t)hi << 32) | lo;
+    const uint32_t lo = __builtin_amdgcn_alignbit(d1, d0, sh);
+    const uint32_t hi = __builtin_amdgcn_alignbit(d2, d1, sh);
+    const uint64_t v = ((uint64_t)hi << 32) | lo;
+    return w >= 64u ? v : (v & ((1ull << w) - 1ull));
 }
 
 // Chunk widths (lanes 0..C-1) and their exclusive prefix (payload word
@@ -317,10 +311,18 @@ __device__ void decode_plane(const uint8_t *rec, int s, double delta,
         const uint32_t b0 = (uint32_t)(4 * p) * w;
         double x[4];
         if (delta == 0.0) {
-            uint64_t d[4];
+            // one branch around all four fields, so their loads are in flight together
+            uint64_t d[4] = {0ull, 0ull, 0ull, 0ull};
+            if (w) {
+                uint64_t f[4];
+                uint32_t bi = b0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                d[i] = w ? unzigzag64(field64(P, b0 + (uint32_t)i * w, w)) : 0ull;
+                for (int i = 0; i < 4; ++i, bi += w)
+                    f[i] = field64(P, bi, w);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    d[i] = unzigzag64(f[i]);
+            }
             const uint64_t s1 = d[0] + d[1], s2 = s1 + d[2], s3 = s2 + d[3];
             const uint64_t incl = wave_scan64(s3);
             const uint64_t base = carry + (incl - s3);
@@ -331,11 +333,16 @@ __device__ void decode_plane(const uint8_t *rec, int s, double delta,
             x[2] = __longlong_as_double((long long)q2);
             x[3] = __longlong_as_double((long long)q3);
         } else {
-            uint32_t d[4];
+            uint32_t d[4] = {0u, 0u, 0u, 0u};
+            if (w) {
+                uint32_t z[4];
+                uint32_t bi = b0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t z = w ? field32(P, b0 + (uint32_t)i * w, w) : 0u;
-                d[i] = (z >> 1) ^ (0u - (z & 1u));
+                for (int i = 0; i < 4; ++i, bi += w)
+                    z[i] = field32(P, bi, w);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    d[i] = (z[i] >> 1) ^ (0u - (z[i] & 1u));
             }
             const uint32_t s1 = d[0] + d[1], s2 = s1 + d[2], s3 = s2 + d[3];
             const uint32_t incl = wave_scan32(s3);
