@@ -859,7 +859,38 @@ struct PassLds {
     uint32_t pack[4][4 * kPackRow];
     uint64_t misc[9];  // segment sums, then record bytes + base
     uint64_t chunk[2]; // this workgroup's current arena chunk [cur, end)
+    uint32_t zero[4];  // per wave: its input plane is all +0
 };
+
+// Whether the gate maps amplitudes that are +0 in both components to +0 in
+// both, for every amplitude index, as evaluated by the gate code itself (a
+// product with a negative matrix entry or a negation yields -0, whose
+// lossless code differs from +0's).  Then a unit whose input planes are all
+// +0 has all-+0 output planes.
+__device__ __forceinline__ bool zero_preserving(const GateArg &G)
+{
+    auto pz = [](double v) { return __double_as_longlong(v) == 0; };
+    switch (G.kind) {
+    case kX:
+    case kSwap:
+        return true;
+    case kU:
+    case kCU: {
+        double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+        gate_pair(G, ~0ull, ar, ai, br, bi);
+        return pz(ar) && pz(ai) && pz(br) && pz(bi);
+    }
+    case kDiag1:
+    case kCPhase:
+    case kCZ: {
+        double ar = 0.0, ai = 0.0;
+        gate_diag(G, ~0ull, ar, ai, nullptr);
+        return pz(ar) && pz(ai);
+    }
+    default:
+        return false;
+    }
+}
 
 // Arena space is taken from the shared bump pointer in chunks of
 // PassArgs::chunk_bytes (or one unit's need, if larger) and handed out unit by
@@ -874,14 +905,98 @@ struct PassLds {
 //   kReplay: encode the planes of block jsel at its chosen level;
 // records are bump-allocated per unit; per-segment normsq of what was
 // encoded.
+// Bump-allocate `mine ? bytes : 0` per wave for this unit's records (all
+// threads); returns this wave's offset, or ~0 when the arena is full (the
+// error is recorded).
+__device__ uint64_t alloc_records(const PassArgs &a, PassLds &S, bool mine, uint64_t bytes)
+{
+    uint64_t *rbytes = S.misc;
+    uint64_t &rbase = S.misc[8];
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    if (lane == 0)
+        rbytes[wave] = mine ? bytes : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint64_t tot = rbytes[0] + rbytes[1] + rbytes[2] + rbytes[3];
+        uint64_t base = 0;
+        if (tot) {
+            if (S.chunk[0] + tot > S.chunk[1]) {
+                const uint64_t want = tot > a.chunk_bytes ? tot : a.chunk_bytes;
+                const uint64_t b0 = atomicAdd(
+                    (unsigned long long *)&a.dev->arena_used[a.out_arena],
+                    (unsigned long long)want);
+                S.chunk[0] = b0;
+                S.chunk[1] = b0 + want;
+            }
+            base = S.chunk[0];
+            S.chunk[0] += tot;
+            if (base + tot > a.arena_cap) {
+                if (atomicOr(&a.dev->err, kErrArena) == 0)
+                    a.dev->err_pass = (uint32_t)a.pass;
+                base = ~0ull;
+            }
+        }
+        rbase = base;
+    }
+    __syncthreads();
+    if (rbase == ~0ull)
+        return ~0ull;
+    uint64_t off = rbase;
+    for (int w2 = 0; w2 < wave; ++w2)
+        off += rbytes[w2];
+    return off;
+}
+
+// Output of a unit whose four input planes are all +0 under a zero-preserving
+// gate: every plane is +0 at every level, so each sized level has no payload
+// and no outliers, each record is its 16-byte header of zeros, and every
+// segment's normsq is +0 -- exactly what the full path computes for it.
+template <int MODE>
+__device__ void zero_unit(const PassArgs &a, const Unit &uc, uint64_t jsel, PassLds &S)
+{
+    const int s = a.geo.s;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int us = wave >> 1, p = wave & 1;
+    const int bs = a.geo.b - s;
+    const uint64_t nplanes = 2 * a.geo.nseg;
+    const bool active = us < uc.nsu;
+    const uint64_t g = active ? uc.seg(us) : 0;
+    const uint64_t j = g >> bs;
+    const uint64_t plane = 2 * g + p;
+    const bool mine = active && (MODE == kFused || j == jsel);
+    if (mine && lane == 0) {
+        const int h = hint_level(a, j);
+        int k0 = 0, k1 = h;
+        if (MODE == kEsc) {
+            k0 = h + 1;
+            k1 = a.lad.L - 1;
+        } else if (MODE == kReplay) {
+            k0 = k1 = a.dout.blk_level[j];
+        }
+        for (int k = k0; k <= k1; ++k)
+            a.psz[(uint64_t)k * nplanes + plane] = 0u;
+    }
+    if (MODE == kEsc)
+        return;
+    const uint64_t off = alloc_records(a, S, mine, kPlaneHdrBytes);
+    if (mine && off != ~0ull && lane < 2) {
+        ((uint64_t *)(a.arena_out + off))[lane] = 0ull;
+        if (lane == 0)
+            a.dout.plane_off[plane] = off;
+    }
+    if (threadIdx.x < (unsigned)uc.nsu) {
+        const uint64_t gs = uc.seg((int)threadIdx.x);
+        if (MODE == kFused || (gs >> bs) == jsel)
+            a.dout.segnorm[gs] = 0.0;
+    }
+}
+
 template <int MODE>
 __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, PassLds &S,
-                          double scale, const double *tdiff)
+                          double scale, const double *tdiff, bool zp)
 {
     Planes &X = S.X;
     double *red = (double *)S.misc;
-    uint64_t *rbytes = S.misc;
-    uint64_t &rbase = S.misc[8];
     const int s = a.geo.s;
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int us = wave >> 1, p = wave & 1;
@@ -890,6 +1005,23 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     const uint64_t nplanes = 2 * a.geo.nseg;
     const int bs = a.geo.b - s;
     const uint32_t padC = pad8(1u << (s - 6));
+    if (zp && !a.src_basis) {
+        // all four input planes +0 (header: anchor 0, no payload, no outliers)?
+        uint32_t z = 1u;
+        if (us < uc.nsu) {
+            const uint64_t *rec =
+                (const uint64_t *)(a.arena_in + a.din.plane_off[2 * uc.seg(us) + p]);
+            z = (rec[0] | rec[1]) == 0ull;
+        }
+        if (lane == 0)
+            S.zero[wave] = z;
+        __syncthreads();
+        const bool all_zero = S.zero[0] & S.zero[1] & S.zero[2] & S.zero[3];
+        if (all_zero) {
+            zero_unit<MODE>(a, uc, jsel, S);
+            return;
+        }
+    }
     load_unit(a, uc, X, scale, do_scale);
     __syncthreads();
     gate_unit(a.gate, uc, s, X, tdiff);
@@ -917,36 +1049,8 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     if (MODE == kEsc)
         return;
     // bump-allocate this unit's records in the output arena
-    if (lane == 0)
-        rbytes[wave] = mine ? rec_bytes(pszv, padC) : 0;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint64_t tot = rbytes[0] + rbytes[1] + rbytes[2] + rbytes[3];
-        uint64_t base = 0;
-        if (tot) {
-            if (S.chunk[0] + tot > S.chunk[1]) {
-                const uint64_t want = tot > a.chunk_bytes ? tot : a.chunk_bytes;
-                const uint64_t b0 = atomicAdd(
-                    (unsigned long long *)&a.dev->arena_used[a.out_arena],
-                    (unsigned long long)want);
-                S.chunk[0] = b0;
-                S.chunk[1] = b0 + want;
-            }
-            base = S.chunk[0];
-            S.chunk[0] += tot;
-            if (base + tot > a.arena_cap) {
-                if (atomicOr(&a.dev->err, kErrArena) == 0)
-                    a.dev->err_pass = (uint32_t)a.pass;
-                base = ~0ull;
-            }
-        }
-        rbase = base;
-    }
-    __syncthreads();
-    if (mine && rbase != ~0ull) {
-        uint64_t off = rbase;
-        for (int w2 = 0; w2 < wave; ++w2)
-            off += rbytes[w2];
+    const uint64_t off = alloc_records(a, S, mine, rec_bytes(pszv, padC));
+    if (mine && off != ~0ull) {
         if (lane == 0)
             a.dout.plane_off[plane] = off;
         encode_plane(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev], a.lad.r[lev], pszv,
@@ -989,9 +1093,10 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
     // bump pointers that every unit updates atomically)
     const double scale = a.dev->scale;
     const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
+    const bool zp = zero_preserving(a.gate);
     for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
         const Unit uc = unit_of(it, a.geo.nseg, Ms);
-        unit_body<kFused>(a, uc, ~0ull, S, scale, tdiff);
+        unit_body<kFused>(a, uc, ~0ull, S, scale, tdiff, zp);
         __syncthreads();
     }
 }
@@ -1018,6 +1123,7 @@ __device__ void fix_body(const PassArgs &a, uint64_t wg, uint64_t nwg, PassLds &
     const uint64_t nitems = nrep_items + nesc;
     const double scale = a.dev->scale;
     const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
+    const bool zp = zero_preserving(a.gate);
     for (uint64_t it = wg; it < nitems; it += nwg) {
         if (it < nrep_items) {
             const uint64_t jsel = a.replay_list[it >> bs];
@@ -1026,7 +1132,7 @@ __device__ void fix_body(const PassArgs &a, uint64_t wg, uint64_t nwg, PassLds &
             const uint64_t other = uc.nsu == 2 ? (uc.g[0] == g ? uc.g[1] : uc.g[0]) : g;
             if ((other >> bs) == jsel && other < g)
                 continue;  // the unit is handled with its first segment
-            unit_body<kReplay>(a, uc, jsel, S, scale, tdiff);
+            unit_body<kReplay>(a, uc, jsel, S, scale, tdiff, zp);
             __syncthreads();
             continue;
         }
@@ -1041,9 +1147,9 @@ __device__ void fix_body(const PassArgs &a, uint64_t wg, uint64_t nwg, PassLds &
                 if ((other >> bs) == jsel && other < g)
                     continue;
                 if (phase == 0)
-                    unit_body<kEsc>(a, uc, jsel, S, scale, tdiff);
+                    unit_body<kEsc>(a, uc, jsel, S, scale, tdiff, zp);
                 else
-                    unit_body<kReplay>(a, uc, jsel, S, scale, tdiff);
+                    unit_body<kReplay>(a, uc, jsel, S, scale, tdiff, zp);
                 __syncthreads();
             }
         }
@@ -1805,6 +1911,7 @@ __global__ __launch_bounds__(kWG) void k_bpass(const PassArgs *__restrict__ args
     bool skip = false;
     double scale = 1.0, tdiff[2] = {0.0, 0.0};
     uint64_t Ms = 0;
+    bool zp = false;
     for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
         const uint32_t st = state_of(upre, nst, it);
         const PassArgs &a = args[st];
@@ -1817,10 +1924,12 @@ __global__ __launch_bounds__(kWG) void k_bpass(const PassArgs *__restrict__ args
             tdiff[0] = a.dev->tdiff[0];
             tdiff[1] = a.dev->tdiff[1];
             Ms = a.gate.mask >> a.geo.s;
+            zp = zero_preserving(a.gate);
         }
         if (skip)
             continue;
-        unit_body<kFused>(a, unit_of(it - upre[st], a.geo.nseg, Ms), ~0ull, S, scale, tdiff);
+        unit_body<kFused>(a, unit_of(it - upre[st], a.geo.nseg, Ms), ~0ull, S, scale, tdiff,
+                          zp);
         __syncthreads();
     }
 }
