@@ -1380,8 +1380,6 @@ __device__ void finalize_block(const PassArgs &a, uint64_t j, int d, uint64_t le
     h[3] = 0;
     a.dout.blk_len[j] = (uint32_t)len;
     a.dout.blk_level[j] = (uint8_t)d;
-    if (!a.src_basis)
-        atomicAdd((unsigned long long *)&a.dev->level_hist[d], 1ull);
 }
 
 // Alg. 2's choice for each block over the levels the fused pass sized
@@ -1527,19 +1525,37 @@ __device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures)
     const uint64_t nb = a.geo.nblocks;
     double N2;
     uint64_t res = 0;
+    // blocks per chosen level, for the statistics
+    uint32_t hist[kMaxL];
+#pragma unroll
+    for (int k = 0; k < kMaxL; ++k)
+        hist[k] = 0;
     if (nb <= 4096) {
         N2 = wave == 0 ? wave_pairwise(a.blknorm, nb) : 0.0;
         if (wave == 0) {
             uint64_t by = 0;
-            for (uint64_t j = lane; j < nb; j += 64)
+            for (uint64_t j = lane; j < nb; j += 64) {
                 by += a.dout.blk_len[j];
+                const int lv = a.dout.blk_level[j];
+#pragma unroll
+                for (int k = 0; k < kMaxL; ++k)
+                    hist[k] += lv == k;
+            }
             res = readlane64(wave_scan64(by), 63);
+#pragma unroll
+            for (int k = 0; k < kMaxL; ++k)
+                hist[k] = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan32(hist[k]), 63);
         }
     } else {
         N2 = wg_tree([&](uint64_t i) { return a.blknorm[i]; }, nb, lds);
         uint64_t by = 0;
-        for (uint64_t j = t; j < nb; j += kWG)
+        for (uint64_t j = t; j < nb; j += kWG) {
             by += a.dout.blk_len[j];
+            const int lv = a.dout.blk_level[j];
+#pragma unroll
+            for (int k = 0; k < kMaxL; ++k)
+                hist[k] += lv == k;
+        }
         ures[t] = by;
         __syncthreads();
         for (int st = kWG / 2; st > 0; st >>= 1) {
@@ -1548,6 +1564,19 @@ __device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures)
             __syncthreads();
         }
         res = ures[0];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kMaxL; ++k) {
+            ures[t] = hist[k];
+            __syncthreads();
+            for (int st = kWG / 2; st > 0; st >>= 1) {
+                if (t < st)
+                    ures[t] += ures[t + st];
+                __syncthreads();
+            }
+            hist[k] = (uint32_t)ures[0];
+            __syncthreads();
+        }
     }
     if (t == 0) {
         DevState *d = a.dev;
@@ -1570,6 +1599,8 @@ __device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures)
             d->passes += 1;
             if (ratio < d->min_ratio)
                 d->min_ratio = ratio;
+            for (int k = 0; k < kMaxL; ++k)
+                d->level_hist[k] += hist[k];
         }
         if (d->arena_used[a.out_arena] > d->arena_peak)
             d->arena_peak = d->arena_used[a.out_arena];
