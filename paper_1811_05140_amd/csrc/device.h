@@ -19,6 +19,12 @@ constexpr int kMaxL = 8;       // ladder levels
 constexpr int kMinS = 6;       // segment log2 range supported by the kernels
 constexpr int kMaxS = 10;
 constexpr double kQMax = 1073741824.0;  // 2^30
+// Per-wave staging of a plane's packed payload (at most 16 chunks x 64 words)
+// and of its first kScratchOutl outliers, written while the encode level is
+// sized and copied into the record once its arena offset is known.
+constexpr uint32_t kScratchOutl = 64;
+constexpr uint64_t kScratchPayload = 16 * 64 * 8;
+constexpr uint64_t kScratchWave = kScratchPayload + kScratchOutl * 16;
 
 // Gate kinds (numbering of the public header).
 enum : uint32_t {
@@ -116,6 +122,8 @@ struct PassArgs {
     int32_t src_basis;
     int32_t pad;
     uint32_t *psz;       // [L][2*nseg]: payload words | n_outliers << 16
+    uint8_t *scratch;    // [scratch_wgs * 4][kScratchWave] staging, by workgroup and wave
+    uint64_t scratch_wgs;  // workgroups the staging covers (grids must not exceed it)
     uint32_t *replay_list;  // [nblocks]
     uint32_t *esc_list;     // [nblocks]
     double *blknorm;     // [nblocks]

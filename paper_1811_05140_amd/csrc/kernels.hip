@@ -606,6 +606,201 @@ __device__ __forceinline__ void or_bits32(uint32_t *pb, uint32_t b, uint32_t v)
 // x is overwritten with the decoded values x-hat for the normsq.  pb is the
 // wave's LDS packing buffer (4 rows of kPackRow dwords, zero on entry and on
 // exit).
+// The encode level in one pass over the plane: the chunk widths and outlier
+// count (as size_levels computes them) and, step by step, each chunk's
+// fields packed through the row's LDS buffer into this wave's staging
+// payload at their final payload offsets (known as the widths accumulate),
+// the first kScratchOutl outliers into the staging list, and x-hat written
+// back over x.  Returns payload words | outliers << 16 (also stored to
+// *psz_slot); wl = width of chunk `lane`; anchor = the plane's first code.
+__device__ uint32_t size_pack_level(double *x, int s, double delta, double e, double r,
+                                    uint32_t *psz_slot, uint8_t *stage, uint32_t *pb,
+                                    uint32_t &wl, uint64_t &anchor)
+{
+    const int lane = lane_id();
+    const int row = lane >> 4, p = lane & 15;
+    const int C = 1 << (s - 6);
+    const int steps = (C + 3) >> 2;
+    uint32_t *spay = (uint32_t *)stage;
+    uint8_t *sout = stage + kScratchPayload;
+    uint32_t *prow = pb + kPackRow * row;
+    uint32_t base_w = 0, nout = 0;
+    uint64_t carry = 0;
+    wl = 0;
+    anchor = 0;
+    // payload word offset of this row's chunk; advances base_w, records widths
+    auto place = [&](uint32_t w, int t) -> uint32_t {
+        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)w, 0);
+        const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)w, 16);
+        const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)w, 32);
+        const uint32_t w3 = (uint32_t)__builtin_amdgcn_readlane((int)w, 48);
+        const uint32_t woff =
+            base_w + (row > 0 ? w0 : 0u) + (row > 1 ? w1 : 0u) + (row > 2 ? w2 : 0u);
+        base_w += w0 + w1 + w2 + w3;
+        const int d = lane - 4 * t;
+        if (d == 0)
+            wl = w0;
+        else if (d == 1)
+            wl = w1;
+        else if (d == 2)
+            wl = w2;
+        else if (d == 3)
+            wl = w3;
+        return woff;
+    };
+    for (int t = 0; t < steps; ++t) {
+        const int c = 4 * t + row;
+        const bool active = c < C;
+        const int cs = active ? c : 0;
+        double2 *pa = (double2 *)(x + cs * kChunk + 2 * p);
+        uint32_t w, woff;
+        if (delta == 0.0) {
+            uint64_t q[4];
+            {
+                const double2 v01 = pa[0], v23 = pa[16];
+                q[0] = (uint64_t)__double_as_longlong(v01.x);
+                q[1] = (uint64_t)__double_as_longlong(v01.y);
+                q[2] = (uint64_t)__double_as_longlong(v23.x);
+                q[3] = (uint64_t)__double_as_longlong(v23.y);
+            }
+            const uint64_t prev = dpp64<kWaveShr1>(t == 0 ? q[0] : carry, q[3]);
+            if (t == 0)
+                anchor = readlane64(q[0], 0);
+            carry = readlane64(q[3], 63);
+            uint64_t z[4];
+            z[0] = zigzag64(q[0] - prev);
+            z[1] = zigzag64(q[1] - q[0]);
+            z[2] = zigzag64(q[2] - q[1]);
+            z[3] = zigzag64(q[3] - q[2]);
+            w = row_max32(active ? bitlen64(z[0] | z[1] | z[2] | z[3]) : 0u);
+            woff = place(w, t);
+            const uint32_t b0 = (uint32_t)(4 * p) * w;
+            if (active && w == 64u) {
+                uint64_t *dst = (uint64_t *)(spay + 2 * woff) + 4 * p;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    dst[i] = z[i];
+            } else if (active && w) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t bi = b0 + (uint32_t)i * w;
+                    const uint32_t sh = bi & 31u;
+                    const uint32_t lo = (uint32_t)z[i], hi = (uint32_t)(z[i] >> 32);
+                    or_bits32(prow, bi, lo);
+                    if (hi) {
+                        const uint32_t k = (bi >> 5) + 1;
+                        atomicOr(&prow[k], hi << sh);
+                        if (sh && (hi >> (32u - sh)))
+                            atomicOr(&prow[k + 1], hi >> (32u - sh));
+                    }
+                }
+            }
+        } else {
+            int32_t q[4];
+            bool out[4];
+            double xs[4], xh[4];
+            {
+                const double2 v01 = pa[0], v23 = pa[16];
+                xs[0] = v01.x;
+                xs[1] = v01.y;
+                xs[2] = v23.x;
+                xs[3] = v23.y;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                lossy_code(xs[i], delta, e, r, q[i], out[i], xh[i]);
+            const int32_t prev =
+                (int32_t)dpp32<kWaveShr1>((uint32_t)(t == 0 ? q[0] : (int32_t)carry),
+                                          (uint32_t)q[3]);
+            if (t == 0)
+                anchor = (uint64_t)(int64_t)__builtin_amdgcn_readlane(q[0], 0);
+            carry = (uint64_t)(int64_t)__builtin_amdgcn_readlane(q[3], 63);
+            uint32_t z[4];
+            z[0] = zigzag32(q[0] - prev);
+            z[1] = zigzag32(q[1] - q[0]);
+            z[2] = zigzag32(q[2] - q[1]);
+            z[3] = zigzag32(q[3] - q[2]);
+            w = row_max32(active ? bitlen32(z[0] | z[1] | z[2] | z[3]) : 0u);
+            woff = place(w, t);
+            const uint32_t b0 = (uint32_t)(4 * p) * w;
+            if (active && w) {
+                if (4u * w <= 32u) {
+                    const uint32_t comb =
+                        z[0] | (z[1] << w) | (z[2] << (2u * w)) | (z[3] << (3u * w));
+                    or_bits32(prow, b0, comb);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        or_bits32(prow, b0 + (uint32_t)i * w, z[i]);
+                }
+            }
+            // outliers, in plane index order (the first kScratchOutl staged)
+            const uint32_t nl = active ? (uint32_t)out[0] + (uint32_t)out[1] +
+                                             (uint32_t)out[2] + (uint32_t)out[3]
+                                       : 0u;
+            if (__ballot(nl != 0u)) {
+                const uint32_t incl = wave_scan32(nl);
+                uint32_t rank = nout + incl - nl;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (active && out[i]) {
+                        if (rank < kScratchOutl) {
+                            uint8_t *ent = sout + (uint64_t)kOutlierBytes * rank;
+                            *(uint32_t *)ent = (uint32_t)(c * kChunk + 4 * p + i);
+                            *(uint32_t *)(ent + 4) = 0u;
+                            *(uint64_t *)(ent + 8) = (uint64_t)__double_as_longlong(xs[i]);
+                        }
+                        ++rank;
+                    }
+                }
+                nout += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            }
+            if (active) {
+                pa[0] = make_double2(xh[0], xh[1]);
+                pa[16] = make_double2(xh[2], xh[3]);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (active && w && w < 64u) {
+            uint32_t *sp = spay + 2 * woff;
+            for (uint32_t k = (uint32_t)p; k < 2u * w; k += 16u) {
+                sp[k] = prow[k];
+                prow[k] = 0u;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    const uint32_t v = base_w | (nout << 16);
+    if (lane == 0)
+        *psz_slot = v;
+    return v;
+}
+
+// The plane record at rec from the staged payload and outliers (outliers at
+// most kScratchOutl).
+__device__ void emit_record(uint8_t *rec, int s, uint32_t pszv, uint32_t wl, uint64_t anchor,
+                            const uint8_t *stage)
+{
+    const int lane = lane_id();
+    const uint32_t C = 1u << (s - 6);
+    const uint32_t pw = pszv & 0xFFFFu, no = pszv >> 16;
+    if (lane == 0) {
+        *(uint64_t *)rec = anchor;
+        *(uint32_t *)(rec + 8) = pw;
+        *(uint32_t *)(rec + 12) = no;
+    }
+    if (pw && (uint32_t)lane < pad8(C))
+        rec[kPlaneHdrBytes + lane] = (uint32_t)lane < C ? (uint8_t)wl : (uint8_t)0;
+    uint64_t *dst = (uint64_t *)(rec + kPlaneHdrBytes + (pw ? pad8(C) : 0u));
+    const uint64_t *src = (const uint64_t *)stage;
+    for (uint32_t k = (uint32_t)lane; k < pw; k += 64u)
+        dst[k] = src[k];
+    uint64_t *od = dst + pw;
+    const uint64_t *os = (const uint64_t *)(stage + kScratchPayload);
+    for (uint32_t k = (uint32_t)lane; k < 2u * no; k += 64u)
+        od[k] = os[k];
+}
+
 __device__ void encode_plane(double *x, int s, double delta, double e, double r,
                              uint32_t pszv, uint32_t wreg, uint8_t *rec,
                              uint32_t *pb, uint32_t *err)
@@ -1033,17 +1228,22 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     const bool mine = active && (MODE == kFused || j == jsel);
     int lev = 0;
     uint32_t pszv = 0, wreg = 0;
+    uint64_t anchor = 0;
+    uint8_t *stage = a.scratch + ((uint64_t)blockIdx.x * 4 + (uint64_t)wave) * kScratchWave;
     if (mine) {
         const int h = hint_level(a, j);
-        if (MODE == kFused) {
-            lev = h;
-            pszv = size_levels(&X[us][p][0], s, a.lad, 0, h, h, a.psz, plane, nplanes, wreg);
-        } else if (MODE == kEsc) {
+        if (MODE == kEsc) {
             size_levels(&X[us][p][0], s, a.lad, h + 1, L - 1, -1, a.psz, plane, nplanes, wreg);
         } else {
-            lev = a.dout.blk_level[j];
-            pszv = size_levels(&X[us][p][0], s, a.lad, lev, lev, lev, a.psz, plane, nplanes,
-                               wreg);
+            // kFused: levels below the speculated one are only sized; the
+            // speculated level is sized and packed together
+            lev = MODE == kFused ? h : (int)a.dout.blk_level[j];
+            if (MODE == kFused && h > 0)
+                size_levels(&X[us][p][0], s, a.lad, 0, h - 1, -1, a.psz, plane, nplanes,
+                            wreg);
+            pszv = size_pack_level(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev],
+                                   a.lad.r[lev], a.psz + (uint64_t)lev * nplanes + plane, stage,
+                                   &S.pack[wave][0], wreg, anchor);
         }
     }
     if (MODE == kEsc)
@@ -1053,8 +1253,11 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     if (mine && off != ~0ull) {
         if (lane == 0)
             a.dout.plane_off[plane] = off;
-        encode_plane(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev], a.lad.r[lev], pszv,
-                     wreg, a.arena_out + off, &S.pack[wave][0], &a.dev->err);
+        if ((pszv >> 16) <= kScratchOutl)
+            emit_record(a.arena_out + off, s, pszv, wreg, anchor, stage);
+        else  // more outliers than staged: encode again from x-hat (same codes)
+            encode_plane(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev], a.lad.r[lev],
+                         pszv, wreg, a.arena_out + off, &S.pack[wave][0], &a.dev->err);
     }
     __syncthreads();
     const double ns = s == kMaxS
@@ -1079,8 +1282,15 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
 __device__ void decide_escalated(const PassArgs &a, uint64_t j, PassLds &S);
 
 // The fused pass over all units.
-__global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
+// Four workgroups per CU (the LDS budget) need at most 128 VGPRs per lane.
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pass(
+    PassArgs a)
 {
+    if (gridDim.x > a.scratch_wgs) {  // launch larger than the staging (host bug)
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            atomicOr(&a.dev->err, kErrSize);
+        return;
+    }
     if (a.dev->err)
         return;
     __shared__ PassLds S;
@@ -1109,6 +1319,11 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a)
 // pack buffers of S must be zero).
 __device__ void fix_body(const PassArgs &a, uint64_t wg, uint64_t nwg, PassLds &S)
 {
+    if (gridDim.x > a.scratch_wgs) {
+        if (wg == 0 && threadIdx.x == 0)
+            atomicOr(&a.dev->err, kErrSize);
+        return;
+    }
     if (a.dev->err)
         return;
     const uint32_t nrep = a.dev->n_replay, nesc = a.dev->n_esc;
@@ -1950,7 +2165,9 @@ __global__ __launch_bounds__(kWG) void k_bpass(const PassArgs *__restrict__ args
             cur = st;
             if (threadIdx.x == 0)
                 S.chunk[0] = S.chunk[1] = 0;  // arena chunks belong to one state
-            skip = a.dev->err != 0;
+            if (gridDim.x > a.scratch_wgs && threadIdx.x == 0)
+                atomicOr(&a.dev->err, kErrSize);
+            skip = a.dev->err != 0 || gridDim.x > a.scratch_wgs;
             scale = a.dev->scale;
             tdiff[0] = a.dev->tdiff[0];
             tdiff[1] = a.dev->tdiff[1];

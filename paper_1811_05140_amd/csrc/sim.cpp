@@ -119,6 +119,8 @@ struct sim {
     Desc desc[2]{};
     uint32_t *psz = nullptr;
     int psz_levels = 0;
+    uint8_t *scratch = nullptr;  // per-wave staging for the unit kernels
+    uint64_t scratch_wgs = 0;
     uint32_t *replay_list = nullptr, *esc_list = nullptr;
     double *blknorm = nullptr, *segsum = nullptr, *blksum = nullptr;
     DevState *dev = nullptr;
@@ -213,6 +215,38 @@ int ensure_psz(sim *S, int L)
     return SIM_OK;
 }
 
+// Staging for `wgs` workgroups of the unit kernels (grown on demand).
+int ensure_scratch(sim *S, uint64_t wgs)
+{
+    if (S->scratch_wgs >= wgs)
+        return SIM_OK;
+    if (S->scratch) {
+        HIPCHK(hipStreamSynchronize(S->stream));
+        for (auto it = S->allocs.begin(); it != S->allocs.end(); ++it)
+            if (*it == S->scratch) {
+                S->allocs.erase(it);
+                break;
+            }
+        S->device_bytes -= S->scratch_wgs * 4 * kScratchWave;
+        (void)hipFree(S->scratch);
+        S->scratch = nullptr;
+        S->scratch_wgs = 0;
+    }
+    int rc = dmalloc(S, (void **)&S->scratch, wgs * 4 * kScratchWave);
+    if (rc)
+        return rc;
+    S->scratch_wgs = wgs;
+    return SIM_OK;
+}
+
+// Workgroups of the unit kernels of a pass (as launch_pass computes them).
+uint64_t unit_grid(const sim *S)
+{
+    const uint64_t u = S->geo.nunits;
+    const uint64_t g = u < S->grid_cap ? u : S->grid_cap;
+    return g ? g : 1;
+}
+
 uint64_t gate_mask(const sim_gate_t *g)
 {
     switch (g->kind) {
@@ -289,6 +323,8 @@ PassArgs make_args(const sim *S, int in, int out, const GateArg &g)
     a.in_arena = in;
     a.pass = S->passes;
     a.psz = S->psz;
+    a.scratch = S->scratch;
+    a.scratch_wgs = S->scratch_wgs;
     a.replay_list = S->replay_list;
     a.esc_list = S->esc_list;
     a.blknorm = S->blknorm;
@@ -482,6 +518,8 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
 
         if (!rc)
             rc = ensure_psz(S, S->lad.L);
+        if (!rc)
+            rc = ensure_scratch(S, unit_grid(S));
         if (!rc)
             rc = dmalloc(S, (void **)&S->blknorm, 8 * nb);
         if (!rc)
@@ -698,8 +736,16 @@ int sim_set_grid(sim_t *S, int max_workgroups)
         return fail(SIM_EINVAL, "sim is NULL");
     if (max_workgroups < 64 || max_workgroups > (1 << 16))
         return fail(SIM_EINVAL, "max_workgroups %d outside [64, 65536]", max_workgroups);
+    if (!S->compressed) {
+        S->grid_cap = (unsigned)max_workgroups;
+        return SIM_OK;
+    }
+    const unsigned old = S->grid_cap;
     S->grid_cap = (unsigned)max_workgroups;
-    return SIM_OK;
+    int rc = ensure_scratch(S, unit_grid(S));
+    if (rc)
+        S->grid_cap = old;
+    return rc;
 }
 
 int sim_amplitude_sum(sim_t *S, double *out)
@@ -1046,6 +1092,7 @@ struct sim_batch {
     int max_states = 0, max_passes = 0;
     size_t slot_bytes = 0;     // one pass: PassArgs[max_states] + 4 prefixes
     uint8_t *dslots = nullptr; // device [max_passes] slots
+    uint8_t *scratch = nullptr; // staging for kMaxBatchGrid workgroups of the unit kernels
     uint8_t *hslots = nullptr; // pinned host mirror
     hipEvent_t uploaded = nullptr;  // the last upload from hslots has finished
     hipEvent_t joined = nullptr;
@@ -1063,6 +1110,7 @@ struct sim_batch {
 namespace {
 
 constexpr size_t kMaxGraphs = 16;
+constexpr unsigned kMaxBatchGrid = 2048;
 
 size_t slot_prefix_off(int max_states)
 {
@@ -1113,6 +1161,8 @@ void batch_free(sim_batch *B)
         (void)hipEventDestroy(B->joined);
     if (B->dslots)
         (void)hipFree(B->dslots);
+    if (B->scratch)
+        (void)hipFree(B->scratch);
     if (B->hslots)
         (void)hipHostFree(B->hslots);
     delete B->prof;
@@ -1151,6 +1201,8 @@ sim_batch_t *sim_batch_create(int max_states, int max_passes, void *hip_stream)
         B->own_stream = ok;
     }
     ok = ok && hipMalloc((void **)&B->dslots, total) == hipSuccess;
+    ok = ok && hipMalloc((void **)&B->scratch, (size_t)kMaxBatchGrid * 4 * kScratchWave) ==
+                   hipSuccess;
     ok = ok && hipHostMalloc((void **)&B->hslots, total, hipHostMallocDefault) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&B->uploaded, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&B->joined, hipEventDisableTiming) == hipSuccess;
@@ -1203,7 +1255,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
                 return fail(rc, "pass %d, sims[%d]: %s", p, k, std::string(g_err).c_str());
         }
     }
-    const unsigned gu = (unsigned)(units < 2048 ? units : 2048);
+    const unsigned gu = (unsigned)(units < kMaxBatchGrid ? units : kMaxBatchGrid);
     const unsigned gb = (unsigned)(blocks < (1u << 20) ? blocks : (1u << 20));
     // the host mirror may still be the source of the previous upload
     HIPCHK(hipEventSynchronize(B->uploaded));
@@ -1241,6 +1293,8 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
                 args[k] = make_args(S, S->cur, 1 - S->cur, none);
             }
             args[k].chunk_bytes = batch_chunk_bytes(S->arena_cap, gu);
+            args[k].scratch = B->scratch;
+            args[k].scratch_wgs = kMaxBatchGrid;
             upre[k + 1] = upre[k] + (on ? S->geo.nunits : 0);
             bpre[k + 1] = bpre[k] + (on ? S->geo.nblocks : 0);
             mpre[k + 1] = mpre[k] + (mean ? S->geo.nunits : 0);

@@ -145,14 +145,19 @@ def reservation_bytes(n, b, arena_factor=1.0, levels=5):
     """Device bytes a state of n qubits holds: two arenas of
     ceil(1.3 * factor * 16 * 2^n) + 1 MiB (the pass's speculative encode at
     the previous level can take up to the raw size before a replay, on top of
-    the kept streams), plus descriptors, size tables and reduction scratch."""
+    the kept streams), plus descriptors, size tables, reduction scratch and
+    the pass kernels' per-wave staging."""
     s = min(b, 10)
     nseg = 1 << (n - s)
     nblocks = 1 << (n - b)
     arena = arena_bytes(n, arena_factor)
     per_seg = 2 * (16 + 8) + 8 * levels + 16
     per_block = 2 * (32 + 4 + 1) + 4 + 4 + 8 + 16
-    return 2 * arena + per_seg * nseg + per_block * nblocks + 4096
+    # staging of the pass kernels: 4 waves x (8 KiB payload + 64 outliers)
+    # per workgroup, one workgroup per segment pair up to 2048
+    nunits = 1 if nseg == 1 else nseg // 2
+    staging = min(nunits, 2048) * 4 * (16 * 64 * 8 + 64 * 16)
+    return 2 * arena + per_seg * nseg + per_block * nblocks + staging + 4096
 
 
 def arena_bytes(n, arena_factor=1.0):
