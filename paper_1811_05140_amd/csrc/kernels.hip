@@ -1200,7 +1200,17 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     const uint64_t nplanes = 2 * a.geo.nseg;
     const int bs = a.geo.b - s;
     const uint32_t padC = pad8(1u << (s - 6));
-    if (zp && !a.src_basis) {
+    if (a.src_basis) {
+        // basis state: every unit but the one holding |basis> is all +0
+        const uint64_t gb = a.basis >> s;
+        bool holds = false;
+        for (int k = 0; k < uc.nsu; ++k)
+            holds = holds || uc.seg(k) == gb;
+        if (!holds) {
+            zero_unit<MODE>(a, uc, jsel, S);
+            return;
+        }
+    } else if (zp) {
         // all four input planes +0 (header: anchor 0, no payload, no outliers)?
         uint32_t z = 1u;
         if (us < uc.nsu) {
