@@ -23,6 +23,10 @@ constexpr double kQMax = 1073741824.0;  // 2^30
 // and of its first kScratchOutl outliers, written while the encode level is
 // sized and copied into the record once its arena offset is known.
 constexpr uint32_t kScratchOutl = 64;
+// Bytes reserved at the start of each arena (bump allocation starts there):
+// [0, 16) holds the one all-zero plane record that every all-+0 plane of a
+// pass points to.
+constexpr uint64_t kArenaBase = 256;
 constexpr uint64_t kScratchPayload = 16 * 64 * 8;
 constexpr uint64_t kScratchWave = kScratchPayload + kScratchOutl * 16;
 
@@ -59,6 +63,7 @@ struct Desc {
     uint8_t *blk_level;   // [nblocks] ladder level of the stream
     uint64_t *plane_off;  // [2*nseg] byte offset of each plane record
     double *segnorm;      // [nseg] pairwise normsq of each segment's x-hat
+    uint8_t *zflag;       // [2*nseg] 1 when the plane's record is the all-zero one
 };
 
 // Device-resident scalars of one sim, read and written only by kernels.

@@ -1054,7 +1054,6 @@ struct PassLds {
     uint32_t pack[4][4 * kPackRow];
     uint64_t misc[9];  // segment sums, then record bytes + base
     uint64_t chunk[2]; // this workgroup's current arena chunk [cur, end)
-    uint32_t zero[4];  // per wave: its input plane is all +0
 };
 
 // Whether the gate maps amplitudes that are +0 in both components to +0 in
@@ -1170,15 +1169,13 @@ __device__ void zero_unit(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         }
         for (int k = k0; k <= k1; ++k)
             a.psz[(uint64_t)k * nplanes + plane] = 0u;
+        if (MODE != kEsc) {
+            a.dout.plane_off[plane] = 0;  // the shared all-zero record
+            a.dout.zflag[plane] = 1;
+        }
     }
     if (MODE == kEsc)
         return;
-    const uint64_t off = alloc_records(a, S, mine, kPlaneHdrBytes);
-    if (mine && off != ~0ull && lane < 2) {
-        ((uint64_t *)(a.arena_out + off))[lane] = 0ull;
-        if (lane == 0)
-            a.dout.plane_off[plane] = off;
-    }
     if (threadIdx.x < (unsigned)uc.nsu) {
         const uint64_t gs = uc.seg((int)threadIdx.x);
         if (MODE == kFused || (gs >> bs) == jsel)
@@ -1211,17 +1208,12 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
             return;
         }
     } else if (zp) {
-        // all four input planes +0 (header: anchor 0, no payload, no outliers)?
-        uint32_t z = 1u;
-        if (us < uc.nsu) {
-            const uint64_t *rec =
-                (const uint64_t *)(a.arena_in + a.din.plane_off[2 * uc.seg(us) + p]);
-            z = (rec[0] | rec[1]) == 0ull;
+        // are all the unit's input planes the all-zero record?
+        bool all_zero = true;
+        for (int k = 0; k < uc.nsu; ++k) {
+            const uint64_t g = uc.seg(k);
+            all_zero = all_zero && (a.din.zflag[2 * g] & a.din.zflag[2 * g + 1]);
         }
-        if (lane == 0)
-            S.zero[wave] = z;
-        __syncthreads();
-        const bool all_zero = S.zero[0] & S.zero[1] & S.zero[2] & S.zero[3];
         if (all_zero) {
             zero_unit<MODE>(a, uc, jsel, S);
             return;
@@ -1258,9 +1250,16 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     }
     if (MODE == kEsc)
         return;
-    // bump-allocate this unit's records in the output arena
-    const uint64_t off = alloc_records(a, S, mine, rec_bytes(pszv, padC));
-    if (mine && off != ~0ull) {
+    // bump-allocate this unit's records in the output arena (an all-zero
+    // record is the shared one)
+    const bool zrec = pszv == 0u && anchor == 0ull;
+    const uint64_t off = alloc_records(a, S, mine && !zrec, rec_bytes(pszv, padC));
+    if (mine && lane == 0)
+        a.dout.zflag[plane] = zrec ? 1 : 0;
+    if (mine && zrec) {
+        if (lane == 0)
+            a.dout.plane_off[plane] = 0;
+    } else if (mine && off != ~0ull) {
         if (lane == 0)
             a.dout.plane_off[plane] = off;
         if ((pszv >> 16) <= kScratchOutl)
@@ -1829,7 +1828,7 @@ __device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures)
         }
         if (d->arena_used[a.out_arena] > d->arena_peak)
             d->arena_peak = d->arena_used[a.out_arena];
-        d->arena_used[a.in_arena] = 0;
+        d->arena_used[a.in_arena] = kArenaBase;
         d->n_replay = 0;
         d->n_esc = 0;
     }
@@ -2334,6 +2333,7 @@ __global__ void k_init_state(DevState *dev, int normalize)
         DevState d = {};
         d.scale = 1.0;
         d.normalize = normalize;
+        d.arena_used[0] = d.arena_used[1] = kArenaBase;
         *dev = d;
     }
 }

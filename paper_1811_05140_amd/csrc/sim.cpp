@@ -360,7 +360,7 @@ int sync_check(sim *S)
             d.err = 0;
             d.err_pass = 0;
             d.passes = 0;
-            d.arena_used[0] = d.arena_used[1] = 0;
+            d.arena_used[0] = d.arena_used[1] = kArenaBase;
             d.n_replay = d.n_esc = 0;
             HIPCHK(hipMemcpy(S->dev, &d, sizeof d, hipMemcpyHostToDevice));
             return fail(bits & kErrSize ? SIM_EDEVICE : SIM_ENOMEM,
@@ -373,7 +373,7 @@ int sync_check(sim *S)
         d.err = 0;
         d.err_pass = 0;
         d.passes = pe;
-        d.arena_used[1 - S->cur] = 0;
+        d.arena_used[1 - S->cur] = kArenaBase;
         d.n_replay = d.n_esc = 0;
         HIPCHK(hipMemcpy(S->dev, &d, sizeof d, hipMemcpyHostToDevice));
         if (bits & kErrSize)
@@ -510,6 +510,10 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
                 rc = dmalloc(S, (void **)&S->desc[k].plane_off, 8 * 2 * ns);
             if (!rc)
                 rc = dmalloc(S, (void **)&S->desc[k].segnorm, 8 * ns);
+            if (!rc)
+                rc = dmalloc(S, (void **)&S->desc[k].zflag, 2 * ns);
+            if (!rc && hipMemset(S->arena[k], 0, kArenaBase) != hipSuccess)
+                rc = fail(SIM_EDEVICE, "arena initialisation failed");
         }
         if (!rc)
             rc = dmalloc(S, (void **)&S->replay_list, 4 * nb);
