@@ -267,6 +267,26 @@ def test_amplitude_sum_and_headers_match_oracle(A):
     assert abs(S.imag - math.fsum(a.imag)) < 1e-12
 
 
+def test_many_outliers_per_plane(A):
+    # Uniform superposition on 8 qubits: every amplitude is 2^-4 exactly.
+    # With the single bound delta = 2^-4 each real part sits on a rounding tie
+    # (y = 0.5 -> q = 0, error exactly delta), so all 256 scalars of a real
+    # plane are outliers: more than the encoder stages, which exercises its
+    # re-encode path; with delta = 2^-3 they are quantised exactly (no
+    # outliers).  Streams must equal the oracle's.
+    n, b = 8, 8
+    for lad in ([2.0 ** -4], [2.0 ** -3], [2.0 ** -5, 2.0 ** -4]):
+        say("many outliers", lad)
+        g = A.Sim(n, b, lad[-1], ladder=lad, theta=4.0)
+        o = orc.OracleSim(n, b, lad, 4.0)
+        gates = [I.h(q) for q in range(n)] + [I.t_gate(3), I.h(5), I.cz(1, 6)]
+        for gate in gates:
+            g.apply(gate)
+            o.apply(gate)
+            assert_streams_equal(g, o, 1, "outliers %s" % lad)
+        g.close()
+
+
 def test_invalid_gates_rejected(A):
     say("invalid gates")
     g = A.Sim(8, 6, 1e-4)
