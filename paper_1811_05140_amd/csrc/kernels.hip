@@ -270,20 +270,16 @@ __device__ __forceinline__ uint64_t field64(const uint32_t *P, uint32_t b, uint3
     return w >= 64u ? v : (v & ((1ull << w) - 1ull));
 }
 
-// Chunk widths (lanes 0..C-1) and their exclusive prefix (payload word
-// offsets) from a plane record's width bytes.
-__device__ __forceinline__ void chunk_table(const uint8_t *widths, bool has, int C,
-                                            uint32_t &wl, uint32_t &ol)
-{
-    const int lane = lane_id();
-    wl = (has && lane < C) ? (uint32_t)widths[lane] : 0u;
-    ol = row_scan32(wl) - wl;  // lanes 0..15 of row 0 hold chunks 0..15
-}
-
-// Decode one plane record into dst[0 .. 2^s) (one wavefront), scaling each
-// value by `scale` when do_scale (normalisation before the gate).  Lossy
-// planes run the prefix sums in 32 bits: a partial sum is the difference of
-// two codes of magnitude below 2^30, so it is exact.
+// Decode one plane record into dst[0 .. 2^s) (one wavefront; dst is the
+// wave's own LDS plane region), scaling each value by `scale` when do_scale
+// (normalisation before the gate).  Lossy planes run the prefix sums in 32
+// bits: a partial sum is the difference of two codes of magnitude below
+// 2^30, so it is exact.
+// The payload is first copied into the top of dst (words 2^s - pw .. 2^s),
+// every load in flight at once, together with the widths and the first 64
+// outliers; the fields are then read from LDS.  A chunk's payload is at most
+// 64 words and its decoded values exactly 64, so the values written in steps
+// 0..t end below the payload of every chunk of a later step.
 __device__ void decode_plane(const uint8_t *rec, int s, double delta,
                              double scale, bool do_scale, double *dst)
 {
@@ -295,10 +291,58 @@ __device__ void decode_plane(const uint8_t *rec, int s, double delta,
     const uint32_t pw = *(const uint32_t *)(rec + 8);
     const uint32_t nout = *(const uint32_t *)(rec + 12);
     const uint8_t *widths = rec + kPlaneHdrBytes;
-    const uint32_t *payload =
-        (const uint32_t *)(rec + kPlaneHdrBytes + (pw ? pad8((uint32_t)C) : 0u));
-    uint32_t wl, ol;
-    chunk_table(widths, pw != 0, C, wl, ol);
+    const uint2 *gpay = (const uint2 *)(rec + kPlaneHdrBytes + (pw ? pad8((uint32_t)C) : 0u));
+    const uint8_t *outl = (const uint8_t *)(gpay + pw);
+    // width byte of chunk `lane` (branch-free: without widths the load reads
+    // the header and the value is dropped)
+    const uint32_t wdw = *((const uint32_t *)(pw ? widths : rec) + ((lane >> 2) & 3));
+    const bool o0 = (uint32_t)lane < nout;
+    uint32_t oidx = 0;
+    uint64_t obits = 0;
+    if (o0) {
+        oidx = *(const uint32_t *)(outl + (uint64_t)kOutlierBytes * lane);
+        obits = *(const uint64_t *)(outl + (uint64_t)kOutlierBytes * lane + 8);
+    }
+    uint32_t *payload = (uint32_t *)dst + 2 * ((1u << s) - pw);
+    // the first 256 words outside the loop, so that their loads go out with
+    // the ones above
+    {
+        uint2 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t k = (uint32_t)lane + 64u * (uint32_t)i;
+            v[i] = k < pw ? gpay[k] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t k = (uint32_t)lane + 64u * (uint32_t)i;
+            if (k < pw) {
+                payload[2 * k] = v[i].x;
+                payload[2 * k + 1] = v[i].y;
+            }
+        }
+    }
+    for (uint32_t k0 = 256u; k0 < pw; k0 += 256u) {
+        uint2 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t k = k0 + (uint32_t)lane + 64u * (uint32_t)i;
+            v[i] = k < pw ? gpay[k] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t k = k0 + (uint32_t)lane + 64u * (uint32_t)i;
+            if (k < pw) {
+                payload[2 * k] = v[i].x;
+                payload[2 * k + 1] = v[i].y;
+            }
+        }
+    }
+    const uint32_t wraw = (pw && lane < C) ? ((wdw >> (8 * (lane & 3))) & 0xFFu) : 0u;
+    // chunk widths (lanes 0..C-1) and their exclusive prefix (payload word
+    // offsets); lanes 0..15 of row 0 hold chunks 0..15
+    const uint32_t wl = wraw;
+    const uint32_t ol = row_scan32(wl) - wl;
     const double e = 2.0 * delta;
     uint64_t carry = anchor;
     for (int t = 0; t < steps; ++t) {
@@ -363,8 +407,13 @@ __device__ void decode_plane(const uint8_t *rec, int s, double delta,
             pa[16] = make_double2(x[2], x[3]);
         }
     }
-    const uint8_t *outl = (const uint8_t *)(payload + 2 * pw);
-    for (uint32_t k = (uint32_t)lane; k < nout; k += 64u) {
+    if (o0) {
+        double v = __longlong_as_double((long long)obits);
+        if (do_scale)
+            v = v * scale;
+        dst[sw(oidx)] = v;
+    }
+    for (uint32_t k = 64u + (uint32_t)lane; k < nout; k += 64u) {
         const uint32_t idx = *(const uint32_t *)(outl + (uint64_t)kOutlierBytes * k);
         double v = *(const double *)(outl + (uint64_t)kOutlierBytes * k + 8);
         if (do_scale)
@@ -791,14 +840,26 @@ __device__ void emit_record(uint8_t *rec, int s, uint32_t pszv, uint32_t wl, uin
     }
     if (pw && (uint32_t)lane < pad8(C))
         rec[kPlaneHdrBytes + lane] = (uint32_t)lane < C ? (uint8_t)wl : (uint8_t)0;
-    uint64_t *dst = (uint64_t *)(rec + kPlaneHdrBytes + (pw ? pad8(C) : 0u));
-    const uint64_t *src = (const uint64_t *)stage;
-    for (uint32_t k = (uint32_t)lane; k < pw; k += 64u)
-        dst[k] = src[k];
-    uint64_t *od = dst + pw;
-    const uint64_t *os = (const uint64_t *)(stage + kScratchPayload);
-    for (uint32_t k = (uint32_t)lane; k < 2u * no; k += 64u)
-        od[k] = os[k];
+    // payload words then outlier words, contiguous in the record; each
+    // round issues all its loads before its stores
+    uint64_t *__restrict__ dst = (uint64_t *)(rec + kPlaneHdrBytes + (pw ? pad8(C) : 0u));
+    const uint64_t *__restrict__ src = (const uint64_t *)stage;
+    const uint64_t *__restrict__ os = (const uint64_t *)(stage + kScratchPayload) - pw;
+    const uint32_t total = pw + 2u * no;
+    for (uint32_t k0 = 0; k0 < total; k0 += 256u) {
+        uint64_t v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t k = k0 + (uint32_t)lane + 64u * (uint32_t)i;
+            v[i] = k < pw ? src[k] : (k < total ? os[k] : 0ull);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t k = k0 + (uint32_t)lane + 64u * (uint32_t)i;
+            if (k < total)
+                dst[k] = v[i];
+        }
+    }
 }
 
 __device__ void encode_plane(double *x, int s, double delta, double e, double r,
@@ -1348,28 +1409,21 @@ __device__ void fix_body(const PassArgs &a, uint64_t wg, uint64_t nwg, PassLds &
     const double scale = a.dev->scale;
     const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
     const bool zp = zero_preserving(a.gate);
+    // one call site per unit_body mode (keeps them inlined)
     for (uint64_t it = wg; it < nitems; it += nwg) {
-        if (it < nrep_items) {
-            const uint64_t jsel = a.replay_list[it >> bs];
-            const uint64_t g = (jsel << bs) | (it & (spb - 1));
-            const Unit uc = unit_of_seg(g, a.geo.nseg, Ms);
-            const uint64_t other = uc.nsu == 2 ? (uc.g[0] == g ? uc.g[1] : uc.g[0]) : g;
-            if ((other >> bs) == jsel && other < g)
-                continue;  // the unit is handled with its first segment
-            unit_body<kReplay>(a, uc, jsel, S, scale, tdiff, zp);
-            __syncthreads();
-            continue;
-        }
-        const uint64_t jsel = a.esc_list[it - nrep_items];
-        for (int phase = 0; phase < 2; ++phase) {
-            if (phase == 1)
+        const bool rep = it < nrep_items;
+        const uint64_t jsel = rep ? a.replay_list[it >> bs] : a.esc_list[it - nrep_items];
+        const uint64_t t0 = rep ? (it & (spb - 1)) : 0;
+        const uint64_t tn = rep ? t0 + 1 : spb;
+        for (int phase = rep ? 1 : 0; phase < 2; ++phase) {
+            if (phase == 1 && !rep)
                 decide_escalated(a, jsel, S);
-            for (uint64_t t = 0; t < spb; ++t) {
+            for (uint64_t t = t0; t < tn; ++t) {
                 const uint64_t g = (jsel << bs) | t;
                 const Unit uc = unit_of_seg(g, a.geo.nseg, Ms);
                 const uint64_t other = uc.nsu == 2 ? (uc.g[0] == g ? uc.g[1] : uc.g[0]) : g;
                 if ((other >> bs) == jsel && other < g)
-                    continue;
+                    continue;  // the unit is handled with its first segment
                 if (phase == 0)
                     unit_body<kEsc>(a, uc, jsel, S, scale, tdiff, zp);
                 else
@@ -2155,7 +2209,7 @@ __device__ __forceinline__ uint32_t state_of(const uint64_t *__restrict__ pre, u
     return lo;
 }
 
-__global__ __launch_bounds__(kWG) void k_bpass(const PassArgs *__restrict__ args,
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_bpass(const PassArgs *__restrict__ args,
                                                const uint64_t *__restrict__ upre, uint32_t nst)
 {
     __shared__ PassLds S;
