@@ -157,6 +157,13 @@ __device__ __forceinline__ uint64_t zigzag64(uint64_t c)
     return (c << 1) ^ (uint64_t)((int64_t)c >> 63);
 }
 
+// |H| folded to H ^ (H >> 31), H the high word of the 64-bit residual d.
+__device__ __forceinline__ uint32_t hi_mag(uint64_t d)
+{
+    const int32_t H = (int32_t)(uint32_t)(d >> 32);
+    return (uint32_t)(H ^ (H >> 31));
+}
+
 __device__ __forceinline__ uint64_t unzigzag64(uint64_t z)
 {
     return (z >> 1) ^ (0 - (z & 1));
@@ -582,9 +589,19 @@ __device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k
                 const uint64_t q2 = (uint64_t)__double_as_longlong(v23.x);
                 const uint64_t q3 = (uint64_t)__double_as_longlong(v23.y);
                 const uint64_t prev = dpp64<kWaveShr1>(t == 0 ? q0 : carry, q3);
-                const uint64_t o = zigzag64(q0 - prev) | zigzag64(q1 - q0) |
-                                   zigzag64(q2 - q1) | zigzag64(q3 - q2);
-                const uint32_t w = row_max32(active ? bitlen64(o) : 0u);
+                // A residual d whose high word H is not 0 or -1 has zigzag
+                // width 33 + bitlen(H ^ (H >> 31)), every other one at most
+                // 33: a row with such a residual has that width from the
+                // high words alone; rows without one take the full widths.
+                const uint32_t oh = hi_mag(q0 - prev) | hi_mag(q1 - q0) | hi_mag(q2 - q1) |
+                                    hi_mag(q3 - q2);
+                uint32_t w = row_max32(active && oh ? 33u + bitlen32(oh) : 0u);
+                if (__ballot(active && w == 0u)) {
+                    const uint64_t o = zigzag64(q0 - prev) | zigzag64(q1 - q0) |
+                                       zigzag64(q2 - q1) | zigzag64(q3 - q2);
+                    const uint32_t we = row_max32(active ? bitlen64(o) : 0u);
+                    w = w ? w : we;
+                }
                 pw_acc += w;
                 if (k == want)
                     gather_widths(w, t, wl);
