@@ -63,7 +63,6 @@ struct Desc {
     uint8_t *blk_level;   // [nblocks] ladder level of the stream
     uint64_t *plane_off;  // [2*nseg] byte offset of each plane record
     double *segnorm;      // [nseg] pairwise normsq of each segment's x-hat
-    uint8_t *zflag;       // [2*nseg] 1 when the plane's record is the all-zero one
 };
 
 // Device-resident scalars of one sim, read and written only by kernels.

@@ -1224,7 +1224,7 @@ __device__ uint64_t alloc_records(const PassArgs &a, PassLds &S, bool mine, uint
 // and no outliers, each record is its 16-byte header of zeros, and every
 // segment's normsq is +0 -- exactly what the full path computes for it.
 template <int MODE>
-__device__ void zero_unit(const PassArgs &a, const Unit &uc, uint64_t jsel, PassLds &S)
+__device__ void zero_unit(const PassArgs &a, const Unit &uc, uint64_t jsel, PassLds &S, int lvl)
 {
     const int s = a.geo.s;
     const int wave = threadIdx.x >> 6, lane = lane_id();
@@ -1237,19 +1237,17 @@ __device__ void zero_unit(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     const uint64_t plane = 2 * g + p;
     const bool mine = active && (MODE == kFused || j == jsel);
     if (mine && lane == 0) {
-        const int h = hint_level(a, j);
-        int k0 = 0, k1 = h;
+        int k0 = 0, k1 = lvl;
         if (MODE == kEsc) {
-            k0 = h + 1;
+            k0 = lvl + 1;
             k1 = a.lad.L - 1;
         } else if (MODE == kReplay) {
-            k0 = k1 = a.dout.blk_level[j];
+            k0 = k1 = lvl;
         }
         for (int k = k0; k <= k1; ++k)
             a.psz[(uint64_t)k * nplanes + plane] = 0u;
         if (MODE != kEsc) {
             a.dout.plane_off[plane] = 0;  // the shared all-zero record
-            a.dout.zflag[plane] = 1;
         }
     }
     if (MODE == kEsc)
@@ -1275,6 +1273,33 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     const uint64_t nplanes = 2 * a.geo.nseg;
     const int bs = a.geo.b - s;
     const uint32_t padC = pad8(1u << (s - 6));
+    const bool active = us < uc.nsu;
+    const uint64_t g = uc.seg(active ? us : 0);
+    const uint64_t j = g >> bs;
+    // The unit's reads that depend on nothing else, in one round trip: the
+    // record offsets of its four planes (offset 0 is the shared all-zero
+    // record, every other record lies at kArenaBase or above), the block's
+    // error bound and its level (kReplay: the decided one; else the one
+    // the previous pass chose, the speculated level here).
+    uint64_t poff = 0, zoff = 1;
+    double pdelta = 0.0;
+    uint32_t lraw = 0;
+    if (MODE == kReplay)
+        lraw = a.dout.blk_level[j];
+    if (!a.src_basis) {
+        pdelta = *(const double *)(a.din.hdr + 32 * j + 16);
+        if (MODE != kReplay)
+            lraw = a.din.blk_level[j];
+        const uint64_t g0 = uc.seg(0), g1 = uc.seg(1);
+        const uint64_t o00 = a.din.plane_off[2 * g0], o01 = a.din.plane_off[2 * g0 + 1];
+        const uint64_t o10 = a.din.plane_off[2 * g1], o11 = a.din.plane_off[2 * g1 + 1];
+        poff = us == 0 ? (p ? o01 : o00) : (p ? o11 : o10);
+        zoff = o00 | o01 | o10 | o11;
+        // keeps the compiler from sinking these loads to their first uses
+        // (one wait for all of them instead of one round trip each)
+        asm volatile("" ::"v"(zoff), "v"(poff), "v"(pdelta), "v"(lraw));
+    }
+    const int lvl = MODE == kReplay ? (int)lraw : ((int)lraw < L ? (int)lraw : L - 1);
     if (a.src_basis) {
         // basis state: every unit but the one holding |basis> is all +0
         const uint64_t gb = a.basis >> s;
@@ -1282,28 +1307,26 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         for (int k = 0; k < uc.nsu; ++k)
             holds = holds || uc.seg(k) == gb;
         if (!holds) {
-            zero_unit<MODE>(a, uc, jsel, S);
+            zero_unit<MODE>(a, uc, jsel, S, lvl);
             return;
         }
-    } else if (zp) {
-        // are all the unit's input planes the all-zero record?
-        bool all_zero = true;
-        for (int k = 0; k < uc.nsu; ++k) {
-            const uint64_t g = uc.seg(k);
-            all_zero = all_zero && (a.din.zflag[2 * g] & a.din.zflag[2 * g + 1]);
-        }
-        if (all_zero) {
-            zero_unit<MODE>(a, uc, jsel, S);
-            return;
+    } else if (zp && zoff == 0) {
+        // every input plane of the unit is the all-zero record
+        zero_unit<MODE>(a, uc, jsel, S, lvl);
+        return;
+    }
+    if (active) {
+        double *dst = &X[us][p][0];
+        if (a.src_basis) {
+            for (int o = lane; o < (1 << s); o += 64)
+                dst[sw(o)] = (p == 0 && ((g << s) | (uint64_t)o) == a.basis) ? 1.0 : 0.0;
+        } else {
+            decode_plane(a.arena_in + poff, s, pdelta, scale, do_scale, dst);
         }
     }
-    load_unit(a, uc, X, scale, do_scale);
     __syncthreads();
     gate_unit(a.gate, uc, s, X, tdiff);
     __syncthreads();
-    const bool active = us < uc.nsu;
-    const uint64_t g = active ? uc.seg(us) : 0;
-    const uint64_t j = g >> bs;
     const uint64_t plane = 2 * g + p;
     const bool mine = active && (MODE == kFused || j == jsel);
     int lev = 0;
@@ -1311,13 +1334,13 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     uint64_t anchor = 0;
     uint8_t *stage = a.scratch + ((uint64_t)blockIdx.x * 4 + (uint64_t)wave) * kScratchWave;
     if (mine) {
-        const int h = hint_level(a, j);
+        const int h = lvl;
         if (MODE == kEsc) {
             size_levels(&X[us][p][0], s, a.lad, h + 1, L - 1, -1, a.psz, plane, nplanes, wreg);
         } else {
             // kFused: levels below the speculated one are only sized; the
             // speculated level is sized and packed together
-            lev = MODE == kFused ? h : (int)a.dout.blk_level[j];
+            lev = h;
             if (MODE == kFused && h > 0)
                 size_levels(&X[us][p][0], s, a.lad, 0, h - 1, -1, a.psz, plane, nplanes,
                             wreg);
@@ -1332,8 +1355,6 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     // record is the shared one)
     const bool zrec = pszv == 0u && anchor == 0ull;
     const uint64_t off = alloc_records(a, S, mine && !zrec, rec_bytes(pszv, padC));
-    if (mine && lane == 0)
-        a.dout.zflag[plane] = zrec ? 1 : 0;
     if (mine && zrec) {
         if (lane == 0)
             a.dout.plane_off[plane] = 0;

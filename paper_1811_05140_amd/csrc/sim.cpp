@@ -510,8 +510,6 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
                 rc = dmalloc(S, (void **)&S->desc[k].plane_off, 8 * 2 * ns);
             if (!rc)
                 rc = dmalloc(S, (void **)&S->desc[k].segnorm, 8 * ns);
-            if (!rc)
-                rc = dmalloc(S, (void **)&S->desc[k].zflag, 2 * ns);
             if (!rc && hipMemset(S->arena[k], 0, kArenaBase) != hipSuccess)
                 rc = fail(SIM_EDEVICE, "arena initialisation failed");
         }

@@ -151,7 +151,7 @@ def reservation_bytes(n, b, arena_factor=1.0, levels=5):
     nseg = 1 << (n - s)
     nblocks = 1 << (n - b)
     arena = arena_bytes(n, arena_factor)
-    per_seg = 2 * (16 + 8 + 2) + 8 * levels + 16
+    per_seg = 2 * (16 + 8) + 8 * levels + 16
     per_block = 2 * (32 + 4 + 1) + 4 + 4 + 8 + 16
     # staging of the pass kernels: 4 waves x (8 KiB payload + 64 outliers)
     # per workgroup, one workgroup per segment pair up to 2048
