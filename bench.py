@@ -362,7 +362,8 @@ SERVE_RATE = None  # requests/s; fixed from a saturated run (see --rate)
 def bench_serve(args, A, inputs, stream):
     """512 requests (QFT / Grover / random, n in [10, 30], eb in {1e-3, 1e-4,
     1e-5}) with Poisson arrivals at `rate`, 200 GB compressed budget, served
-    with continuous batching and, on the same arrivals, one circuit at a
+    with continuous batching (at most one large request active: one whose
+    pass has 8192 or more units) and, on the same arrivals, one circuit at a
     time; p50/p99 latency, gates/s and per-request fidelity."""
     from paper_1811_05140_amd import autotune, serve as SV
     specs = inputs.serving_workload(count=args.requests)
@@ -391,7 +392,7 @@ def bench_serve(args, A, inputs, stream):
         ex = SV.GpuExecutor(A, slots, G, sequential=sequential, tune=table)
         if sequential:
             return SV.serve(specs, Progress(ex), budget, 1, 10 ** 9, rate)
-        return SV.serve(specs, Progress(ex), budget, slots, G, rate)
+        return SV.serve(specs, Progress(ex), budget, slots, G, rate, max_large=1)
 
     out = {"metric": METRIC, "unit": "gates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -433,6 +434,7 @@ def bench_serve(args, A, inputs, stream):
         "config": {"workload": "serve512", "requests": len(specs), "rate_per_s": rate,
                    "n_range": [10, 30], "error_bounds": [1e-3, 1e-4, 1e-5],
                    "budget_bytes": budget, "slots": slots, "gates_per_step": G,
+                   "max_large": 1, "large_units": 8192,
                    "gates": sum(len(s["gates"]) for s in specs)},
         "batched": summ, "one_at_a_time": summ1,
         "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],

@@ -5,6 +5,12 @@ Scheduling (continuous batching):
   * requests are admitted in arrival order while a slot is free and their
     memory reservation fits the budget still unreserved (a request that does
     not fit waits, and so do the ones behind it);
+  * optionally (`max_large`), at most that many "large" requests -- states
+    that fill the GPU by themselves, as the executor judges -- are active at
+    once, taken first come first served; a large request that must wait
+    keeps its place but does not hold back smaller requests behind it.
+    Batching adds nothing to the throughput of such states, while sharing
+    steps between several of them stretches each one's latency;
   * each step applies the next `gates_per_step` gates of every admitted
     request in one batched launch sequence (one kernel set for all states);
   * a request whose last gate went out in step k is retired after step k + 1
@@ -32,7 +38,7 @@ class Overflow(Exception):
 class Request:
     __slots__ = ("rid", "arrival", "kind", "n", "eb", "basis", "gates", "marked",
                  "iterations", "arena_factor", "restarts", "admitted", "ready", "done",
-                 "result", "reserved", "handle", "pos")
+                 "result", "reserved", "handle", "pos", "large")
 
     def __init__(self, spec, rate):
         self.rid = spec["id"]
@@ -51,6 +57,7 @@ class Request:
         self.reserved = 0
         self.handle = None
         self.pos = 0
+        self.large = False
 
 
 def percentile(values, q):
@@ -61,31 +68,42 @@ def percentile(values, q):
 
 
 def serve(specs, executor, budget_bytes, max_slots, gates_per_step=1, rate=math.inf,
-          clock=time.perf_counter, sleep=time.sleep):
-    """Run the request stream; returns (requests, summary)."""
+          clock=time.perf_counter, sleep=time.sleep, max_large=None):
+    """Run the request stream; returns (requests, summary).  max_large: at
+    most this many requests for which executor.is_large(r) holds are active
+    at once (None: no such limit)."""
     reqs = [Request(s, rate) for s in specs]
-    pending = collections.deque(sorted(reqs, key=lambda r: (r.arrival, r.rid)))
+    pending = sorted(reqs, key=lambda r: (r.arrival, r.rid))
     active = []
     retiring = []
     reserved = 0
+    large_active = 0
     steps = 0
     peak_active = 0
     peak_reserved = 0
     t0 = clock()
     while pending or active or retiring:
         now = clock() - t0
-        # admission: arrival order, slots and budget
-        while pending and pending[0].arrival <= now and len(active) < max_slots:
-            r = pending[0]
+        # admission: arrival order, slots and budget; a large request over
+        # the limit is passed over (it keeps its place)
+        i = 0
+        while i < len(pending) and pending[i].arrival <= now and len(active) < max_slots:
+            r = pending[i]
+            big = max_large is not None and executor.is_large(r)
+            if big and large_active >= max_large:
+                i += 1
+                continue
             need = executor.reservation(r)
             if need > budget_bytes:
                 raise ValueError("request %d needs %d bytes, more than the budget"
                                  % (r.rid, need))
             if reserved + need > budget_bytes:
                 break
-            pending.popleft()
+            del pending[i]
             r.reserved = need
             reserved += need
+            r.large = big
+            large_active += int(big)
             r.handle = executor.open(r)
             r.pos = 0
             if r.admitted is None:
@@ -110,14 +128,16 @@ def serve(specs, executor, budget_bytes, max_slots, gates_per_step=1, rate=math.
             except Overflow:
                 r.restarts += 1
                 r.arena_factor *= 2.0
-                pending.appendleft(r)
+                pending.insert(0, r)
             r.handle = None
             reserved -= r.reserved
             r.reserved = 0
+            large_active -= int(r.large)
+            r.large = False
         retiring = [r for r in active if r.pos >= len(r.gates)]
         active = [r for r in active if r.pos < len(r.gates)]
         if not active and not retiring and pending:
-            wait = pending[0].arrival - (clock() - t0)
+            wait = min(q.arrival for q in pending) - (clock() - t0)
             if wait > 0:
                 sleep(wait)
     lat = [r.ready - r.arrival for r in reqs]
@@ -166,15 +186,19 @@ def arena_bytes(n, arena_factor=1.0):
 
 class GpuExecutor:
     """Opens one compressed sim per request (own stream), steps them with a
-    shared batch, and measures results at retirement."""
+    shared batch, and measures results at retirement.  A request is large
+    when a pass over its state has at least `large_units` workgroup units
+    (8192: eight per resident workgroup of a full MI355X, so the state keeps
+    the GPU busy by itself)."""
 
     def __init__(self, A, max_slots, gates_per_step=1, sequential=False, tune=None,
-                 probs_qubits=4):
+                 probs_qubits=4, large_units=8192):
         self.A = A
         self.sequential = sequential
         self.batch = None if sequential else A.Batch(max_slots, gates_per_step)
         self.tune = tune or {}
         self.probs_qubits = probs_qubits
+        self.large_units = large_units
 
     def block_log2(self, r):
         from paper_1811_05140_amd import autotune, inputs
@@ -185,6 +209,11 @@ class GpuExecutor:
 
     def reservation(self, r):
         return reservation_bytes(r.n, self.block_log2(r), r.arena_factor)
+
+    def is_large(self, r):
+        s = min(self.block_log2(r), 10)
+        units = 1 if r.n == s else 1 << (r.n - s - 1)
+        return units >= self.large_units
 
     def open(self, r):
         sim = self.A.Sim(r.n, self.block_log2(r), r.eb,

@@ -28,6 +28,11 @@ def test_serving_mix_equals_alone_and_oracle():
     seq = SV.GpuExecutor(A, max_slots=1, sequential=True)
     reqs1, summ1 = SV.serve(specs, seq, budget, 1, 10 ** 6, rate=200.0)
     byid = {r.rid: r for r in reqs1}
+    # at most one large request (here: 8 units or more) active at a time
+    exl = SV.GpuExecutor(A, max_slots=6, gates_per_step=2, large_units=8)
+    assert any(exl.is_large(r) for r in reqs) and not all(exl.is_large(r) for r in reqs)
+    reqs2, summ2 = SV.serve(specs, exl, budget, 6, 2, rate=200.0, max_large=1)
+    byid2 = {r.rid: r for r in reqs2}
     for r in reqs:
         s = specs[r.rid]
         b = ex.block_log2(r)
@@ -37,6 +42,7 @@ def test_serving_mix_equals_alone_and_oracle():
         sim.run(s["gates"])
         assert SV.signature(sim, r) == r.result["signature"], r.rid
         assert byid[r.rid].result["signature"] == r.result["signature"], r.rid
+        assert byid2[r.rid].result["signature"] == r.result["signature"], r.rid
         if r.n <= 9:
             o = orc.OracleSim(r.n, b, I.default_ladder(r.eb), 4.0)
             o.set_basis(r.basis)

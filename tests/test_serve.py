@@ -156,3 +156,39 @@ def test_serving_workload_shape():
     assert ts == sorted(ts) and ts[0] > 0
     # unit-rate arrivals: mean gap close to 1
     assert 0.8 < ts[-1] / len(ts) < 1.2
+
+
+def test_large_requests_one_at_a_time_first_come_first_served():
+    """max_large=1: no step holds two large states; large requests open in
+    arrival order; a small request may pass a large one that waits."""
+    clk = Clock()
+    budget = 1 << 16
+    ex = Fake(clk, budget)
+    ex.is_large = lambda r: r.n >= 8
+    sp = specs(80, seed=5)
+    reqs, summ = SV.serve(sp, ex, budget, 16, 2, 200.0, clock=clk, sleep=clk.sleep,
+                          max_large=1)
+    for s in sp:
+        assert ex.applied[s["id"]] == s["gates"]
+    large = {s["id"] for s in sp if s["n"] >= 8}
+    assert large and len(large) < len(sp)
+    for st in ex.steps:
+        assert sum(1 for rid, _ in st if rid in large) <= 1
+    order = [rid for rid in ex.open_order if rid in large]
+    assert order == sorted(order, key=lambda i: (sp[i]["t1"], i))
+    # some small request was opened before a large one that arrived earlier
+    pos = {rid: k for k, rid in enumerate(ex.open_order)}
+    passed = any(pos[s] < pos[l] and sp[l]["t1"] < sp[s]["t1"]
+                 for l in large for s in pos if s not in large)
+    assert passed
+    assert summ["requests"] == 80
+
+
+def test_no_large_limit_keeps_arrival_order():
+    clk = Clock()
+    budget = 1 << 16
+    ex = Fake(clk, budget)
+    ex.is_large = lambda r: r.n >= 8
+    sp = specs(40, seed=6)
+    SV.serve(sp, ex, budget, 16, 2, 4.0, clock=clk, sleep=clk.sleep)
+    assert ex.open_order == sorted(ex.open_order, key=lambda i: (sp[i]["t1"], i))
