@@ -516,19 +516,14 @@ __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
 __device__ __forceinline__ void lossy_code(double x, double delta, double e, double r,
                                            int32_t &q, bool &out, double &xh)
 {
+    // branch-free: a code out of range (or NaN) becomes 0 and an outlier
     const double y = x * r;
-    if (fabs(y) < kQMax) {
-        const double qr = __builtin_rint(y);
-        q = (int32_t)qr;
-        xh = qr * e;
-        out = !(fabs(x - xh) < delta);
-        if (out)
-            xh = x;
-    } else {
-        q = 0;
-        out = true;
-        xh = x;
-    }
+    const bool in = fabs(y) < kQMax;
+    const double qr = in ? __builtin_rint(y) : 0.0;
+    q = (int32_t)qr;
+    const double xq = qr * e;
+    out = !in || !(fabs(x - xq) < delta);
+    xh = out ? x : xq;
 }
 
 __device__ __forceinline__ uint32_t zigzag32(int32_t d)
@@ -549,15 +544,9 @@ __device__ __forceinline__ void gather_widths(uint32_t w, int t, uint32_t &wl)
     const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)w, 16);
     const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)w, 32);
     const uint32_t w3 = (uint32_t)__builtin_amdgcn_readlane((int)w, 48);
-    const int d = lane - 4 * t;
-    if (d == 0)
-        wl = w0;
-    else if (d == 1)
-        wl = w1;
-    else if (d == 2)
-        wl = w2;
-    else if (d == 3)
-        wl = w3;
+    const uint32_t d = (uint32_t)(lane - 4 * t);
+    const uint32_t ws = d == 0u ? w0 : (d == 1u ? w1 : (d == 2u ? w2 : w3));
+    wl = d < 4u ? ws : wl;
 }
 
 // Sizes of one plane at ladder levels k0 .. k1 (one wavefront; levels outer
@@ -659,12 +648,12 @@ constexpr int kPackRow = 126;
 // the bits above 32 - (b & 31) spill into the next dword).
 __device__ __forceinline__ void or_bits32(uint32_t *pb, uint32_t b, uint32_t v)
 {
-    if (!v)
-        return;
+    // branch-free: ORing 0 is harmless and cheaper than masking lanes off.
+    // A spill into dword 126 is never non-zero (a chunk's bits end below
+    // 64 * 63), so that index is clamped into the row.
     const uint32_t k = b >> 5, sh = b & 31u;
     atomicOr(&pb[k], v << sh);
-    if (sh && (v >> (32u - sh)))
-        atomicOr(&pb[k + 1], v >> (32u - sh));
+    atomicOr(&pb[min(k + 1u, (uint32_t)kPackRow - 1u)], (uint32_t)(((uint64_t)v << sh) >> 32));
 }
 
 // Encode one plane at one level into its record (one wavefront).  Lane c
@@ -703,15 +692,9 @@ __device__ uint32_t size_pack_level(double *x, int s, double delta, double e, do
         const uint32_t woff =
             base_w + (row > 0 ? w0 : 0u) + (row > 1 ? w1 : 0u) + (row > 2 ? w2 : 0u);
         base_w += w0 + w1 + w2 + w3;
-        const int d = lane - 4 * t;
-        if (d == 0)
-            wl = w0;
-        else if (d == 1)
-            wl = w1;
-        else if (d == 2)
-            wl = w2;
-        else if (d == 3)
-            wl = w3;
+        const uint32_t d = (uint32_t)(lane - 4 * t);
+        const uint32_t ws = d == 0u ? w0 : (d == 1u ? w1 : (d == 2u ? w2 : w3));
+        wl = d < 4u ? ws : wl;
         return woff;
     };
     for (int t = 0; t < steps; ++t) {
