@@ -148,6 +148,9 @@ CASES = [
     (12, 9, [0.0, 1e-9, 1e-7, 1e-5, 1e-3], 4.0, 60, 4),
     (8, 6, [0.0, 1e-3, 1e-2], 32.0, 60, 5),
     (13, 12, [0.0, 1e-8, 1e-6], 2.0, 30, 6),
+    # one segment per state (units of a single segment)
+    (8, 8, [0.0, 1e-6, 1e-4], 4.0, 40, 7),
+    (6, 6, [0.0, 1e-3], 8.0, 30, 8),
 ]
 
 
