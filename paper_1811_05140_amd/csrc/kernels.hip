@@ -1244,7 +1244,8 @@ __device__ void zero_unit(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
 
 template <int MODE>
 __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, PassLds &S,
-                          double scale, const double *tdiff, bool zp)
+                          double scale, const double *tdiff, bool zp,
+                          const DevState *lazy = nullptr)
 {
     Planes &X = S.X;
     double *red = (double *)S.misc;
@@ -1252,7 +1253,6 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int us = wave >> 1, p = wave & 1;
     const int L = a.lad.L;
-    const bool do_scale = !a.src_basis && scale != 1.0;
     const uint64_t nplanes = 2 * a.geo.nseg;
     const int bs = a.geo.b - s;
     const uint32_t padC = pad8(1u << (s - 6));
@@ -1267,6 +1267,15 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     uint64_t poff = 0, zoff = 1;
     double pdelta = 0.0;
     uint32_t lraw = 0;
+    // lazy: s and 2*mean read here, with the unit's reads, instead of in a
+    // round trip of their own at the kernel's start
+    double tdl[2] = {0.0, 0.0};
+    if (lazy) {
+        scale = lazy->scale;
+        tdl[0] = lazy->tdiff[0];
+        tdl[1] = lazy->tdiff[1];
+        tdiff = tdl;
+    }
     if (MODE == kReplay)
         lraw = a.dout.blk_level[j];
     if (!a.src_basis) {
@@ -1280,7 +1289,7 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         zoff = o00 | o01 | o10 | o11;
         // keeps the compiler from sinking these loads to their first uses
         // (one wait for all of them instead of one round trip each)
-        asm volatile("" ::"v"(zoff), "v"(poff), "v"(pdelta), "v"(lraw));
+        asm volatile("" ::"v"(zoff), "v"(poff), "v"(pdelta), "v"(lraw), "v"(scale));
     }
     const int lvl = MODE == kReplay ? (int)lraw : ((int)lraw < L ? (int)lraw : L - 1);
     if (a.src_basis) {
@@ -1304,7 +1313,7 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
             for (int o = lane; o < (1 << s); o += 64)
                 dst[sw(o)] = (p == 0 && ((g << s) | (uint64_t)o) == a.basis) ? 1.0 : 0.0;
         } else {
-            decode_plane(a.arena_in + poff, s, pdelta, scale, do_scale, dst);
+            decode_plane(a.arena_in + poff, s, pdelta, scale, scale != 1.0, dst);
         }
     }
     __syncthreads();
@@ -1390,14 +1399,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     if (threadIdx.x == 0)
         S.chunk[0] = S.chunk[1] = 0;
     const uint64_t Ms = a.gate.mask >> a.geo.s;
-    // kernel-uniform device state, read once (its cache line also holds the
-    // bump pointers that every unit updates atomically)
-    const double scale = a.dev->scale;
-    const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
+    // s and 2*mean are read by each unit together with its own reads
     const bool zp = zero_preserving(a.gate);
     for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
         const Unit uc = unit_of(it, a.geo.nseg, Ms);
-        unit_body<kFused>(a, uc, ~0ull, S, scale, tdiff, zp);
+        unit_body<kFused>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
         __syncthreads();
     }
 }
