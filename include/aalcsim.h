@@ -158,7 +158,7 @@ int sim_export_block(sim_t *sim, uint64_t j, void *buf, size_t cap,
                      size_t *len);
 
 /* Launch shape of the per-gate pass: at most max_workgroups workgroups
- * (64..65536, default 2048) loop over the segment pairs of the state.  A
+ * (64..65536, default 3072) loop over the segment pairs of the state.  A
  * tuning knob only: results do not depend on it. */
 int sim_set_grid(sim_t *sim, int max_workgroups);
 

@@ -25,7 +25,7 @@ if __package__ in (None, ""):
 from paper_1811_05140_amd import inputs
 
 B_RANGE = (12, 20)
-GRIDS = (1024, 2048, 4096)
+GRIDS = (1024, 2048, 3072, 4096, 8192)
 TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
 
 

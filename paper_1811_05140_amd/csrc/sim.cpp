@@ -127,7 +127,8 @@ struct sim {
     int cur = 0;
     uint64_t passes = 0;
     bool valid = false;  // the current descriptor set holds a complete state
-    unsigned grid_cap = 2048;  // workgroups of the per-gate unit kernels
+    unsigned grid_cap = 3072;  // workgroups of the per-gate unit kernels (three per
+                               // resident slot of 256 CUs x 4)
     // uncompressed path
     double *amp = nullptr;
     double *sv_scratch = nullptr;

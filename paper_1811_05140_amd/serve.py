@@ -174,9 +174,10 @@ def reservation_bytes(n, b, arena_factor=1.0, levels=5):
     per_seg = 2 * (16 + 8) + 8 * levels + 16
     per_block = 2 * (32 + 4 + 1) + 4 + 4 + 8 + 16
     # staging of the pass kernels: 4 waves x (8 KiB payload + 64 outliers)
-    # per workgroup, one workgroup per segment pair up to 2048
+    # per workgroup, one workgroup per segment pair up to the default grid
+    # of 3072
     nunits = 1 if nseg == 1 else nseg // 2
-    staging = min(nunits, 2048) * 4 * (16 * 64 * 8 + 64 * 16)
+    staging = min(nunits, 3072) * 4 * (16 * 64 * 8 + 64 * 16)
     return 2 * arena + per_seg * nseg + per_block * nblocks + staging + 4096
 
 
