@@ -1113,7 +1113,7 @@ struct sim_batch {
 namespace {
 
 constexpr size_t kMaxGraphs = 16;
-constexpr unsigned kMaxBatchGrid = 2048;
+constexpr unsigned kMaxBatchGrid = 4096;
 
 size_t slot_prefix_off(int max_states)
 {
