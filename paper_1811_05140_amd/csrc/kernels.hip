@@ -1475,6 +1475,39 @@ __device__ void mean_unit(const PassArgs &a, uint64_t u, Planes &X, double *red,
                           double scale)
 {
     const Unit uc = unit_of(u, a.geo.nseg, 0);
+    const int s = a.geo.s;
+    // A unit whose plane records carry neither payload nor outliers holds
+    // one value per plane (the anchor's: the bit pattern, or code times 2
+    // delta), and the pairwise tree of 2^s equal values v is exactly 2^s v
+    // (each addition doubles): its sums need no decode, LDS or barrier.
+    // (Grover states are almost entirely such units.)
+    {
+        const uint64_t g0 = uc.seg(0), g1 = uc.seg(1);
+        const uint64_t o0 = a.din.plane_off[2 * g0], o1 = a.din.plane_off[2 * g0 + 1];
+        const uint64_t o2 = a.din.plane_off[2 * g1], o3 = a.din.plane_off[2 * g1 + 1];
+        // payload words | outliers << 32 of each record
+        const uint64_t h0 = *(const uint64_t *)(a.arena_in + o0 + 8);
+        const uint64_t h1 = *(const uint64_t *)(a.arena_in + o1 + 8);
+        const uint64_t h2 = *(const uint64_t *)(a.arena_in + o2 + 8);
+        const uint64_t h3 = *(const uint64_t *)(a.arena_in + o3 + 8);
+        if ((h0 | h1 | h2 | h3) == 0) {
+            const unsigned t = threadIdx.x;
+            if (t < 2u * (unsigned)uc.nsu) {
+                const uint64_t g = (t >> 1) ? g1 : g0;
+                const uint64_t o = t == 0 ? o0 : (t == 1 ? o1 : (t == 2 ? o2 : o3));
+                const uint64_t anc = *(const uint64_t *)(a.arena_in + o);
+                const double delta =
+                    *(const double *)(a.din.hdr + 32 * (g >> (a.geo.b - s)) + 16);
+                const double e = 2.0 * delta;
+                double v = delta == 0.0 ? __longlong_as_double((long long)anc)
+                                        : (double)(int32_t)(uint32_t)anc * e;
+                if (scale != 1.0)
+                    v = v * scale;
+                a.segsum[(uint64_t)(t & 1) * a.geo.nseg + g] = v * (double)(1u << s);
+            }
+            return;
+        }
+    }
     load_unit(a, uc, X, scale, scale != 1.0);
     __syncthreads();
     for (int c = 0; c < 2; ++c) {
