@@ -1408,6 +1408,163 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     }
 }
 
+// The value of plane i (segment i >> 1, component i & 1) of a unit whose
+// records hold one value each, after decode, normalisation and the gate
+// (DIFFUSE: 2 mean - a; PHASE_FLIP outside its index: unchanged).
+__device__ __forceinline__ double const_plane_value(const PassArgs &a, uint64_t anchor,
+                                                    double delta_in, int comp, double scale,
+                                                    double td)
+{
+    double x = delta_in == 0.0 ? __longlong_as_double((long long)anchor)
+                               : (double)(int32_t)(uint32_t)anchor * (2.0 * delta_in);
+    if (scale != 1.0)
+        x = x * scale;
+    (void)comp;
+    return a.gate.kind == kDiffuse ? td - x : x;
+}
+
+// Fast path of a DIFFUSE or PHASE_FLIP pass for a unit whose four input
+// records carry neither payload nor outliers (Grover states are almost
+// entirely such units).  Each plane then holds one value y after the gate,
+// and its encoding follows from y alone: at every level all codes are equal
+// (every Lorenzo residual and chunk width is 0, so no payload), a lossy level
+// has either no outlier or all 2^s of them, and the record is the anchor.
+// The segment normsq is 2^s times fl(fl(re^2) + fl(im^2)) of the x-hat
+// values (the pairwise tree of equal leaves doubles exactly).  Units whose
+// speculated level would hold outliers, and the unit holding PHASE_FLIP's
+// index, take the full path.  Returns whether the unit was handled
+// (workgroup-uniform).
+__device__ bool const_unit(const PassArgs &a, const Unit &uc, PassLds &S, double scale,
+                           const double *tdiff)
+{
+    if (a.src_basis)
+        return false;
+    const int s = a.geo.s, bs = a.geo.b - s, L = a.lad.L;
+    if (a.gate.kind == kPhaseFlip) {
+        const uint64_t gm = a.gate.index >> s;
+        if (uc.seg(0) == gm || uc.seg(1) == gm)
+            return false;
+    }
+    const uint64_t g0 = uc.seg(0), g1 = uc.seg(1);
+    const uint64_t o[4] = {a.din.plane_off[2 * g0], a.din.plane_off[2 * g0 + 1],
+                           a.din.plane_off[2 * g1], a.din.plane_off[2 * g1 + 1]};
+    uint64_t hv = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        hv |= *(const uint64_t *)(a.arena_in + o[i] + 8);  // payload words | outliers
+    if (hv != 0)
+        return false;
+    // every thread evaluates all four planes (a few scalars): the decision
+    // below is then uniform without LDS
+    double y[4], xh[4];
+    uint64_t anc_out[4];
+    int lev[2];
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t g = (i >> 1) ? g1 : g0;
+        const uint64_t j = g >> bs;
+        const double delta_in = *(const double *)(a.din.hdr + 32 * j + 16);
+        const int hl = a.din.blk_level[j];
+        const int h = hl < L ? hl : L - 1;
+        lev[i >> 1] = h;
+        const uint64_t anc = *(const uint64_t *)(a.arena_in + o[i]);
+        y[i] = const_plane_value(a, anc, delta_in, i & 1, scale, tdiff[i & 1]);
+        const double dh = a.lad.delta[h];
+        if (dh == 0.0) {
+            xh[i] = y[i];
+            anc_out[i] = (uint64_t)__double_as_longlong(y[i]);
+        } else {
+            int32_t q;
+            bool out;
+            double xq;
+            lossy_code(y[i], dh, a.lad.e[h], a.lad.r[h], q, out, xq);
+            ok = ok && !out;
+            xh[i] = xq;
+            anc_out[i] = (uint64_t)(int64_t)q;
+        }
+    }
+    if (!ok)
+        return false;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int us = wave >> 1, p = wave & 1;
+    const bool active = us < uc.nsu;
+    const uint64_t g = us ? g1 : g0;
+    const uint64_t plane = 2 * g + p;
+    const uint64_t nplanes = 2 * a.geo.nseg;
+    const int i = 2 * us + p;
+    const double yi = i == 0 ? y[0] : (i == 1 ? y[1] : (i == 2 ? y[2] : y[3]));
+    const uint64_t ai = i == 0 ? anc_out[0]
+                               : (i == 1 ? anc_out[1] : (i == 2 ? anc_out[2] : anc_out[3]));
+    const int h = us ? lev[1] : lev[0];
+    // sizes of levels 0..h: no payload; a lossy level below h has 2^s
+    // outliers when y misses its bound
+    if (active && lane <= h) {
+        const int k = lane;
+        uint32_t v = 0;
+        if (a.lad.delta[k] != 0.0) {
+            int32_t q;
+            bool out;
+            double xq;
+            lossy_code(yi, a.lad.delta[k], a.lad.e[k], a.lad.r[k], q, out, xq);
+            v = out ? (1u << s) << 16 : 0u;
+        }
+        a.psz[(uint64_t)k * nplanes + plane] = v;
+    }
+    // the record: the anchor alone (the shared zero record when it is 0)
+    const bool zrec = ai == 0ull;
+    const uint64_t off = alloc_records(a, S, active && !zrec, kPlaneHdrBytes);
+    if (active && lane == 0) {
+        if (zrec) {
+            a.dout.plane_off[plane] = 0;
+        } else if (off != ~0ull) {
+            a.dout.plane_off[plane] = off;
+            uint4 r;
+            r.x = (uint32_t)ai;
+            r.y = (uint32_t)(ai >> 32);
+            r.z = 0u;
+            r.w = 0u;
+            *(uint4 *)(a.arena_out + off) = r;
+        }
+    }
+    if (threadIdx.x < (unsigned)uc.nsu) {
+        const int k = (int)threadIdx.x;
+        const double re = k ? xh[2] : xh[0], im = k ? xh[3] : xh[1];
+        const double rr = re * re;
+        const double ii = im * im;
+        a.dout.segnorm[uc.seg(k)] = (rr + ii) * (double)(1u << s);
+    }
+    return true;
+}
+
+// The pass for DIFFUSE and PHASE_FLIP gates: k_pass with const_unit's fast
+// path in front of the unit body.
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pass_const(
+    PassArgs a)
+{
+    if (gridDim.x > a.scratch_wgs) {  // launch larger than the staging (host bug)
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            atomicOr(&a.dev->err, kErrSize);
+        return;
+    }
+    if (a.dev->err)
+        return;
+    __shared__ PassLds S;
+    for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
+        (&S.pack[0][0])[k] = 0u;
+    if (threadIdx.x == 0)
+        S.chunk[0] = S.chunk[1] = 0;
+    const double scale = a.dev->scale;
+    const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
+    const bool zp = zero_preserving(a.gate);
+    for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
+        const Unit uc = unit_of(it, a.geo.nseg, 0);
+        if (!const_unit(a, uc, S, scale, tdiff))
+            unit_body<kFused>(a, uc, ~0ull, S, scale, tdiff, zp);
+        __syncthreads();
+    }
+}
+
 // Replays and escalations left by k_decide.  Items: (replayed block,
 // segment) pairs, one unit each, encoded again at the chosen level; then
 // one item per escalated block, whose workgroup sizes the remaining levels
@@ -2486,7 +2643,10 @@ void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *pr
     const unsigned gfix = gu < 256 ? gu : 256;
     PassArgs a = a0;
     a.chunk_bytes = batch_chunk_bytes(a.arena_cap, gu);
-    TIMED(prof, kIdPass, st, hipLaunchKernelGGL(k_pass, dim3(gu), dim3(kWG), 0, st, a));
+    if (a.gate.kind == kDiffuse || a.gate.kind == kPhaseFlip)
+        TIMED(prof, kIdPass, st, hipLaunchKernelGGL(k_pass_const, dim3(gu), dim3(kWG), 0, st, a));
+    else
+        TIMED(prof, kIdPass, st, hipLaunchKernelGGL(k_pass, dim3(gu), dim3(kWG), 0, st, a));
     TIMED(prof, kIdDecide, st, hipLaunchKernelGGL(k_decide, dim3(gb), dim3(kWG), 0, st, a));
     if (a.lad.L > 1)
         TIMED(prof, kIdReplay, st, hipLaunchKernelGGL(k_fix, dim3(gfix), dim3(kWG), 0, st, a));

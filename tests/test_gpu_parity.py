@@ -240,6 +240,31 @@ def test_grover_n16_full_parity(A):
     assert abs(p - I.grover_success(n, k)) < 1e-6
 
 
+@pytest.mark.parametrize("lad,theta", [
+    ([1e-3], 4.0),                       # one lossy level
+    ([1e-9, 1e-3], 4.0),                 # the finest lossy level suffices
+    ([0.0, 1e-9, 1e-6, 1e-3], 1000.0),   # theta above every ratio: the last level,
+                                         # lossless and lossy levels sized below it
+])
+def test_grover_constant_planes_every_level_kind(A, lad, theta):
+    """Grover states are made of planes that hold one value; their DIFFUSE
+    and PHASE_FLIP passes encode such units from the value alone.  Streams
+    after every gate equal the oracle's for lossless, lossy and last-level
+    choices (levels below the chosen one sized)."""
+    n, k, b = 12, 3, 10
+    m = 0x5A5
+    say("grover constant planes", lad, theta)
+    gates = I.grover(n, m, k)
+    g = A.Sim(n, b, lad[-1], ladder=lad, theta=theta)
+    o = orc.OracleSim(n, b, lad, theta)
+    for q, gate in enumerate(gates):
+        g.apply(gate)
+        o.apply(gate)
+        assert_streams_equal(g, o, 1 << (n - b), "gate %d kind %d" % (q, gate[0]))
+    assert g.stats()["level_hist"] == o.stats()["level_hist"]
+    assert same_bits(g.amplitudes(), o.amplitudes())
+
+
 def test_amplitude_sum_and_headers_match_oracle(A):
     for name, n, b, lad, x, gates in (
             ("grover", 16, 12, I.default_ladder(1e-5), 0, I.grover(16, 0xBEEF, 3)),
