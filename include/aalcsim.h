@@ -46,7 +46,7 @@ enum {
     SIM_EBUDGET = -3,       /* reserved for budgeted contexts */
     SIM_EDEVICE = -4,       /* HIP runtime error */
     SIM_ECOLLAPSED = -5,    /* N^2 of the stored state was 0 or not finite */
-    SIM_EUNSUPPORTED = -6   /* valid request this build does not implement */
+    SIM_EUNSUPPORTED = -6   /* valid request that the library does not implement */
 };
 
 /* Gate kinds.  u is a 2x2 complex matrix, row-major, (re, im) pairs:
