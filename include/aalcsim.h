@@ -157,6 +157,34 @@ int sim_get_amplitudes(sim_t *sim, uint64_t first, uint64_t count,
 int sim_export_block(sim_t *sim, uint64_t j, void *buf, size_t cap,
                      size_t *len);
 
+/* Checkpoint of the whole state: the canonical block streams of every block,
+ * block 0 first, concatenated into host memory buf (cap bytes); *len
+ * receives the total (also when cap is too small or buf is NULL, in which
+ * case SIM_ENOMEM is returned).  This is the state Alg. 1 keeps (each stride
+ * stored compressed); the scale of the next gate follows from the normsq
+ * fields, so these bytes are the whole resumable state.  The streams are
+ * staged in the sim's idle arena (no device allocation).  Synchronises.
+ * SIM_EUNSUPPORTED on the uncompressed path. */
+int sim_export_state(sim_t *sim, void *buf, size_t cap, size_t *len);
+
+/* Resume from a checkpoint: replace the state by the concatenated block
+ * streams in host memory buf[0..len) as sim_export_state writes them (or any
+ * producer of block stream v1).  Every stream must have this sim's segment
+ * and block sizes and a level of this sim's ladder whose bound equals its
+ * delta bit for bit (set the ladder first with sim_set_aalc), its records
+ * must be well formed (sizes, chunk widths, first residual 0, lossy anchors
+ * within +-(2^30 - 1), ascending in-plane outlier indices, none in lossless
+ * planes), and its normsq field must equal the normsq of its decoded values.
+ * The host checks the headers, then the streams are copied into the idle
+ * arena and checked there by kernels.  On success the sim holds that state:
+ * N^2 and the scale of the next gate are recomputed from the decoded values
+ * exactly as after a pass, the pass count restarts at 0, and the following
+ * gates give the streams the exporting sim would have produced.  Returns
+ * SIM_EINVAL (state unchanged) on a malformed or mismatched stream,
+ * SIM_ENOMEM when the streams exceed the arena, SIM_ECOLLAPSED (state
+ * replaced) when the imported N^2 is 0 or not finite.  Synchronises. */
+int sim_import_state(sim_t *sim, const void *buf, size_t len);
+
 /* Launch shape of the per-gate pass: at most max_workgroups workgroups
  * (64..65536, default 3072) loop over the segment pairs of the state.  A
  * tuning knob only: results do not depend on it. */

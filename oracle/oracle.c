@@ -31,7 +31,11 @@
 #define PLANE_HDR_BYTES 16u
 #define OUTLIER_BYTES 16u
 #define CHUNK 64u
-#define QMAX 1073741824.0 /* 2^30: largest |y| accepted by the quantiser */
+/* Bound on |y| for an in-range code: 2^30 - 1, so that every code lies in
+ * [-(2^30 - 1), 2^30 - 1] and every Lorenzo residual of two codes fits in 32
+ * signed bits (the lossy residual of the format is then the same whether it
+ * is formed in 32- or 64-bit arithmetic). */
+#define QMAX 1073741823.0
 
 /* ------------------------------------------------------------------------ */
 /* growable byte buffer                                                     */
@@ -118,7 +122,7 @@ static uint64_t unzigzag(uint64_t z) { return (z >> 1) ^ (0 - (z & 1)); }
  * Lossy (delta > 0), reading of Sec. III's bound D_i - delta <= D'_i <=
  * D_i + delta, applied per real component:
  *   e = 2 delta, r = fl(1/e), y = fl(x r)
- *   if |y| < 2^30:  q = round-half-even(y), xhat = fl(q e),
+ *   if |y| < 2^30 - 1:  q = round-half-even(y), xhat = fl(q e),
  *                   outlier iff not (|fl(x - xhat)| < delta)
  *   else (also NaN): q = 0, outlier.
  * Lossless (delta == 0, the zstd role of Sec. III): q = the 64 bits of x.
@@ -239,6 +243,9 @@ static size_t decode_plane(const uint8_t *p, const uint8_t *end, size_t m,
     if ((size_t)(end - p) < PLANE_HDR_BYTES)
         return 0;
     uint64_t anchor = rd_u64(p);
+    /* a lossy anchor is a code: a sign-extended value within +-(2^30 - 1) */
+    if (delta != 0.0 && ((int64_t)anchor > (int64_t)QMAX || (int64_t)anchor < -(int64_t)QMAX))
+        return 0;
     uint32_t pw = rd_u32(p + 8);
     uint32_t nout = rd_u32(p + 12);
     const uint8_t *cur = p + PLANE_HDR_BYTES;
@@ -253,8 +260,11 @@ static size_t decode_plane(const uint8_t *p, const uint8_t *end, size_t m,
         memcpy(wid, cur, nch);
         cur += padded;
         uint32_t sum = 0;
+        /* a lossy residual fits 32 signed bits (codes are at most
+         * 2^30 - 1 in magnitude), so its zigzag is at most 32 bits wide */
+        int wmax = delta == 0.0 ? 64 : 32;
         for (size_t c = 0; c < nch; c++) {
-            if (wid[c] > 64)
+            if (wid[c] > wmax)
                 return 0;
             sum += wid[c];
         }
@@ -1048,6 +1058,79 @@ int or_export_block(const or_sim *sim, uint64_t j, uint8_t *buf, size_t cap,
         return OR_ENOMEM;
     memcpy(buf, sim->streams[j], sim->lens[j]);
     return OR_OK;
+}
+
+/* Checkpoint resume: the state becomes the one whose block streams are
+ * given, exactly as if those streams had just been written by a pass (the
+ * per-block normsq fields give N^2 and the scale of the next gate, as after
+ * every pass).  Each stream is checked before anything is replaced: header
+ * fields against this simulator (magic, s, b, a ladder level whose bound
+ * equals the header's delta bit for bit), the records as or_decode_block
+ * checks them, and the header normsq against the normsq of the decoded
+ * values.  On any failure the state is left unchanged. */
+int or_import_state(or_sim *sim, const uint8_t *buf, size_t len)
+{
+    if (!sim || (!buf && len))
+        return OR_EINVAL;
+    size_t namp = (size_t)1 << sim->b;
+    uint64_t nb = sim->nblocks;
+    size_t *off = (size_t *)malloc(nb * sizeof(size_t));
+    size_t *ln = (size_t *)malloc(nb * sizeof(size_t));
+    double *x = (double *)malloc(2 * namp * sizeof(double));
+    uint8_t **copies = (uint8_t **)calloc(nb, sizeof(uint8_t *));
+    int rc = OR_ENOMEM;
+    if (!off || !ln || !x || !copies)
+        goto done;
+    rc = OR_EINVAL;
+    size_t pos = 0;
+    for (uint64_t j = 0; j < nb; j++) {
+        if (len - pos < HDR_BYTES)
+            goto done;
+        const uint8_t *h = buf + pos;
+        uint32_t total = rd_u32(h + 12);
+        int level = h[4];
+        if (rd_u32(h) != OR_MAGIC || h[5] != 0 || h[6] != sim->s || h[7] != sim->b ||
+            level >= sim->L || dbits(rd_f64(h + 16)) != dbits(sim->ladder[level]) ||
+            total < HDR_BYTES || total > len - pos)
+            goto done;
+        if (or_decode_block(h, total, x) != OR_OK)
+            goto done;
+        if (dbits(block_normsq(x, namp)) != dbits(rd_f64(h + 24)))
+            goto done;
+        off[j] = pos;
+        ln[j] = total;
+        pos += total;
+    }
+    if (pos != len)
+        goto done;
+    rc = OR_ENOMEM;
+    for (uint64_t j = 0; j < nb; j++) {
+        copies[j] = (uint8_t *)malloc(ln[j]);
+        if (!copies[j])
+            goto done;
+        memcpy(copies[j], buf + off[j], ln[j]);
+    }
+    for (uint64_t j = 0; j < nb; j++) {
+        free(sim->streams[j]);
+        sim->streams[j] = copies[j];
+        sim->lens[j] = ln[j];
+        copies[j] = NULL;
+    }
+    sim->collapsed = 0;
+    sim->scale = 1.0;
+    sim->passes = 0;
+    memset(sim->level_hist, 0, sizeof sim->level_hist);
+    update_norm(sim);
+    rc = sim->collapsed ? OR_ECOLLAPSED : OR_OK;
+done:
+    if (copies)
+        for (uint64_t j = 0; j < nb; j++)
+            free(copies[j]);
+    free(copies);
+    free(x);
+    free(ln);
+    free(off);
+    return rc;
 }
 
 int or_get_stats(const or_sim *sim, or_stats *st)

@@ -103,6 +103,15 @@ int or_get_amplitudes(const or_sim *sim, uint64_t first, uint64_t count,
 int or_export_block(const or_sim *sim, uint64_t j, uint8_t *buf, size_t cap,
                     size_t *len);
 
+/* Replace the state by the concatenated block streams buf[0..len) (block 0
+ * first, each as or_export_block writes it).  Every stream must match this
+ * simulator's s, b and ladder (its delta equal to the bound of its level)
+ * and decode cleanly, and its normsq field must equal the normsq of its
+ * decoded values; otherwise OR_EINVAL and the state is unchanged.  Returns
+ * OR_ECOLLAPSED (state replaced) when N^2 of the imported state is 0 or not
+ * finite. */
+int or_import_state(or_sim *sim, const uint8_t *buf, size_t len);
+
 typedef struct {
     double normsq;           /* N^2 of the stored state after the last pass */
     double scale;            /* s applied at the next decode */

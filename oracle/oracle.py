@@ -90,6 +90,7 @@ def lib():
         L.or_fidelity.restype = ctypes.c_double
         L.or_fidelity.argtypes = [dp, dp, ctypes.c_int]
         L.or_amplitude_sum.argtypes = [ctypes.c_void_p, dp]
+        L.or_import_state.argtypes = [ctypes.c_void_p, u8p, ctypes.c_size_t]
     return _lib
 
 
@@ -264,6 +265,21 @@ class OracleSim:
         if rc:
             raise ValueError("or_export_block rc=%d" % rc)
         return bytes(out[:n.value])
+
+    def export_state(self):
+        """Every block's stream, block 0 first (the checkpoint of the state)."""
+        return b"".join(self.export_block(j)
+                        for j in range(1 << (self.n - self.b)))
+
+    def import_state(self, data):
+        """Replace the state by concatenated block streams; returns the code
+        (0, or -5 when N^2 of the imported state is 0 or not finite) and
+        raises ValueError when a stream is rejected."""
+        buf = np.frombuffer(bytes(data), dtype=np.uint8).copy()
+        rc = lib().or_import_state(self.h, _u8p(buf), buf.size)
+        if rc not in (0, -5):
+            raise ValueError("or_import_state rc=%d" % rc)
+        return rc
 
     def stats(self):
         st = Stats()

@@ -27,7 +27,7 @@ EXPORTS = [
     "sim_export_headers", "sim_amplitude_sum",
     "sim_batch_create", "sim_batch_destroy", "sim_batch_apply", "sim_batch_sync",
     "sim_batch_info", "sim_set_grid", "sim_batch_profile", "sim_batch_profile_read",
-    "sim_fourier_overlap",
+    "sim_fourier_overlap", "sim_export_state", "sim_import_state",
 ]
 
 
@@ -97,6 +97,8 @@ def _load():
     L.sim_export_headers.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, vp,
                                      ctypes.c_size_t]
     L.sim_amplitude_sum.argtypes = [vp, dp]
+    L.sim_export_state.argtypes = [vp, vp, ctypes.c_size_t, P(ctypes.c_size_t)]
+    L.sim_import_state.argtypes = [vp, vp, ctypes.c_size_t]
     L.sim_set_grid.argtypes = [vp, ctypes.c_int]
     L.sim_fourier_overlap.argtypes = [vp, ctypes.c_uint64, dp]
     L.sim_stats.argtypes = [vp, P(Stats)]
@@ -270,6 +272,33 @@ class Sim:
         buf = ctypes.create_string_buffer(max(ln.value, 1))
         check(lib.sim_export_block(self.h, j, buf, ln.value, ctypes.byref(ln)), True)
         return buf.raw[:ln.value]
+
+    def export_state(self, out=None):
+        """Checkpoint: every block's stream, block 0 first, as bytes (or into
+        `out`, a writable buffer such as a pinned uint8 tensor's numpy view,
+        when given; then the byte count is returned)."""
+        ln = ctypes.c_size_t(0)
+        rc = lib.sim_export_state(self.h, None, 0, ctypes.byref(ln))
+        if rc not in (SIM_OK, SIM_ENOMEM, SIM_ECOLLAPSED):
+            check(rc)
+        if out is not None:
+            arr = np.frombuffer(out, dtype=np.uint8)
+            if arr.size < ln.value:
+                raise SimError(SIM_ENOMEM, "buffer of %d bytes too small for %d"
+                               % (arr.size, ln.value))
+            check(lib.sim_export_state(self.h, arr.ctypes.data, arr.size,
+                                       ctypes.byref(ln)), True)
+            return ln.value
+        buf = ctypes.create_string_buffer(max(ln.value, 1))
+        check(lib.sim_export_state(self.h, buf, ln.value, ctypes.byref(ln)), True)
+        return buf.raw[:ln.value]
+
+    def import_state(self, data, nbytes=None):
+        """Resume from a checkpoint (bytes, or any buffer with `nbytes`)."""
+        arr = np.frombuffer(data, dtype=np.uint8)
+        if nbytes is not None:
+            arr = arr[:nbytes]
+        return check(lib.sim_import_state(self.h, arr.ctypes.data, arr.size), True)
 
     def export_headers(self, first=0, count=None):
         """32-byte stream headers of blocks [first, first+count), normsq filled."""

@@ -18,7 +18,10 @@ constexpr int kWG = 256;       // threads per workgroup: four wavefronts
 constexpr int kMaxL = 8;       // ladder levels
 constexpr int kMinS = 6;       // segment log2 range supported by the kernels
 constexpr int kMaxS = 10;
-constexpr double kQMax = 1073741824.0;  // 2^30
+// Largest |y| (exclusive) that quantises to a code: 2^30 - 1, so codes lie
+// in [-(2^30 - 1), 2^30 - 1] and the Lorenzo residual of two codes always
+// fits 32 signed bits (the format defines it in 64-bit arithmetic).
+constexpr double kQMax = 1073741823.0;
 // Per-wave staging of a plane's packed payload (at most 16 chunks x 64 words)
 // and of its first kScratchOutl outliers, written while the encode level is
 // sized and copied into the record once its arena offset is known.
@@ -96,7 +99,9 @@ struct DevState {
 static_assert(offsetof(DevState, arena_used) == 128 && offsetof(DevState, n_replay) == 256,
               "DevState counters must start on their own 128-byte lines");
 
-enum : uint32_t { kErrArena = 1u, kErrSize = 2u };
+// kErrImport: an imported stream's records are inconsistent;
+// kErrImportNorm: a block's normsq field differs from its decoded values'.
+enum : uint32_t { kErrArena = 1u, kErrSize = 2u, kErrImport = 4u, kErrImportNorm = 8u };
 
 // Pass index recorded by the basis-state encode (set_basis), which has no
 // earlier state to fall back to.
@@ -140,7 +145,8 @@ struct PassArgs {
 enum KernelId : int {
     kIdPass, kIdDecide, kIdEscSize, kIdEscDecide, kIdReplay, kIdBlockNorm,
     kIdReduce, kIdMean, kIdMeanTree, kIdMeanFinal, kIdInitState, kIdSvPair,
-    kIdSvDiag, kIdSvPartial, kIdSvFinal, kNumKernelIds
+    kIdSvDiag, kIdSvPartial, kIdSvFinal, kIdExport, kIdImportScan, kIdImportCheck,
+    kIdImportNorm, kIdImportBlocks, kNumKernelIds
 };
 extern const char *const kKernelNames[kNumKernelIds];
 
@@ -175,6 +181,14 @@ void launch_fourier(const PassArgs &a, const double *amp, uint64_t x, double *pa
 void launch_export(const PassArgs &a, uint64_t j, uint8_t *out, hipStream_t st);
 void launch_export_headers(const PassArgs &a, uint64_t first, uint64_t count, uint8_t *out,
                            hipStream_t st);
+// Streams of blocks [first, first + count) into out, block first + k at
+// out + offs[k] (device pointers).
+void launch_export_range(const PassArgs &a, uint64_t first, uint64_t count,
+                         const uint64_t *offs, uint8_t *out, hipStream_t st, Prof *prof);
+// Checkpoint import: streams already copied to a.arena_out + kArenaBase + boff[j]
+// become descriptor set a.dout; then N^2 and s as after a pass (a.src_basis
+// set: no pass is counted).  Errors set kErrImport / kErrImportNorm.
+void launch_import(const PassArgs &a, const uint64_t *boff, hipStream_t st, Prof *prof);
 
 // One batched pass over nst states (device pointers; each prefix has nst + 1
 // entries).  upre/bpre count the units/blocks of the states with a gate in

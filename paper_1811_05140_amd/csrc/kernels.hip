@@ -280,8 +280,8 @@ __device__ __forceinline__ uint64_t field64(const uint32_t *P, uint32_t b, uint3
 // Decode one plane record into dst[0 .. 2^s) (one wavefront; dst is the
 // wave's own LDS plane region), scaling each value by `scale` when do_scale
 // (normalisation before the gate).  Lossy planes run the prefix sums in 32
-// bits: a partial sum is the difference of two codes of magnitude below
-// 2^30, so it is exact.
+// bits: a partial sum is the difference of two codes of magnitude at most
+// 2^30 - 1, so it is exact.
 // The payload is first copied into the top of dst (words 2^s - pw .. 2^s),
 // every load in flight at once, together with the widths and the first 64
 // outliers; the fields are then read from LDS.  A chunk's payload is at most
@@ -2325,10 +2325,12 @@ __global__ void k_rsqrt(const double *in, double *out, uint64_t count)
 
 // Canonical stream of block j (header + plane records in plane order) into
 // `out` (one workgroup).
-__global__ __launch_bounds__(kWG) void k_export(PassArgs a, uint64_t j, uint8_t *out)
+// Block j's canonical stream into out (its header, with the normsq field
+// formed from the block's segment sums, then its plane records in plane
+// order).  One workgroup; offs and red are workgroup scratch.
+__device__ void export_body(const PassArgs &a, uint64_t j, uint8_t *out, uint64_t *offs,
+                            uint64_t *red, double *lds)
 {
-    __shared__ uint64_t offs[2 << 10];  // planes per block: at most 2^(1 + 20 - 10)
-    __shared__ uint64_t red[kWG];
     const int t = threadIdx.x;
     const int s = a.geo.s;
     const uint64_t npb = 2ull << (a.geo.b - s);
@@ -2366,7 +2368,6 @@ __global__ __launch_bounds__(kWG) void k_export(PassArgs a, uint64_t j, uint8_t 
         // header normsq: pairwise over the block's segment sums
         const uint64_t spb = 1ull << (a.geo.b - s);
         const double *src = a.din.segnorm + j * spb;
-        __shared__ double lds[kWG];
         const double ns = wg_tree([&](uint64_t i) { return src[i]; }, spb, lds);
         if (t == 0)
             *(double *)(out + 24) = ns;
@@ -2381,6 +2382,216 @@ __global__ __launch_bounds__(kWG) void k_export(PassArgs a, uint64_t j, uint8_t 
         uint64_t *dst = (uint64_t *)(out + offs[q]);
         for (uint64_t k = lane; k < nw; k += 64)
             dst[k] = src[k];
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kWG) void k_export(PassArgs a, uint64_t j, uint8_t *out)
+{
+    __shared__ uint64_t offs[2 << 10];  // planes per block: at most 2^(1 + 20 - 10)
+    __shared__ uint64_t red[kWG];
+    __shared__ double lds[kWG];
+    export_body(a, j, out, offs, red, lds);
+}
+
+// Streams of blocks [first, first + count), block first + k at out + offs[k]
+// (the exclusive prefix of their lengths): a whole-state checkpoint.
+__global__ __launch_bounds__(kWG) void k_export_range(PassArgs a, uint64_t first,
+                                                      uint64_t count,
+                                                      const uint64_t *__restrict__ offs_out,
+                                                      uint8_t *out)
+{
+    __shared__ uint64_t offs[2 << 10];
+    __shared__ uint64_t red[kWG];
+    __shared__ double lds[kWG];
+    for (uint64_t k = blockIdx.x; k < count; k += gridDim.x)
+        export_body(a, first + k, out + offs_out[k], offs, red, lds);
+}
+
+// ------------------------------------------------------ import ------------
+//
+// Checkpoint resume: concatenated block streams, copied into the arena that
+// becomes the state's (arena_out, from kArenaBase on; block j's stream at
+// kArenaBase + boff[j]), are turned into the descriptor set dout in place:
+// every plane record stays where the copy put it.  The host has checked each
+// block header (magic, s, b, level, delta, length within the buffer); these
+// kernels check the records, and any failure sets an error bit that every
+// later import kernel (and k_reduce) honours by doing nothing.
+
+// One thread per block walks its plane records (each record's size follows
+// from its own header), records where each one starts, and checks that the
+// records fill the stream exactly and that their outlier counts add up to
+// the header's.  Every read lies inside the block's stream: a record header
+// is read only when 16 bytes remain, and a record is accepted only when it
+// ends within the stream.
+__global__ __launch_bounds__(kWG) void k_import_scan(PassArgs a, const uint64_t *__restrict__ boff)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    if (j >= a.geo.nblocks)
+        return;
+    const int s = a.geo.s;
+    const uint64_t npb = 2ull << (a.geo.b - s);
+    const uint32_t C = 1u << (s - 6);
+    const uint32_t padC = pad8(C);
+    const uint8_t *base = a.arena_out;
+    const uint64_t start = kArenaBase + boff[j];
+    const uint64_t *h = (const uint64_t *)(base + start);
+    const uint64_t h0 = h[0], h1 = h[1], h2 = h[2], h3 = h[3];
+    uint64_t *hd = (uint64_t *)(a.dout.hdr + 32 * j);
+    hd[0] = h0;
+    hd[1] = h1;
+    hd[2] = h2;
+    hd[3] = h3;
+    const uint32_t nout_hdr = (uint32_t)h1;
+    const uint32_t total = (uint32_t)(h1 >> 32);
+    a.dout.blk_len[j] = total;
+    a.dout.blk_level[j] = (uint8_t)(h0 >> 32);
+    const uint64_t end = start + total;
+    uint64_t pos = start + kHdrBytes;
+    uint64_t nsum = 0;
+    bool ok = true;
+    for (uint64_t q = 0; q < npb; ++q) {
+        if (end - pos < kPlaneHdrBytes) {
+            ok = false;
+            break;
+        }
+        const uint64_t anc = *(const uint64_t *)(base + pos);
+        const uint64_t v = *(const uint64_t *)(base + pos + 8);
+        const uint32_t pw = (uint32_t)v, no = (uint32_t)(v >> 32);
+        if (pw > 64u * C || no > (1u << s)) {
+            ok = false;
+            break;
+        }
+        const uint64_t sz = kPlaneHdrBytes + (pw ? padC : 0u) + 8ull * pw +
+                            (uint64_t)kOutlierBytes * no;
+        if (end - pos < sz) {
+            ok = false;
+            break;
+        }
+        // an all-zero record (anchor 0, no payload, no outliers) decodes to
+        // all +0: point it at the shared zero record, as a pass does
+        a.dout.plane_off[j * npb + q] = (anc | v) == 0 ? 0 : pos;
+        nsum += no;
+        pos += sz;
+    }
+    if (!ok || pos != end || nsum != nout_hdr)
+        atomicOr(&a.dev->err, kErrImport);
+}
+
+// One thread per plane record: the chunk widths (at most 32 bits for a lossy
+// plane, 64 for a lossless one) sum to the payload words; the first residual
+// of the plane is 0 (c_0 = 0 by definition); a lossy anchor is a code within
+// +-(2^30 - 1); outlier indices lie in the plane and ascend strictly; a
+// lossless plane has no outliers.  Reads stay inside the record, whose
+// extent k_import_scan has checked.
+__global__ __launch_bounds__(kWG) void k_import_check(PassArgs a)
+{
+    if (a.dev->err)
+        return;
+    const int s = a.geo.s, bs = a.geo.b - s;
+    const uint32_t C = 1u << (s - 6);
+    const uint32_t padC = pad8(C);
+    const uint64_t nplanes = 2 * a.geo.nseg;
+    for (uint64_t q = (uint64_t)blockIdx.x * kWG + threadIdx.x; q < nplanes;
+         q += (uint64_t)gridDim.x * kWG) {
+        const uint64_t off = a.dout.plane_off[q];
+        if (off == 0)
+            continue;
+        const uint8_t *rec = a.arena_out + off;
+        const int64_t anc = *(const int64_t *)rec;
+        const uint32_t pw = *(const uint32_t *)(rec + 8);
+        const uint32_t no = *(const uint32_t *)(rec + 12);
+        const uint64_t j = (q >> 1) >> bs;
+        const double delta = *(const double *)(a.dout.hdr + 32 * j + 16);
+        const bool lossy = delta != 0.0;
+        const int64_t qlim = (int64_t)kQMax;
+        bool ok = lossy ? (anc >= -qlim && anc <= qlim) : no == 0;
+        if (pw) {
+            const uint32_t wmax = lossy ? 32u : 64u;
+            uint32_t sum = 0;
+            bool wok = true;
+            for (uint32_t c = 0; c < C; ++c) {
+                const uint32_t w = rec[kPlaneHdrBytes + c];
+                sum += w;
+                wok = wok && w <= wmax;
+            }
+            ok = ok && wok && sum == pw;
+            const uint32_t w0 = rec[kPlaneHdrBytes];
+            if (w0 && w0 <= 64u) {
+                const uint64_t word0 = *(const uint64_t *)(rec + kPlaneHdrBytes + padC);
+                const uint64_t m = w0 == 64u ? ~0ull : ((1ull << w0) - 1);
+                ok = ok && (word0 & m) == 0;
+            }
+        }
+        const uint8_t *ol = rec + kPlaneHdrBytes + (pw ? padC : 0u) + 8ull * pw;
+        uint32_t last = 0;
+        for (uint32_t k = 0; k < no; ++k) {
+            const uint32_t idx = *(const uint32_t *)(ol + (uint64_t)kOutlierBytes * k);
+            ok = ok && idx < (1u << s) && (k == 0 || idx > last);
+            last = idx;
+        }
+        if (!ok)
+            atomicOr(&a.dev->err, kErrImport);
+    }
+}
+
+// Segment normsq of every unit, from the decoded (unscaled) values with the
+// pass's own tree and leaf fl(fl(re^2) + fl(im^2)); all-zero units give +0
+// as in the pass.  a.din/a.arena_in are the imported set (the same as dout).
+__global__ __launch_bounds__(kWG) void k_import_norm(PassArgs a)
+{
+    if (a.dev->err)
+        return;
+    __shared__ __attribute__((aligned(16))) Planes X;
+    __shared__ double red[8];
+    const int s = a.geo.s;
+    for (uint64_t u = blockIdx.x; u < a.geo.nunits; u += gridDim.x) {
+        const Unit uc = unit_of(u, a.geo.nseg, 0);
+        const uint64_t g0 = uc.seg(0), g1 = uc.seg(1);
+        const uint64_t zero = a.din.plane_off[2 * g0] | a.din.plane_off[2 * g0 + 1] |
+                              (uc.nsu > 1 ? a.din.plane_off[2 * g1] | a.din.plane_off[2 * g1 + 1]
+                                          : 0ull);
+        if (zero == 0) {
+            if (threadIdx.x < (unsigned)uc.nsu)
+                a.din.segnorm[uc.seg((int)threadIdx.x)] = 0.0;
+            continue;
+        }
+        load_unit(a, uc, X, 1.0, false);
+        __syncthreads();
+        const double ns = s == kMaxS
+            ? segment_tree10(uc, X, red, [](double re, double im) {
+                  const double rr = re * re;
+                  const double ii = im * im;
+                  return rr + ii;
+              })
+            : segment_tree(uc, s, red, [&](int su, int o) {
+                  const double re = X[su][0][sw(o)], im = X[su][1][sw(o)];
+                  const double rr = re * re;
+                  const double ii = im * im;
+                  return rr + ii;
+              });
+        if (threadIdx.x < (unsigned)uc.nsu)
+            a.din.segnorm[uc.seg((int)threadIdx.x)] = ns;
+    }
+}
+
+// Block normsq (pairwise over the block's segment sums) for the reduction,
+// checked bit for bit against the header's normsq field.
+__global__ __launch_bounds__(kWG) void k_import_blocks(PassArgs a)
+{
+    if (a.dev->err)
+        return;
+    __shared__ double lds[kWG];
+    const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
+    for (uint64_t j = blockIdx.x; j < a.geo.nblocks; j += gridDim.x) {
+        const double *src = a.dout.segnorm + j * spb;
+        const double v = wg_tree([&](uint64_t i) { return src[i]; }, spb, lds);
+        if (threadIdx.x == 0) {
+            a.blknorm[j] = v;
+            const uint64_t want = *(const uint64_t *)(a.dout.hdr + 32 * j + 24);
+            if ((uint64_t)__double_as_longlong(v) != want)
+                atomicOr(&a.dev->err, kErrImportNorm);
+        }
     }
 }
 
@@ -2580,7 +2791,8 @@ __global__ __launch_bounds__(kWG) void k_bmeanfinal(const PassArgs *__restrict__
 const char *const kKernelNames[kNumKernelIds] = {
     "pass", "decide", "esc_size", "esc_decide", "fix", "block_norm", "reduce",
     "mean", "mean_tree", "mean_final", "init_state", "sv_pair", "sv_diag",
-    "sv_partial", "sv_final"};
+    "sv_partial", "sv_final", "export", "import_scan", "import_check", "import_norm",
+    "import_blocks"};
 
 static unsigned grid_for(uint64_t items)
 {
@@ -2750,6 +2962,40 @@ void launch_rsqrt(const double *in, double *out, uint64_t count, hipStream_t st)
 void launch_export(const PassArgs &a, uint64_t j, uint8_t *out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_export, dim3(1), dim3(kWG), 0, st, a, j, out);
+}
+
+void launch_export_range(const PassArgs &a, uint64_t first, uint64_t count,
+                         const uint64_t *offs, uint8_t *out, hipStream_t st, Prof *prof)
+{
+    TIMED(prof, kIdExport, st,
+          hipLaunchKernelGGL(k_export_range, dim3(grid_for(count < 4096 ? count : 4096)),
+                             dim3(kWG), 0, st, a, first, count, offs, out));
+}
+
+void launch_import(const PassArgs &a0, const uint64_t *boff, hipStream_t st, Prof *prof)
+{
+    // a: din = dout = the imported set, arena_in = arena_out = its arena; the
+    // reduction alone runs as a state encode (no pass counted)
+    PassArgs a = a0;
+    a.src_basis = 0;
+    PassArgs r = a0;
+    r.src_basis = 1;
+    TIMED(prof, kIdImportScan, st,
+          hipLaunchKernelGGL(k_import_scan, dim3(grid_for((a.geo.nblocks + kWG - 1) / kWG)),
+                             dim3(kWG), 0, st, a, boff));
+    const uint64_t np = 2 * a.geo.nseg;
+    const uint64_t gq = (np + kWG - 1) / kWG;
+    TIMED(prof, kIdImportCheck, st,
+          hipLaunchKernelGGL(k_import_check, dim3(grid_for(gq < 4096 ? gq : 4096)), dim3(kWG),
+                             0, st, a));
+    const uint64_t gu = a.geo.nunits < 3072 ? a.geo.nunits : 3072;
+    TIMED(prof, kIdImportNorm, st,
+          hipLaunchKernelGGL(k_import_norm, dim3(grid_for(gu)), dim3(kWG), 0, st, a));
+    TIMED(prof, kIdImportBlocks, st,
+          hipLaunchKernelGGL(k_import_blocks,
+                             dim3(grid_for(a.geo.nblocks < 4096 ? a.geo.nblocks : 4096)),
+                             dim3(kWG), 0, st, a));
+    TIMED(prof, kIdReduce, st, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, r));
 }
 
 void launch_export_headers(const PassArgs &a, uint64_t first, uint64_t count, uint8_t *out,

@@ -126,6 +126,8 @@ struct sim {
     DevState *dev = nullptr;
     int cur = 0;
     uint64_t passes = 0;
+    int par = 0;  // arena of the state at passes == 0 (cur == (passes + par) & 1)
+    uint64_t *xoff = nullptr;  // [nblocks] stream offsets for whole-state export/import
     bool valid = false;  // the current descriptor set holds a complete state
     unsigned grid_cap = 3072;  // workgroups of the per-gate unit kernels (three per
                                // resident slot of 256 CUs x 4)
@@ -358,6 +360,7 @@ int sync_check(sim *S)
             S->valid = false;
             S->passes = 0;
             S->cur = 0;
+            S->par = 0;
             d.err = 0;
             d.err_pass = 0;
             d.passes = 0;
@@ -370,7 +373,7 @@ int sync_check(sim *S)
                         (unsigned long long)S->arena_cap);
         }
         S->passes = pe;
-        S->cur = (int)(pe & 1);
+        S->cur = (int)((pe + (uint64_t)S->par) & 1);
         d.err = 0;
         d.err_pass = 0;
         d.passes = pe;
@@ -422,6 +425,7 @@ int run_basis(sim *S, uint64_t x)
     launch_encode_basis(a, S->grid_cap, S->stream, S->prof);
     HIPCHK(hipGetLastError());
     S->cur = 0;
+    S->par = 0;
     S->passes = 0;
     S->valid = true;  // until a synchronising call reports otherwise
     return SIM_OK;
@@ -801,6 +805,144 @@ int sim_export_headers(sim_t *S, uint64_t first, uint64_t count, void *buf, size
     if (e != hipSuccess)
         return fail(SIM_EDEVICE, "export headers: %s", hipGetErrorString(e));
     return rc;
+}
+
+int sim_export_state(sim_t *S, void *buf, size_t cap, size_t *len)
+{
+    if (!S || !len)
+        return fail(SIM_EINVAL, "NULL argument");
+    if (!S->compressed)
+        return fail(SIM_EUNSUPPORTED, "the uncompressed path has no block streams");
+    int rc = sync_state(S);
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    const uint64_t nb = S->geo.nblocks;
+    std::vector<uint32_t> bl(nb);
+    HIPCHK(hipMemcpy(bl.data(), S->desc[S->cur].blk_len, 4 * nb, hipMemcpyDeviceToHost));
+    // the idle arena stages the streams (above its reserved head, which
+    // holds the shared zero record of the next pass)
+    const uint64_t room = S->arena_cap - kArenaBase;
+    uint64_t total = 0;
+    for (uint64_t j = 0; j < nb; ++j) {
+        if (bl[j] < kHdrBytes || bl[j] > room)
+            return fail(SIM_EDEVICE, "block %llu has an implausible stream length %u",
+                        (unsigned long long)j, bl[j]);
+        total += bl[j];
+    }
+    *len = (size_t)total;
+    if (!buf || cap < total)
+        return fail(SIM_ENOMEM, "buffer of %zu bytes too small for %llu", cap,
+                    (unsigned long long)total);
+    if (!S->xoff) {
+        int r2 = dmalloc(S, (void **)&S->xoff, 8 * nb);
+        if (r2)
+            return r2;
+    }
+    uint8_t *stage = S->arena[1 - S->cur] + kArenaBase;
+    const PassArgs a = make_args(S, S->cur, 1 - S->cur, GateArg{});
+    std::vector<uint64_t> offs(nb);
+    uint64_t done = 0;
+    for (uint64_t j0 = 0; j0 < nb;) {
+        // the longest run of blocks whose streams fit the staging area
+        uint64_t j1 = j0, bytes = 0;
+        while (j1 < nb && bytes + bl[j1] <= room) {
+            offs[j1 - j0] = bytes;
+            bytes += bl[j1];
+            ++j1;
+        }
+        HIPCHK(hipMemcpyAsync(S->xoff, offs.data(), 8 * (j1 - j0), hipMemcpyHostToDevice,
+                              S->stream));
+        launch_export_range(a, j0, j1 - j0, S->xoff, stage, S->stream, S->prof);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync((uint8_t *)buf + done, stage, bytes, hipMemcpyDeviceToHost,
+                              S->stream));
+        HIPCHK(hipStreamSynchronize(S->stream));
+        done += bytes;
+        j0 = j1;
+    }
+    return rc;
+}
+
+int sim_import_state(sim_t *S, const void *buf, size_t len)
+{
+    if (!S || (!buf && len))
+        return fail(SIM_EINVAL, "NULL argument");
+    if (!S->compressed)
+        return fail(SIM_EUNSUPPORTED, "the uncompressed path has no block streams");
+    const uint64_t nb = S->geo.nblocks;
+    const uint8_t *p = (const uint8_t *)buf;
+    std::vector<uint64_t> boff(nb);
+    uint64_t pos = 0;
+    for (uint64_t j = 0; j < nb; ++j) {
+        if (len - pos < kHdrBytes)
+            return fail(SIM_EINVAL, "stream of block %llu truncated", (unsigned long long)j);
+        const uint8_t *h = p + pos;
+        uint32_t magic, total;
+        double delta;
+        memcpy(&magic, h, 4);
+        memcpy(&total, h + 12, 4);
+        memcpy(&delta, h + 16, 8);
+        const int level = h[4];
+        if (magic != kMagic || h[5] != 0 || h[6] != S->s || h[7] != S->b)
+            return fail(SIM_EINVAL, "block %llu: bad magic or geometry (s %d, b %d expected)",
+                        (unsigned long long)j, S->s, S->b);
+        if (level >= S->lad.L || memcmp(&delta, &S->lad.delta[level], 8) != 0)
+            return fail(SIM_EINVAL, "block %llu: level %d with bound %.17g is not a level of "
+                        "this sim's ladder", (unsigned long long)j, level, delta);
+        if (total < kHdrBytes || total % 8 != 0 || total > len - pos)
+            return fail(SIM_EINVAL, "block %llu: stream length %u invalid",
+                        (unsigned long long)j, total);
+        boff[j] = pos;
+        pos += total;
+    }
+    if (pos != len)
+        return fail(SIM_EINVAL, "%llu bytes after the last block stream",
+                    (unsigned long long)(len - pos));
+    if (len > S->arena_cap - kArenaBase)
+        return fail(SIM_ENOMEM, "%zu bytes of streams exceed the arena (%llu bytes)", len,
+                    (unsigned long long)S->arena_cap);
+    if (!S->xoff) {
+        int r2 = dmalloc(S, (void **)&S->xoff, 8 * nb);
+        if (r2)
+            return r2;
+    }
+    // the current state (if any) stays intact in the other arena and
+    // descriptor set until the import has passed every check
+    HIPCHK(hipStreamSynchronize(S->stream));
+    DevState keep;
+    HIPCHK(hipMemcpy(&keep, S->dev, sizeof keep, hipMemcpyDeviceToHost));
+    const int out = 1 - S->cur;
+    DevState d{};
+    d.scale = 1.0;
+    d.normalize = S->normalize;
+    d.arena_used[0] = d.arena_used[1] = kArenaBase;
+    d.arena_used[out] = kArenaBase + ((len + 255) & ~255ull);
+    HIPCHK(hipMemcpyAsync(S->dev, &d, sizeof d, hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipMemcpyAsync(S->arena[out] + kArenaBase, buf, len, hipMemcpyHostToDevice,
+                          S->stream));
+    HIPCHK(hipMemcpyAsync(S->xoff, boff.data(), 8 * nb, hipMemcpyHostToDevice, S->stream));
+    PassArgs a = make_args(S, out, out, GateArg{});
+    a.in_arena = 1 - out;  // the reduction frees the previous state's arena
+    a.pass = kBasisPass;
+    launch_import(a, S->xoff, S->stream, S->prof);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(S->stream));
+    HIPCHK(hipMemcpy(&d, S->dev, sizeof d, hipMemcpyDeviceToHost));
+    if (d.err & (kErrImport | kErrImportNorm)) {
+        HIPCHK(hipMemcpy(S->dev, &keep, sizeof keep, hipMemcpyHostToDevice));
+        return fail(SIM_EINVAL, (d.err & kErrImport)
+                                    ? "a plane record is malformed (sizes, widths, anchor "
+                                      "or outliers); state unchanged"
+                                    : "a block's normsq field differs from its decoded "
+                                      "values; state unchanged");
+    }
+    if (d.err)
+        return fail(SIM_EDEVICE, "device error %u during import", d.err);
+    S->cur = out;
+    S->par = out;
+    S->passes = 0;
+    S->valid = true;
+    return sync_check(S);
 }
 
 int sim_stats(sim_t *S, sim_stats_t *st)

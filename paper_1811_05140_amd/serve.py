@@ -21,7 +21,12 @@ The one-circuit-at-a-time baseline is the same loop with one slot and the
 whole circuit as one step, run through sim_apply_gate.
 
 A state whose arena overflows (the library reports SIM_ENOMEM and rolls the
-state back) is restarted with twice the arena once memory allows it.
+state back to the input of the gate that overflowed) is evicted: the
+executor copies its block streams to host memory (a checkpoint) and frees
+its device memory, and the request goes back to the head of the queue with
+twice the arena; when it is admitted again it resumes from that gate (the
+executor sets `resume`, the gate index the checkpoint holds), so no gate is
+computed twice.
 
 The executor is the only part that touches the GPU; the scheduler is plain
 Python and is tested on the CPU against a fake executor.
@@ -32,13 +37,13 @@ import time
 
 
 class Overflow(Exception):
-    """The state outgrew its arena (it is restarted with a larger one)."""
+    """The state outgrew its arena (it resumes later with a larger one)."""
 
 
 class Request:
     __slots__ = ("rid", "arrival", "kind", "n", "eb", "basis", "gates", "marked",
                  "iterations", "arena_factor", "restarts", "admitted", "ready", "done",
-                 "result", "reserved", "handle", "pos", "large")
+                 "result", "reserved", "handle", "pos", "large", "resume", "checkpoint")
 
     def __init__(self, spec, rate):
         self.rid = spec["id"]
@@ -58,6 +63,8 @@ class Request:
         self.handle = None
         self.pos = 0
         self.large = False
+        self.resume = 0          # gate index a re-admitted request starts at
+        self.checkpoint = None   # executor-owned host copy of an evicted state
 
 
 def percentile(values, q):
@@ -105,7 +112,7 @@ def serve(specs, executor, budget_bytes, max_slots, gates_per_step=1, rate=math.
             r.large = big
             large_active += int(big)
             r.handle = executor.open(r)
-            r.pos = 0
+            r.pos = r.resume
             if r.admitted is None:
                 r.admitted = now
             active.append(r)
@@ -193,8 +200,9 @@ class GpuExecutor:
     the GPU busy by itself)."""
 
     def __init__(self, A, max_slots, gates_per_step=1, sequential=False, tune=None,
-                 probs_qubits=4, large_units=8192):
+                 probs_qubits=4, large_units=8192, arena_scale=1.0):
         self.A = A
+        self.arena_scale = arena_scale  # first arena relative to the default
         self.sequential = sequential
         self.batch = None if sequential else A.Batch(max_slots, gates_per_step)
         self.tune = tune or {}
@@ -209,7 +217,7 @@ class GpuExecutor:
         return min(r.n, 14)
 
     def reservation(self, r):
-        return reservation_bytes(r.n, self.block_log2(r), r.arena_factor)
+        return reservation_bytes(r.n, self.block_log2(r), self.arena_scale * r.arena_factor)
 
     def is_large(self, r):
         s = min(self.block_log2(r), 10)
@@ -218,8 +226,12 @@ class GpuExecutor:
 
     def open(self, r):
         sim = self.A.Sim(r.n, self.block_log2(r), r.eb,
-                         arena_bytes=arena_bytes(r.n, r.arena_factor))
-        sim.set_basis(r.basis)
+                         arena_bytes=arena_bytes(r.n, self.arena_scale * r.arena_factor))
+        if r.checkpoint is not None:
+            sim.import_state(r.checkpoint)  # resume an evicted state at r.resume
+            r.checkpoint = None
+        else:
+            sim.set_basis(r.basis)
         return sim
 
     def step(self, items):
@@ -241,9 +253,16 @@ class GpuExecutor:
             nq = min(self.probs_qubits, r.n)
             probs = sim.probs(list(range(nq)))
         except A.SimError as e:
-            sim.close()
             if e.code == A.SIM_ENOMEM:
+                # rolled back to the input of the gate that overflowed (the
+                # passes counted since the state was set or imported): evict
+                # it to host memory and resume from that gate later
+                done = sim.stats()["passes"]
+                r.checkpoint = sim.export_state()
+                r.resume += done
+                sim.close()
                 raise Overflow(str(e))
+            sim.close()
             raise
         ready = time.perf_counter()
         st = sim.stats()

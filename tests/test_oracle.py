@@ -540,3 +540,32 @@ def test_splitmix64_published_vector():
     r = I.SplitMix64(0)
     assert [r.next() for _ in range(3)] == [
         0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_quantiser_code_range_edge():
+    """Codes stay within +-(2^30 - 1) (the quantiser accepts |y| < 2^30 - 1),
+    so a lossy residual always fits 32 signed bits.  delta = 0.25 (e = 0.5,
+    r = 2, y = 2x): x = +-(2^30 - 0.5)/2 gives |y| = 2^30 - 0.5, out of range:
+    outliers with code 0 (under a 2^30 bound they would take codes +-2^30 and
+    the residual +2^31 would need 33 bits).  x = +-(2^30 - 1.75)/2 gives
+    y = +-(2^30 - 1.75), code +-(2^30 - 2), xhat = +-(2^29 - 1) within 0.125.
+    Codes [0, 0, 2^30-2, -(2^30-2), 0, ...] give residuals c_2 = 2^30-2,
+    c_3 = -(2^31-4), c_4 = 2^30-2 and zigzags 2^31-4, 2^32-9, 2^31-4: one
+    32-bit chunk (fields 2, 3, 4 in words 1 and 2)."""
+    xa = (2.0 ** 30 - 0.5) / 2
+    xb = (2.0 ** 30 - 1.75) / 2
+    x = np.zeros(128)
+    x[0:8:2] = [-xa, xa, xb, -xb]
+    st = orc.encode_block(x, 6, 6, 0.25, 0)
+    anc, pw, no = struct.unpack_from("<qII", st, 32)
+    assert (anc, pw, no) == (0, 32, 2)
+    assert st[48] == 32
+    words = struct.unpack_from("<32Q", st, 56)
+    assert words[0] == 0
+    assert words[1] == (2 ** 31 - 4) | ((2 ** 32 - 9) << 32)
+    assert words[2] == 2 ** 31 - 4
+    assert all(w == 0 for w in words[3:])
+    o = 56 + 8 * 32
+    assert struct.unpack_from("<IIdIId", st, o) == (0, 0, -xa, 1, 0, xa)
+    xh = orc.decode_block(st)
+    assert list(xh.real[:4]) == [-xa, xa, 2.0 ** 29 - 1, -(2.0 ** 29 - 1)]
