@@ -17,6 +17,14 @@ circuits run one at a time and checks that both give the same states.
 three error bounds) with Poisson arrivals and a 200 GB compressed-memory
 budget, served with continuous batching and one circuit at a time.
 
+--workload qft24sweep: QFT-24 at error bounds 1e-3, 1e-4, 1e-5, each with
+the default ladder at ratio thresholds 4, 8, 16, 32 and with the fixed bound
+alone; throughput, ratios and fidelity per point.
+
+--workload checkpoint: export the whole compressed state to pinned host
+memory and import it into a second sim (QFT-24 final state, or --state
+grover36); GB/s of checkpoint bytes, the import kernels' roofline entry.
+
 --workload grover36: Grover search on 36 qubits (2^36 amplitudes, 1 TiB as
 complex128, more than the 288 GB of HBM), 65536 blocks of 2^20, eb = 1e-5:
 H on every qubit, then 8 x (phase flip of a seeded index, diffusion).  One
@@ -452,6 +460,222 @@ def bench_serve(args, A, inputs, stream):
     return out
 
 
+def bench_checkpoint(args, A, inputs, stream):
+    """Checkpoint and resume of a resident compressed state: the QFT-24 state
+    after all 312 gates (default) or the Grover-36 state after its 8
+    iterations (--state grover36).  One step = export the whole state
+    (kernels stage the block streams in the idle arena, one copy to pinned
+    host memory) + import it into a second sim (one copy to the device, the
+    record checks, the decode that re-forms the segment norms, N^2).  The
+    resumed state is checked to re-export the same bytes and, for QFT-24,
+    to finish its circuit identically to the uninterrupted run."""
+    import numpy as np
+    import torch
+    grover = args.state == "grover36"
+    w = inputs.grover36_workload() if grover else inputs.qft24_workload()
+    eb = 1e-5 if grover else 1e-4
+    n, b = w["n"], w["b"]
+    src = A.Sim(n, b, eb, stream=stream)
+    src.set_basis(w["basis"])
+    src.run(w["gates"])
+    src.sync()
+    nbytes = src.stats()["resident_bytes"]
+    host = torch.empty(nbytes + 4096, dtype=torch.uint8, pin_memory=True)
+    hv = host.numpy()
+    dst = A.Sim(n, b, eb, stream=stream)
+    print("checkpoint: %s state, %d bytes" % (args.state, nbytes), file=sys.stderr, flush=True)
+
+    def step(timed_kernels=False):
+        assert src.export_state(out=hv) == nbytes
+        dst.import_state(hv, nbytes)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    # separate legs and pageable host memory, for the record
+    te0 = time.perf_counter()
+    for _ in range(args.steps):
+        src.export_state(out=hv)
+    te1 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.import_state(hv, nbytes)
+    te2 = time.perf_counter()
+    pageable = src.export_state()
+    tp0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.import_state(pageable)
+    tp1 = time.perf_counter()
+    # device kernels, all timed with events on the sim streams
+    src.profile(True)
+    dst.profile(True)
+    src.profile_read()
+    dst.profile_read()
+    for _ in range(args.steps):
+        step()
+    prof = dict(src.profile_read())
+    prof.update(dst.profile_read())
+    src.profile(False)
+    dst.profile(False)
+    same = dst.export_state() == bytes(hv[:nbytes])
+    st = dst.stats()
+    ss = src.stats()
+    same = same and st["normsq"] == ss["normsq"] and st["scale"] == ss["scale"]
+    if not grover:
+        # resume: finish a second copy of the circuit's last 60 gates from a
+        # checkpoint taken before them, compare with the uninterrupted run
+        cut = len(w["gates"]) - 60
+        a = A.Sim(n, b, eb, stream=stream)
+        a.set_basis(w["basis"])
+        a.run(w["gates"][:cut])
+        r = A.Sim(n, b, eb, stream=stream)
+        r.import_state(a.export_state())
+        a.run(w["gates"][cut:])
+        r.run(w["gates"][cut:])
+        same = same and a.export_state() == r.export_state()
+        a.close()
+        r.close()
+    spb = 1 << (b - min(b, 10))
+    nblocks = 1 << (n - b)
+    nseg = nblocks * spb
+    planes = 2 * nseg
+    # algorithmic bytes per launch of each kernel
+    alg = {
+        "export": 2 * nbytes,                       # read the records, write the streams
+        "import_scan": 24 * planes + 64 * nblocks,  # plane headers in, offsets + headers out
+        "import_check": 32 * planes,                # headers, widths, first word, offsets
+        "import_norm": nbytes + 8 * planes + 8 * nseg,  # every record decoded, norms out
+        "import_blocks": 8 * nseg + 8 * nblocks,
+    }
+    kern = {}
+    for name, (cnt, tot, mn, mx) in prof.items():
+        kern[name] = {"launches": cnt, "avg_ms": round(tot / cnt, 4)}
+        if name in alg:
+            kern[name]["gbs"] = round(alg[name] / (tot / cnt / 1000.0) / 1e9, 1)
+    name = max((k for k in prof if k in alg), key=lambda k: prof[k][1])
+    cnt, tot = prof[name][0], prof[name][1]
+    achieved = alg[name] / (tot / cnt / 1000.0) / 1e9
+    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_launch_ms": round(tot / cnt, 4), "launches": cnt,
+                "algorithmic_bytes_per_launch": alg[name], "kernels": kern}
+    cpu = None
+    if args.cpu_budget > 0:
+        # the oracle's import is, per block, or_decode_block (records checked
+        # as they are read) plus the block normsq: timed on random blocks of
+        # this checkpoint until the budget is spent, scaled by bytes
+        from oracle import oracle as orc
+        starts = [0]
+        for _ in range(nblocks):
+            starts.append(starts[-1] + int.from_bytes(pageable[starts[-1] + 12:starts[-1] + 16],
+                                                      "little"))
+        rng = np.random.default_rng(11)
+        done_bytes, tcpu, k = 0, 0.0, 0
+        budget = min(args.cpu_budget, 20.0)
+        while tcpu < budget and k < 4 * nblocks:
+            j = int(rng.integers(0, nblocks))
+            blk = pageable[starts[j]:starts[j + 1]]
+            c0 = time.perf_counter()
+            xh = orc.decode_block(blk)
+            v = np.ascontiguousarray(xh).view(np.float64)
+            orc.pairwise((v[0::2] * v[0::2]) + (v[1::2] * v[1::2]))
+            tcpu += time.perf_counter() - c0
+            done_bytes += len(blk)
+            k += 1
+        t_full = tcpu * nbytes / done_bytes
+        cpu = {"value": round(nbytes / t_full / 1e9, 4), "unit": "GB/s of checkpoint imported",
+               "cores": 1, "kind": "oracle",
+               "sample": "%d random blocks of the checkpoint decoded by the oracle's block "
+                         "decoder with the block normsq (%.1f s), scaled by bytes to all %d "
+                         "blocks" % (k, tcpu, nblocks)}
+    gbs = 2 * nbytes * args.steps / elapsed / 1e9
+    return {
+        "metric": "checkpoint export + import of the compressed state (GB/s of streams, "
+                  "both directions, pinned host memory)",
+        "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1000.0 * elapsed / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded basis state, generated circuit)",
+        "config": {"workload": "checkpoint", "state": args.state, "n_qubits": n,
+                   "block_log2": b, "error_bound": eb, "checkpoint_bytes": nbytes,
+                   "logical_state_bytes": 16 << n},
+        "export_ms": round(1000.0 * (te1 - te0) / args.steps, 3),
+        "import_ms": round(1000.0 * (te2 - te1) / args.steps, 3),
+        "import_pageable_ms": round(1000.0 * (tp1 - tp0) / args.steps, 3),
+        "resume_identical": bool(same),
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+
+
+def bench_qft24_sweep(args, A, inputs, stream):
+    """QFT-24 over the error bounds {1e-3, 1e-4, 1e-5}: the default ladder at
+    ratio thresholds 4, 8, 16 and 32 (the paper's AALC runs vary the
+    threshold), and the fixed bound alone (one lossy level, the paper's
+    fixed-bound SZ runs).  Per point: gates/s, amplitude-GB/s and its HBM
+    fraction, minimum / last compression ratio, peak resident bytes, level
+    histogram, replays, and the fidelity against one uncompressed FP64 run."""
+    import torch
+    w = inputs.qft24_workload()
+    n, b, x, gates = w["n"], w["b"], w["basis"], w["gates"]
+    ref = A.Sim(n, b, -1.0, stream=stream)
+    ref.set_basis(x)
+    ref.run(gates)
+    points = []
+    for eb in (1e-3, 1e-4, 1e-5):
+        confs = [("aalc", inputs.default_ladder(eb), th) for th in (4.0, 8.0, 16.0, 32.0)]
+        confs.append(("fixed", [eb], 4.0))
+        for mode, lad, th in confs:
+            sim = A.Sim(n, b, eb, stream=stream, ladder=lad, theta=th)
+
+            def step():
+                sim.set_basis(x)
+                sim.run(gates)
+            for _ in range(args.warmup):
+                step()
+            sim.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                step()
+            sim.sync()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            gps = len(gates) * args.steps / el
+            gbs = gps * LOGICAL_BYTES_PER_AMP * (1 << n) / 1e9
+            st = sim.stats()
+            F = sim.fidelity(ref)
+            pt = {"error_bound": eb, "mode": mode, "theta": th if mode == "aalc" else None,
+                  "gates_per_s": round(gps, 1), "amplitude_gbs": round(gbs, 1),
+                  "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                  "min_ratio": round(st["min_ratio"], 3), "last_ratio": round(st["last_ratio"], 3),
+                  "peak_resident_bytes": st["peak_resident"], "fidelity": F,
+                  "fidelity_ok": bool(F >= 0.999), "collapsed": st["collapsed"],
+                  "level_hist_per_step": [v // (args.warmup + args.steps) for v in st["level_hist"]],
+                  "replays_per_step": st["replays"] // (args.warmup + args.steps)}
+            print("sweep: %s" % json.dumps(pt), file=sys.stderr, flush=True)
+            points.append(pt)
+            sim.close()
+    ref.close()
+    head = [p for p in points if p["error_bound"] == 1e-4 and p["theta"] == 4.0][0]
+    return {
+        "metric": METRIC, "value": head["gates_per_s"], "unit": "gates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * len(gates) / head["gates_per_s"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded basis state, generated circuit)",
+        "config": {"workload": "qft24sweep", "n_qubits": n, "block_log2": b, "basis": x,
+                   "gates_per_step": len(gates), "error_bounds": [1e-3, 1e-4, 1e-5],
+                   "thetas": [4, 8, 16, 32], "value_point": "eb 1e-4, theta 4"},
+        "fidelity_reference": "uncompressed FP64 GPU run",
+        "points": points, "roofline": None, "cpu_baseline": None,
+    }
+
+
 def grover_fidelity(sim, n, m, k):
     """P(m) and F against the closed-form Grover state after k iterations:
     sin((2k+1)t) on m and cos((2k+1)t)/sqrt(2^n - 1) elsewhere, sin t =
@@ -469,8 +693,11 @@ def grover_fidelity(sim, n, m, k):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("qft24", "grover36", "batch64", "serve512"),
+    ap.add_argument("--workload", choices=("qft24", "grover36", "batch64", "serve512",
+                                           "checkpoint", "qft24sweep"),
                     default="qft24")
+    ap.add_argument("--state", choices=("qft24", "grover36"), default="qft24",
+                    help="checkpoint workload: the state exported and imported")
     ap.add_argument("--rate", type=float, default=SERVE_RATE,
                     help="serve512 arrival rate (requests/s); default: 0.7 x the "
                          "saturated batched throughput, measured first")
@@ -490,7 +717,7 @@ def main():
     args = ap.parse_args()
     grover = args.workload == "grover36"
     if args.steps is None:
-        args.steps = 5 if args.workload == "qft24" else 1
+        args.steps = 5 if args.workload == "qft24" else (3 if args.workload == "qft24sweep" else 1)
     if args.warmup is None:
         args.warmup = 1 if args.workload != "grover36" else 0
     eb = args.error_bound if args.error_bound is not None else (1e-5 if grover else 1e-4)
@@ -516,6 +743,12 @@ def main():
         return
     if args.workload == "serve512":
         print(json.dumps(bench_serve(args, A, inputs, stream)), flush=True)
+        return
+    if args.workload == "qft24sweep":
+        print(json.dumps(bench_qft24_sweep(args, A, inputs, stream)), flush=True)
+        return
+    if args.workload == "checkpoint":
+        print(json.dumps(bench_checkpoint(args, A, inputs, stream)), flush=True)
         return
     w = inputs.grover36_workload() if grover else inputs.qft24_workload()
     n, b, x, gates = w["n"], w["b"], w["basis"], w["gates"]

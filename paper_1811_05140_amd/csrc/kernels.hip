@@ -2329,7 +2329,7 @@ __global__ void k_rsqrt(const double *in, double *out, uint64_t count)
 // formed from the block's segment sums, then its plane records in plane
 // order).  One workgroup; offs and red are workgroup scratch.
 __device__ void export_body(const PassArgs &a, uint64_t j, uint8_t *out, uint64_t *offs,
-                            uint64_t *red, double *lds)
+                            uint64_t *poff, uint64_t *red, double *lds)
 {
     const int t = threadIdx.x;
     const int s = a.geo.s;
@@ -2340,12 +2340,14 @@ __device__ void export_body(const PassArgs &a, uint64_t j, uint8_t *out, uint64_
     // sizes of this thread's planes, from their record headers
     uint64_t local = 0;
     for (uint64_t q = t * per; q < (t + 1) * per && q < npb; ++q) {
-        const uint8_t *rec = a.arena_in + a.din.plane_off[base + q];
+        const uint64_t po = a.din.plane_off[base + q];
+        const uint8_t *rec = a.arena_in + po;
         const uint32_t pw = *(const uint32_t *)(rec + 8);
         const uint32_t no = *(const uint32_t *)(rec + 12);
         const uint64_t sz = kPlaneHdrBytes + (pw ? padC : 0u) + 8ull * pw +
                             (uint64_t)kOutlierBytes * no;
         offs[q] = sz;
+        poff[q] = po;
         local += sz;
     }
     red[t] = local;
@@ -2373,15 +2375,37 @@ __device__ void export_body(const PassArgs &a, uint64_t j, uint8_t *out, uint64_
             *(double *)(out + 24) = ns;
     }
     __syncthreads();
-    // copy records: wave w takes planes w, w+4, ...
-    const int wave = t >> 6, lane = lane_id();
-    for (uint64_t q = wave; q < npb; q += 4) {
-        const uint64_t *src = (const uint64_t *)(a.arena_in + a.din.plane_off[base + q]);
-        const uint64_t end = (q + 1 < npb) ? offs[q + 1] : (uint64_t)a.din.blk_len[j];
-        const uint64_t nw = (end - offs[q]) / 8;
-        uint64_t *dst = (uint64_t *)(out + offs[q]);
-        for (uint64_t k = lane; k < nw; k += 64)
-            dst[k] = src[k];
+    const uint64_t nwords = ((uint64_t)a.din.blk_len[j] - kHdrBytes) / 8;
+    if (nwords >= 32 * npb) {
+        // records of 32 words or more on average: wave w copies records w,
+        // w+4, ... with its 64 lanes
+        const int wave = t >> 6, lane = lane_id();
+        for (uint64_t q = wave; q < npb; q += 4) {
+            const uint64_t *src = (const uint64_t *)(a.arena_in + poff[q]);
+            const uint64_t end = (q + 1 < npb) ? offs[q + 1] : (uint64_t)a.din.blk_len[j];
+            const uint64_t nw = (end - offs[q]) / 8;
+            uint64_t *dst = (uint64_t *)(out + offs[q]);
+            for (uint64_t k = lane; k < nw; k += 64)
+                dst[k] = src[k];
+        }
+        __syncthreads();
+        return;
+    }
+    // small records: the records as one run of words, thread t writing words
+    // t, t+256, ... of the stream after the header (coalesced), each read
+    // from the record holding it (binary search over the record starts)
+    uint64_t *dst = (uint64_t *)(out + kHdrBytes);
+    for (uint64_t k = t; k < nwords; k += kWG) {
+        const uint64_t pos = kHdrBytes + 8 * k;
+        uint64_t lo = 0, hi = npb;  // offs[lo] <= pos < offs[hi] (offs[npb]: the end)
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (offs[mid] <= pos)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        dst[k] = *(const uint64_t *)(a.arena_in + poff[lo] + (pos - offs[lo]));
     }
     __syncthreads();
 }
@@ -2389,9 +2413,10 @@ __device__ void export_body(const PassArgs &a, uint64_t j, uint8_t *out, uint64_
 __global__ __launch_bounds__(kWG) void k_export(PassArgs a, uint64_t j, uint8_t *out)
 {
     __shared__ uint64_t offs[2 << 10];  // planes per block: at most 2^(1 + 20 - 10)
+    __shared__ uint64_t poff[2 << 10];
     __shared__ uint64_t red[kWG];
     __shared__ double lds[kWG];
-    export_body(a, j, out, offs, red, lds);
+    export_body(a, j, out, offs, poff, red, lds);
 }
 
 // Streams of blocks [first, first + count), block first + k at out + offs[k]
@@ -2402,10 +2427,11 @@ __global__ __launch_bounds__(kWG) void k_export_range(PassArgs a, uint64_t first
                                                       uint8_t *out)
 {
     __shared__ uint64_t offs[2 << 10];
+    __shared__ uint64_t poff[2 << 10];
     __shared__ uint64_t red[kWG];
     __shared__ double lds[kWG];
     for (uint64_t k = blockIdx.x; k < count; k += gridDim.x)
-        export_body(a, first + k, out + offs_out[k], offs, red, lds);
+        export_body(a, first + k, out + offs_out[k], offs, poff, red, lds);
 }
 
 // ------------------------------------------------------ import ------------
@@ -2536,42 +2562,80 @@ __global__ __launch_bounds__(kWG) void k_import_check(PassArgs a)
 }
 
 // Segment normsq of every unit, from the decoded (unscaled) values with the
-// pass's own tree and leaf fl(fl(re^2) + fl(im^2)); all-zero units give +0
-// as in the pass.  a.din/a.arena_in are the imported set (the same as dout).
-__global__ __launch_bounds__(kWG) void k_import_norm(PassArgs a)
+// pass's own tree and leaf fl(fl(re^2) + fl(im^2)).  A unit whose records
+// carry neither payload nor outliers holds one value per plane (the anchor's:
+// its bit pattern, or code times 2 delta; +0 for the shared zero record), and
+// the pairwise tree of 2^s equal leaves is 2^s times the leaf (each addition
+// doubles): those units need no decode, as in the pass.  a.din/a.arena_in
+// are the imported set (the same as dout).
+__global__ __launch_bounds__(kWG) void k_import_norm(PassArgs a, uint32_t batch)
 {
     if (a.dev->err)
         return;
     __shared__ __attribute__((aligned(16))) Planes X;
     __shared__ double red[8];
-    const int s = a.geo.s;
-    for (uint64_t u = blockIdx.x; u < a.geo.nunits; u += gridDim.x) {
-        const Unit uc = unit_of(u, a.geo.nseg, 0);
-        const uint64_t g0 = uc.seg(0), g1 = uc.seg(1);
-        const uint64_t zero = a.din.plane_off[2 * g0] | a.din.plane_off[2 * g0 + 1] |
-                              (uc.nsu > 1 ? a.din.plane_off[2 * g1] | a.din.plane_off[2 * g1 + 1]
-                                          : 0ull);
-        if (zero == 0) {
-            if (threadIdx.x < (unsigned)uc.nsu)
-                a.din.segnorm[uc.seg((int)threadIdx.x)] = 0.0;
-            continue;
-        }
-        load_unit(a, uc, X, 1.0, false);
+    __shared__ uint32_t list[kWG];
+    __shared__ uint32_t nlist;
+    const int s = a.geo.s, bs = a.geo.b - s;
+    const uint64_t nu = a.geo.nunits;
+    // `batch` units per round: one thread each settles a one-value unit on
+    // its own; the others are queued and decoded by the whole workgroup
+    for (uint64_t base = (uint64_t)blockIdx.x * batch; base < nu;
+         base += (uint64_t)gridDim.x * batch) {
+        if (threadIdx.x == 0)
+            nlist = 0;
         __syncthreads();
-        const double ns = s == kMaxS
-            ? segment_tree10(uc, X, red, [](double re, double im) {
-                  const double rr = re * re;
-                  const double ii = im * im;
-                  return rr + ii;
-              })
-            : segment_tree(uc, s, red, [&](int su, int o) {
-                  const double re = X[su][0][sw(o)], im = X[su][1][sw(o)];
-                  const double rr = re * re;
-                  const double ii = im * im;
-                  return rr + ii;
-              });
-        if (threadIdx.x < (unsigned)uc.nsu)
-            a.din.segnorm[uc.seg((int)threadIdx.x)] = ns;
+        const uint64_t u = base + threadIdx.x;
+        if (threadIdx.x < batch && u < nu) {
+            const Unit uc = unit_of(u, a.geo.nseg, 0);
+            uint64_t hv = 0;
+            for (int i = 0; i < 2 * uc.nsu; ++i) {
+                const uint64_t off = a.din.plane_off[2 * uc.seg(i >> 1) + (i & 1)];
+                hv |= *(const uint64_t *)(a.arena_in + off + 8);  // payload words | outliers
+            }
+            if (hv == 0) {
+                for (int k = 0; k < uc.nsu; ++k) {
+                    const uint64_t g = uc.seg(k);
+                    const double delta = *(const double *)(a.din.hdr + 32 * (g >> bs) + 16);
+                    const double e = 2.0 * delta;
+                    double v[2];
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const uint64_t off = a.din.plane_off[2 * g + p];
+                        const uint64_t anc = *(const uint64_t *)(a.arena_in + off);
+                        v[p] = delta == 0.0 ? __longlong_as_double((long long)anc)
+                                            : (double)(int32_t)(uint32_t)anc * e;
+                    }
+                    const double rr = v[0] * v[0];
+                    const double ii = v[1] * v[1];
+                    a.din.segnorm[g] = (rr + ii) * (double)(1u << s);
+                }
+            } else {
+                list[atomicAdd(&nlist, 1u)] = threadIdx.x;
+            }
+        }
+        __syncthreads();
+        const uint32_t cnt = nlist;
+        for (uint32_t i = 0; i < cnt; ++i) {
+            const Unit uc = unit_of(base + list[i], a.geo.nseg, 0);
+            load_unit(a, uc, X, 1.0, false);
+            __syncthreads();
+            const double ns = s == kMaxS
+                ? segment_tree10(uc, X, red, [](double re, double im) {
+                      const double rr = re * re;
+                      const double ii = im * im;
+                      return rr + ii;
+                  })
+                : segment_tree(uc, s, red, [&](int su, int o) {
+                      const double re = X[su][0][sw(o)], im = X[su][1][sw(o)];
+                      const double rr = re * re;
+                      const double ii = im * im;
+                      return rr + ii;
+                  });
+            if (threadIdx.x < (unsigned)uc.nsu)
+                a.din.segnorm[uc.seg((int)threadIdx.x)] = ns;
+        }
+        __syncthreads();
     }
 }
 
@@ -2988,9 +3052,15 @@ void launch_import(const PassArgs &a0, const uint64_t *boff, hipStream_t st, Pro
     TIMED(prof, kIdImportCheck, st,
           hipLaunchKernelGGL(k_import_check, dim3(grid_for(gq < 4096 ? gq : 4096)), dim3(kWG),
                              0, st, a));
-    const uint64_t gu = a.geo.nunits < 3072 ? a.geo.nunits : 3072;
+    // units per workgroup round: enough that a grid of about 3072
+    // workgroups covers the state, at most one per thread
+    uint32_t batch = 1;
+    while (batch < (uint32_t)kWG && (uint64_t)batch * 2 * 3072 <= a.geo.nunits)
+        batch *= 2;
+    const uint64_t rounds = (a.geo.nunits + batch - 1) / batch;
+    const uint64_t gu = rounds < 12288 ? rounds : 12288;
     TIMED(prof, kIdImportNorm, st,
-          hipLaunchKernelGGL(k_import_norm, dim3(grid_for(gu)), dim3(kWG), 0, st, a));
+          hipLaunchKernelGGL(k_import_norm, dim3(grid_for(gu)), dim3(kWG), 0, st, a, batch));
     TIMED(prof, kIdImportBlocks, st,
           hipLaunchKernelGGL(k_import_blocks,
                              dim3(grid_for(a.geo.nblocks < 4096 ? a.geo.nblocks : 4096)),

@@ -140,6 +140,32 @@ def test_qft12_fixed_bound(A):
     assert_streams_equal(g, o, 1 << (n - b), "end")
 
 
+@pytest.mark.parametrize("eb,theta,fixed", [(1e-3, 4.0, False), (1e-3, 32.0, False),
+                                             (1e-4, 8.0, False), (1e-4, 16.0, False),
+                                             (1e-5, 32.0, False), (1e-3, 4.0, True),
+                                             (1e-5, 4.0, True)])
+def test_qft12_error_bounds_and_thresholds(A, eb, theta, fixed):
+    """The error-bound / threshold grid of the QFT runs at 12 qubits: streams
+    after every gate, the level histogram and the ratios equal the oracle's
+    (the grid reaches every ladder level: thresholds of 32 push most blocks
+    to the last one)."""
+    w = I.qft12_workload()
+    n, b = w["n"], w["b"]
+    lad = [eb] if fixed else I.default_ladder(eb)
+    say("qft12", "fixed" if fixed else "aalc", eb, theta)
+    g = A.Sim(n, b, eb, ladder=lad, theta=theta)
+    g.set_basis(w["basis"])
+    o = orc.OracleSim(n, b, lad, theta)
+    o.set_basis(w["basis"])
+    for k, gate in enumerate(w["gates"]):
+        g.apply(gate)
+        o.apply(gate)
+        assert_streams_equal(g, o, 1 << (n - b), "gate %d" % k)
+    sg, so = g.stats(), o.stats()
+    assert sg["level_hist"] == so["level_hist"] and sg["min_ratio"] == so["min_ratio"]
+    assert sg["collapsed"] == so["collapsed"] and sg["normsq"] == so["normsq"]
+
+
 CASES = [
     # n, b, ladder, theta, ngates, seed
     (9, 7, [0.0], 4.0, 60, 1),
