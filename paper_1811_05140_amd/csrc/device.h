@@ -129,7 +129,7 @@ struct PassArgs {
     uint64_t chunk_bytes;  // arena space a workgroup takes per bump-pointer update
     uint64_t basis;      // source state |basis> when src_basis != 0
     int32_t src_basis;
-    int32_t pad;
+    int32_t unit_batch;  // units per workgroup round of the bulk phase (<= 1: none)
     uint32_t *psz;       // [L][2*nseg]: payload words | n_outliers << 16
     uint8_t *scratch;    // [scratch_wgs * 4][kScratchWave] staging, by workgroup and wave
     uint64_t scratch_wgs;  // workgroups the staging covers (grids must not exceed it)

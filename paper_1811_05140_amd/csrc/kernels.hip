@@ -1160,6 +1160,28 @@ __device__ __forceinline__ bool zero_preserving(const GateArg &G)
 //   kReplay: encode the planes of block jsel at its chosen level;
 // records are bump-allocated per unit; per-segment normsq of what was
 // encoded.
+// `tot` bytes from the workgroup's arena chunk, taking a new chunk from the
+// arena's bump pointer when the current one is too small (one thread);
+// ~0 when the arena is full (the error is recorded).
+__device__ __forceinline__ uint64_t take_arena(const PassArgs &a, PassLds &S, uint64_t tot)
+{
+    if (S.chunk[0] + tot > S.chunk[1]) {
+        const uint64_t want = tot > a.chunk_bytes ? tot : a.chunk_bytes;
+        const uint64_t b0 = atomicAdd((unsigned long long *)&a.dev->arena_used[a.out_arena],
+                                      (unsigned long long)want);
+        S.chunk[0] = b0;
+        S.chunk[1] = b0 + want;
+    }
+    const uint64_t base = S.chunk[0];
+    S.chunk[0] += tot;
+    if (base + tot > a.arena_cap) {
+        if (atomicOr(&a.dev->err, kErrArena) == 0)
+            a.dev->err_pass = (uint32_t)a.pass;
+        return ~0ull;
+    }
+    return base;
+}
+
 // Bump-allocate `mine ? bytes : 0` per wave for this unit's records (all
 // threads); returns this wave's offset, or ~0 when the arena is full (the
 // error is recorded).
@@ -1173,25 +1195,7 @@ __device__ uint64_t alloc_records(const PassArgs &a, PassLds &S, bool mine, uint
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint64_t tot = rbytes[0] + rbytes[1] + rbytes[2] + rbytes[3];
-        uint64_t base = 0;
-        if (tot) {
-            if (S.chunk[0] + tot > S.chunk[1]) {
-                const uint64_t want = tot > a.chunk_bytes ? tot : a.chunk_bytes;
-                const uint64_t b0 = atomicAdd(
-                    (unsigned long long *)&a.dev->arena_used[a.out_arena],
-                    (unsigned long long)want);
-                S.chunk[0] = b0;
-                S.chunk[1] = b0 + want;
-            }
-            base = S.chunk[0];
-            S.chunk[0] += tot;
-            if (base + tot > a.arena_cap) {
-                if (atomicOr(&a.dev->err, kErrArena) == 0)
-                    a.dev->err_pass = (uint32_t)a.pass;
-                base = ~0ull;
-            }
-        }
-        rbase = base;
+        rbase = tot ? take_arena(a, S, tot) : 0;
     }
     __syncthreads();
     if (rbase == ~0ull)
@@ -1381,8 +1385,143 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
 
 __device__ void decide_escalated(const PassArgs &a, uint64_t j, PassLds &S);
 
+// ------------------------------------------------------- bulk rounds ----
+//
+// With many more units than workgroups (a.unit_batch > 1), a workgroup takes
+// its units in rounds of unit_batch.  First each thread settles one unit on
+// its own where it can, writing exactly what the unit body writes for it:
+// an all-zero unit under a zero-preserving gate (in a basis encode, every
+// unit without the basis index), or, in a DIFFUSE or PHASE_FLIP pass, a unit
+// of one-value planes.  The units left are marked in per-wave masks and run
+// through the unit body by the whole workgroup.  States of a few thousand
+// units keep unit_batch 1: one unit per round, no first phase.
+
+// Units per round for a state of nunits units on a grid of at most grid
+// workgroups: the largest power of two up to one per thread that leaves
+// every workgroup at least two rounds.
+__host__ __device__ inline uint32_t unit_batch_for(uint64_t nunits, uint64_t grid)
+{
+    uint32_t b = 1;
+    while (b < (uint32_t)kWG && (uint64_t)b * 4 * grid <= nunits)
+        b *= 2;
+    return b;
+}
+
+// One thread's all-zero unit (see zero_unit).  Returns whether it was one.
+__device__ bool bulk_zero_unit(const PassArgs &a, const Unit &uc)
+{
+    const int s = a.geo.s, bs = a.geo.b - s;
+    const uint64_t nplanes = 2 * a.geo.nseg;
+    if (a.src_basis) {
+        const uint64_t gb = a.basis >> s;
+        for (int k = 0; k < uc.nsu; ++k)
+            if (uc.seg(k) == gb)
+                return false;
+    } else {
+        uint64_t o = 0;
+        for (int i = 0; i < 2 * uc.nsu; ++i)
+            o |= a.din.plane_off[2 * uc.seg(i >> 1) + (i & 1)];
+        if (o != 0)
+            return false;
+    }
+    for (int k = 0; k < uc.nsu; ++k) {
+        const uint64_t g = uc.seg(k);
+        const int lvl = hint_level(a, g >> bs);
+        for (int p = 0; p < 2; ++p) {
+            const uint64_t plane = 2 * g + p;
+            for (int l = 0; l <= lvl; ++l)
+                a.psz[(uint64_t)l * nplanes + plane] = 0u;
+            a.dout.plane_off[plane] = 0;  // the shared all-zero record
+        }
+        a.dout.segnorm[g] = 0.0;
+    }
+    return true;
+}
+
+// Arena space for one bulk round: `bytes` from this thread, one allocation
+// for the workgroup (all threads).  Returns this thread's offset, ~0 after an
+// overflow (recorded).
+__device__ uint64_t bulk_alloc(const PassArgs &a, PassLds &S, uint32_t bytes)
+{
+    uint32_t *cnt = (uint32_t *)&S.misc[0];
+    if (threadIdx.x == 0)
+        *cnt = 0u;
+    __syncthreads();
+    const uint32_t mine = bytes ? atomicAdd(cnt, bytes) : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint64_t tot = *cnt;
+        S.misc[8] = tot ? take_arena(a, S, tot) : 0;
+    }
+    __syncthreads();
+    const uint64_t base = S.misc[8];
+    return base == ~0ull ? ~0ull : base + mine;
+}
+
+// One thread's one-value unit (see const_unit), from const_eval's results:
+// sizes of levels 0..h, the records (the k-th nonzero anchor at rec + 16 k;
+// rec is ~0 after an overflow), segment norms.
+__device__ void bulk_const_write(const PassArgs &a, const Unit &uc, const double *y,
+                                 const double *xh, const uint64_t *anc, const int *lev,
+                                 uint64_t rec)
+{
+    const int s = a.geo.s;
+    const uint64_t nplanes = 2 * a.geo.nseg;
+    uint64_t at = rec;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t plane = 2 * uc.seg(i >> 1) + (i & 1);
+        const int h = lev[i >> 1];
+        for (int k = 0; k <= h; ++k) {
+            uint32_t v = 0;
+            if (a.lad.delta[k] != 0.0) {
+                int32_t q;
+                bool out;
+                double xq;
+                lossy_code(y[i], a.lad.delta[k], a.lad.e[k], a.lad.r[k], q, out, xq);
+                v = out ? (1u << s) << 16 : 0u;
+            }
+            a.psz[(uint64_t)k * nplanes + plane] = v;
+        }
+        if (anc[i] == 0ull) {
+            a.dout.plane_off[plane] = 0;
+        } else {
+            if (rec != ~0ull) {
+                a.dout.plane_off[plane] = at;
+                uint4 r;
+                r.x = (uint32_t)anc[i];
+                r.y = (uint32_t)(anc[i] >> 32);
+                r.z = 0u;
+                r.w = 0u;
+                *(uint4 *)(a.arena_out + at) = r;
+            }
+            at += kPlaneHdrBytes;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double rr = xh[2 * k] * xh[2 * k];
+        const double ii = xh[2 * k + 1] * xh[2 * k + 1];
+        a.dout.segnorm[uc.seg(k)] = (rr + ii) * (double)(1u << s);
+    }
+}
+
+// The workgroup-uniform 64-bit mask of wave w's threads that left their unit
+// to the unit body (published in S.misc[4 + w]).
+__device__ __forceinline__ uint64_t left_mask(const PassLds &S, int w)
+{
+    const uint64_t m = S.misc[4 + w];
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)m);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(m >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // The fused pass over all units.
 // Four workgroups per CU (the LDS budget) need at most 128 VGPRs per lane.
+// BULK: rounds of a.unit_batch units with the per-thread first phase (a
+// kernel of its own, so that the one-unit-per-round form that smaller states
+// run keeps exactly its earlier code).
+template <bool BULK>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pass(
     PassArgs a)
 {
@@ -1401,10 +1540,45 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     const uint64_t Ms = a.gate.mask >> a.geo.s;
     // s and 2*mean are read by each unit together with its own reads
     const bool zp = zero_preserving(a.gate);
-    for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
-        const Unit uc = unit_of(it, a.geo.nseg, Ms);
-        unit_body<kFused>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
-        __syncthreads();
+    if (!BULK) {
+        for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
+            const Unit uc = unit_of(it, a.geo.nseg, Ms);
+            unit_body<kFused>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
+            __syncthreads();
+        }
+        return;
+    }
+    const uint64_t B = a.unit_batch > 1 ? (uint64_t)a.unit_batch : 1;
+    const uint64_t nu = a.geo.nunits;
+    const int wave = threadIdx.x >> 6;
+    for (uint64_t base = blockIdx.x * B; base < nu; base += gridDim.x * B) {
+        if (B > 1) {
+            bool left = false;
+            if (threadIdx.x < B && base + threadIdx.x < nu) {
+                const Unit uc = unit_of(base + threadIdx.x, a.geo.nseg, Ms);
+                left = !((zp || a.src_basis) && bulk_zero_unit(a, uc));
+            }
+            const uint64_t bw = __ballot(left);
+            if (lane_id() == 0)
+                S.misc[4 + wave] = bw;
+            __syncthreads();
+        }
+        // the units left, in wave-mask order, through one call site
+        int w = 0;
+        uint64_t mw = B > 1 ? left_mask(S, 0) : 1;
+        for (;;) {
+            while (mw == 0 && B > 1 && w < 3)
+                mw = left_mask(S, ++w);
+            if (mw == 0)
+                break;
+            const uint64_t it = base + 64 * (uint64_t)w + (uint64_t)__builtin_ctzll(mw);
+            mw &= mw - 1;
+            const Unit uc = unit_of(it, a.geo.nseg, Ms);
+            unit_body<kFused>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
+            __syncthreads();
+        }
+        if (B > 1)
+            __syncthreads();  // the masks are read before the next round writes them
     }
 }
 
@@ -1434,8 +1608,13 @@ __device__ __forceinline__ double const_plane_value(const PassArgs &a, uint64_t 
 // speculated level would hold outliers, and the unit holding PHASE_FLIP's
 // index, take the full path.  Returns whether the unit was handled
 // (workgroup-uniform).
-__device__ bool const_unit(const PassArgs &a, const Unit &uc, PassLds &S, double scale,
-                           const double *tdiff)
+// The evaluation half of const_unit, by one thread for a whole unit: whether
+// the unit qualifies, and then each plane's value after the gate (y), its
+// x-hat and output anchor at the speculated level, and the speculated level
+// of each segment.
+__device__ __forceinline__ bool const_eval(const PassArgs &a, const Unit &uc, double scale,
+                                           const double *tdiff, double *y, double *xh,
+                                           uint64_t *anc_out, int *lev)
 {
     if (a.src_basis)
         return false;
@@ -1454,11 +1633,6 @@ __device__ bool const_unit(const PassArgs &a, const Unit &uc, PassLds &S, double
         hv |= *(const uint64_t *)(a.arena_in + o[i] + 8);  // payload words | outliers
     if (hv != 0)
         return false;
-    // every thread evaluates all four planes (a few scalars): the decision
-    // below is then uniform without LDS
-    double y[4], xh[4];
-    uint64_t anc_out[4];
-    int lev[2];
     bool ok = true;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -1484,8 +1658,21 @@ __device__ bool const_unit(const PassArgs &a, const Unit &uc, PassLds &S, double
             anc_out[i] = (uint64_t)(int64_t)q;
         }
     }
-    if (!ok)
+    return ok;
+}
+
+__device__ bool const_unit(const PassArgs &a, const Unit &uc, PassLds &S, double scale,
+                           const double *tdiff)
+{
+    // every thread evaluates all four planes (a few scalars): the decision
+    // below is then uniform without LDS
+    double y[4], xh[4];
+    uint64_t anc_out[4];
+    int lev[2];
+    if (!const_eval(a, uc, scale, tdiff, y, xh, anc_out, lev))
         return false;
+    const int s = a.geo.s;
+    const uint64_t g0 = uc.seg(0), g1 = uc.seg(1);
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int us = wave >> 1, p = wave & 1;
     const bool active = us < uc.nsu;
@@ -1539,6 +1726,7 @@ __device__ bool const_unit(const PassArgs &a, const Unit &uc, PassLds &S, double
 
 // The pass for DIFFUSE and PHASE_FLIP gates: k_pass with const_unit's fast
 // path in front of the unit body.
+template <bool BULK>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pass_const(
     PassArgs a)
 {
@@ -1557,11 +1745,60 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     const double scale = a.dev->scale;
     const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
     const bool zp = zero_preserving(a.gate);
-    for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
-        const Unit uc = unit_of(it, a.geo.nseg, 0);
-        if (!const_unit(a, uc, S, scale, tdiff))
+    if (!BULK) {
+        for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
+            const Unit uc = unit_of(it, a.geo.nseg, 0);
+            if (!const_unit(a, uc, S, scale, tdiff))
+                unit_body<kFused>(a, uc, ~0ull, S, scale, tdiff, zp);
+            __syncthreads();
+        }
+        return;
+    }
+    const uint64_t B = a.unit_batch > 1 ? (uint64_t)a.unit_batch : 1;
+    const uint64_t nu = a.geo.nunits;
+    const int wave = threadIdx.x >> 6;
+    for (uint64_t base = blockIdx.x * B; base < nu; base += gridDim.x * B) {
+        if (B > 1) {
+            bool left = false, mine = false;
+            double y[4], xh[4];
+            uint64_t anc[4];
+            int lev[2];
+            Unit uc{};
+            uint32_t bytes = 0;
+            if (threadIdx.x < B && base + threadIdx.x < nu) {
+                uc = unit_of(base + threadIdx.x, a.geo.nseg, 0);
+                mine = const_eval(a, uc, scale, tdiff, y, xh, anc, lev);
+                left = !mine;
+                if (mine)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        bytes += anc[i] != 0ull ? kPlaneHdrBytes : 0u;
+            }
+            const uint64_t rec = bulk_alloc(a, S, bytes);
+            if (mine)
+                bulk_const_write(a, uc, y, xh, anc, lev, rec);
+            const uint64_t bw = __ballot(left);
+            if (lane_id() == 0)
+                S.misc[4 + wave] = bw;
+            __syncthreads();
+        }
+        // the units left, in wave-mask order, through one call site
+        int w = 0;
+        uint64_t mw = B > 1 ? left_mask(S, 0) : 1;
+        for (;;) {
+            while (mw == 0 && B > 1 && w < 3)
+                mw = left_mask(S, ++w);
+            if (mw == 0)
+                break;
+            const uint64_t it = base + 64 * (uint64_t)w + (uint64_t)__builtin_ctzll(mw);
+            mw &= mw - 1;
+            const Unit uc = unit_of(it, a.geo.nseg, 0);
+            // (a unit left here failed the one-value check in the first phase)
             unit_body<kFused>(a, uc, ~0ull, S, scale, tdiff, zp);
-        __syncthreads();
+            __syncthreads();
+        }
+        if (B > 1)
+            __syncthreads();  // the masks are read before the next round writes them
     }
 }
 
@@ -1677,15 +1914,86 @@ __device__ void mean_unit(const PassArgs &a, uint64_t u, Planes &X, double *red,
     __syncthreads();
 }
 
+// mean_unit's one-value case by one thread for a whole unit (bulk rounds);
+// returns whether the unit was one.
+__device__ bool bulk_mean_unit(const PassArgs &a, uint64_t u, double scale)
+{
+    const Unit uc = unit_of(u, a.geo.nseg, 0);
+    const int s = a.geo.s;
+    uint64_t o[4];
+    uint64_t hv = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        o[i] = i < 2 * uc.nsu ? a.din.plane_off[2 * uc.seg(i >> 1) + (i & 1)] : 0ull;
+        hv |= *(const uint64_t *)(a.arena_in + o[i] + 8);
+    }
+    if (hv != 0)
+        return false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i >= 2 * uc.nsu)
+            break;
+        const uint64_t g = uc.seg(i >> 1);
+        const uint64_t anc = *(const uint64_t *)(a.arena_in + o[i]);
+        const double delta = *(const double *)(a.din.hdr + 32 * (g >> (a.geo.b - s)) + 16);
+        const double e = 2.0 * delta;
+        double v = delta == 0.0 ? __longlong_as_double((long long)anc)
+                                : (double)(int32_t)(uint32_t)anc * e;
+        if (scale != 1.0)
+            v = v * scale;
+        a.segsum[(uint64_t)(i & 1) * a.geo.nseg + g] = v * (double)(1u << s);
+    }
+    return true;
+}
+
+template <bool BULK>
 __global__ __launch_bounds__(kWG) void k_mean(PassArgs a)
 {
     if (a.dev->err)
         return;
     __shared__ __attribute__((aligned(16))) Planes X;
     __shared__ double red[8];
+    __shared__ uint64_t lmask[4];
     const double scale = a.dev->scale;
-    for (uint64_t u = blockIdx.x; u < a.geo.nunits; u += gridDim.x)
-        mean_unit(a, u, X, red, scale);
+    // bulk rounds as in the pass: one-value units settled one per thread,
+    // the others through mean_unit by the whole workgroup
+    if (!BULK) {
+        for (uint64_t u = blockIdx.x; u < a.geo.nunits; u += gridDim.x)
+            mean_unit(a, u, X, red, scale);
+        return;
+    }
+    const uint64_t B = a.unit_batch > 1 ? (uint64_t)a.unit_batch : 1;
+    const uint64_t nu = a.geo.nunits;
+    const int wave = threadIdx.x >> 6;
+    auto mask = [&](int w) {
+        const uint64_t v = lmask[w];
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+        return ((uint64_t)hi << 32) | lo;
+    };
+    for (uint64_t base = blockIdx.x * B; base < nu; base += gridDim.x * B) {
+        if (B > 1) {
+            bool left = false;
+            if (threadIdx.x < B && base + threadIdx.x < nu)
+                left = !bulk_mean_unit(a, base + threadIdx.x, scale);
+            const uint64_t bw = __ballot(left);
+            if (lane_id() == 0)
+                lmask[wave] = bw;
+            __syncthreads();
+        }
+        int w = 0;
+        uint64_t mw = B > 1 ? mask(0) : 1;
+        for (;;) {
+            while (mw == 0 && B > 1 && w < 3)
+                mw = mask(++w);
+            if (mw == 0)
+                break;
+            const uint64_t u = base + 64 * (uint64_t)w + (uint64_t)__builtin_ctzll(mw);
+            mw &= mw - 1;
+            mean_unit(a, u, X, red, scale);
+        }
+        __syncthreads();  // the masks are read before the next round writes them
+    }
 }
 
 // ------------------------------------------------------ reductions --------
@@ -2894,8 +3202,17 @@ void launch_init_state(DevState *dev, int normalize, hipStream_t st, Prof *prof)
 void launch_mean(const PassArgs &a, double mul, double *out, hipStream_t st, Prof *prof)
 {
     PassArgs m = a;
-    TIMED(prof, kIdMean, st,
-          hipLaunchKernelGGL(k_mean, dim3(grid_for(a.geo.nunits)), dim3(kWG), 0, st, m));
+    // up to 12288 workgroups: one unit each (the earlier launch shape); past
+    // that, bulk rounds (unit_batch_for)
+    const unsigned gm = grid_for(a.geo.nunits < 12288 ? a.geo.nunits : 12288);
+    m.unit_batch = a.geo.nunits <= 12288 ? 1 : (int32_t)unit_batch_for(a.geo.nunits, gm);
+    const unsigned gl = m.unit_batch > 1 ? gm : grid_for(a.geo.nunits);
+    if (m.unit_batch > 1)
+        TIMED(prof, kIdMean, st,
+              hipLaunchKernelGGL(k_mean<true>, dim3(gl), dim3(kWG), 0, st, m));
+    else
+        TIMED(prof, kIdMean, st,
+              hipLaunchKernelGGL(k_mean<false>, dim3(gl), dim3(kWG), 0, st, m));
     const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
     for (int c = 0; c < 2; ++c)
         TIMED(prof, kIdMeanTree, st,
@@ -2919,10 +3236,23 @@ void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *pr
     const unsigned gfix = gu < 256 ? gu : 256;
     PassArgs a = a0;
     a.chunk_bytes = batch_chunk_bytes(a.arena_cap, gu);
-    if (a.gate.kind == kDiffuse || a.gate.kind == kPhaseFlip)
-        TIMED(prof, kIdPass, st, hipLaunchKernelGGL(k_pass_const, dim3(gu), dim3(kWG), 0, st, a));
-    else
-        TIMED(prof, kIdPass, st, hipLaunchKernelGGL(k_pass, dim3(gu), dim3(kWG), 0, st, a));
+    a.unit_batch = (int32_t)unit_batch_for(a0.geo.nunits, gu);
+    const bool bulk = a.unit_batch > 1;
+    if (a.gate.kind == kDiffuse || a.gate.kind == kPhaseFlip) {
+        if (bulk)
+            TIMED(prof, kIdPass, st,
+                  hipLaunchKernelGGL(k_pass_const<true>, dim3(gu), dim3(kWG), 0, st, a));
+        else
+            TIMED(prof, kIdPass, st,
+                  hipLaunchKernelGGL(k_pass_const<false>, dim3(gu), dim3(kWG), 0, st, a));
+    } else {
+        if (bulk)
+            TIMED(prof, kIdPass, st,
+                  hipLaunchKernelGGL(k_pass<true>, dim3(gu), dim3(kWG), 0, st, a));
+        else
+            TIMED(prof, kIdPass, st,
+                  hipLaunchKernelGGL(k_pass<false>, dim3(gu), dim3(kWG), 0, st, a));
+    }
     TIMED(prof, kIdDecide, st, hipLaunchKernelGGL(k_decide, dim3(gb), dim3(kWG), 0, st, a));
     if (a.lad.L > 1)
         TIMED(prof, kIdReplay, st, hipLaunchKernelGGL(k_fix, dim3(gfix), dim3(kWG), 0, st, a));

@@ -166,6 +166,48 @@ def test_qft12_error_bounds_and_thresholds(A, eb, theta, fixed):
     assert sg["collapsed"] == so["collapsed"] and sg["normsq"] == so["normsq"]
 
 
+def test_bulk_rounds_grover21_small_grid(A):
+    """A grid of 64 workgroups over 1024 units: the pass, the one-value pass
+    and the mean pre-pass take their units in bulk rounds of 4 (zero units
+    and one-value units settled one per thread).  Streams after every gate
+    equal the oracle's."""
+    n, b, m, it = 21, 14, 0x15A3C, 2
+    gates = I.grover(n, m, it)
+    say("bulk rounds: grover", n, "grid 64")
+    g = A.Sim(n, b, 1e-5)
+    g.set_grid(64)
+    g.set_basis(0)
+    o = orc.OracleSim(n, b, I.default_ladder(1e-5), 4.0)
+    assert g.export_state() == o.export_state()
+    for k, gate in enumerate(gates):
+        g.apply(gate)
+        o.apply(gate)
+        assert g.export_state() == o.export_state(), "gate %d" % k
+    sg, so = g.stats(), o.stats()
+    assert sg["normsq"] == so["normsq"] and sg["level_hist"] == so["level_hist"]
+
+
+def test_bulk_rounds_sparse_random_n20(A):
+    """Bulk rounds of 2 units (n = 20, grid 64) on a sparse state: a basis
+    state opened on a few high qubits, then gates of every kind; the basis
+    encode and the zero units go through the per-thread path."""
+    n, b = 20, 12
+    rng = np.random.default_rng(20)
+    gates = [I.h(q) for q in (19, 16, 12, 3)] + random_gates(n, 30, rng)
+    x = int(rng.integers(0, 1 << n))
+    say("bulk rounds: sparse random n=20 grid 64 basis", x)
+    g = A.Sim(n, b, 1e-4)
+    g.set_grid(64)
+    g.set_basis(x)
+    o = orc.OracleSim(n, b, I.default_ladder(1e-4), 4.0)
+    o.set_basis(x)
+    assert g.export_state() == o.export_state()
+    for k, gate in enumerate(gates):
+        g.apply(gate)
+        o.apply(gate)
+        assert g.export_state() == o.export_state(), "gate %d %s" % (k, gate[:3])
+
+
 CASES = [
     # n, b, ladder, theta, ngates, seed
     (9, 7, [0.0], 4.0, 60, 1),
