@@ -1516,72 +1516,6 @@ __device__ __forceinline__ uint64_t left_mask(const PassLds &S, int w)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// The fused pass over all units.
-// Four workgroups per CU (the LDS budget) need at most 128 VGPRs per lane.
-// BULK: rounds of a.unit_batch units with the per-thread first phase (a
-// kernel of its own, so that the one-unit-per-round form that smaller states
-// run keeps exactly its earlier code).
-template <bool BULK>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pass(
-    PassArgs a)
-{
-    if (gridDim.x > a.scratch_wgs) {  // launch larger than the staging (host bug)
-        if (blockIdx.x == 0 && threadIdx.x == 0)
-            atomicOr(&a.dev->err, kErrSize);
-        return;
-    }
-    if (a.dev->err)
-        return;
-    __shared__ PassLds S;
-    for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
-        (&S.pack[0][0])[k] = 0u;
-    if (threadIdx.x == 0)
-        S.chunk[0] = S.chunk[1] = 0;
-    const uint64_t Ms = a.gate.mask >> a.geo.s;
-    // s and 2*mean are read by each unit together with its own reads
-    const bool zp = zero_preserving(a.gate);
-    if (!BULK) {
-        for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
-            const Unit uc = unit_of(it, a.geo.nseg, Ms);
-            unit_body<kFused>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
-            __syncthreads();
-        }
-        return;
-    }
-    const uint64_t B = a.unit_batch > 1 ? (uint64_t)a.unit_batch : 1;
-    const uint64_t nu = a.geo.nunits;
-    const int wave = threadIdx.x >> 6;
-    for (uint64_t base = blockIdx.x * B; base < nu; base += gridDim.x * B) {
-        if (B > 1) {
-            bool left = false;
-            if (threadIdx.x < B && base + threadIdx.x < nu) {
-                const Unit uc = unit_of(base + threadIdx.x, a.geo.nseg, Ms);
-                left = !((zp || a.src_basis) && bulk_zero_unit(a, uc));
-            }
-            const uint64_t bw = __ballot(left);
-            if (lane_id() == 0)
-                S.misc[4 + wave] = bw;
-            __syncthreads();
-        }
-        // the units left, in wave-mask order, through one call site
-        int w = 0;
-        uint64_t mw = B > 1 ? left_mask(S, 0) : 1;
-        for (;;) {
-            while (mw == 0 && B > 1 && w < 3)
-                mw = left_mask(S, ++w);
-            if (mw == 0)
-                break;
-            const uint64_t it = base + 64 * (uint64_t)w + (uint64_t)__builtin_ctzll(mw);
-            mw &= mw - 1;
-            const Unit uc = unit_of(it, a.geo.nseg, Ms);
-            unit_body<kFused>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
-            __syncthreads();
-        }
-        if (B > 1)
-            __syncthreads();  // the masks are read before the next round writes them
-    }
-}
-
 // The value of plane i (segment i >> 1, component i & 1) of a unit whose
 // records hold one value each, after decode, normalisation and the gate
 // (DIFFUSE: 2 mean - a; PHASE_FLIP outside its index: unchanged).
@@ -1612,6 +1546,30 @@ __device__ __forceinline__ double const_plane_value(const PassArgs &a, uint64_t 
 // the unit qualifies, and then each plane's value after the gate (y), its
 // x-hat and output anchor at the speculated level, and the speculated level
 // of each segment.
+// Whether a gate applies the same operation to every position of a segment
+// (with, for a pair gate, the partner at the same position of the coupled
+// segment): DIFFUSE, PHASE_FLIP away from its index, and gates whose qubits
+// are all at or above s.  Planes of one value then stay planes of one value.
+__device__ __forceinline__ bool segment_uniform(const GateArg &G, int s)
+{
+    switch (G.kind) {
+    case kDiffuse:
+    case kPhaseFlip:
+        return true;
+    case kU:
+    case kX:
+    case kDiag1:
+        return G.q0 >= s;
+    case kCU:
+    case kCPhase:
+    case kCZ:
+    case kSwap:
+        return G.q0 >= s && G.q1 >= s;
+    default:
+        return false;
+    }
+}
+
 __device__ __forceinline__ bool const_eval(const PassArgs &a, const Unit &uc, double scale,
                                            const double *tdiff, double *y, double *xh,
                                            uint64_t *anc_out, int *lev)
@@ -1644,6 +1602,21 @@ __device__ __forceinline__ bool const_eval(const PassArgs &a, const Unit &uc, do
         lev[i >> 1] = h;
         const uint64_t anc = *(const uint64_t *)(a.arena_in + o[i]);
         y[i] = const_plane_value(a, anc, delta_in, i & 1, scale, tdiff[i & 1]);
+    }
+    // gates other than DIFFUSE and PHASE_FLIP: the value pair of each
+    // position through the gate's own pair or diagonal update (every
+    // position of a segment gets the same operation: segment_uniform)
+    if (a.gate.kind != kDiffuse && a.gate.kind != kPhaseFlip) {
+        if (a.gate.mask >> s) {
+            gate_pair(a.gate, g0 << s, y[0], y[1], y[2], y[3]);
+        } else {
+            gate_diag(a.gate, g0 << s, y[0], y[1], tdiff);
+            gate_diag(a.gate, g1 << s, y[2], y[3], tdiff);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int h = lev[i >> 1];
         const double dh = a.lad.delta[h];
         if (dh == 0.0) {
             xh[i] = y[i];
@@ -1724,10 +1697,13 @@ __device__ bool const_unit(const PassArgs &a, const Unit &uc, PassLds &S, double
     return true;
 }
 
-// The pass for DIFFUSE and PHASE_FLIP gates: k_pass with const_unit's fast
-// path in front of the unit body.
+// The fused pass over all units.
+// Four workgroups per CU (the LDS budget) need at most 128 VGPRs per lane.
+// BULK: rounds of a.unit_batch units with the per-thread first phase (a
+// kernel of its own, so that the one-unit-per-round form that smaller states
+// run keeps exactly its earlier code).
 template <bool BULK>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pass_const(
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pass(
     PassArgs a)
 {
     if (gridDim.x > a.scratch_wgs) {  // launch larger than the staging (host bug)
@@ -1742,14 +1718,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         (&S.pack[0][0])[k] = 0u;
     if (threadIdx.x == 0)
         S.chunk[0] = S.chunk[1] = 0;
-    const double scale = a.dev->scale;
-    const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
+    const uint64_t Ms = a.gate.mask >> a.geo.s;
+    // s and 2*mean are read by each unit together with its own reads
     const bool zp = zero_preserving(a.gate);
     if (!BULK) {
         for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
-            const Unit uc = unit_of(it, a.geo.nseg, 0);
-            if (!const_unit(a, uc, S, scale, tdiff))
-                unit_body<kFused>(a, uc, ~0ull, S, scale, tdiff, zp);
+            const Unit uc = unit_of(it, a.geo.nseg, Ms);
+            unit_body<kFused>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
             __syncthreads();
         }
         return;
@@ -1757,6 +1732,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     const uint64_t B = a.unit_batch > 1 ? (uint64_t)a.unit_batch : 1;
     const uint64_t nu = a.geo.nunits;
     const int wave = threadIdx.x >> 6;
+    const bool su = !a.src_basis && segment_uniform(a.gate, a.geo.s);
+    const double scale = a.dev->scale;
+    const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
     for (uint64_t base = blockIdx.x * B; base < nu; base += gridDim.x * B) {
         if (B > 1) {
             bool left = false, mine = false;
@@ -1766,13 +1744,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             Unit uc{};
             uint32_t bytes = 0;
             if (threadIdx.x < B && base + threadIdx.x < nu) {
-                uc = unit_of(base + threadIdx.x, a.geo.nseg, 0);
-                mine = const_eval(a, uc, scale, tdiff, y, xh, anc, lev);
-                left = !mine;
-                if (mine)
+                uc = unit_of(base + threadIdx.x, a.geo.nseg, Ms);
+                if (!((zp || a.src_basis) && bulk_zero_unit(a, uc))) {
+                    mine = su && const_eval(a, uc, scale, tdiff, y, xh, anc, lev);
+                    left = !mine;
+                    if (mine)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        bytes += anc[i] != 0ull ? kPlaneHdrBytes : 0u;
+                        for (int i = 0; i < 4; ++i)
+                            bytes += anc[i] != 0ull ? kPlaneHdrBytes : 0u;
+                }
             }
             const uint64_t rec = bulk_alloc(a, S, bytes);
             if (mine)
@@ -1792,13 +1772,40 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                 break;
             const uint64_t it = base + 64 * (uint64_t)w + (uint64_t)__builtin_ctzll(mw);
             mw &= mw - 1;
-            const Unit uc = unit_of(it, a.geo.nseg, 0);
-            // (a unit left here failed the one-value check in the first phase)
-            unit_body<kFused>(a, uc, ~0ull, S, scale, tdiff, zp);
+            const Unit uc = unit_of(it, a.geo.nseg, Ms);
+            unit_body<kFused>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
             __syncthreads();
         }
         if (B > 1)
             __syncthreads();  // the masks are read before the next round writes them
+    }
+}
+
+// The pass for DIFFUSE and PHASE_FLIP gates: k_pass with const_unit's fast
+// path in front of the unit body.
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pass_const(
+    PassArgs a)
+{
+    if (gridDim.x > a.scratch_wgs) {  // launch larger than the staging (host bug)
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            atomicOr(&a.dev->err, kErrSize);
+        return;
+    }
+    if (a.dev->err)
+        return;
+    __shared__ PassLds S;
+    for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
+        (&S.pack[0][0])[k] = 0u;
+    if (threadIdx.x == 0)
+        S.chunk[0] = S.chunk[1] = 0;
+    const double scale = a.dev->scale;
+    const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
+    const bool zp = zero_preserving(a.gate);
+    for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
+        const Unit uc = unit_of(it, a.geo.nseg, 0);
+        if (!const_unit(a, uc, S, scale, tdiff))
+            unit_body<kFused>(a, uc, ~0ull, S, scale, tdiff, zp);
+        __syncthreads();
     }
 }
 
@@ -3237,22 +3244,17 @@ void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *pr
     PassArgs a = a0;
     a.chunk_bytes = batch_chunk_bytes(a.arena_cap, gu);
     a.unit_batch = (int32_t)unit_batch_for(a0.geo.nunits, gu);
-    const bool bulk = a.unit_batch > 1;
-    if (a.gate.kind == kDiffuse || a.gate.kind == kPhaseFlip) {
-        if (bulk)
-            TIMED(prof, kIdPass, st,
-                  hipLaunchKernelGGL(k_pass_const<true>, dim3(gu), dim3(kWG), 0, st, a));
-        else
-            TIMED(prof, kIdPass, st,
-                  hipLaunchKernelGGL(k_pass_const<false>, dim3(gu), dim3(kWG), 0, st, a));
-    } else {
-        if (bulk)
-            TIMED(prof, kIdPass, st,
-                  hipLaunchKernelGGL(k_pass<true>, dim3(gu), dim3(kWG), 0, st, a));
-        else
-            TIMED(prof, kIdPass, st,
-                  hipLaunchKernelGGL(k_pass<false>, dim3(gu), dim3(kWG), 0, st, a));
-    }
+    // bulk rounds (every gate kind: zero and one-value units per thread) for
+    // states with many more units than workgroups; otherwise one unit per
+    // round, with the one-value fast path for DIFFUSE and PHASE_FLIP
+    if (a.unit_batch > 1)
+        TIMED(prof, kIdPass, st,
+              hipLaunchKernelGGL(k_pass<true>, dim3(gu), dim3(kWG), 0, st, a));
+    else if (a.gate.kind == kDiffuse || a.gate.kind == kPhaseFlip)
+        TIMED(prof, kIdPass, st, hipLaunchKernelGGL(k_pass_const, dim3(gu), dim3(kWG), 0, st, a));
+    else
+        TIMED(prof, kIdPass, st,
+              hipLaunchKernelGGL(k_pass<false>, dim3(gu), dim3(kWG), 0, st, a));
     TIMED(prof, kIdDecide, st, hipLaunchKernelGGL(k_decide, dim3(gb), dim3(kWG), 0, st, a));
     if (a.lad.L > 1)
         TIMED(prof, kIdReplay, st, hipLaunchKernelGGL(k_fix, dim3(gfix), dim3(kWG), 0, st, a));

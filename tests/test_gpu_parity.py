@@ -208,6 +208,39 @@ def test_bulk_rounds_sparse_random_n20(A):
         assert g.export_state() == o.export_state(), "gate %d %s" % (k, gate[:3])
 
 
+@pytest.mark.parametrize("ladder", [None, [1e-4]])
+def test_bulk_rounds_one_value_planes_every_gate_kind(A, ladder):
+    """Bulk rounds (n = 20, grid 64: 2 units per round) over planes of one
+    value: the uniform superposition, then gates of every kind whose qubits
+    are all at or above s = 10 (one-value planes stay one-value planes and
+    are settled per thread), mixed with gates on low qubits (full path).
+    Streams after every gate equal the oracle's."""
+    n, b = 20, 12
+    rng = np.random.default_rng(33)
+    hi = lambda: int(rng.integers(10, n))
+    gates = [I.h(q) for q in range(n)]
+    for rep in range(2):
+        a, c = hi(), hi()
+        while c == a:
+            c = hi()
+        gates += [I.u_gate(hi(), random_unitary(rng)), I.x(hi()), I.cu(a, c, random_unitary(rng)),
+                  I.swap(a, c), I.diag1(hi(), math.cos(0.3), math.sin(0.3)),
+                  I.cphase(a, c, 1.1), I.cz(a, c), I.phase_flip(int(rng.integers(0, 1 << n))),
+                  I.diffuse()]
+        if rep == 0:
+            gates += [I.u_gate(3, random_unitary(rng)), I.cz(2, 15)]
+    lad = I.default_ladder(1e-4) if ladder is None else ladder
+    say("bulk rounds: one-value planes, ladder", lad)
+    g = A.Sim(n, b, 1e-4, ladder=ladder, theta=4.0)
+    g.set_grid(64)
+    g.set_basis(0)
+    o = orc.OracleSim(n, b, lad, 4.0)
+    for k, gate in enumerate(gates):
+        g.apply(gate)
+        o.apply(gate)
+        assert g.export_state() == o.export_state(), "gate %d %s" % (k, gate[:3])
+
+
 CASES = [
     # n, b, ladder, theta, ngates, seed
     (9, 7, [0.0], 4.0, 60, 1),
