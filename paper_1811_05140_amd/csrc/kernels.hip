@@ -3,24 +3,28 @@
 // One pass of a gate runs Alg. 2 of the paper (decompress, normalise,
 // gateComputation, compress at delta_0, delta_1, ... until the ratio reaches
 // theta) for every stride, as these kernels on the sim stream:
-//   k_pass<kFused>   per unit of two segments: decode + normalise + gate in
-//                    LDS; the size of each plane record at the ladder levels
-//                    the block can plausibly take (0 .. previous level + 1);
-//                    encode at the block's previous level (the speculation),
-//                    write the records, per-segment normsq
-//   k_decide<false>  per block: the first computed level whose ratio reaches
+//   k_pass           per unit of two segments: decode + normalise + gate in
+//                    LDS; the size of each plane record at ladder levels
+//                    0 .. the block's previous level; encode at that level
+//                    (the speculation), write the records, per-segment
+//                    normsq.  k_pass<true> takes the units in bulk rounds
+//                    (all-zero and one-value units settled one per thread);
+//                    k_pass_const adds a one-value fast path per unit for
+//                    DIFFUSE and PHASE_FLIP on smaller states
+//   k_decide         per block: the first computed level whose ratio reaches
 //                    theta; a block whose choice differs from the speculation
 //                    joins the replay list, one whose computed levels all
 //                    miss theta joins the escalation list
-//   k_pass<kEsc>     escalated blocks only: sizes of the remaining levels
-//   k_decide<true>   escalated blocks: the choice among the remaining levels
-//   k_pass<kReplay>  replayed blocks only: encode again at the chosen level
-//   k_segtree        per block: pairwise normsq into the stream header
+//   k_fix            replayed blocks: encode again at the chosen level;
+//                    escalated blocks: size the remaining levels, choose,
+//                    encode
+//   k_segtree        per block: pairwise normsq from the segment sums
 //   k_reduce         N^2 over blocks, s = 1/sqrt(N^2), statistics
 // The level chosen is always exactly the one of Alg. 2 (the first level
 // whose full-block ratio reaches theta, else the last); speculation only
 // decides which records have to be written twice.  DIFFUSE adds a read-only
-// mean pre-pass (k_mean + k_segtree + k_mean_final).
+// mean pre-pass (k_mean + k_segtree + k_mean_final).  Checkpoints: k_export_range
+// and the k_import_* kernels.
 //
 // Work decomposition: a workgroup of four wave64s takes one unit of two
 // segments (2 x 2^s amplitudes); wave w decodes / encodes plane (w & 1) of
@@ -2197,9 +2201,13 @@ __device__ void finalize_block(const PassArgs &a, uint64_t j, int d, uint64_t le
 // reaches theta.  When that is the speculated level h the block is done;
 // another level sends the block to the replay list; when none qualifies and
 // levels above h remain, the block joins the escalation list.
+template <int VEC>
 __device__ void decide_block(const PassArgs &a, uint64_t j);
 
 // One wavefront per block.
+// VEC: 1 = blocks of 256 planes or more (vector loads), 0 = smaller blocks,
+// -1 = either (chosen per block).
+template <int VEC>
 __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
 {
     if (a.dev->err)
@@ -2207,9 +2215,10 @@ __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
     const uint64_t nw = (uint64_t)gridDim.x * (kWG / 64);
     for (uint64_t j = (uint64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
          j < a.geo.nblocks; j += nw)
-        decide_block(a, j);
+        decide_block<VEC>(a, j);
 }
 
+template <int VEC>
 __device__ void decide_block(const PassArgs &a, uint64_t j)
 {
     // sizes of levels 0..h summed over the block's planes by one wavefront
@@ -2231,13 +2240,30 @@ __device__ void decide_block(const PassArgs &a, uint64_t j)
         by[k] = 0;
         no[k] = 0;
     }
-    for (uint64_t q = lane; q < npb; q += 64) {
+    if (VEC == 1 || (VEC < 0 && npb % 256 == 0)) {
+        // blocks of 256 planes or more: four planes per lane per load, four
+        // loads in flight (the sums are of integers: any order is exact)
+#pragma unroll 4
+        for (uint64_t q = 4 * (uint64_t)lane; q < npb; q += 256) {
 #pragma unroll
-        for (int k = 0; k < kMaxL; ++k) {
-            if (k <= h) {
-                const uint32_t v = a.psz[(uint64_t)k * nplanes + base + q];
-                by[k] += rec_bytes(v, padC);
-                no[k] += v >> 16;
+            for (int k = 0; k < kMaxL; ++k) {
+                if (k <= h) {
+                    const uint4 v = *(const uint4 *)(a.psz + (uint64_t)k * nplanes + base + q);
+                    by[k] += rec_bytes(v.x, padC) + rec_bytes(v.y, padC) +
+                             rec_bytes(v.z, padC) + rec_bytes(v.w, padC);
+                    no[k] += (v.x >> 16) + (v.y >> 16) + (v.z >> 16) + (v.w >> 16);
+                }
+            }
+        }
+    } else {
+        for (uint64_t q = lane; q < npb; q += 64) {
+#pragma unroll
+            for (int k = 0; k < kMaxL; ++k) {
+                if (k <= h) {
+                    const uint32_t v = a.psz[(uint64_t)k * nplanes + base + q];
+                    by[k] += rec_bytes(v, padC);
+                    no[k] += v >> 16;
+                }
             }
         }
     }
@@ -2359,6 +2385,7 @@ __device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures)
     } else {
         N2 = wg_tree([&](uint64_t i) { return a.blknorm[i]; }, nb, lds);
         uint64_t by = 0;
+#pragma unroll 8
         for (uint64_t j = t; j < nb; j += kWG) {
             by += a.dout.blk_len[j];
             const int lv = a.dout.blk_level[j];
@@ -3064,7 +3091,7 @@ __global__ __launch_bounds__(kWG) void k_bdecide(const PassArgs *__restrict__ ar
         const PassArgs &a = args[st];
         if (a.dev->err)
             continue;
-        decide_block(a, it - bpre[st]);
+        decide_block<-1>(a, it - bpre[st]);
     }
 }
 
@@ -3255,7 +3282,12 @@ void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *pr
     else
         TIMED(prof, kIdPass, st,
               hipLaunchKernelGGL(k_pass<false>, dim3(gu), dim3(kWG), 0, st, a));
-    TIMED(prof, kIdDecide, st, hipLaunchKernelGGL(k_decide, dim3(gb), dim3(kWG), 0, st, a));
+    if ((2ull << (a.geo.b - a.geo.s)) % 256 == 0)
+        TIMED(prof, kIdDecide, st,
+              hipLaunchKernelGGL(k_decide<1>, dim3(gb), dim3(kWG), 0, st, a));
+    else
+        TIMED(prof, kIdDecide, st,
+              hipLaunchKernelGGL(k_decide<0>, dim3(gb), dim3(kWG), 0, st, a));
     if (a.lad.L > 1)
         TIMED(prof, kIdReplay, st, hipLaunchKernelGGL(k_fix, dim3(gfix), dim3(kWG), 0, st, a));
     TIMED(prof, kIdReduce, st, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, a));
