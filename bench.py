@@ -17,6 +17,9 @@ circuits run one at a time and checks that both give the same states.
 three error bounds) with Poisson arrivals and a 200 GB compressed-memory
 budget, served with continuous batching and one circuit at a time.
 
+--workload qft12: the 12-qubit QFT (64 KiB state, launch-bound): gates/s and
+microseconds per gate, beside the whole oracle run.
+
 --workload qft24sweep: QFT-24 at error bounds 1e-3, 1e-4, 1e-5, each with
 the default ladder at ratio thresholds 4, 8, 16, 32 and with the fixed bound
 alone; throughput, ratios and fidelity per point.
@@ -612,6 +615,70 @@ def bench_checkpoint(args, A, inputs, stream):
     }
 
 
+def bench_qft12(args, A, inputs, stream):
+    """The 12-qubit QFT (84 gates, 16 blocks of 2^8, eb = 1e-4, default
+    ladder): a state of 64 KiB, so a pass is bound by launch latency, and the
+    figure is microseconds per gate.  The oracle runs the whole circuit (no
+    sampling) on one core, repeated for about 10 s."""
+    import torch
+    w = inputs.qft12_workload()
+    n, b, x, gates = w["n"], w["b"], w["basis"], w["gates"]
+    sim = A.Sim(n, b, 1e-4, stream=stream)
+
+    def step():
+        sim.set_basis(x)
+        sim.run(gates)
+    for _ in range(args.warmup):
+        step()
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    sim.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gps = len(gates) * args.steps / el
+    ref = A.Sim(n, b, -1.0, stream=stream)
+    ref.set_basis(x)
+    ref.run(gates)
+    F = sim.fidelity(ref)
+    ref.close()
+    st = sim.stats()
+    cpu = None
+    if args.cpu_budget > 0:
+        from oracle import oracle as orc
+        runs, tcpu = 0, 0.0
+        while tcpu < min(args.cpu_budget, 10.0):
+            o = orc.OracleSim(n, b, inputs.default_ladder(1e-4), 4.0)
+            c0 = time.perf_counter()
+            o.set_basis(x)
+            o.run(gates)
+            tcpu += time.perf_counter() - c0
+            runs += 1
+            o.close()
+        cpu = {"value": round(len(gates) * runs / tcpu, 2), "unit": "gates/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "the whole QFT-12 circuit (basis encode + 84 gates), %d runs in "
+                         "%.1f s, single thread" % (runs, tcpu)}
+    sim.close()
+    return {
+        "metric": METRIC, "value": round(gps, 1), "unit": "gates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * el / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded basis state, generated circuit)",
+        "config": {"workload": "qft12", "n_qubits": n, "block_log2": b, "error_bound": 1e-4,
+                   "basis": x, "gates_per_step": len(gates)},
+        "us_per_gate": round(1e6 / gps, 2),
+        "amplitude_gbs": round(gps * LOGICAL_BYTES_PER_AMP * (1 << n) / 1e9, 2),
+        "fidelity": F, "fidelity_reference": "uncompressed FP64 GPU run",
+        "min_ratio": st["min_ratio"], "roofline": None, "cpu_baseline": cpu,
+        "note": "64 KiB state: every pass is four kernel launches of a few microseconds; "
+                "launch latency, not bandwidth, bounds it",
+    }
+
+
 def bench_qft24_sweep(args, A, inputs, stream):
     """QFT-24 over the error bounds {1e-3, 1e-4, 1e-5}: the default ladder at
     ratio thresholds 4, 8, 16 and 32 (the paper's AALC runs vary the
@@ -694,7 +761,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=("qft24", "grover36", "batch64", "serve512",
-                                           "checkpoint", "qft24sweep"),
+                                           "checkpoint", "qft24sweep", "qft12"),
                     default="qft24")
     ap.add_argument("--state", choices=("qft24", "grover36"), default="qft24",
                     help="checkpoint workload: the state exported and imported")
@@ -717,7 +784,7 @@ def main():
     args = ap.parse_args()
     grover = args.workload == "grover36"
     if args.steps is None:
-        args.steps = 5 if args.workload == "qft24" else (3 if args.workload == "qft24sweep" else 1)
+        args.steps = {"qft24": 5, "qft24sweep": 3, "qft12": 200}.get(args.workload, 1)
     if args.warmup is None:
         args.warmup = 1 if args.workload != "grover36" else 0
     eb = args.error_bound if args.error_bound is not None else (1e-5 if grover else 1e-4)
@@ -743,6 +810,9 @@ def main():
         return
     if args.workload == "serve512":
         print(json.dumps(bench_serve(args, A, inputs, stream)), flush=True)
+        return
+    if args.workload == "qft12":
+        print(json.dumps(bench_qft12(args, A, inputs, stream)), flush=True)
         return
     if args.workload == "qft24sweep":
         print(json.dumps(bench_qft24_sweep(args, A, inputs, stream)), flush=True)

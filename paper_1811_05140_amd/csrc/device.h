@@ -146,7 +146,7 @@ enum KernelId : int {
     kIdPass, kIdDecide, kIdEscSize, kIdEscDecide, kIdReplay, kIdBlockNorm,
     kIdReduce, kIdMean, kIdMeanTree, kIdMeanFinal, kIdInitState, kIdSvPair,
     kIdSvDiag, kIdSvPartial, kIdSvFinal, kIdExport, kIdImportScan, kIdImportCheck,
-    kIdImportNorm, kIdImportBlocks, kNumKernelIds
+    kIdImportNorm, kIdImportBlocks, kIdPassBulk, kNumKernelIds
 };
 extern const char *const kKernelNames[kNumKernelIds];
 

@@ -1701,6 +1701,18 @@ __device__ bool const_unit(const PassArgs &a, const Unit &uc, PassLds &S, double
     return true;
 }
 
+// Bulk rounds serve states whose last pass left a compression ratio of at
+// least kBulkRatio (and every basis encode): mostly all-zero or one-value
+// units.  For a state with many units both k_pass<true> and the one-unit
+// kernel are launched and each reads the ratio at its start, so exactly one
+// of them runs the pass: dense states keep the one-unit kernel's code.
+constexpr double kBulkRatio = 32.0;
+
+__device__ __forceinline__ bool bulk_turn(const PassArgs &a)
+{
+    return a.src_basis || a.dev->last_ratio >= kBulkRatio;
+}
+
 // The fused pass over all units.
 // Four workgroups per CU (the LDS budget) need at most 128 VGPRs per lane.
 // BULK: rounds of a.unit_batch units with the per-thread first phase (a
@@ -1717,6 +1729,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     }
     if (a.dev->err)
         return;
+    if (BULK ? !bulk_turn(a) : (a.unit_batch > 1 && bulk_turn(a)))
+        return;  // the other kernel of the pair runs this pass
     __shared__ PassLds S;
     for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
         (&S.pack[0][0])[k] = 0u;
@@ -1739,8 +1753,29 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     const bool su = !a.src_basis && segment_uniform(a.gate, a.geo.s);
     const double scale = a.dev->scale;
     const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
-    for (uint64_t base = blockIdx.x * B; base < nu; base += gridDim.x * B) {
-        if (B > 1) {
+    // A workgroup whose last two first phases settled no unit (a dense
+    // state) skips the first phase, trying it again every 16th round: the
+    // first phase is then no cost to states it cannot help.
+    uint32_t quiet = 0, round = 0;
+    for (uint64_t base = blockIdx.x * B; base < nu; base += gridDim.x * B, ++round) {
+        const bool probe = quiet < 2 || (round & 15) == 0;
+        uint64_t m0 = 1, m1 = 0, m2 = 0, m3 = 0;  // one unit per round: base
+        if (B > 1 && !probe) {
+            // every unit of the round goes to the unit body
+            const uint64_t cnt = nu - base < B ? nu - base : B;
+            auto bits = [&](int w) -> uint64_t {
+                const uint64_t lo = 64ull * (uint64_t)w;
+                if (cnt <= lo)
+                    return 0ull;
+                const uint64_t k = cnt - lo;
+                return k >= 64 ? ~0ull : ((1ull << k) - 1);
+            };
+            m0 = bits(0);
+            m1 = bits(1);
+            m2 = bits(2);
+            m3 = bits(3);
+        }
+        if (B > 1 && probe) {
             bool left = false, mine = false;
             double y[4], xh[4];
             uint64_t anc[4];
@@ -1765,13 +1800,24 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             if (lane_id() == 0)
                 S.misc[4 + wave] = bw;
             __syncthreads();
+            m0 = left_mask(S, 0);
+            m1 = left_mask(S, 1);
+            m2 = left_mask(S, 2);
+            m3 = left_mask(S, 3);
+            __syncthreads();  // the masks are read before the next round writes them
+            const uint64_t cnt = nu - base < B ? nu - base : B;
+            const uint64_t nleft = (uint64_t)(__builtin_popcountll(m0) + __builtin_popcountll(m1) +
+                                              __builtin_popcountll(m2) + __builtin_popcountll(m3));
+            quiet = nleft == cnt ? quiet + 1 : 0;
         }
         // the units left, in wave-mask order, through one call site
         int w = 0;
-        uint64_t mw = B > 1 ? left_mask(S, 0) : 1;
+        uint64_t mw = m0;
         for (;;) {
-            while (mw == 0 && B > 1 && w < 3)
-                mw = left_mask(S, ++w);
+            while (mw == 0 && w < 3) {
+                ++w;
+                mw = w == 1 ? m1 : (w == 2 ? m2 : m3);
+            }
             if (mw == 0)
                 break;
             const uint64_t it = base + 64 * (uint64_t)w + (uint64_t)__builtin_ctzll(mw);
@@ -1780,8 +1826,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             unit_body<kFused>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
             __syncthreads();
         }
-        if (B > 1)
-            __syncthreads();  // the masks are read before the next round writes them
     }
 }
 
@@ -1797,6 +1841,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     }
     if (a.dev->err)
         return;
+    if (a.unit_batch > 1 && bulk_turn(a))
+        return;  // k_pass<true> runs this pass
     __shared__ PassLds S;
     for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
         (&S.pack[0][0])[k] = 0u;
@@ -3198,7 +3244,7 @@ const char *const kKernelNames[kNumKernelIds] = {
     "pass", "decide", "esc_size", "esc_decide", "fix", "block_norm", "reduce",
     "mean", "mean_tree", "mean_final", "init_state", "sv_pair", "sv_diag",
     "sv_partial", "sv_final", "export", "import_scan", "import_check", "import_norm",
-    "import_blocks"};
+    "import_blocks", "pass_bulk"};
 
 static unsigned grid_for(uint64_t items)
 {
@@ -3271,13 +3317,14 @@ void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *pr
     PassArgs a = a0;
     a.chunk_bytes = batch_chunk_bytes(a.arena_cap, gu);
     a.unit_batch = (int32_t)unit_batch_for(a0.geo.nunits, gu);
-    // bulk rounds (every gate kind: zero and one-value units per thread) for
-    // states with many more units than workgroups; otherwise one unit per
-    // round, with the one-value fast path for DIFFUSE and PHASE_FLIP
+    // states with many more units than workgroups: the bulk-round kernel
+    // (every gate kind) beside the one-unit kernel, exactly one of which
+    // runs (bulk_turn); the one-unit kernels have the one-value fast path
+    // for DIFFUSE and PHASE_FLIP
     if (a.unit_batch > 1)
-        TIMED(prof, kIdPass, st,
+        TIMED(prof, kIdPassBulk, st,
               hipLaunchKernelGGL(k_pass<true>, dim3(gu), dim3(kWG), 0, st, a));
-    else if (a.gate.kind == kDiffuse || a.gate.kind == kPhaseFlip)
+    if (a.gate.kind == kDiffuse || a.gate.kind == kPhaseFlip)
         TIMED(prof, kIdPass, st, hipLaunchKernelGGL(k_pass_const, dim3(gu), dim3(kWG), 0, st, a));
     else
         TIMED(prof, kIdPass, st,

@@ -74,7 +74,7 @@ struct EventProf final : Prof {
     }
     void begin(int id, hipStream_t st) override
     {
-        if (only_pass && id != kIdPass)
+        if (only_pass && id != kIdPass && id != kIdPassBulk)
             return;
         pending = get();
         pending_id = id;
@@ -83,7 +83,7 @@ struct EventProf final : Prof {
     }
     void end(int id, hipStream_t st) override
     {
-        if (only_pass && id != kIdPass)
+        if (only_pass && id != kIdPass && id != kIdPassBulk)
             return;
         hipEvent_t e = get();
         if (!e || !pending || id != pending_id)
