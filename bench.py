@@ -743,6 +743,27 @@ def bench_qft24_sweep(args, A, inputs, stream):
     }
 
 
+def pass_stream_bytes(sim, x, gates, n, b):
+    """Algorithmic HBM bytes of one step's pass launches (the roofline's
+    per-launch figure is this over the launches): each pass reads its input
+    state's compressed streams and writes its output's, and per plane reads
+    and writes a record offset (16 B) and writes a size word (4 B), per
+    segment a normsq (8 B).  Measured by replaying the step untimed with the
+    resident bytes read after every gate; the basis encode reads nothing."""
+    s = min(b, 10)
+    planes = 2 << (n - s)
+    meta = 20 * planes + 8 * (planes // 2)
+    sim.set_basis(x)
+    prev = sim.stats()["resident_bytes"]
+    total = prev + meta
+    for g in gates:
+        sim.apply(g)
+        cur = sim.stats()["resident_bytes"]
+        total += prev + cur + meta
+        prev = cur
+    return total
+
+
 def grover_fidelity(sim, n, m, k):
     """P(m) and F against the closed-form Grover state after k iterations:
     sin((2k+1)t) on m and cos((2k+1)t)/sqrt(2^n - 1) elsewhere, sin t =
@@ -876,17 +897,28 @@ def main():
     if prof:
         name, (cnt, tot, mn, mx) = max(prof.items(), key=lambda kv: kv[1][1])
         avg_s = tot / cnt / 1000.0
-        alg_bytes = LOGICAL_BYTES_PER_AMP * (1 << n)
+        # algorithmic bytes of the pass launches of one step (untimed replay)
+        alg_step = pass_stream_bytes(sim, x, gates, n, b)
+        launches_per_step = len(gates) + 1  # the basis encode is a pass too
+        alg_bytes = alg_step / launches_per_step
         achieved = alg_bytes / avg_s / 1e9
+        logical = LOGICAL_BYTES_PER_AMP * (1 << n) / avg_s / 1e9
         roofline = {
             "bound": "hbm", "kernel": name,
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.workload, name),
             "avg_launch_ms": round(tot / cnt, 4), "launches": cnt,
-            "algorithmic_bytes_per_launch": alg_bytes,
+            "algorithmic_bytes_per_launch": int(alg_bytes),
+            "algorithmic_bytes": "compressed streams in + out and per-plane metadata, "
+                                 "averaged over the step's pass launches",
+            "logical_gbs": round(logical, 1),
+            "logical_frac": round(logical / HBM_PEAK_GBS, 4),
             "kernels_ms_one_step": split,
         }
+        if not grover:
+            roofline["binding"] = ("VALU issue and memory latency, not HBM bandwidth: see the "
+                                   "SQ counters in profiles/pass_qft24.md")
 
     cpu = None
     if args.cpu_budget > 0:
