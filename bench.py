@@ -645,6 +645,31 @@ def bench_qft12(args, A, inputs, stream):
     F = sim.fidelity(ref)
     ref.close()
     st = sim.stats()
+    # the same circuit as one captured HIP graph of 84 passes (a batch of one
+    # state), replayed each step after the basis encode
+    sim2 = A.Sim(n, b, 1e-4, stream=stream)
+    batch = A.Batch(1, len(gates), stream=stream)
+    passes = [[g] for g in gates]
+
+    def gstep():
+        sim2.set_basis(x)
+        batch.apply([sim2], passes, use_graph=True)
+    for _ in range(max(args.warmup, 1)):
+        gstep()
+    batch.sync()
+    sim2.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gstep()
+    batch.sync()
+    sim2.sync()
+    torch.cuda.synchronize()
+    gel = time.perf_counter() - t0
+    ggps = len(gates) * args.steps / gel
+    graph_same = sim2.export_state() == sim.export_state()
+    batch.close()
+    sim2.close()
     cpu = None
     if args.cpu_budget > 0:
         from oracle import oracle as orc
@@ -671,6 +696,9 @@ def bench_qft12(args, A, inputs, stream):
         "config": {"workload": "qft12", "n_qubits": n, "block_log2": b, "error_bound": 1e-4,
                    "basis": x, "gates_per_step": len(gates)},
         "us_per_gate": round(1e6 / gps, 2),
+        "graph_gates_per_s": round(ggps, 1),
+        "graph_us_per_gate": round(1e6 / ggps, 2),
+        "graph_state_identical": bool(graph_same),
         "amplitude_gbs": round(gps * LOGICAL_BYTES_PER_AMP * (1 << n) / 1e9, 2),
         "fidelity": F, "fidelity_reference": "uncompressed FP64 GPU run",
         "min_ratio": st["min_ratio"], "roofline": None, "cpu_baseline": cpu,
