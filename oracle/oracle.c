@@ -18,13 +18,18 @@
  * follows the readings listed in the design notes of the repository and in
  * the block-stream format definition; each such place says which reading.
  *
- * Build: cc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
+ * Build: cc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
+ * (OpenMP only spreads the independent block groups of a pass over threads;
+ * every result is the same with one thread or many.)
  */
 #include "oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_MAGIC 0x31424141u /* "AAB1" little-endian */
 #define HDR_BYTES 32u
@@ -316,6 +321,23 @@ static size_t decode_plane(const uint8_t *p, const uint8_t *end, size_t m,
     return (size_t)(cur - p);
 }
 
+/* Header byte 5 holds flags; bit 0 (OR_HDR_SCALED) says that the 8 bytes
+ * after the header are the block's deferred scale c (an f64, finite, > 0
+ * and not 1), counted in total_bytes.  The records follow; normsq is that
+ * of the stored values x-hat, without c. */
+#define OR_HDR_SCALED 1u
+
+/* The deferred scale of a stream (1 when it has none); 0 when malformed. */
+static double stream_scale(const uint8_t *stream, size_t len)
+{
+    if (!(stream[5] & OR_HDR_SCALED))
+        return 1.0;
+    if (len < HDR_BYTES + 8)
+        return 0.0;
+    const double c = rd_f64(stream + HDR_BYTES);
+    return (isfinite(c) && c > 0.0 && c != 1.0) ? c : 0.0;
+}
+
 int or_decode_block(const uint8_t *stream, size_t len, double *x)
 {
     if (len < HDR_BYTES || rd_u32(stream) != OR_MAGIC)
@@ -328,7 +350,10 @@ int or_decode_block(const uint8_t *stream, size_t len, double *x)
     double delta = rd_f64(stream + 16);
     if (!(delta >= 0.0))
         return OR_EINVAL;
-    const uint8_t *p = stream + HDR_BYTES, *end = stream + len;
+    if ((stream[5] & ~OR_HDR_SCALED) || stream_scale(stream, len) == 0.0)
+        return OR_EINVAL;
+    const uint8_t *p = stream + HDR_BYTES + ((stream[5] & OR_HDR_SCALED) ? 8 : 0);
+    const uint8_t *end = stream + len;
     size_t m = (size_t)1 << s;
     size_t nseg = (size_t)1 << (b - s);
     uint32_t nout = 0;
@@ -710,11 +735,13 @@ int or_sv_apply_gate(double *amp, int n, const or_gate *g)
 
 struct or_sim {
     int n, b, s, L, normalize;
+    int shortcut;        /* OR_SC_* flags (Sec. V); 0 = Alg. 2 as written */
     double ladder[8];
     double theta;
     uint64_t nblocks;
-    uint8_t **streams;
+    uint8_t **streams;   /* plain block streams (header byte 5 is 0) */
     size_t *lens;
+    double *bscale;      /* per-block deferred scale c_j (1.0 unless skipped) */
     double normsq, scale;
     int collapsed;
     double min_ratio, last_ratio;
@@ -730,14 +757,25 @@ static void normalize_block(double *x, size_t nscalar, double scale)
         x[i] = x[i] * scale;
 }
 
+/* Encode one block at level `level` only (no other level tried). */
+static int fixed_encode_obuf(obuf *out, const double *x, int b, int s,
+                             const double *ladder, int level)
+{
+    return encode_block_obuf(out, x, b, s, ladder[level], level) ? OR_ENOMEM : level;
+}
+
 /* Decompress, normalise, gateComputation and AALC-compress one group: the
  * body of Alg. 2 for the stride(s) a gate touches together.  A gate whose
  * pairs span two strides processes both strides of each coupled pair as one
- * group (reading of Alg. 1 for high qubits). */
-static int group_run(int n, int b, int s, const double *ladder, int L,
-                     double theta, double scale, const double *tdiff,
-                     const or_gate *g, uint64_t j0, const uint8_t *const *in,
-                     const size_t *inlen, obuf *out, int *levels)
+ * group (reading of Alg. 1 for high qubits).  fac[k] is the factor the
+ * decoded values of block k are multiplied by (the normalisation s, times
+ * the block's deferred scale when it has one); force[k] >= 0 encodes block k
+ * at that level instead of running the ladder (permutation shortcut). */
+static int group_run_f(int n, int b, int s, const double *ladder, int L,
+                       double theta, const double *fac, const int *force,
+                       const double *tdiff, const or_gate *g, uint64_t j0,
+                       const uint8_t *const *in, const size_t *inlen, obuf *out,
+                       int *levels)
 {
     (void)n;
     uint64_t mb = gate_mask(g) >> b;
@@ -755,14 +793,16 @@ static int group_run(int n, int b, int s, const double *ladder, int L,
             rc = OR_EINVAL;
             goto done;
         }
-        normalize_block(x[k], 2 * namp, scale);
+        normalize_block(x[k], 2 * namp, fac[k]);
     }
     {
         gview v = {{x[0], x[1]}, {j0, j0 ^ mb}, nb, b};
         gate_apply(g, &v, tdiff);
     }
     for (int k = 0; k < nb; k++) {
-        int lev = aalc_encode_obuf(&out[k], x[k], b, s, ladder, L, theta, NULL);
+        int lev = (force && force[k] >= 0)
+                      ? fixed_encode_obuf(&out[k], x[k], b, s, ladder, force[k])
+                      : aalc_encode_obuf(&out[k], x[k], b, s, ladder, L, theta, NULL);
         if (lev < 0) {
             rc = lev;
             goto done;
@@ -773,6 +813,16 @@ done:
     free(x[0]);
     free(x[1]);
     return rc;
+}
+
+static int group_run(int n, int b, int s, const double *ladder, int L,
+                     double theta, double scale, const double *tdiff,
+                     const or_gate *g, uint64_t j0, const uint8_t *const *in,
+                     const size_t *inlen, obuf *out, int *levels)
+{
+    const double fac[2] = {scale, scale};
+    return group_run_f(n, b, s, ladder, L, theta, fac, NULL, tdiff, g, j0, in,
+                       inlen, out, levels);
 }
 
 int or_process_group(int n, int b, int s, const double *ladder, int L,
@@ -820,13 +870,39 @@ static double stream_normsq(const uint8_t *p) { return rd_f64(p + 24); }
  * aligned subtrees of the tree over all 2^n amplitudes); s = 1/sqrt(N^2),
  * applied before the next gate (Sec. III: the state vector is normalised
  * before the gate computation). */
+/* Bytes of block j as exported: its stream, plus the 8-byte deferred scale
+ * when that is not 1. */
+static size_t export_len(const or_sim *sim, uint64_t j)
+{
+    return sim->lens[j] + (sim->bscale[j] != 1.0 ? 8 : 0);
+}
+
+/* Weight of block j in N^2: its normsq, times fl(c_j^2) when the block
+ * carries a deferred scale c_j != 1. */
+static double block_weight(const or_sim *sim, uint64_t j)
+{
+    const double ns = stream_normsq(sim->streams[j]);
+    const double c = sim->bscale[j];
+    if (c == 1.0)
+        return ns;
+    const double c2 = c * c;
+    return ns * c2;
+}
+
+/* Factor the decoded values of block j are multiplied by before the gate
+ * (and in every read-out): fl(c_j * s); s itself when c_j is 1. */
+static double block_factor(const or_sim *sim, uint64_t j)
+{
+    return sim->bscale[j] * sim->scale;
+}
+
 static void update_norm(or_sim *sim)
 {
     double *v = (double *)malloc(sim->nblocks * sizeof(double));
     uint64_t total = 0;
     for (uint64_t j = 0; j < sim->nblocks; j++) {
-        v[j] = stream_normsq(sim->streams[j]);
-        total += sim->lens[j];
+        v[j] = block_weight(sim, j);
+        total += export_len(sim, j);
     }
     sim->normsq = or_pairwise(v, sim->nblocks);
     free(v);
@@ -863,7 +939,8 @@ or_sim *or_create(int n, int b, int s, const double *ladder, int L,
     sim->nblocks = (uint64_t)1 << (n - b);
     sim->streams = (uint8_t **)calloc(sim->nblocks, sizeof(uint8_t *));
     sim->lens = (size_t *)calloc(sim->nblocks, sizeof(size_t));
-    if (!sim->streams || !sim->lens || or_set_basis(sim, 0)) {
+    sim->bscale = (double *)malloc(sim->nblocks * sizeof(double));
+    if (!sim->streams || !sim->lens || !sim->bscale || or_set_basis(sim, 0)) {
         or_destroy(sim);
         return NULL;
     }
@@ -879,6 +956,7 @@ void or_destroy(or_sim *sim)
             free(sim->streams[j]);
     free(sim->streams);
     free(sim->lens);
+    free(sim->bscale);
     free(sim);
 }
 
@@ -907,6 +985,7 @@ int or_set_basis(or_sim *sim, uint64_t x)
         free(sim->streams[j]);
         sim->streams[j] = o.p;
         sim->lens[j] = o.len;
+        sim->bscale[j] = 1.0;
     }
     free(blk);
     sim->collapsed = 0;
@@ -934,7 +1013,7 @@ int or_amplitude_sum(const or_sim *sim, double *S)
         rc = or_decode_block(sim->streams[j], sim->lens[j], x);
         if (rc)
             goto done;
-        normalize_block(x, 2 * namp, sim->scale);
+        normalize_block(x, 2 * namp, block_factor(sim, j));
         for (int c = 0; c < 2; c++) {
             for (size_t i = 0; i < namp; i++)
                 tmp[i] = x[2 * i + c];
@@ -952,9 +1031,74 @@ done:
     return rc;
 }
 
+/* Whether the gate leaves amplitude i as it is, by the structure of the
+ * gate alone (its kind and qubits, not its matrix entries): a diagonal or
+ * controlled gate acts only where its qubits are 1, PHASE_FLIP only at its
+ * index, SWAP only where its two bits differ. */
+static int leaves_unchanged(const or_gate *g, uint64_t i)
+{
+    switch (g->kind) {
+    case OR_G_DIAG1:
+        return !bit(i, g->q0);
+    case OR_G_CPHASE:
+    case OR_G_CZ:
+        return !(bit(i, g->q0) && bit(i, g->q1));
+    case OR_G_CU:
+        return !bit(i, g->q0);
+    case OR_G_PHASE_FLIP:
+        return i != g->index;
+    case OR_G_SWAP:
+        return bit(i, g->q0) == bit(i, g->q1);
+    default:
+        return 0;
+    }
+}
+
+/* A stride none of whose amplitudes the gate changes (Sec. V: such strides
+ * need not be compressed again). */
+static int block_untouched(const or_gate *g, int b, uint64_t j)
+{
+    const uint64_t per = (uint64_t)1 << b;
+    for (uint64_t li = 0; li < per; li++)
+        if (!leaves_unchanged(g, (j << b) | li))
+            return 0;
+    return 1;
+}
+
+/* Gates that only reorder amplitudes (Sec. V: X, CNOT; SWAP likewise): X,
+ * SWAP, and the controlled form of exactly [[0, 1], [1, 0]]. */
+static int is_permutation(const or_gate *g)
+{
+    if (g->kind == OR_G_X || g->kind == OR_G_SWAP)
+        return 1;
+    if (g->kind != OR_G_CU)
+        return 0;
+    static const double X[8] = {0.0, 0.0, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < 8; k++)
+        if (dbits(g->u[k]) != dbits(X[k]))
+            return 0;
+    return 1;
+}
+
+int or_set_shortcut(or_sim *sim, int flags)
+{
+    if (!sim || (flags & ~(OR_SC_PERMUTE | OR_SC_SKIP)))
+        return OR_EINVAL;
+    sim->shortcut = flags;
+    return OR_OK;
+}
+
 /* Alg. 2: for each gate, for each stride (group): decompress, normalize,
  * gateComputation, AALC compress.  Every block is re-encoded on every gate,
- * including blocks the gate leaves unchanged, as Alg. 1 states. */
+ * including blocks the gate leaves unchanged, as Alg. 1 states -- unless a
+ * shortcut of Sec. V is on:
+ *   OR_SC_PERMUTE: under a gate that only reorders amplitudes (X, SWAP,
+ *     CNOT) each block is compressed at the ladder level its own previous
+ *     stream used, without trying other levels;
+ *   OR_SC_SKIP: a block the gate leaves unchanged keeps its stream; its
+ *     normalisation is deferred into the block's scale c_j <- fl(c_j s), and
+ *     a block is decoded with the factor fl(c_j s) (c_j back to 1 once it is
+ *     compressed again). */
 int or_apply_gate(or_sim *sim, const or_gate *g)
 {
     if (!sim || !g || !gate_valid(g, sim->n))
@@ -968,47 +1112,87 @@ int or_apply_gate(or_sim *sim, const or_gate *g)
         for (int c = 0; c < 2; c++)
             t[c] = t[c] * ldexp(1.0, 1 - sim->n);
     }
+    const int perm = (sim->shortcut & OR_SC_PERMUTE) && is_permutation(g);
+    const int skip = (sim->shortcut & OR_SC_SKIP) != 0;
     uint64_t mb = gate_mask(g) >> sim->b;
     uint8_t **ns = (uint8_t **)calloc(sim->nblocks, sizeof(uint8_t *));
     size_t *nl = (size_t *)calloc(sim->nblocks, sizeof(size_t));
-    int hist[8] = {0};
+    uint8_t *lv = (uint8_t *)calloc(sim->nblocks, 1);
+    double *nc = (double *)malloc(sim->nblocks * sizeof(double));
     int rc = OR_OK;
-    if (!ns || !nl) {
+    if (!ns || !nl || !lv || !nc) {
         rc = OR_ENOMEM;
         goto fail;
     }
+    /* The groups are independent (each reads its own input streams and
+     * writes its own output streams), so they may run on several threads;
+     * the result does not depend on the order. */
+#pragma omp parallel for schedule(dynamic, 1)
     for (uint64_t j = 0; j < sim->nblocks; j++) {
         if (mb && (j ^ mb) < j)
             continue;
-        const uint8_t *in[2] = {sim->streams[j], mb ? sim->streams[j ^ mb] : NULL};
-        size_t inl[2] = {sim->lens[j], mb ? sim->lens[j ^ mb] : 0};
-        obuf out[2] = {{0}, {0}};
-        int lev[2] = {0, 0};
-        rc = group_run(sim->n, sim->b, sim->s, sim->ladder, sim->L, sim->theta,
-                       sim->scale, t, g, j, in, inl, out, lev);
-        if (rc) {
-            free(out[0].p);
-            free(out[1].p);
-            goto fail;
+        const int nbk = mb ? 2 : 1;
+        const uint64_t jj[2] = {j, j ^ mb};
+        int r = OR_OK;
+        if (skip && block_untouched(g, sim->b, jj[0]) &&
+            (nbk == 1 || block_untouched(g, sim->b, jj[1]))) {
+            for (int k = 0; k < nbk && !r; k++) {
+                const uint64_t q = jj[k];
+                uint8_t *cp = (uint8_t *)malloc(sim->lens[q]);
+                if (!cp) {
+                    r = OR_ENOMEM;
+                    break;
+                }
+                memcpy(cp, sim->streams[q], sim->lens[q]);
+                ns[q] = cp;
+                nl[q] = sim->lens[q];
+                lv[q] = sim->streams[q][4];
+                nc[q] = sim->bscale[q] * sim->scale;
+            }
+        } else {
+            const uint8_t *in[2] = {sim->streams[j], mb ? sim->streams[j ^ mb] : NULL};
+            size_t inl[2] = {sim->lens[j], mb ? sim->lens[j ^ mb] : 0};
+            const double fac[2] = {block_factor(sim, j), mb ? block_factor(sim, j ^ mb) : 1.0};
+            const int force[2] = {perm ? (int)sim->streams[j][4] : -1,
+                                  perm && mb ? (int)sim->streams[j ^ mb][4] : -1};
+            obuf out[2] = {{0}, {0}};
+            int lev[2] = {0, 0};
+            r = group_run_f(sim->n, sim->b, sim->s, sim->ladder, sim->L, sim->theta, fac,
+                            force, t, g, j, in, inl, out, lev);
+            if (r) {
+                free(out[0].p);
+                free(out[1].p);
+            } else {
+                for (int k = 0; k < nbk; k++) {
+                    ns[jj[k]] = out[k].p;
+                    nl[jj[k]] = out[k].len;
+                    lv[jj[k]] = (uint8_t)lev[k];
+                    nc[jj[k]] = 1.0;
+                }
+            }
         }
-        ns[j] = out[0].p;
-        nl[j] = out[0].len;
-        hist[lev[0]]++;
-        if (mb) {
-            ns[j ^ mb] = out[1].p;
-            nl[j ^ mb] = out[1].len;
-            hist[lev[1]]++;
+        if (r) {
+#pragma omp critical(or_rc)
+            rc = rc ? rc : r;
         }
     }
+    if (rc)
+        goto fail;
+    uint64_t hist[8] = {0};
+    for (uint64_t j = 0; j < sim->nblocks; j++)
+        hist[lv[j]]++;
     for (uint64_t j = 0; j < sim->nblocks; j++) {
         free(sim->streams[j]);
         sim->streams[j] = ns[j];
         sim->lens[j] = nl[j];
     }
+    memcpy(sim->bscale, nc, sim->nblocks * sizeof(double));
     free(ns);
     free(nl);
+    free(lv);
+    free(nc);
     for (int k = 0; k < 8; k++)
-        sim->level_hist[k] += (uint64_t)hist[k];
+        sim->level_hist[k] += hist[k];
     sim->passes++;
     update_norm(sim);
     return sim->collapsed ? OR_ECOLLAPSED : OR_OK;
@@ -1018,7 +1202,22 @@ fail:
             free(ns[j]);
     free(ns);
     free(nl);
+    free(lv);
+    free(nc);
     return rc;
+}
+
+int or_set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads < 1)
+        return OR_EINVAL;
+    omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
 }
 
 int or_get_amplitudes(const or_sim *sim, uint64_t first, uint64_t count,
@@ -1038,7 +1237,7 @@ int or_get_amplitudes(const or_sim *sim, uint64_t first, uint64_t count,
                 free(x);
                 return OR_EINVAL;
             }
-            normalize_block(x, 2 * namp, sim->scale);
+            normalize_block(x, 2 * namp, block_factor(sim, j));
             cur = j;
         }
         out[2 * k] = x[2 * (i & (namp - 1))];
@@ -1053,10 +1252,21 @@ int or_export_block(const or_sim *sim, uint64_t j, uint8_t *buf, size_t cap,
 {
     if (!sim || j >= sim->nblocks)
         return OR_EINVAL;
-    *len = sim->lens[j];
-    if (cap < sim->lens[j])
+    const size_t L = export_len(sim, j);
+    *len = L;
+    if (cap < L)
         return OR_ENOMEM;
-    memcpy(buf, sim->streams[j], sim->lens[j]);
+    if (L == sim->lens[j]) {
+        memcpy(buf, sim->streams[j], L);
+        return OR_OK;
+    }
+    /* a deferred scale: flag it in the header, place it after the header */
+    memcpy(buf, sim->streams[j], HDR_BYTES);
+    buf[5] |= OR_HDR_SCALED;
+    const uint32_t total = (uint32_t)L;
+    memcpy(buf + 12, &total, 4);
+    memcpy(buf + HDR_BYTES, &sim->bscale[j], 8);
+    memcpy(buf + HDR_BYTES + 8, sim->streams[j] + HDR_BYTES, sim->lens[j] - HDR_BYTES);
     return OR_OK;
 }
 
@@ -1089,9 +1299,10 @@ int or_import_state(or_sim *sim, const uint8_t *buf, size_t len)
         const uint8_t *h = buf + pos;
         uint32_t total = rd_u32(h + 12);
         int level = h[4];
-        if (rd_u32(h) != OR_MAGIC || h[5] != 0 || h[6] != sim->s || h[7] != sim->b ||
-            level >= sim->L || dbits(rd_f64(h + 16)) != dbits(sim->ladder[level]) ||
-            total < HDR_BYTES || total > len - pos)
+        if (rd_u32(h) != OR_MAGIC || (h[5] & ~OR_HDR_SCALED) || h[6] != sim->s ||
+            h[7] != sim->b || level >= sim->L ||
+            dbits(rd_f64(h + 16)) != dbits(sim->ladder[level]) || total < HDR_BYTES ||
+            total > len - pos)
             goto done;
         if (or_decode_block(h, total, x) != OR_OK)
             goto done;
@@ -1104,16 +1315,26 @@ int or_import_state(or_sim *sim, const uint8_t *buf, size_t len)
     if (pos != len)
         goto done;
     rc = OR_ENOMEM;
+    /* stored as plain streams, the deferred scales beside them */
     for (uint64_t j = 0; j < nb; j++) {
-        copies[j] = (uint8_t *)malloc(ln[j]);
+        const uint8_t *h = buf + off[j];
+        const size_t extra = (h[5] & OR_HDR_SCALED) ? 8 : 0;
+        copies[j] = (uint8_t *)malloc(ln[j] - extra);
         if (!copies[j])
             goto done;
-        memcpy(copies[j], buf + off[j], ln[j]);
+        memcpy(copies[j], h, HDR_BYTES);
+        copies[j][5] = 0;
+        const uint32_t plain = (uint32_t)(ln[j] - extra);
+        memcpy(copies[j] + 12, &plain, 4);
+        memcpy(copies[j] + HDR_BYTES, h + HDR_BYTES + extra, ln[j] - extra - HDR_BYTES);
     }
     for (uint64_t j = 0; j < nb; j++) {
+        const uint8_t *h = buf + off[j];
+        const size_t extra = (h[5] & OR_HDR_SCALED) ? 8 : 0;
         free(sim->streams[j]);
         sim->streams[j] = copies[j];
-        sim->lens[j] = ln[j];
+        sim->lens[j] = ln[j] - extra;
+        sim->bscale[j] = stream_scale(h, ln[j]);
         copies[j] = NULL;
     }
     sim->collapsed = 0;
@@ -1142,7 +1363,7 @@ int or_get_stats(const or_sim *sim, or_stats *st)
     st->scale = sim->scale;
     st->collapsed = sim->collapsed;
     for (uint64_t j = 0; j < sim->nblocks; j++)
-        st->resident_bytes += sim->lens[j];
+        st->resident_bytes += export_len(sim, j);
     st->min_ratio = sim->min_ratio;
     st->last_ratio = sim->last_ratio;
     st->passes = sim->passes;
@@ -1174,7 +1395,7 @@ int or_measure_probs(const or_sim *sim, const int *qubits, int nq,
             free(x);
             return OR_EINVAL;
         }
-        normalize_block(x, 2 * namp, sim->scale);
+        normalize_block(x, 2 * namp, block_factor(sim, j));
         for (size_t li = 0; li < namp; li++) {
             uint64_t i = (j << sim->b) | li;
             uint64_t o = 0;

@@ -146,6 +146,26 @@ int or_process_group(int n, int b, int s, const double *ladder, int L,
                      uint8_t *out0, size_t cap0, size_t *olen0, uint8_t *out1,
                      size_t cap1, size_t *olen1);
 
+/* Shortcuts of the paper's Sec. V (off by default: Alg. 2 as written).
+ *   OR_SC_PERMUTE: a gate that only reorders amplitudes (X, SWAP, and CU
+ *     whose matrix is exactly [[0, 1], [1, 0]], i.e. CNOT) compresses each
+ *     block at the ladder level its previous stream used, trying no other.
+ *   OR_SC_SKIP: a block whose amplitudes the gate leaves unchanged (by the
+ *     gate's structure: a diagonal or controlled gate whose qubit at or
+ *     above b is 0 in the block index, PHASE_FLIP away from its index, SWAP
+ *     where both bits are equal) keeps its stream; the normalisation s of
+ *     that pass is deferred into the block's scale, c_j <- fl(c_j s).  A
+ *     block is decoded with the factor fl(c_j s) (s when c_j = 1), its weight
+ *     in N^2 is fl(normsq_j fl(c_j c_j)), and c_j returns to 1 when the block
+ *     is compressed again.  An exported stream with c_j != 1 sets bit 0 of
+ *     header byte 5 and carries c_j as an f64 right after the header. */
+enum { OR_SC_PERMUTE = 1, OR_SC_SKIP = 2 };
+int or_set_shortcut(or_sim *sim, int flags);
+
+/* Threads for the block groups of a pass (OpenMP); returns the number in
+ * effect (1 when built without OpenMP).  Results do not depend on it. */
+int or_set_threads(int nthreads);
+
 /* Fidelity |<a|b>|^2 / (<a|a><b|b>) of two 2^n complex arrays. */
 double or_fidelity(const double *a, const double *b, int n);
 

@@ -18,7 +18,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-          "-shared", "-fPIC"]
+          "-fopenmp", "-shared", "-fPIC"]
 
 
 def build(force=False):
@@ -91,7 +91,15 @@ def lib():
         L.or_fidelity.argtypes = [dp, dp, ctypes.c_int]
         L.or_amplitude_sum.argtypes = [ctypes.c_void_p, dp]
         L.or_import_state.argtypes = [ctypes.c_void_p, u8p, ctypes.c_size_t]
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_set_shortcut.argtypes = [ctypes.c_void_p, ctypes.c_int]
     return _lib
+
+
+def set_threads(nthreads):
+    """Threads for the block groups of each pass; returns the number in
+    effect.  Every result is the same for any thread count."""
+    return lib().or_set_threads(int(nthreads))
 
 
 def _dp(a):
@@ -193,6 +201,13 @@ def sv_run(n, gates, basis=0):
     return amp[0::2] + 1j * amp[1::2]
 
 
+def sv_run_from(psi, n, gate):
+    """One plain uncompressed gate applied to a copy of complex vector psi."""
+    amp = _as_complex_interleaved(np.asarray(psi, dtype=np.complex128)).copy()
+    sv_apply(amp, n, gate)
+    return amp[0::2] + 1j * amp[1::2]
+
+
 def fidelity(a, b, n):
     ai = _as_complex_interleaved(a)
     bi = _as_complex_interleaved(b)
@@ -231,6 +246,16 @@ class OracleSim:
         except Exception:
             pass
 
+    SC_PERMUTE, SC_SKIP = 1, 2
+
+    def set_shortcut(self, flags):
+        """Sec. V shortcuts: SC_PERMUTE (permutation gates keep each block's
+        previous level), SC_SKIP (blocks a gate leaves unchanged keep their
+        streams, normalisation deferred into a per-block scale)."""
+        rc = lib().or_set_shortcut(self.h, int(flags))
+        if rc:
+            raise ValueError("or_set_shortcut rc=%d" % rc)
+
     def set_basis(self, x):
         rc = lib().or_set_basis(self.h, x)
         if rc:
@@ -258,7 +283,7 @@ class OracleSim:
         return out[0::2] + 1j * out[1::2]
 
     def export_block(self, j):
-        cap = 64 + (48 << self.b) * 2
+        cap = 72 + (48 << self.b) * 2
         out = np.zeros(cap, dtype=np.uint8)
         n = ctypes.c_size_t(0)
         rc = lib().or_export_block(self.h, j, _u8p(out), cap, ctypes.byref(n))

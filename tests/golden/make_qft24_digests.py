@@ -1,0 +1,72 @@
+"""Write tests/golden/qft24_digests.json from the CPU oracle alone.
+
+For the 24-qubit QFT workload (blocks of 2^16, seeded random basis state),
+for each listed (error bound, theta) with the default ladder, the oracle runs
+Alg. 2 gate by gate; after the basis encode and after every gate it records
+the SHA-256 of the whole state (every block stream, block 0 first), N^2 and
+the level histogram.  The GPU parity test compares its own streams with these
+digests after every gate.  Only oracle/ and the seeded input generator are
+used.  Run: python tests/golden/make_qft24_digests.py  (about a minute per
+configuration on 8 cores).
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as orc  # noqa: E402
+from paper_1811_05140_amd import inputs as I  # noqa: E402
+
+CONFIGS = [(1e-4, 4.0), (1e-3, 16.0), (1e-5, 16.0)]
+OUT = os.path.join(HERE, "qft24_digests.json")
+
+
+def run(delta, theta):
+    w = I.qft24_workload()
+    n, b = w["n"], w["b"]
+    lad = I.default_ladder(delta)
+    sim = orc.OracleSim(n, b, lad, theta)
+    sim.set_basis(w["basis"])
+    digests, normsq, hist = [], [], []
+
+    def record():
+        digests.append(hashlib.sha256(sim.export_state()).hexdigest())
+        st = sim.stats()
+        normsq.append(st["normsq"].hex())
+        hist.append(st["level_hist"][:len(lad)])
+
+    record()
+    for g in w["gates"]:
+        rc = sim.apply(g)
+        if rc not in (0, -5):
+            raise RuntimeError("oracle rc %d" % rc)
+        record()
+    return {"n": n, "b": b, "basis": w["basis"], "delta": delta, "theta": theta,
+            "ladder": lad, "gates": len(w["gates"]),
+            "sha256_after_gate": digests, "normsq_after_gate": normsq,
+            "level_hist_after_gate": hist}
+
+
+def main():
+    orc.set_threads(os.cpu_count() or 1)
+    out = {"what": "SHA-256 of the concatenated block streams of the 24-qubit "
+                   "QFT workload after the basis encode (entry 0) and after "
+                   "each gate (entry k), from the CPU oracle",
+           "configs": []}
+    for delta, theta in CONFIGS:
+        t0 = time.time()
+        out["configs"].append(run(delta, theta))
+        print("delta %g theta %g: %.1f s" % (delta, theta, time.time() - t0), flush=True)
+    with open(OUT, "w") as f:
+        json.dump(out, f, indent=0)
+        f.write("\n")
+    print(OUT)
+
+
+if __name__ == "__main__":
+    main()

@@ -569,3 +569,119 @@ def test_quantiser_code_range_edge():
     assert struct.unpack_from("<IIdIId", st, o) == (0, 0, -xa, 1, 0, xa)
     xh = orc.decode_block(st)
     assert list(xh.real[:4]) == [-xa, xa, 2.0 ** 29 - 1, -(2.0 ** 29 - 1)]
+
+
+# ------------------------------------------- outcome probabilities (Sec. II) --
+
+def test_measure_probs_basis_state_nonmonotone_qubits():
+    """|x> has all probability on one outcome: bit k of o is bit qubits[k] of
+    x.  Qubits listed out of order (5, 0, 3, 7) with bits 0, 5 and 6 of x set
+    give o = 0b0011 = 3; the sorted list (0, 3, 5, 7) would spell 5 and the
+    reversed list (7, 3, 0, 5) 12, so only the stated mapping passes."""
+    n = 8
+    x = (1 << 0) | (1 << 5) | (1 << 6)
+    qubits = [5, 0, 3, 7]
+    o_want = sum(((x >> q) & 1) << k for k, q in enumerate(qubits))
+    assert o_want == 0b0011
+    assert sum(((x >> q) & 1) << k for k, q in enumerate(sorted(qubits))) == 5
+    assert sum(((x >> q) & 1) << k for k, q in enumerate(qubits[::-1])) == 12
+    sim = orc.OracleSim(n, 6, I.default_ladder(1e-4), theta=4.0)
+    sim.set_basis(x)
+    p = sim.measure_probs(qubits)
+    want = np.zeros(16)
+    want[o_want] = 1.0
+    assert np.array_equal(p, want)
+
+
+def test_measure_probs_hand_computed_product_state():
+    """Real rotations R(a) = [[cos a, -sin a], [sin a, cos a]] on qubits 1, 4
+    and 2 of |0>: a product state, so P(o) is the product over listed qubits
+    of cos^2 (bit 0) or sin^2 (bit 1) of that qubit's angle; qubit 6 is
+    untouched (always 0).  Listed as (4, 6, 1, 2)."""
+    n = 7
+    ang = {1: 0.3, 4: 1.1, 2: 2.0}
+    gates = []
+    for q, a in ang.items():
+        c, s_ = math.cos(a), math.sin(a)
+        gates.append(I.u_gate(q, (c, 0.0, -s_, 0.0, s_, 0.0, c, 0.0)))
+    qubits = [4, 6, 1, 2]
+    sim = orc.OracleSim(n, 6, [0.0], theta=4.0)
+    sim.run(gates)
+    p = sim.measure_probs(qubits)
+    want = np.zeros(16)
+    for o in range(16):
+        v = 1.0
+        for k, q in enumerate(qubits):
+            bit = (o >> k) & 1
+            if q not in ang:
+                v *= 0.0 if bit else 1.0
+            else:
+                v *= math.sin(ang[q]) ** 2 if bit else math.cos(ang[q]) ** 2
+        want[o] = v
+    assert np.max(np.abs(p - want)) < 1e-14
+    # the mapping has teeth: P is far from uniform and not symmetric under
+    # reversing the qubit list
+    assert np.max(np.abs(p - want.reshape(2, 2, 2, 2).transpose().reshape(-1))) > 0.05
+
+
+def test_measure_probs_two_qubit_entangled_by_hand():
+    """R(a) on qubit 3, then CNOT (controlled X) from 3 to 0: amplitudes
+    cos a at |0> and sin a at |1001>.  Listing (0, 5, 3): outcomes 0b000 with
+    cos^2 a and 0b101 with sin^2 a, nothing else."""
+    a = 0.4
+    c, s_ = math.cos(a), math.sin(a)
+    sim = orc.OracleSim(6, 6, [0.0], theta=4.0)
+    sim.run([I.u_gate(3, (c, 0.0, -s_, 0.0, s_, 0.0, c, 0.0)),
+             I.cu(3, 0, (0.0, 0.0, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0))])
+    p = sim.measure_probs([0, 5, 3])
+    want = np.zeros(8)
+    want[0b000] = c * c
+    want[0b101] = s_ * s_
+    assert np.max(np.abs(p - want)) < 1e-15
+
+
+# ------------------------ normalisation before the gate (Sec. III, Alg. 2) --
+
+def lossless_one_value_plane(vals):
+    """Hand encoding (block stream v1) of one lossless 64-scalar plane whose
+    nonzero entries are `vals` = {index: value}: q_i = bits(x_i), c_0 = 0,
+    c_i = q_i - q_{i-1} mod 2^64, z = zigzag(c), one chunk of width
+    max bitlen(z), field l at bits [l w, l w + w)."""
+    q = [bits(vals.get(i, 0.0)) for i in range(64)]
+    z = [0] + [(((q[i] - q[i - 1]) & (2 ** 64 - 1)) << 1 ^
+                (2 ** 64 - 1 if (q[i] - q[i - 1]) & (2 ** 64 - 1) >= 2 ** 63 else 0))
+               & (2 ** 64 - 1) for i in range(1, 64)]
+    w = max(v.bit_length() for v in z)
+    stream = 0
+    for l, v in enumerate(z):
+        stream |= v << (l * w)
+    words = [(stream >> (64 * k)) & (2 ** 64 - 1) for k in range(w)]
+    anchor = struct.unpack("<q", struct.pack("<Q", q[0]))[0]
+    return plane(anchor, w, 0, bytes([w]) if w else b"", words if w else ())
+
+
+def test_normalise_before_gate_hand_derived_stream():
+    """A stored, unnormalised state with one amplitude 7.0 (n = b = s = 6,
+    lossless ladder): N^2 = 49, s = fl(1/fl(sqrt 49)) = fl(1/7).  Alg. 2
+    normalises before the gate: x = fl(7 s) = 1.0 exactly, then H on qubit 0
+    gives y = fl(h * 1.0) = h at indices 0 and 1 (h = fl(sqrt(1/2))).  Gating
+    first and scaling after would give fl(fl(7 h) s) = h - 1 ulp, and skipping
+    the normalisation fl(7 h): the stream pins the order."""
+    h = math.sqrt(0.5)
+    s = 1.0 / math.sqrt(49.0)
+    y = h * (7.0 * s)
+    assert y == h and (h * 7.0) * s != y
+    zero = plane(0, 0, 0)
+    re_in = lossless_one_value_plane({0: 7.0})
+    inp = hdr(0, 6, 6, 0, 32 + len(re_in) + len(zero), 0.0, 49.0) + re_in + zero
+    re_out = lossless_one_value_plane({0: y, 1: y})
+    ns = (y * y) + (y * y)  # pairwise over [y^2, y^2, 0, ...]
+    want = hdr(0, 6, 6, 0, 32 + len(re_out) + len(zero), 0.0, ns) + re_out + zero
+    wrong = lossless_one_value_plane({0: (h * 7.0) * s, 1: (h * 7.0) * s})
+    assert wrong != re_out
+    sim = orc.OracleSim(6, 6, [0.0], theta=4.0)
+    assert sim.import_state(inp) == 0
+    st = sim.stats()
+    assert st["normsq"] == 49.0 and st["scale"] == s
+    sim.apply(I.h(0))
+    assert sim.export_block(0) == want
