@@ -279,15 +279,14 @@ class GpuExecutor:
 
 
 def signature(sim, r):
-    """Bytes that pin a final state: the first and last block streams, N^2,
-    the scale and the resident bytes (compared between a request run in the
-    mix and alone, and across an eviction; the level histogram and replay
-    counts are history since the state was set or imported, not state)."""
+    """Bytes that pin a final state: every block stream (the whole-state
+    export, block 0 first), N^2, the scale and the resident bytes (compared
+    between a request run in the mix and alone, and across an eviction; the
+    level histogram and replay counts are history since the state was set
+    or imported, not state)."""
     import hashlib
-    nb = 1 << (r.n - sim.b)
     h = hashlib.sha256()
-    h.update(sim.export_block(0))
-    h.update(sim.export_block(nb - 1))
+    h.update(sim.export_state())
     st = sim.stats()
     h.update(repr((st["normsq"], st["scale"], st["resident_bytes"])).encode())
     return h.hexdigest()
