@@ -129,6 +129,17 @@ int sim_apply_gates(sim_t *sim, const sim_gate_t *gates, size_t count);
  * probs is host memory of 2^nq doubles.  Synchronises. */
 int sim_measure_probs(sim_t *sim, const int *qubits, int nq, double *probs);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as sim_measure_probs with no device allocation and no free.  The
+ * outcome bins and the qubit list live in one array that the library holds
+ * on each GPU until the process ends (2^16 doubles + 256 bytes), so nq is
+ * limited to 1..16 (SIM_EINVAL above that).  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (sims on different streams,
+ * several host threads) race and must be serialised by the caller.  Host
+ * memory probs (2^nq doubles) is the caller's.  Synchronises. */
+int sim_measure_probs_noalloc(sim_t *sim, const int *qubits, int nq, double *probs);
+
 /* Fidelity of two states with the same n (Sec. II, with the modulus squared
  * and both norms divided out): F = |<a|b>|^2 / (<a|a><b|b>).  Either sim may
  * be compressed or uncompressed.  Synchronises. */

@@ -28,6 +28,7 @@ EXPORTS = [
     "sim_batch_create", "sim_batch_destroy", "sim_batch_apply", "sim_batch_sync",
     "sim_batch_info", "sim_set_grid", "sim_batch_profile", "sim_batch_profile_read",
     "sim_fourier_overlap", "sim_export_state", "sim_import_state",
+    "sim_measure_probs_noalloc",
 ]
 
 
@@ -87,6 +88,7 @@ def _load():
     L.sim_apply_gate.argtypes = [vp, P(Gate)]
     L.sim_apply_gates.argtypes = [vp, P(Gate), ctypes.c_size_t]
     L.sim_measure_probs.argtypes = [vp, P(ctypes.c_int), ctypes.c_int, dp]
+    L.sim_measure_probs_noalloc.argtypes = [vp, P(ctypes.c_int), ctypes.c_int, dp]
     L.sim_fidelity.argtypes = [vp, vp, dp]
     L.sim_set_basis.argtypes = [vp, ctypes.c_uint64]
     L.sim_set_aalc.argtypes = [vp, dp, ctypes.c_int, ctypes.c_double]
@@ -257,6 +259,14 @@ class Sim:
         q = (ctypes.c_int * len(qubits))(*qubits)
         out = np.zeros(1 << len(qubits), dtype=np.float64)
         check(lib.sim_measure_probs(self.h, q, len(qubits), _dp(out)), True)
+        return out
+
+    def probs_noalloc(self, qubits):
+        """As probs, through the entry point that allocates no device memory
+        (bins in a library-held array per GPU; at most 16 qubits)."""
+        q = (ctypes.c_int * len(qubits))(*qubits)
+        out = np.zeros(1 << len(qubits), dtype=np.float64)
+        check(lib.sim_measure_probs_noalloc(self.h, q, len(qubits), _dp(out)), True)
         return out
 
     def fidelity(self, other):

@@ -206,6 +206,16 @@ void launch_batch_pass(const BatchLaunch &b, hipStream_t st, Prof *prof);
 // Arena chunk a workgroup takes per bump-pointer update.
 uint64_t batch_chunk_bytes(uint64_t arena_cap, unsigned grid);
 
+// Allocation-free marginals: the library-held device array (bins of up to
+// 2^kNoAllocMaxQ outcomes, then the qubit list) of the current GPU, and a
+// fill kernel that clears it (a kernel, so that a captured graph holds no
+// memset node).
+constexpr int kNoAllocMaxQ = 16;
+constexpr uint64_t kNoAllocBinBytes = 8ull << kNoAllocMaxQ;
+constexpr uint64_t kNoAllocBytes = kNoAllocBinBytes + 256;
+hipError_t noalloc_scratch(int device, void **ptr);
+void launch_zero_f64(double *p, uint64_t count, hipStream_t st);
+
 // Uncompressed path (sv.hip).
 void sv_set_basis(double *amp, int n, uint64_t x, hipStream_t st);
 void sv_apply(double *amp, int n, const GateArg &g, double *scratch,

@@ -42,6 +42,8 @@
 // definitions fix, so codes and streams match the CPU reference bit for bit.
 #pragma clang fp contract(off)
 
+#include <mutex>
+
 #include "device.h"
 #include "gates.h"
 
@@ -3484,6 +3486,61 @@ void launch_export_headers(const PassArgs &a, uint64_t first, uint64_t count, ui
 {
     hipLaunchKernelGGL(k_export_headers, dim3(grid_for(count)), dim3(kWG), 0, st, a, first,
                        count, out);
+}
+
+
+// ------------------------------------------- allocation-free marginals ----
+//
+// sim_measure_probs_noalloc runs the probability kernels with their outcome
+// bins and qubit list in this file-scope array instead of device memory
+// allocated per call.  Each GPU holds its own copy until the process ends.
+// In host code the array's name is only a stand-in: its device address on
+// the current GPU comes from hipGetSymbolAddress, taken once per device and
+// kept in g_noalloc_ptr; kernels, fills and copies use that address.  Every
+// call on one GPU shares the array, so calls that overlap on one GPU race.
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoAllocDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void **ptr)
+{
+    *ptr = nullptr;
+    if (device < 0 || device >= kNoAllocDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess)
+            return e;
+        if (cur != device)
+            return hipErrorInvalidDevice;  // the caller makes `device` current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_noalloc_ptr[device] = p;
+    }
+    *ptr = g_noalloc_ptr[device];
+    return hipSuccess;
+}
+
+__global__ void k_zero_f64(double *p, uint64_t count)
+{
+    for (uint64_t k = blockIdx.x * (uint64_t)kWG + threadIdx.x; k < count;
+         k += (uint64_t)gridDim.x * kWG)
+        p[k] = 0.0;
+}
+
+void launch_zero_f64(double *p, uint64_t count, hipStream_t st)
+{
+    const uint64_t g = (count + kWG - 1) / kWG;
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(g < 1024 ? g : 1024)), dim3(kWG), 0, st, p,
+                       count);
 }
 
 }  // namespace aalc

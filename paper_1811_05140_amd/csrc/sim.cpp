@@ -107,6 +107,7 @@ struct EventProf final : Prof {
 
 struct sim {
     int n = 0, b = 0, s = 0;
+    int device = 0;  // the GPU current when the sim was created
     bool compressed = true;
     int normalize = 1;
     Ladder lad{};
@@ -456,6 +457,11 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
     S->compressed = compressed;
     S->b = block_log2 > n ? n : block_log2;
     S->s = S->b < kMaxS ? S->b : kMaxS;
+    if (hipGetDevice(&S->device) != hipSuccess) {
+        fail(SIM_EDEVICE, "hipGetDevice failed");
+        delete S;
+        return nullptr;
+    }
     if (stream) {
         S->stream = (hipStream_t)stream;
     } else {
@@ -1012,12 +1018,16 @@ int sim_set_stream(sim_t *S, void *hip_stream)
     return SIM_OK;
 }
 
-int sim_measure_probs(sim_t *S, const int *qubits, int nq, double *probs)
+}  // extern "C"
+
+namespace {
+
+int probs_args_ok(const sim *S, const int *qubits, int nq, const double *probs, int max_nq)
 {
     if (!S || !qubits || !probs)
         return fail(SIM_EINVAL, "NULL argument");
-    if (nq < 1 || nq > 24)
-        return fail(SIM_EINVAL, "nq %d out of range", nq);
+    if (nq < 1 || nq > max_nq)
+        return fail(SIM_EINVAL, "nq %d out of range [1, %d]", nq, max_nq);
     for (int k = 0; k < nq; ++k) {
         if (qubits[k] < 0 || qubits[k] >= S->n)
             return fail(SIM_EINVAL, "qubit %d out of range", qubits[k]);
@@ -1025,21 +1035,20 @@ int sim_measure_probs(sim_t *S, const int *qubits, int nq, double *probs)
             if (qubits[m] == qubits[k])
                 return fail(SIM_EINVAL, "qubit %d listed twice", qubits[k]);
     }
-    int rc = S->compressed ? sync_state(S) : SIM_OK;
-    if (rc && rc != SIM_ECOLLAPSED)
-        return rc;
-    int *dq = nullptr;
-    double *dp = nullptr;
+    return SIM_OK;
+}
+
+// The marginal probabilities with bins dp (2^nq doubles) and qubit list dq
+// (nq ints) in device memory the caller provides; dp is cleared here.
+hipError_t probs_into(sim *S, int *dq, double *dp, const int *qubits, int nq, double *probs)
+{
     const size_t nb = (size_t)1 << nq;
-    HIPCHK(hipMalloc((void **)&dq, sizeof(int) * nq));
-    if (hipMalloc((void **)&dp, 8 * nb) != hipSuccess) {
-        (void)hipFree(dq);
-        return fail(SIM_ENOMEM, "probability buffer");
-    }
     hipError_t e = hipMemcpyAsync(dq, qubits, sizeof(int) * nq, hipMemcpyHostToDevice,
                                   S->stream);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(dp, 0, 8 * nb, S->stream);
+    if (e == hipSuccess) {
+        launch_zero_f64(dp, nb, S->stream);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) {
         if (S->compressed)
             launch_probs(make_args(S, S->cur, 1 - S->cur, GateArg{}), dq, nq, dp, S->stream);
@@ -1051,10 +1060,62 @@ int sim_measure_probs(sim_t *S, const int *qubits, int nq, double *probs)
         e = hipMemcpyAsync(probs, dp, 8 * nb, hipMemcpyDeviceToHost, S->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(S->stream);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_measure_probs(sim_t *S, const int *qubits, int nq, double *probs)
+{
+    int rc = probs_args_ok(S, qubits, nq, probs, 24);
+    if (rc)
+        return rc;
+    rc = S->compressed ? sync_state(S) : SIM_OK;
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    int *dq = nullptr;
+    double *dp = nullptr;
+    const size_t nb = (size_t)1 << nq;
+    HIPCHK(hipMalloc((void **)&dq, sizeof(int) * nq));
+    if (hipMalloc((void **)&dp, 8 * nb) != hipSuccess) {
+        (void)hipFree(dq);
+        return fail(SIM_ENOMEM, "probability buffer");
+    }
+    hipError_t e = probs_into(S, dq, dp, qubits, nq, probs);
     (void)hipFree(dq);
     (void)hipFree(dp);
     if (e != hipSuccess)
         return fail(SIM_EDEVICE, "measure: %s", hipGetErrorString(e));
+    return rc;
+}
+
+int sim_measure_probs_noalloc(sim_t *S, const int *qubits, int nq, double *probs)
+{
+    int rc = probs_args_ok(S, qubits, nq, probs, kNoAllocMaxQ);
+    if (rc)
+        return rc;
+    rc = S->compressed ? sync_state(S) : SIM_OK;
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    // the library-held array of the sim's GPU (its address is looked up on
+    // the first call on that GPU, with that GPU current)
+    int prev = -1;
+    HIPCHK(hipGetDevice(&prev));
+    if (prev != S->device)
+        HIPCHK(hipSetDevice(S->device));
+    void *base = nullptr;
+    hipError_t e = noalloc_scratch(S->device, &base);
+    if (e == hipSuccess) {
+        double *dp = (double *)base;
+        int *dq = (int *)((uint8_t *)base + kNoAllocBinBytes);
+        e = probs_into(S, dq, dp, qubits, nq, probs);
+    }
+    if (prev != S->device)
+        (void)hipSetDevice(prev);
+    if (e != hipSuccess)
+        return fail(SIM_EDEVICE, "measure (no allocation): %s", hipGetErrorString(e));
     return rc;
 }
 
