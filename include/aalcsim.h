@@ -14,7 +14,10 @@
  *   - Qubit q is bit q of the amplitude index.
  *   - Pointers named host_* or documented as host are host memory, borrowed
  *     for the duration of the call only.  Device memory is owned by the
- *     sim and released by sim_destroy.
+ *     sim and released by sim_destroy: either allocated by the library
+ *     (sim_create, sim_create_ex) or carved from a caller-owned device
+ *     buffer (sim_context_create + sim_create_in), in which case the sim
+ *     and every call on it allocate no device memory of their own.
  *   - Calls on one sim are ordered on that sim's HIP stream.  sim_apply_gate
  *     is asynchronous; every call that returns data to the host synchronises
  *     the stream first.  A sim is not thread-safe; different sims are
@@ -43,7 +46,7 @@ enum {
     SIM_OK = 0,
     SIM_EINVAL = -1,        /* bad argument */
     SIM_ENOMEM = -2,        /* device allocation or arena capacity exhausted */
-    SIM_EBUDGET = -3,       /* reserved for budgeted contexts */
+    SIM_EBUDGET = -3,       /* the sim's memory context cannot hold a request */
     SIM_EDEVICE = -4,       /* HIP runtime error */
     SIM_ECOLLAPSED = -5,    /* N^2 of the stored state was 0 or not finite */
     SIM_EUNSUPPORTED = -6   /* valid request that the library does not implement */
@@ -114,6 +117,39 @@ sim_t *sim_create_ex(int n_qubits, int block_log2, double error_bound,
 
 void sim_destroy(sim_t *sim);
 
+/* Memory contexts: device memory that the caller owns (for example the
+ * storage of a torch tensor), from which sims created in the context take
+ * all of their device memory -- arenas, descriptors, size tables, staging,
+ * reduction buffers and the temporaries of queries.  The sim path itself
+ * then calls no hipMalloc.  Nothing else of the method changes.  */
+typedef struct sim_ctx sim_ctx_t;
+
+/* Wrap dev_buf (device memory of the current GPU, >= 4096 bytes, owned by
+ * the caller and kept alive until sim_context_destroy) as a context.  Sims
+ * created in it use hip_stream (NULL: each creates its own stream).  The
+ * buffer is carved first fit in 256-byte aligned ranges; ranges freed by
+ * sim_destroy are reused.  SIM_EINVAL if dev_buf is not device memory.  A
+ * context is not thread-safe: create and destroy its sims from one thread. */
+int sim_context_create(void *dev_buf, size_t bytes, void *hip_stream, sim_ctx_t **ctx);
+
+/* Release the context (not the buffer).  SIM_EINVAL while sims created in it
+ * are alive. */
+int sim_context_destroy(sim_ctx_t *ctx);
+
+/* Bytes of the context: usable capacity, in use, peak in use, and the
+ * largest free range (any pointer may be NULL). */
+int sim_context_info(const sim_ctx_t *ctx, uint64_t *capacity, uint64_t *used,
+                     uint64_t *peak, uint64_t *largest_free);
+
+/* As sim_create_ex, with all device memory taken from ctx (on its GPU, on
+ * its stream).  Returns SIM_OK and *out, or SIM_EBUDGET when the context
+ * cannot hold the sim (nothing is kept), or another SIM_E* code.  Later
+ * calls on the sim that need device memory (a longer ladder, a larger grid,
+ * whole-state export and import, queries) take it from the context too and
+ * return SIM_EBUDGET when it is exhausted, with the state unchanged. */
+int sim_create_in(sim_ctx_t *ctx, int n_qubits, int block_log2, double error_bound,
+                  uint64_t arena_bytes, sim_t **out);
+
 /* Apply one gate (Alg. 2 for every block).  Asynchronous on the sim stream;
  * the gate record is copied.  Returns SIM_EINVAL for an invalid gate (qubit
  * out of range, equal qubits, index >= 2^n, unknown kind, pad != 0). */
@@ -122,6 +158,29 @@ int sim_apply_gate(sim_t *sim, const sim_gate_t *gate);
 /* Apply `count` gates in order (same contract as sim_apply_gate; stops at
  * the first invalid gate, whose position is in sim_last_error()). */
 int sim_apply_gates(sim_t *sim, const sim_gate_t *gates, size_t count);
+
+/* Shortcuts of Sec. V (off by default, where every gate runs Alg. 2 on
+ * every block):
+ *   SIM_SC_PERMUTE: under a gate that only reorders amplitudes (X, SWAP, and
+ *     CU whose matrix is exactly [[0, 1], [1, 0]], i.e. CNOT) each block is
+ *     compressed at the ladder level its previous stream used; no other
+ *     level is tried.
+ *   SIM_SC_SKIP: a block that the gate leaves unchanged by its structure (a
+ *     diagonal or controlled gate whose qubit at or above block_log2 is 0 in
+ *     the block's index, PHASE_FLIP away from its index, SWAP of two such
+ *     qubits that are equal there) keeps its stream; the pass's
+ *     normalisation s is deferred into the block's scale, c_j <- fl(c_j s).
+ *     A block is decoded with the factor fl(c_j s), weighs fl(normsq_j
+ *     fl(c_j c_j)) in N^2 when c_j != 1, and returns to c_j = 1 when it is
+ *     compressed again.  Exported streams of blocks with c_j != 1 set bit 0
+ *     of header byte 5 and carry c_j as an f64 right after the header
+ *     (counted in total_bytes); sim_import_state accepts them.
+ * Both change which streams are produced (the results differ from Alg. 2's
+ * where a skipped block would have been re-encoded at another level), so
+ * they are opt-in.  Flags take effect from the next gate.  SIM_EINVAL for
+ * unknown flags, SIM_EUNSUPPORTED on the uncompressed path. */
+enum { SIM_SC_PERMUTE = 1, SIM_SC_SKIP = 2 };
+int sim_set_shortcut(sim_t *sim, int flags);
 
 /* Probabilities of every outcome of `qubits` (nq distinct qubits, 1..24):
  * probs[o] = sum over indices whose listed bits spell o (bit k of o is

@@ -29,6 +29,8 @@ EXPORTS = [
     "sim_batch_info", "sim_set_grid", "sim_batch_profile", "sim_batch_profile_read",
     "sim_fourier_overlap", "sim_export_state", "sim_import_state",
     "sim_measure_probs_noalloc",
+    "sim_context_create", "sim_context_destroy", "sim_context_info", "sim_create_in",
+    "sim_set_shortcut",
 ]
 
 
@@ -70,6 +72,14 @@ class Stats(ctypes.Structure):
 
 
 def _load():
+    # PyTorch bundles its own HIP runtime under the same soname as the one the
+    # library links; loading torch first makes both use that one runtime, so
+    # torch streams and device buffers are valid handles for the library
+    # (the other order leaves torch unable to initialise the GPU).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             "libaalcsim.so is not built (run `python -c 'import __graft_entry__ as g; "
@@ -93,6 +103,7 @@ def _load():
     L.sim_set_basis.argtypes = [vp, ctypes.c_uint64]
     L.sim_set_aalc.argtypes = [vp, dp, ctypes.c_int, ctypes.c_double]
     L.sim_set_normalize.argtypes = [vp, ctypes.c_int]
+    L.sim_set_shortcut.argtypes = [vp, ctypes.c_int]
     L.sim_get_amplitudes.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, dp]
     L.sim_export_block.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t,
                                    P(ctypes.c_size_t)]
@@ -120,6 +131,11 @@ def _load():
     L.sim_batch_info.argtypes = [vp, P(ctypes.c_uint64), P(ctypes.c_uint64)]
     L.sim_batch_profile.argtypes = [vp, ctypes.c_int]
     L.sim_batch_profile_read.argtypes = [vp, P(KernelTime), ctypes.c_int, P(ctypes.c_int)]
+    L.sim_context_create.argtypes = [vp, ctypes.c_size_t, vp, P(vp)]
+    L.sim_context_destroy.argtypes = [vp]
+    L.sim_context_info.argtypes = [vp] + [P(ctypes.c_uint64)] * 4
+    L.sim_create_in.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                ctypes.c_uint64, P(vp)]
     L.sim_last_error.restype = ctypes.c_char_p
     L.sim_last_error.argtypes = []
     return L
@@ -179,10 +195,17 @@ class Sim:
     """
 
     def __init__(self, n, block_log2, error_bound, arena_bytes=0, stream=None,
-                 ladder=None, theta=None, normalize=True):
+                 ladder=None, theta=None, normalize=True, context=None):
         self._stream_obj = stream  # keep a torch stream alive
-        self.h = lib.sim_create_ex(n, block_log2, float(error_bound),
-                                   int(arena_bytes), _stream_handle(stream))
+        self._context = context    # keep the context (and its buffer) alive
+        if context is not None:
+            h = ctypes.c_void_p()
+            check(lib.sim_create_in(context.h, n, block_log2, float(error_bound),
+                                    int(arena_bytes), ctypes.byref(h)))
+            self.h = h.value
+        else:
+            self.h = lib.sim_create_ex(n, block_log2, float(error_bound),
+                                       int(arena_bytes), _stream_handle(stream))
         if not self.h:
             raise SimError(SIM_EINVAL, last_error())
         self.n = n
@@ -219,6 +242,14 @@ class Sim:
     def set_aalc(self, ladder, theta):
         lad = np.ascontiguousarray(ladder, dtype=np.float64)
         check(lib.sim_set_aalc(self.h, _dp(lad), lad.size, float(theta)))
+
+    SC_PERMUTE, SC_SKIP = 1, 2
+
+    def set_shortcut(self, flags):
+        """Sec. V shortcuts: SC_PERMUTE (permutation gates keep each block's
+        previous level), SC_SKIP (blocks a gate leaves unchanged keep their
+        streams, normalisation deferred into a per-block scale)."""
+        check(lib.sim_set_shortcut(self.h, int(flags)))
 
     def set_normalize(self, on):
         check(lib.sim_set_normalize(self.h, 1 if on else 0))
@@ -350,6 +381,32 @@ class Sim:
                 "device_bytes": st.device_bytes,
                 "replays": st.replays, "escalations": st.escalations,
                 "arena_peak": st.arena_peak}
+
+
+class Context:
+    """Caller-owned device memory for sims (sim_context_create): `buffer` is
+    a device tensor (any dtype; its storage is used as raw bytes) that every
+    sim created with context=this takes all of its device memory from."""
+
+    def __init__(self, buffer, stream=None):
+        self._buffer = buffer  # the storage must outlive the context
+        self._stream_obj = stream
+        h = ctypes.c_void_p()
+        nbytes = buffer.numel() * buffer.element_size()
+        check(lib.sim_context_create(ctypes.c_void_p(buffer.data_ptr()), nbytes,
+                                     _stream_handle(stream), ctypes.byref(h)))
+        self.h = h.value
+
+    def info(self):
+        v = [ctypes.c_uint64(0) for _ in range(4)]
+        check(lib.sim_context_info(self.h, *[ctypes.byref(x) for x in v]))
+        return {"capacity": v[0].value, "used": v[1].value, "peak": v[2].value,
+                "largest_free": v[3].value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(lib.sim_context_destroy(self.h))
+            self.h = None
 
 
 class Batch:

@@ -11,6 +11,11 @@ namespace aalc {
 // Block stream v1 constants (format of the compressed stride, Sec. III).
 constexpr uint32_t kMagic = 0x31424141u;  // "AAB1"
 constexpr uint32_t kHdrBytes = 32;
+// Header byte 5, bit 0: the 8 bytes after the header hold the block's
+// deferred scale c (finite, > 0, not 1), counted in total_bytes; the records
+// follow.  Set only on streams of blocks kept by the skip shortcut.
+constexpr uint32_t kHdrScaled = 1u;
+constexpr uint32_t kScaleBytes = 8;
 constexpr uint32_t kPlaneHdrBytes = 16;
 constexpr uint32_t kOutlierBytes = 16;
 constexpr int kChunk = 64;     // scalars per chunk: one wavefront
@@ -66,6 +71,8 @@ struct Desc {
     uint8_t *blk_level;   // [nblocks] ladder level of the stream
     uint64_t *plane_off;  // [2*nseg] byte offset of each plane record
     double *segnorm;      // [nseg] pairwise normsq of each segment's x-hat
+    double *bscale;       // [nblocks] deferred scale c_j of each block (1 unless the
+                          // block was kept by the skip shortcut)
 };
 
 // Device-resident scalars of one sim, read and written only by kernels.
@@ -130,6 +137,16 @@ struct PassArgs {
     uint64_t basis;      // source state |basis> when src_basis != 0
     int32_t src_basis;
     int32_t unit_batch;  // units per workgroup round of the bulk phase (<= 1: none)
+    // Sec. V shortcuts of this pass: sc_skip -- blocks the gate leaves
+    // unchanged by its structure keep their records (copied), their scale
+    // becomes fl(c_j s); sc_perm -- the gate only reorders amplitudes, so
+    // every block is encoded at its previous level and no other is sized
+    int32_t sc_skip;
+    int32_t sc_perm;
+    // some block of the input may carry a deferred scale (c_j != 1): the
+    // unit kernels then read each block's scale (instances with SC = true)
+    int32_t sc_scaled;
+    int32_t sc_pad;
     uint32_t *psz;       // [L][2*nseg]: payload words | n_outliers << 16
     uint8_t *scratch;    // [scratch_wgs * 4][kScratchWave] staging, by workgroup and wave
     uint64_t scratch_wgs;  // workgroups the staging covers (grids must not exceed it)
@@ -164,6 +181,7 @@ void launch_init_state(DevState *dev, int normalize, hipStream_t st, Prof *prof)
 // (device pointer).
 void launch_mean(const PassArgs &a, double mul, double *out, hipStream_t st, Prof *prof);
 // grid_cap: most workgroups of the unit kernels (they loop over units).
+unsigned unit_grid_for(uint64_t units, unsigned cap);
 void launch_pass(const PassArgs &a, unsigned grid_cap, hipStream_t st, Prof *prof);
 void launch_encode_basis(const PassArgs &a, unsigned grid_cap, hipStream_t st, Prof *prof);
 void launch_decode_range(const PassArgs &a, uint64_t first, uint64_t count,
@@ -201,6 +219,7 @@ struct BatchLaunch {
     uint32_t nst;
     unsigned grid_units, grid_blocks;
     bool any_mean, any_ladder;
+    bool any_sc;  // some state skips blocks or holds scaled blocks
 };
 void launch_batch_pass(const BatchLaunch &b, hipStream_t st, Prof *prof);
 // Arena chunk a workgroup takes per bump-pointer update.

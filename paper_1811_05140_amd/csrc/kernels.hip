@@ -293,8 +293,8 @@ __device__ __forceinline__ uint64_t field64(const uint32_t *P, uint32_t b, uint3
 // outliers; the fields are then read from LDS.  A chunk's payload is at most
 // 64 words and its decoded values exactly 64, so the values written in steps
 // 0..t end below the payload of every chunk of a later step.
-__device__ void decode_plane(const uint8_t *rec, int s, double delta,
-                             double scale, bool do_scale, double *dst)
+__device__ uint32_t decode_plane(const uint8_t *rec, int s, double delta,
+                                 double scale, bool do_scale, double *dst)
 {
     const int lane = lane_id();
     const int r = lane >> 4, p = lane & 15;
@@ -433,12 +433,17 @@ __device__ void decode_plane(const uint8_t *rec, int s, double delta,
             v = v * scale;
         dst[sw(idx)] = v;
     }
+    // whether some chunk of the plane has width 0 (a flat run of equal
+    // codes, such as zeros): only then can the codec's step skips apply
+    return __ballot(wraw == 0u && (uint32_t)lane < (uint32_t)C) != 0ull ? 1u : 0u;
 }
 
 // Decode (or synthesise, for the basis-state source) the planes of a unit
-// into LDS; wave w owns plane (w & 1) of segment (w >> 1).
+// into LDS; wave w owns plane (w & 1) of segment (w >> 1).  normalise: each
+// value times its block's factor fl(c_j s) (the deferred scale c_j of the
+// skip shortcut, 1 otherwise), else the stored x-hat as it is.
 __device__ void load_unit(const PassArgs &a, const Unit &uc, Planes &X,
-                          double scale, bool do_scale)
+                          double scale, bool normalise)
 {
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int us = wave >> 1, p = wave & 1;
@@ -454,7 +459,8 @@ __device__ void load_unit(const PassArgs &a, const Unit &uc, Planes &X,
     }
     const uint64_t j = g >> (a.geo.b - s);
     const double delta = *(const double *)(a.din.hdr + 32 * j + 16);
-    decode_plane(a.arena_in + a.din.plane_off[2 * g + p], s, delta, scale, do_scale, dst);
+    const double fac = normalise ? a.din.bscale[j] * scale : 1.0;
+    decode_plane(a.arena_in + a.din.plane_off[2 * g + p], s, delta, fac, fac != 1.0, dst);
 }
 
 __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
@@ -555,13 +561,97 @@ __device__ __forceinline__ void gather_widths(uint32_t w, int t, uint32_t &wl)
     wl = d < 4u ? ws : wl;
 }
 
+// What the codec may skip in one plane, by step t (four chunks, row r on
+// chunk 4t + r): key[t] bounds the largest |x| of the step from above (the
+// high word of |x|, plus one when the low word is not zero, capped at the
+// high word of +inf, so NaN and inf never look small) and bit t of zpos says
+// that every value of the step is +0.  At a lossy level with bound delta a
+// step whose values all have |x| < delta quantises to codes 0 with no
+// outliers (|fl(x r)| <= 1/2, and |x - 0| < delta); at the lossless level a
+// step of +0 has codes 0.  When the code before the step is 0 as well, every
+// residual of the step is 0, so all four chunk widths are 0: the step adds
+// nothing to the size and nothing to the payload.
+struct StepSum {
+    uint32_t k0, k1, k2, k3;
+    uint32_t zpos;
+};
+
+__device__ StepSum step_summary(const double *x, int s)
+{
+    const int lane = lane_id();
+    const int r = lane >> 4, p = lane & 15;
+    const int C = 1 << (s - 6);
+    const int steps = (C + 3) >> 2;
+    StepSum q = {0x7FF00000u, 0x7FF00000u, 0x7FF00000u, 0x7FF00000u, 0u};
+    for (int t = 0; t < steps; ++t) {
+        const int c = 4 * t + r;
+        const bool active = c < C;
+        const double2 *pa = (const double2 *)(x + (active ? c : 0) * kChunk + 2 * p);
+        const double2 v01 = pa[0], v23 = pa[16];
+        const uint64_t b[4] = {(uint64_t)__double_as_longlong(v01.x),
+                               (uint64_t)__double_as_longlong(v01.y),
+                               (uint64_t)__double_as_longlong(v23.x),
+                               (uint64_t)__double_as_longlong(v23.y)};
+        uint32_t key = 0, any = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t lo = (uint32_t)b[i], hi = (uint32_t)(b[i] >> 32);
+            const uint32_t ha = hi & 0x7FFFFFFFu;
+            uint32_t kv = ha + (lo != 0u ? 1u : 0u);
+            kv = ha >= 0x7FF00000u ? 0x7FF00000u : kv;
+            key = kv > key ? kv : key;
+            any |= lo | hi;
+        }
+        key = active ? key : 0u;
+        any = active ? any : 0u;
+        const uint32_t km = wave_max32(key);
+        const bool zero = __ballot(any != 0u) == 0ull;
+        if (t == 0)
+            q.k0 = km;
+        else if (t == 1)
+            q.k1 = km;
+        else if (t == 2)
+            q.k2 = km;
+        else
+            q.k3 = km;
+        q.zpos |= zero ? (1u << t) : 0u;
+    }
+    return q;
+}
+
+// Steps (bit t) whose four chunks have width 0 at a level with bound delta
+// whenever the code before the step is 0: at a lossy level those whose
+// values all lie below delta in magnitude, at the lossless level those of
+// +0 only.
+__device__ __forceinline__ uint32_t size_skip_mask(const StepSum &q, double delta)
+{
+    if (delta == 0.0)
+        return q.zpos;
+    const double d = delta;
+    return (__hiloint2double((int)q.k0, 0) < d ? 1u : 0u) |
+           (__hiloint2double((int)q.k1, 0) < d ? 2u : 0u) |
+           (__hiloint2double((int)q.k2, 0) < d ? 4u : 0u) |
+           (__hiloint2double((int)q.k3, 0) < d ? 8u : 0u);
+}
+
+// Steps the encoder may skip: besides width 0, every value must already be
+// its own x-hat, which holds for +-0 at a lossy level (codes 0, x-hat of the
+// same sign) and for +0 at the lossless level.
+__device__ __forceinline__ uint32_t pack_skip_mask(const StepSum &q, double delta)
+{
+    if (delta == 0.0)
+        return q.zpos;
+    return (q.k0 == 0u ? 1u : 0u) | (q.k1 == 0u ? 2u : 0u) | (q.k2 == 0u ? 4u : 0u) |
+           (q.k3 == 0u ? 8u : 0u);
+}
+
 // Sizes of one plane at ladder levels k0 .. k1 (one wavefront; levels outer
 // so that only one level's state is live).  Returns the (payload words,
 // outliers) word of level `want` when it lies in the range; lane c (< 16)
 // of `wl` then holds that level's width of chunk c.
 __device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k0, int k1,
                                 int want, uint32_t *psz, uint64_t plane, uint64_t nplanes,
-                                uint32_t &wl)
+                                uint32_t &wl, const StepSum &sum)
 {
     const int lane = lane_id();
     const int r = lane >> 4, p = lane & 15;
@@ -571,10 +661,13 @@ __device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k
     wl = 0;
     for (int k = k0; k <= k1; ++k) {
         const double delta = lad.delta[k];
+        const uint32_t skip = size_skip_mask(sum, delta);
         uint32_t pw_acc = 0, no_acc = 0;
         if (delta == 0.0) {
             uint64_t carry = 0;
             for (int t = 0; t < steps; ++t) {
+                if (((skip >> t) & 1u) && carry == 0ull)
+                    continue;  // codes 0 after a code 0: widths 0 (carry stays 0)
                 const int c = 4 * t + r;
                 const bool active = c < C;
                 const double2 *pa = (const double2 *)(x + (active ? c : 0) * kChunk + 2 * p);
@@ -606,6 +699,8 @@ __device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k
             const double e = lad.e[k], rr = lad.r[k];
             int32_t carry = 0;
             for (int t = 0; t < steps; ++t) {
+                if (((skip >> t) & 1u) && carry == 0)
+                    continue;  // codes 0 after a code 0: widths 0, no outliers
                 const int c = 4 * t + r;
                 const bool active = c < C;
                 const double2 *pa = (const double2 *)(x + (active ? c : 0) * kChunk + 2 * p);
@@ -676,7 +771,7 @@ __device__ __forceinline__ void or_bits32(uint32_t *pb, uint32_t b, uint32_t v)
 // *psz_slot); wl = width of chunk `lane`; anchor = the plane's first code.
 __device__ uint32_t size_pack_level(double *x, int s, double delta, double e, double r,
                                     uint32_t *psz_slot, uint8_t *stage, uint32_t *pb,
-                                    uint32_t &wl, uint64_t &anchor)
+                                    uint32_t &wl, uint64_t &anchor, const StepSum &sum)
 {
     const int lane = lane_id();
     const int row = lane >> 4, p = lane & 15;
@@ -703,7 +798,12 @@ __device__ uint32_t size_pack_level(double *x, int s, double delta, double e, do
         wl = d < 4u ? ws : wl;
         return woff;
     };
+    const uint32_t skip = pack_skip_mask(sum, delta);
     for (int t = 0; t < steps; ++t) {
+        // a step of codes 0 after a code 0: widths 0, no outliers, nothing
+        // to pack, x-hat = x (anchor and carry stay 0)
+        if (((skip >> t) & 1u) && carry == 0ull)
+            continue;
         const int c = 4 * t + row;
         const bool active = c < C;
         const int cs = active ? c : 0;
@@ -1113,6 +1213,69 @@ __device__ __forceinline__ int hint_level(const PassArgs &a, uint64_t j)
     return h < a.lad.L ? h : a.lad.L - 1;
 }
 
+// Whether the gate leaves every amplitude of block j as it is, by the
+// gate's structure alone (Sec. V): a diagonal or controlled gate acts only
+// where its qubits are 1, PHASE_FLIP only at its index, SWAP only where its
+// two bits differ.  A qubit inside the block (below b) varies over the
+// block, so only qubits at or above b can leave a whole block unchanged.
+__device__ __forceinline__ bool block_untouched(const GateArg &G, int b, uint64_t j)
+{
+    auto hi = [&](int q) -> int { return q >= b ? (int)((j >> (q - b)) & 1u) : -1; };
+    switch (G.kind) {
+    case kDiag1:
+    case kCU:
+        return hi(G.q0) == 0;
+    case kCPhase:
+    case kCZ:
+        return hi(G.q0) == 0 || hi(G.q1) == 0;
+    case kPhaseFlip:
+        return (G.index >> b) != j;
+    case kSwap: {
+        const int x = hi(G.q0), y = hi(G.q1);
+        return x >= 0 && x == y;
+    }
+    default:
+        return false;
+    }
+}
+
+// A block whose stream this pass keeps (skip shortcut).
+__device__ __forceinline__ bool block_kept(const PassArgs &a, uint64_t j)
+{
+    return a.sc_skip && !a.src_basis && block_untouched(a.gate, a.geo.b, j);
+}
+
+// Bytes of the plane record at rec.
+__device__ __forceinline__ uint32_t record_bytes(const uint8_t *rec, uint32_t padC)
+{
+    const uint32_t pw = *(const uint32_t *)(rec + 8);
+    const uint32_t no = *(const uint32_t *)(rec + 12);
+    return kPlaneHdrBytes + (pw ? padC : 0u) + 8u * pw + kOutlierBytes * no;
+}
+
+// Copy a record of `bytes` (a multiple of 8) with one wavefront.
+__device__ void copy_record(const uint8_t *src, uint8_t *dst, uint32_t bytes)
+{
+    const int lane = lane_id();
+    const uint64_t *s8 = (const uint64_t *)src;
+    uint64_t *d8 = (uint64_t *)dst;
+    const uint32_t nw = bytes / 8;
+    for (uint32_t k0 = 0; k0 < nw; k0 += 256u) {
+        uint64_t v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t k = k0 + (uint32_t)lane + 64u * (uint32_t)i;
+            v[i] = k < nw ? s8[k] : 0ull;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t k = k0 + (uint32_t)lane + 64u * (uint32_t)i;
+            if (k < nw)
+                d8[k] = v[i];
+        }
+    }
+}
+
 // Workgroup-shared storage of the pass kernels (40.9 KiB: four workgroups
 // fit a CU).  After a unit's records are written, X doubles as scratch for
 // the block decisions and reductions.
@@ -1252,7 +1415,10 @@ __device__ void zero_unit(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     }
 }
 
-template <int MODE>
+// SC: the instance for passes with the skip shortcut or states that may hold
+// blocks with a deferred scale (reads each block's scale, keeps untouched
+// blocks); the other instance has none of that code.
+template <int MODE, bool SC>
 __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, PassLds &S,
                           double scale, const double *tdiff, bool zp,
                           const DevState *lazy = nullptr)
@@ -1275,7 +1441,7 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     // error bound and its level (kReplay: the decided one; else the one
     // the previous pass chose, the speculated level here).
     uint64_t poff = 0, zoff = 1;
-    double pdelta = 0.0;
+    double pdelta = 0.0, cin = 1.0;
     uint32_t lraw = 0;
     // lazy: s and 2*mean read here, with the unit's reads, instead of in a
     // round trip of their own at the kernel's start
@@ -1290,6 +1456,8 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         lraw = a.dout.blk_level[j];
     if (!a.src_basis) {
         pdelta = *(const double *)(a.din.hdr + 32 * j + 16);
+        if (SC)
+            cin = a.din.bscale[j];
         if (MODE != kReplay)
             lraw = a.din.blk_level[j];
         const uint64_t g0 = uc.seg(0), g1 = uc.seg(1);
@@ -1299,9 +1467,33 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         zoff = o00 | o01 | o10 | o11;
         // keeps the compiler from sinking these loads to their first uses
         // (one wait for all of them instead of one round trip each)
-        asm volatile("" ::"v"(zoff), "v"(poff), "v"(pdelta), "v"(lraw), "v"(scale));
+        asm volatile("" ::"v"(zoff), "v"(poff), "v"(pdelta), "v"(lraw), "v"(scale), "v"(cin));
     }
     const int lvl = MODE == kReplay ? (int)lraw : ((int)lraw < L ? (int)lraw : L - 1);
+    // skip shortcut: segments of blocks the gate leaves unchanged keep their
+    // records (copied into the output arena) and their segment norms
+    const bool keep0 = SC && MODE == kFused && block_kept(a, uc.seg(0) >> bs);
+    const bool keep1 = SC && MODE == kFused && uc.nsu == 2 && block_kept(a, uc.seg(1) >> bs);
+    const bool keep_me = SC && active && (us ? keep1 : keep0);
+    if (SC && keep0 && (uc.nsu == 1 || keep1)) {
+        const uint32_t rb = (active && poff) ? record_bytes(a.arena_in + poff, padC) : 0u;
+        const uint64_t off = alloc_records(a, S, active && poff != 0, rb);
+        if (active) {
+            if (poff == 0) {
+                if (lane == 0)
+                    a.dout.plane_off[2 * g + p] = 0;
+            } else if (off != ~0ull) {
+                if (lane == 0)
+                    a.dout.plane_off[2 * g + p] = off;
+                copy_record(a.arena_in + poff, a.arena_out + off, rb);
+            }
+        }
+        if (threadIdx.x < (unsigned)uc.nsu) {
+            const uint64_t gs = uc.seg((int)threadIdx.x);
+            a.dout.segnorm[gs] = a.din.segnorm[gs];
+        }
+        return;
+    }
     if (a.src_basis) {
         // basis state: every unit but the one holding |basis> is all +0
         const uint64_t gb = a.basis >> s;
@@ -1317,38 +1509,52 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         zero_unit<MODE>(a, uc, jsel, S, lvl);
         return;
     }
-    if (active) {
+    uint32_t flat = 1;  // this plane's input has a chunk of width 0
+    if (active && !keep_me) {
         double *dst = &X[us][p][0];
         if (a.src_basis) {
             for (int o = lane; o < (1 << s); o += 64)
                 dst[sw(o)] = (p == 0 && ((g << s) | (uint64_t)o) == a.basis) ? 1.0 : 0.0;
         } else {
-            decode_plane(a.arena_in + poff, s, pdelta, scale, scale != 1.0, dst);
+            // normalisation with the block's deferred scale: fl(c_j s)
+            const double fac = SC ? cin * scale : scale;
+            flat = decode_plane(a.arena_in + poff, s, pdelta, fac, fac != 1.0, dst);
         }
     }
+    if (lane == 0)
+        S.misc[4 + wave] = flat;
     __syncthreads();
     gate_unit(a.gate, uc, s, X, tdiff);
     __syncthreads();
+    // a unit none of whose input planes has a flat chunk is dense: the gate
+    // mixes within the unit only, so its output has no zero steps to skip
+    // and the step summary is not formed
+    const bool sparse = (S.misc[4] | S.misc[5] | S.misc[6] | S.misc[7]) != 0;
     const uint64_t plane = 2 * g + p;
-    const bool mine = active && (MODE == kFused || j == jsel);
+    const bool mine = active && !keep_me && (MODE == kFused || j == jsel);
     int lev = 0;
     uint32_t pszv = 0, wreg = 0;
     uint64_t anchor = 0;
     uint8_t *stage = a.scratch + ((uint64_t)blockIdx.x * 4 + (uint64_t)wave) * kScratchWave;
     if (mine) {
         const int h = lvl;
+        const StepSum sum = sparse ? step_summary(&X[us][p][0], s)
+                                   : StepSum{0x7FF00000u, 0x7FF00000u, 0x7FF00000u,
+                                             0x7FF00000u, 0u};
         if (MODE == kEsc) {
-            size_levels(&X[us][p][0], s, a.lad, h + 1, L - 1, -1, a.psz, plane, nplanes, wreg);
+            size_levels(&X[us][p][0], s, a.lad, h + 1, L - 1, -1, a.psz, plane, nplanes, wreg,
+                        sum);
         } else {
             // kFused: levels below the speculated one are only sized; the
             // speculated level is sized and packed together
             lev = h;
-            if (MODE == kFused && h > 0)
+            // (permutation shortcut: the previous level only, no other sized)
+            if (MODE == kFused && h > 0 && !a.sc_perm)
                 size_levels(&X[us][p][0], s, a.lad, 0, h - 1, -1, a.psz, plane, nplanes,
-                            wreg);
+                            wreg, sum);
             pszv = size_pack_level(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev],
                                    a.lad.r[lev], a.psz + (uint64_t)lev * nplanes + plane, stage,
-                                   &S.pack[wave][0], wreg, anchor);
+                                   &S.pack[wave][0], wreg, anchor, sum);
         }
     }
     if (MODE == kEsc)
@@ -1356,8 +1562,21 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     // bump-allocate this unit's records in the output arena (an all-zero
     // record is the shared one)
     const bool zrec = pszv == 0u && anchor == 0ull;
-    const uint64_t off = alloc_records(a, S, mine && !zrec, rec_bytes(pszv, padC));
-    if (mine && zrec) {
+    // a kept segment of a unit whose other segment is processed (a unit over
+    // two blocks): its records are copied
+    const uint32_t kb = (SC && keep_me && poff) ? record_bytes(a.arena_in + poff, padC) : 0u;
+    const uint64_t off = alloc_records(a, S, (mine && !zrec) || kb != 0u,
+                                       keep_me ? kb : rec_bytes(pszv, padC));
+    if (SC && keep_me) {
+        if (poff == 0) {
+            if (lane == 0)
+                a.dout.plane_off[plane] = 0;
+        } else if (off != ~0ull) {
+            if (lane == 0)
+                a.dout.plane_off[plane] = off;
+            copy_record(a.arena_in + poff, a.arena_out + off, kb);
+        }
+    } else if (mine && zrec) {
         if (lane == 0)
             a.dout.plane_off[plane] = 0;
     } else if (mine && off != ~0ull) {
@@ -1384,7 +1603,9 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
           });
     if (threadIdx.x < (unsigned)uc.nsu) {
         const uint64_t gs = uc.seg((int)threadIdx.x);
-        if (MODE == kFused || (gs >> bs) == jsel)
+        if (SC && (threadIdx.x ? keep1 : keep0))
+            a.dout.segnorm[gs] = a.din.segnorm[gs];
+        else if (MODE == kFused || (gs >> bs) == jsel)
             a.dout.segnorm[gs] = ns;
     }
 }
@@ -1467,7 +1688,8 @@ __device__ uint64_t bulk_alloc(const PassArgs &a, PassLds &S, uint32_t bytes)
 // One thread's one-value unit (see const_unit), from const_eval's results:
 // sizes of levels 0..h, the records (the k-th nonzero anchor at rec + 16 k;
 // rec is ~0 after an overflow), segment norms.
-__device__ void bulk_const_write(const PassArgs &a, const Unit &uc, const double *y,
+__device__ __forceinline__ void bulk_const_write(const PassArgs &a, const Unit &uc,
+                                                 const double *y,
                                  const double *xh, const uint64_t *anc, const int *lev,
                                  uint64_t rec)
 {
@@ -1607,7 +1829,8 @@ __device__ __forceinline__ bool const_eval(const PassArgs &a, const Unit &uc, do
         const int h = hl < L ? hl : L - 1;
         lev[i >> 1] = h;
         const uint64_t anc = *(const uint64_t *)(a.arena_in + o[i]);
-        y[i] = const_plane_value(a, anc, delta_in, i & 1, scale, tdiff[i & 1]);
+        y[i] = const_plane_value(a, anc, delta_in, i & 1, a.din.bscale[j] * scale,
+                                 tdiff[i & 1]);
     }
     // gates other than DIFFUSE and PHASE_FLIP: the value pair of each
     // position through the gate's own pair or diagonal update (every
@@ -1720,7 +1943,7 @@ __device__ __forceinline__ bool bulk_turn(const PassArgs &a)
 // BULK: rounds of a.unit_batch units with the per-thread first phase (a
 // kernel of its own, so that the one-unit-per-round form that smaller states
 // run keeps exactly its earlier code).
-template <bool BULK>
+template <bool BULK, bool SC>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pass(
     PassArgs a)
 {
@@ -1742,9 +1965,12 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     // s and 2*mean are read by each unit together with its own reads
     const bool zp = zero_preserving(a.gate);
     if (!BULK) {
+        // grid-stride over the units; the launch makes the grid odd, so
+        // nonzero units on a power-of-two stride (a QFT's first half) fall
+        // on distinct workgroups
         for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
             const Unit uc = unit_of(it, a.geo.nseg, Ms);
-            unit_body<kFused>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
+            unit_body<kFused, SC>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
             __syncthreads();
         }
         return;
@@ -1786,7 +2012,14 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             uint32_t bytes = 0;
             if (threadIdx.x < B && base + threadIdx.x < nu) {
                 uc = unit_of(base + threadIdx.x, a.geo.nseg, Ms);
-                if (!((zp || a.src_basis) && bulk_zero_unit(a, uc))) {
+                // units of blocks kept by the skip shortcut go to the unit
+                // body, which copies their records
+                const int bs = a.geo.b - a.geo.s;
+                const bool kept =
+                    block_kept(a, uc.seg(0) >> bs) || block_kept(a, uc.seg(1) >> bs);
+                if (kept) {
+                    left = true;
+                } else if (!((zp || a.src_basis) && bulk_zero_unit(a, uc))) {
                     mine = su && const_eval(a, uc, scale, tdiff, y, xh, anc, lev);
                     left = !mine;
                     if (mine)
@@ -1825,7 +2058,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             const uint64_t it = base + 64 * (uint64_t)w + (uint64_t)__builtin_ctzll(mw);
             mw &= mw - 1;
             const Unit uc = unit_of(it, a.geo.nseg, Ms);
-            unit_body<kFused>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
+            unit_body<kFused, SC>(a, uc, ~0ull, S, 1.0, nullptr, zp, a.dev);
             __syncthreads();
         }
     }
@@ -1833,6 +2066,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 
 // The pass for DIFFUSE and PHASE_FLIP gates: k_pass with const_unit's fast
 // path in front of the unit body.
+template <bool SC>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pass_const(
     PassArgs a)
 {
@@ -1853,10 +2087,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     const double scale = a.dev->scale;
     const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
     const bool zp = zero_preserving(a.gate);
+    const int bs = a.geo.b - a.geo.s;
     for (uint64_t it = blockIdx.x; it < a.geo.nunits; it += gridDim.x) {
         const Unit uc = unit_of(it, a.geo.nseg, 0);
-        if (!const_unit(a, uc, S, scale, tdiff))
-            unit_body<kFused>(a, uc, ~0ull, S, scale, tdiff, zp);
+        // units of blocks kept by the skip shortcut go to the unit body,
+        // which copies their records
+        const bool kept =
+            SC && (block_kept(a, uc.seg(0) >> bs) || block_kept(a, uc.seg(1) >> bs));
+        if (kept || !const_unit(a, uc, S, scale, tdiff))
+            unit_body<kFused, SC>(a, uc, ~0ull, S, scale, tdiff, zp);
         __syncthreads();
     }
 }
@@ -1867,6 +2106,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 // over all the block's units, decides, and re-encodes the block itself.
 // Workgroup wg of nwg working on one state's replays and escalations (the
 // pack buffers of S must be zero).
+template <bool SC>
 __device__ void fix_body(const PassArgs &a, uint64_t wg, uint64_t nwg, PassLds &S)
 {
     if (gridDim.x > a.scratch_wgs) {
@@ -1905,21 +2145,23 @@ __device__ void fix_body(const PassArgs &a, uint64_t wg, uint64_t nwg, PassLds &
                 if ((other >> bs) == jsel && other < g)
                     continue;  // the unit is handled with its first segment
                 if (phase == 0)
-                    unit_body<kEsc>(a, uc, jsel, S, scale, tdiff, zp);
+                    unit_body<kEsc, SC>(a, uc, jsel, S, scale, tdiff, zp);
                 else
-                    unit_body<kReplay>(a, uc, jsel, S, scale, tdiff, zp);
+                    unit_body<kReplay, SC>(a, uc, jsel, S, scale, tdiff, zp);
                 __syncthreads();
             }
         }
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_fix(PassArgs a)
+template <bool SC>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3, 4))) void k_fix(
+    PassArgs a)
 {
     __shared__ PassLds S;
     for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
         (&S.pack[0][0])[k] = 0u;
-    fix_body(a, blockIdx.x, gridDim.x, S);
+    fix_body<SC>(a, blockIdx.x, gridDim.x, S);
 }
 
 // Read-only DIFFUSE pre-pass: per-segment pairwise sums of the normalised
@@ -1949,19 +2191,20 @@ __device__ void mean_unit(const PassArgs &a, uint64_t u, Planes &X, double *red,
                 const uint64_t g = (t >> 1) ? g1 : g0;
                 const uint64_t o = t == 0 ? o0 : (t == 1 ? o1 : (t == 2 ? o2 : o3));
                 const uint64_t anc = *(const uint64_t *)(a.arena_in + o);
-                const double delta =
-                    *(const double *)(a.din.hdr + 32 * (g >> (a.geo.b - s)) + 16);
+                const uint64_t j = g >> (a.geo.b - s);
+                const double delta = *(const double *)(a.din.hdr + 32 * j + 16);
                 const double e = 2.0 * delta;
                 double v = delta == 0.0 ? __longlong_as_double((long long)anc)
                                         : (double)(int32_t)(uint32_t)anc * e;
-                if (scale != 1.0)
-                    v = v * scale;
+                const double fac = a.din.bscale[j] * scale;
+                if (fac != 1.0)
+                    v = v * fac;
                 a.segsum[(uint64_t)(t & 1) * a.geo.nseg + g] = v * (double)(1u << s);
             }
             return;
         }
     }
-    load_unit(a, uc, X, scale, scale != 1.0);
+    load_unit(a, uc, X, scale, true);
     __syncthreads();
     for (int c = 0; c < 2; ++c) {
         const double sm = a.geo.s == kMaxS
@@ -1994,12 +2237,14 @@ __device__ bool bulk_mean_unit(const PassArgs &a, uint64_t u, double scale)
             break;
         const uint64_t g = uc.seg(i >> 1);
         const uint64_t anc = *(const uint64_t *)(a.arena_in + o[i]);
-        const double delta = *(const double *)(a.din.hdr + 32 * (g >> (a.geo.b - s)) + 16);
+        const uint64_t j = g >> (a.geo.b - s);
+        const double delta = *(const double *)(a.din.hdr + 32 * j + 16);
         const double e = 2.0 * delta;
         double v = delta == 0.0 ? __longlong_as_double((long long)anc)
                                 : (double)(int32_t)(uint32_t)anc * e;
-        if (scale != 1.0)
-            v = v * scale;
+        const double fac = a.din.bscale[j] * scale;
+        if (fac != 1.0)
+            v = v * fac;
         a.segsum[(uint64_t)(i & 1) * a.geo.nseg + g] = v * (double)(1u << s);
     }
     return true;
@@ -2074,6 +2319,44 @@ __device__ __forceinline__ double seq_tree(Load load, uint64_t base)
     return v[0];
 }
 
+// Pairwise sum of cnt (a power of two, at most 2^kCounterLevels) aligned
+// subtrees of 32 values load(base ..): the subtrees are combined through a
+// binary counter -- pend[l] holds the pending left operand of level l, and a
+// new subtree carries up through the levels whose pending slot is full --
+// which gives exactly the perfect tree over the run.  Every level is
+// unrolled with a fixed index, so pend stays in registers (no private
+// memory).
+constexpr int kCounterLevels = 16;
+
+template <class Load>
+__device__ __forceinline__ double counter_tree(Load load, uint64_t base, uint64_t cnt)
+{
+    double pend[kCounterLevels + 1];
+#pragma unroll
+    for (int l = 0; l <= kCounterLevels; ++l)
+        pend[l] = 0.0;
+    for (uint64_t i = 0; i < cnt; ++i) {
+        double x = seq_tree<32>(load, base + 32 * i);
+        bool carry = true;
+#pragma unroll
+        for (int l = 0; l <= kCounterLevels; ++l) {
+            const bool full = ((i >> l) & 1u) != 0;
+            if (carry && full)
+                x = pend[l] + x;
+            else if (carry)
+                pend[l] = x;
+            carry = carry && full;
+        }
+    }
+    // the whole run ends up in the slot of level log2(cnt)
+    const int top = 63 - __builtin_clzll(cnt);
+    double v = 0.0;
+#pragma unroll
+    for (int l = 0; l <= kCounterLevels; ++l)
+        v = l == top ? pend[l] : v;
+    return v;
+}
+
 // Pairwise sum of m = 2^k values load(0..m) by one workgroup: each thread
 // sums m/256 consecutive values (an aligned subtree), then a tree in LDS.
 template <class Load>
@@ -2092,18 +2375,8 @@ __device__ double wg_tree(Load load, uint64_t m, double *lds)
         case 8: v = seq_tree<8>(load, base); break;
         case 16: v = seq_tree<16>(load, base); break;
         case 32: v = seq_tree<32>(load, base); break;
-        default: {
-            // longer runs: subtrees of 32 combined through a binary counter
-            double stack[40];
-            int sp = 0;
-            for (uint64_t i = 0; i < per / 32; ++i) {
-                double x = seq_tree<32>(load, base + 32 * i);
-                for (uint64_t k = i; k & 1; k >>= 1)
-                    x = stack[--sp] + x;
-                stack[sp++] = x;
-            }
-            v = stack[0];
-        }
+        default:
+            v = counter_tree(load, base, per / 32);
         }
         lds[t] = v;
         nact = kWG;
@@ -2140,17 +2413,8 @@ __device__ double wave_pairwise(const double *src, uint64_t m)
         case 8: v = seq_tree<8>(load, base); break;
         case 16: v = seq_tree<16>(load, base); break;
         case 32: v = seq_tree<32>(load, base); break;
-        default: {
-            double stack[40];
-            int sp = 0;
-            for (uint64_t i = 0; i < per / 32; ++i) {
-                double x = seq_tree<32>(load, base + 32 * i);
-                for (uint64_t k = i; k & 1; k >>= 1)
-                    x = stack[--sp] + x;
-                stack[sp++] = x;
-            }
-            v = stack[0];
-        }
+        default:
+            v = counter_tree(load, base, per / 32);
         }
     } else {
         v = (uint64_t)lane < m ? src[lane] : 0.0;
@@ -2242,6 +2506,42 @@ __device__ void finalize_block(const PassArgs &a, uint64_t j, int d, uint64_t le
     h[3] = 0;
     a.dout.blk_len[j] = (uint32_t)len;
     a.dout.blk_level[j] = (uint8_t)d;
+    a.dout.bscale[j] = 1.0;
+}
+
+// A block kept by the skip shortcut (one wavefront): its header, level and
+// records stay (the pass copied the records and segment norms); its scale
+// becomes c' = fl(c s), which the stream carries after its header when it
+// is not 1; its weight in N^2 is its normsq, times fl(c' c') when c' != 1.
+__device__ void keep_block(const PassArgs &a, uint64_t j)
+{
+    const int lane = lane_id();
+    const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
+    const double *segn = a.dout.segnorm + j * spb;
+    const double sn0 = (spb <= 64 && (uint64_t)lane < spb) ? segn[lane] : 0.0;
+    const double ns = spb <= 64 ? wave_tree_sum(sn0) : wave_pairwise(segn, spb);
+    if (lane == 0) {
+        const double cin = a.din.bscale[j];
+        const double c = cin * a.dev->scale;
+        const uint64_t *hi = (const uint64_t *)(a.din.hdr + 32 * j);
+        uint64_t *ho = (uint64_t *)(a.dout.hdr + 32 * j);
+        const uint64_t plain = (uint64_t)a.din.blk_len[j] - (cin != 1.0 ? kScaleBytes : 0u);
+        const uint64_t len = plain + (c != 1.0 ? kScaleBytes : 0u);
+        const uint64_t h0 = hi[0] & ~(0xFFull << 40);
+        ho[0] = h0 | ((uint64_t)(c != 1.0 ? kHdrScaled : 0u) << 40);
+        ho[1] = (hi[1] & 0xFFFFFFFFull) | (len << 32);
+        ho[2] = hi[2];
+        ho[3] = 0;
+        a.dout.blk_len[j] = (uint32_t)len;
+        a.dout.blk_level[j] = a.din.blk_level[j];
+        a.dout.bscale[j] = c;
+        double w = ns;
+        if (c != 1.0) {
+            const double c2 = c * c;
+            w = ns * c2;
+        }
+        a.blknorm[j] = w;
+    }
 }
 
 // Alg. 2's choice for each block over the levels the fused pass sized
@@ -2269,10 +2569,16 @@ __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
 template <int VEC>
 __device__ void decide_block(const PassArgs &a, uint64_t j)
 {
+    if (block_kept(a, j)) {
+        keep_block(a, j);
+        return;
+    }
     // sizes of levels 0..h summed over the block's planes by one wavefront
+    // (permutation shortcut: level h only, taken without the theta test)
     const int lane = lane_id();
     const int L = a.lad.L;
     const int h = hint_level(a, j);
+    const int k0 = a.sc_perm ? h : 0;
     const uint64_t npb = 2ull << (a.geo.b - a.geo.s);
     const uint64_t nplanes = 2 * a.geo.nseg;
     const uint32_t padC = pad8(1u << (a.geo.s - 6));
@@ -2295,7 +2601,7 @@ __device__ void decide_block(const PassArgs &a, uint64_t j)
         for (uint64_t q = 4 * (uint64_t)lane; q < npb; q += 256) {
 #pragma unroll
             for (int k = 0; k < kMaxL; ++k) {
-                if (k <= h) {
+                if (k >= k0 && k <= h) {
                     const uint4 v = *(const uint4 *)(a.psz + (uint64_t)k * nplanes + base + q);
                     by[k] += rec_bytes(v.x, padC) + rec_bytes(v.y, padC) +
                              rec_bytes(v.z, padC) + rec_bytes(v.w, padC);
@@ -2307,7 +2613,7 @@ __device__ void decide_block(const PassArgs &a, uint64_t j)
         for (uint64_t q = lane; q < npb; q += 64) {
 #pragma unroll
             for (int k = 0; k < kMaxL; ++k) {
-                if (k <= h) {
+                if (k >= k0 && k <= h) {
                     const uint32_t v = a.psz[(uint64_t)k * nplanes + base + q];
                     by[k] += rec_bytes(v, padC);
                     no[k] += v >> 16;
@@ -2320,9 +2626,9 @@ __device__ void decide_block(const PassArgs &a, uint64_t j)
     uint64_t tot_d = 0, nout_d = 0;
 #pragma unroll
     for (int k = 0; k < kMaxL; ++k) {
-        if (k <= h && d < 0) {
+        if (k >= k0 && k <= h && d < 0) {
             const uint64_t tk = readlane64(wave_scan64(by[k]), 63) + kHdrBytes;
-            if (raw >= a.lad.theta * (double)tk || (k == h && h == L - 1)) {
+            if (raw >= a.lad.theta * (double)tk || (k == h && h == L - 1) || a.sc_perm) {
                 d = k;
                 tot_d = tk;
                 nout_d = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan32(no[k]), 63);
@@ -2504,10 +2810,9 @@ __global__ __launch_bounds__(kWG) void k_decode_range(PassArgs a, uint64_t u0,
     __shared__ __attribute__((aligned(16))) Planes X;
     const int s = a.geo.s;
     const double scale = a.dev->scale;
-    const bool do_scale = scale != 1.0;
     for (uint64_t u = u0 + blockIdx.x; u < u1; u += gridDim.x) {
         const Unit uc = unit_of(u, a.geo.nseg, 0);
-        load_unit(a, uc, X, scale, do_scale);
+        load_unit(a, uc, X, scale, true);
         __syncthreads();
         for (int us = 0; us < uc.nsu; ++us)
             for (uint32_t o = threadIdx.x; o < (1u << s); o += kWG) {
@@ -2528,7 +2833,6 @@ __global__ __launch_bounds__(kWG) void k_probs(PassArgs a, const int *qubits, in
     __shared__ double bins[1024];
     const int s = a.geo.s;
     const double scale = a.dev->scale;
-    const bool do_scale = scale != 1.0;
     const bool lds_bins = nq <= 10;
     const uint32_t nb = 1u << nq;
     if (lds_bins)
@@ -2537,7 +2841,7 @@ __global__ __launch_bounds__(kWG) void k_probs(PassArgs a, const int *qubits, in
     __syncthreads();
     for (uint64_t u = blockIdx.x; u < a.geo.nunits; u += gridDim.x) {
         const Unit uc = unit_of(u, a.geo.nseg, 0);
-        load_unit(a, uc, X, scale, do_scale);
+        load_unit(a, uc, X, scale, true);
         __syncthreads();
         for (int us = 0; us < uc.nsu; ++us)
             for (uint32_t o = threadIdx.x; o < (1u << s); o += kWG) {
@@ -2565,7 +2869,7 @@ __global__ __launch_bounds__(kWG) void k_probs(PassArgs a, const int *qubits, in
 // Inner products of two states over ranges of 2^S amplitudes.  Planes of A
 // go to X[0], of B to X[1]; an uncompressed state is read from its array.
 __device__ void load_range(const PassArgs &a, const double *amp, uint64_t first,
-                           int S, double *dst, int p, double scale, bool do_scale)
+                           int S, double *dst, int p, double scale)
 {
     const int lane = lane_id();
     const int cnt = 1 << S;
@@ -2579,7 +2883,8 @@ __device__ void load_range(const PassArgs &a, const double *amp, uint64_t first,
         const uint64_t g = (first + off) >> s;
         const uint64_t j = g >> (a.geo.b - s);
         const double delta = *(const double *)(a.din.hdr + 32 * j + 16);
-        decode_plane(a.arena_in + a.din.plane_off[2 * g + p], s, delta, scale, do_scale,
+        const double fac = a.din.bscale[j] * scale;  // fl(c_j s)
+        decode_plane(a.arena_in + a.din.plane_off[2 * g + p], s, delta, fac, fac != 1.0,
                      dst + off);
     }
 }
@@ -2597,9 +2902,9 @@ __global__ __launch_bounds__(kWG) void k_inner(PassArgs A, PassArgs B,
     for (uint64_t u = blockIdx.x; u < nranges; u += gridDim.x) {
         const uint64_t first = u << S;
         if (wave < 2)
-            load_range(A, ampA, first, S, &X[0][wave][0], wave, sa, sa != 1.0);
+            load_range(A, ampA, first, S, &X[0][wave][0], wave, sa);
         else
-            load_range(B, ampB, first, S, &X[1][wave - 2][0], wave - 2, sb, sb != 1.0);
+            load_range(B, ampB, first, S, &X[1][wave - 2][0], wave - 2, sb);
         __syncthreads();
         const uint64_t m = 1ull << S;
         for (int c = 0; c < 4; ++c) {
@@ -2664,7 +2969,7 @@ __global__ __launch_bounds__(kWG) void k_fourier(PassArgs A, const double *amp, 
     for (uint64_t u = blockIdx.x; u < nranges; u += gridDim.x) {
         const uint64_t first = u << S;
         if (wave < 2)
-            load_range(A, amp, first, S, &X[0][wave][0], wave, sa, sa != 1.0);
+            load_range(A, amp, first, S, &X[0][wave][0], wave, sa);
         __syncthreads();
         const uint64_t m = 1ull << S;
         for (int c = 0; c < 3; ++c) {
@@ -2748,7 +3053,11 @@ __device__ void export_body(const PassArgs &a, uint64_t j, uint8_t *out, uint64_
         red[t] += add;
         __syncthreads();
     }
-    uint64_t run = kHdrBytes + red[t] - local;
+    // a block with a deferred scale carries it right after the header (its
+    // header already has the flag and counts the 8 bytes)
+    const double cj = a.din.bscale[j];
+    const uint64_t rec0 = kHdrBytes + (cj != 1.0 ? kScaleBytes : 0u);
+    uint64_t run = rec0 + red[t] - local;
     for (uint64_t q = t * per; q < (t + 1) * per && q < npb; ++q) {
         const uint64_t sz = offs[q];
         offs[q] = run;
@@ -2756,6 +3065,8 @@ __device__ void export_body(const PassArgs &a, uint64_t j, uint8_t *out, uint64_
     }
     if (t < 3)
         ((uint64_t *)out)[t] = ((const uint64_t *)(a.din.hdr + 32 * j))[t];
+    if (t == 3 && cj != 1.0)
+        *(double *)(out + kHdrBytes) = cj;
     {
         // header normsq: pairwise over the block's segment sums
         const uint64_t spb = 1ull << (a.geo.b - s);
@@ -2765,7 +3076,7 @@ __device__ void export_body(const PassArgs &a, uint64_t j, uint8_t *out, uint64_
             *(double *)(out + 24) = ns;
     }
     __syncthreads();
-    const uint64_t nwords = ((uint64_t)a.din.blk_len[j] - kHdrBytes) / 8;
+    const uint64_t nwords = ((uint64_t)a.din.blk_len[j] - rec0) / 8;
     if (nwords >= 32 * npb) {
         // records of 32 words or more on average: wave w copies records w,
         // w+4, ... with its 64 lanes
@@ -2784,9 +3095,9 @@ __device__ void export_body(const PassArgs &a, uint64_t j, uint8_t *out, uint64_
     // small records: the records as one run of words, thread t writing words
     // t, t+256, ... of the stream after the header (coalesced), each read
     // from the record holding it (binary search over the record starts)
-    uint64_t *dst = (uint64_t *)(out + kHdrBytes);
+    uint64_t *dst = (uint64_t *)(out + rec0);
     for (uint64_t k = t; k < nwords; k += kWG) {
-        const uint64_t pos = kHdrBytes + 8 * k;
+        const uint64_t pos = rec0 + 8 * k;
         uint64_t lo = 0, hi = npb;  // offs[lo] <= pos < offs[hi] (offs[npb]: the end)
         while (hi - lo > 1) {
             const uint64_t mid = (lo + hi) >> 1;
@@ -2863,7 +3174,10 @@ __global__ __launch_bounds__(kWG) void k_import_scan(PassArgs a, const uint64_t 
     a.dout.blk_len[j] = total;
     a.dout.blk_level[j] = (uint8_t)(h0 >> 32);
     const uint64_t end = start + total;
-    uint64_t pos = start + kHdrBytes;
+    // a deferred scale (checked by the host) sits between header and records
+    const bool scaled = ((h0 >> 40) & kHdrScaled) != 0;
+    a.dout.bscale[j] = scaled ? *(const double *)(base + start + kHdrBytes) : 1.0;
+    uint64_t pos = start + kHdrBytes + (scaled ? kScaleBytes : 0u);
     uint64_t nsum = 0;
     bool ok = true;
     for (uint64_t q = 0; q < npb; ++q) {
@@ -3041,7 +3355,14 @@ __global__ __launch_bounds__(kWG) void k_import_blocks(PassArgs a)
         const double *src = a.dout.segnorm + j * spb;
         const double v = wg_tree([&](uint64_t i) { return src[i]; }, spb, lds);
         if (threadIdx.x == 0) {
-            a.blknorm[j] = v;
+            // weight in N^2: times fl(c c) for a block with a deferred scale
+            const double c = a.dout.bscale[j];
+            double w = v;
+            if (c != 1.0) {
+                const double c2 = c * c;
+                w = v * c2;
+            }
+            a.blknorm[j] = w;
             const uint64_t want = *(const uint64_t *)(a.dout.hdr + 32 * j + 24);
             if ((uint64_t)__double_as_longlong(v) != want)
                 atomicOr(&a.dev->err, kErrImportNorm);
@@ -3091,8 +3412,9 @@ __device__ __forceinline__ uint32_t state_of(const uint64_t *__restrict__ pre, u
     return lo;
 }
 
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_bpass(const PassArgs *__restrict__ args,
-                                               const uint64_t *__restrict__ upre, uint32_t nst)
+template <bool SC>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_bpass(
+    const PassArgs *__restrict__ args, const uint64_t *__restrict__ upre, uint32_t nst)
 {
     __shared__ PassLds S;
     for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
@@ -3121,8 +3443,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         }
         if (skip)
             continue;
-        unit_body<kFused>(a, unit_of(it - upre[st], a.geo.nseg, Ms), ~0ull, S, scale, tdiff,
-                          zp);
+        unit_body<kFused, SC>(a, unit_of(it - upre[st], a.geo.nseg, Ms), ~0ull, S, scale,
+                              tdiff, zp);
         __syncthreads();
     }
 }
@@ -3146,6 +3468,7 @@ __global__ __launch_bounds__(kWG) void k_bdecide(const PassArgs *__restrict__ ar
 // Every workgroup takes its share of the replay and escalation items of
 // every state that has any.  The states are screened 64 at a time, one lane
 // each; the resulting mask is the same in every wave.
+template <bool SC>
 __global__ __launch_bounds__(kWG) void k_bfix(const PassArgs *__restrict__ args,
                                               const uint64_t *__restrict__ upre, uint32_t nst)
 {
@@ -3163,7 +3486,7 @@ __global__ __launch_bounds__(kWG) void k_bfix(const PassArgs *__restrict__ args,
         while (m) {
             const int l = __builtin_ctzll(m);
             m &= m - 1;
-            fix_body(args[base + l], blockIdx.x, gridDim.x, S);
+            fix_body<SC>(args[base + l], blockIdx.x, gridDim.x, S);
             __syncthreads();
         }
     }
@@ -3309,9 +3632,19 @@ void launch_mean(const PassArgs &a, double mul, double *out, hipStream_t st, Pro
 
 uint64_t batch_chunk_bytes(uint64_t arena_cap, unsigned grid);
 
+// Workgroups of a unit kernel over `units` units with at most `cap`: odd
+// when the workgroups loop, so that units on a power-of-two stride spread
+// over distinct workgroups instead of a 1/stride share of them.
+unsigned unit_grid_for(uint64_t units, unsigned cap)
+{
+    if (units <= cap)
+        return grid_for(units);
+    return grid_for(cap > 1 ? ((cap - 1) | 1u) : 1u);
+}
+
 void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *prof)
 {
-    const unsigned gu = grid_for(a0.geo.nunits < grid_cap ? a0.geo.nunits : grid_cap);
+    const unsigned gu = unit_grid_for(a0.geo.nunits, grid_cap);
     const unsigned gb = grid_for((a0.geo.nblocks + 3) / 4);
     // replays are a few blocks per pass at most; a small grid launches and
     // retires faster when there are none
@@ -3323,22 +3656,45 @@ void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *pr
     // (every gate kind) beside the one-unit kernel, exactly one of which
     // runs (bulk_turn); the one-unit kernels have the one-value fast path
     // for DIFFUSE and PHASE_FLIP
-    if (a.unit_batch > 1)
-        TIMED(prof, kIdPassBulk, st,
-              hipLaunchKernelGGL(k_pass<true>, dim3(gu), dim3(kWG), 0, st, a));
-    if (a.gate.kind == kDiffuse || a.gate.kind == kPhaseFlip)
-        TIMED(prof, kIdPass, st, hipLaunchKernelGGL(k_pass_const, dim3(gu), dim3(kWG), 0, st, a));
-    else
+    // the instances with the shortcut code only when this pass keeps blocks
+    // or the state may hold scaled blocks
+    const bool sc = a.sc_skip || a.sc_scaled;
+    if (a.unit_batch > 1) {
+        if (sc)
+            TIMED(prof, kIdPassBulk, st,
+                  hipLaunchKernelGGL((k_pass<true, true>), dim3(gu), dim3(kWG), 0, st, a));
+        else
+            TIMED(prof, kIdPassBulk, st,
+                  hipLaunchKernelGGL((k_pass<true, false>), dim3(gu), dim3(kWG), 0, st, a));
+    }
+    if (a.gate.kind == kDiffuse || a.gate.kind == kPhaseFlip) {
+        if (sc)
+            TIMED(prof, kIdPass, st,
+                  hipLaunchKernelGGL(k_pass_const<true>, dim3(gu), dim3(kWG), 0, st, a));
+        else
+            TIMED(prof, kIdPass, st,
+                  hipLaunchKernelGGL(k_pass_const<false>, dim3(gu), dim3(kWG), 0, st, a));
+    } else if (sc) {
         TIMED(prof, kIdPass, st,
-              hipLaunchKernelGGL(k_pass<false>, dim3(gu), dim3(kWG), 0, st, a));
+              hipLaunchKernelGGL((k_pass<false, true>), dim3(gu), dim3(kWG), 0, st, a));
+    } else {
+        TIMED(prof, kIdPass, st,
+              hipLaunchKernelGGL((k_pass<false, false>), dim3(gu), dim3(kWG), 0, st, a));
+    }
     if ((2ull << (a.geo.b - a.geo.s)) % 256 == 0)
         TIMED(prof, kIdDecide, st,
               hipLaunchKernelGGL(k_decide<1>, dim3(gb), dim3(kWG), 0, st, a));
     else
         TIMED(prof, kIdDecide, st,
               hipLaunchKernelGGL(k_decide<0>, dim3(gb), dim3(kWG), 0, st, a));
-    if (a.lad.L > 1)
-        TIMED(prof, kIdReplay, st, hipLaunchKernelGGL(k_fix, dim3(gfix), dim3(kWG), 0, st, a));
+    if (a.lad.L > 1) {
+        if (sc)
+            TIMED(prof, kIdReplay, st,
+                  hipLaunchKernelGGL(k_fix<true>, dim3(gfix), dim3(kWG), 0, st, a));
+        else
+            TIMED(prof, kIdReplay, st,
+                  hipLaunchKernelGGL(k_fix<false>, dim3(gfix), dim3(kWG), 0, st, a));
+    }
     TIMED(prof, kIdReduce, st, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, a));
 }
 
@@ -3354,16 +3710,25 @@ void launch_batch_pass(const BatchLaunch &b, hipStream_t st, Prof *prof)
         TIMED(prof, kIdMeanFinal, st,
               hipLaunchKernelGGL(k_bmeanfinal, dim3(b.nst), dim3(kWG), 0, st, b.args, b.mpre));
     }
-    TIMED(prof, kIdPass, st,
-          hipLaunchKernelGGL(k_bpass, dim3(b.grid_units), dim3(kWG), 0, st, b.args, b.upre,
-                             b.nst));
+    if (b.any_sc)
+        TIMED(prof, kIdPass, st,
+              hipLaunchKernelGGL(k_bpass<true>, dim3(b.grid_units), dim3(kWG), 0, st, b.args,
+                                 b.upre, b.nst));
+    else
+        TIMED(prof, kIdPass, st,
+              hipLaunchKernelGGL(k_bpass<false>, dim3(b.grid_units), dim3(kWG), 0, st, b.args,
+                                 b.upre, b.nst));
     TIMED(prof, kIdDecide, st,
           hipLaunchKernelGGL(k_bdecide, dim3((b.grid_blocks + 3) / 4), dim3(kWG), 0, st,
                              b.args, b.bpre, b.nst));
-    if (b.any_ladder)
+    if (b.any_ladder && b.any_sc)
         TIMED(prof, kIdReplay, st,
-              hipLaunchKernelGGL(k_bfix, dim3(b.grid_units), dim3(kWG), 0, st, b.args, b.upre,
-                                 b.nst));
+              hipLaunchKernelGGL(k_bfix<true>, dim3(b.grid_units), dim3(kWG), 0, st, b.args,
+                                 b.upre, b.nst));
+    else if (b.any_ladder)
+        TIMED(prof, kIdReplay, st,
+              hipLaunchKernelGGL(k_bfix<false>, dim3(b.grid_units), dim3(kWG), 0, st, b.args,
+                                 b.upre, b.nst));
     TIMED(prof, kIdReduce, st,
           hipLaunchKernelGGL(k_breduce, dim3(b.nst), dim3(kWG), 0, st, b.args, b.upre));
 }

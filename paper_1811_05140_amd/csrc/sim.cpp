@@ -13,6 +13,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <iterator>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -24,9 +26,11 @@ using namespace aalc;
 namespace {
 
 thread_local std::string g_err;
+thread_local int g_code = SIM_OK;
 
 int fail(int code, const char *fmt, ...)
 {
+    g_code = code;
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -105,10 +109,70 @@ struct EventProf final : Prof {
 
 }  // namespace
 
+// A device-memory context: a caller-owned device buffer (for example a
+// torch tensor's storage) that sims created in it carve all their device
+// memory from.  First fit over an ordered free list with 256-byte
+// alignment; freed ranges merge with their neighbours.
+struct sim_ctx {
+    uint8_t *base = nullptr;
+    uint64_t cap = 0;
+    hipStream_t stream = nullptr;  // stream of sims created in it (may be null)
+    std::map<uint64_t, uint64_t> free_;  // offset -> bytes
+    uint64_t used = 0, peak = 0;
+    int nsims = 0;
+    int device = 0;
+
+    void *take(uint64_t bytes)
+    {
+        bytes = (bytes + 255) & ~255ull;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes)
+                continue;
+            const uint64_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > bytes)
+                free_[off + bytes] = len - bytes;
+            used += bytes;
+            peak = used > peak ? used : peak;
+            return base + off;
+        }
+        return nullptr;
+    }
+    void give(void *p, uint64_t bytes)
+    {
+        bytes = (bytes + 255) & ~255ull;
+        uint64_t off = (uint64_t)((uint8_t *)p - base);
+        used -= bytes;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + bytes == next->first) {
+            bytes += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += bytes;
+                return;
+            }
+        }
+        free_[off] = bytes;
+    }
+    uint64_t largest_free() const
+    {
+        uint64_t m = 0;
+        for (const auto &f : free_)
+            m = f.second > m ? f.second : m;
+        return m;
+    }
+};
+
 struct sim {
     int n = 0, b = 0, s = 0;
     int device = 0;  // the GPU current when the sim was created
     bool compressed = true;
+    int shortcut = 0;     // SIM_SC_* flags (Sec. V shortcuts), 0 = Alg. 2 as written
+    bool scaled = false;  // some block may carry a deferred scale (after a skip pass
+                          // or the import of scaled streams, until set_basis)
     int normalize = 1;
     Ladder lad{};
     Geo geo{};
@@ -136,18 +200,31 @@ struct sim {
     double *amp = nullptr;
     double *sv_scratch = nullptr;
     double *sv_tdiff = nullptr;
-    std::vector<void *> allocs;
+    std::vector<std::pair<void *, uint64_t>> allocs;
     uint64_t device_bytes = 0;
+    sim_ctx *ctx = nullptr;  // device memory comes from this context when set
     EventProf *prof = nullptr;
 };
 
 namespace {
 
-int dmalloc(sim *S, void **p, uint64_t bytes)
+// Device memory of a sim: from its context when it has one (SIM_EBUDGET
+// when the context cannot hold it), else hipMalloc (SIM_ENOMEM).
+int raw_alloc(sim *S, void **p, uint64_t bytes)
 {
     *p = nullptr;
     if (bytes == 0)
         bytes = 8;
+    if (S->ctx) {
+        *p = S->ctx->take(bytes);
+        if (!*p)
+            return fail(SIM_EBUDGET, "context exhausted: %llu bytes requested, %llu of %llu "
+                        "in use, largest free range %llu",
+                        (unsigned long long)bytes, (unsigned long long)S->ctx->used,
+                        (unsigned long long)S->ctx->cap,
+                        (unsigned long long)S->ctx->largest_free());
+        return SIM_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -155,17 +232,63 @@ int dmalloc(sim *S, void **p, uint64_t bytes)
         return fail(SIM_ENOMEM, "hipMalloc(%llu bytes) failed: %s",
                     (unsigned long long)bytes, hipGetErrorString(e));
     }
-    S->allocs.push_back(*p);
+    return SIM_OK;
+}
+
+void raw_free(sim *S, void *p, uint64_t bytes)
+{
+    if (!p)
+        return;
+    if (S->ctx)
+        S->ctx->give(p, bytes ? bytes : 8);
+    else
+        (void)hipFree(p);
+}
+
+// A buffer held for the life of the sim.
+int dmalloc(sim *S, void **p, uint64_t bytes)
+{
+    int rc = raw_alloc(S, p, bytes);
+    if (rc)
+        return rc;
+    S->allocs.push_back({*p, bytes});
     S->device_bytes += bytes;
     return SIM_OK;
 }
 
+// Release one buffer obtained from dmalloc (the stream must be idle).
+void dfree(sim *S, void *p)
+{
+    for (auto it = S->allocs.begin(); it != S->allocs.end(); ++it)
+        if (it->first == p) {
+            raw_free(S, p, it->second);
+            S->device_bytes -= it->second;
+            S->allocs.erase(it);
+            return;
+        }
+}
+
 void free_all(sim *S)
 {
-    for (void *p : S->allocs)
-        (void)hipFree(p);
+    for (auto &a : S->allocs)
+        raw_free(S, a.first, a.second);
     S->allocs.clear();
+    S->device_bytes = 0;
 }
+
+// A temporary buffer of one call (from the context when the sim has one).
+struct Tmp {
+    sim *S;
+    void *p = nullptr;
+    uint64_t bytes = 0;
+    explicit Tmp(sim *s) : S(s) {}
+    int get(uint64_t n)
+    {
+        bytes = n;
+        return raw_alloc(S, &p, n);
+    }
+    ~Tmp() { raw_free(S, p, bytes); }
+};
 
 bool ladder_ok(const double *ladder, int L, double theta)
 {
@@ -203,13 +326,7 @@ int ensure_psz(sim *S, int L)
         return SIM_OK;
     if (S->psz) {
         HIPCHK(hipStreamSynchronize(S->stream));
-        for (auto it = S->allocs.begin(); it != S->allocs.end(); ++it)
-            if (*it == S->psz) {
-                S->allocs.erase(it);
-                break;
-            }
-        S->device_bytes -= (uint64_t)S->psz_levels * 2 * S->geo.nseg * 4;
-        (void)hipFree(S->psz);
+        dfree(S, S->psz);
         S->psz = nullptr;
     }
     int rc = dmalloc(S, (void **)&S->psz, (uint64_t)L * 2 * S->geo.nseg * 4);
@@ -226,13 +343,7 @@ int ensure_scratch(sim *S, uint64_t wgs)
         return SIM_OK;
     if (S->scratch) {
         HIPCHK(hipStreamSynchronize(S->stream));
-        for (auto it = S->allocs.begin(); it != S->allocs.end(); ++it)
-            if (*it == S->scratch) {
-                S->allocs.erase(it);
-                break;
-            }
-        S->device_bytes -= S->scratch_wgs * 4 * kScratchWave;
-        (void)hipFree(S->scratch);
+        dfree(S, S->scratch);
         S->scratch = nullptr;
         S->scratch_wgs = 0;
     }
@@ -312,6 +423,40 @@ GateArg to_arg(const sim_gate_t *g)
     return a;
 }
 
+// Whether the gate can leave whole blocks of 2^b amplitudes unchanged by
+// its structure (a diagonal or controlled gate with a qubit at or above b,
+// PHASE_FLIP, SWAP of two qubits at or above b): only then does the skip
+// shortcut have blocks to keep in the pass.
+bool gate_may_keep(const GateArg &g, int b)
+{
+    switch (g.kind) {
+    case kDiag1:
+    case kCU:
+        return g.q0 >= b;
+    case kCPhase:
+    case kCZ:
+        return g.q0 >= b || g.q1 >= b;
+    case kPhaseFlip:
+        return true;
+    case kSwap:
+        return g.q0 >= b && g.q1 >= b;
+    default:
+        return false;
+    }
+}
+
+// A gate that only reorders amplitudes: X, SWAP, and CU whose matrix is
+// exactly [[0, 1], [1, 0]] (CNOT), compared bit for bit.
+bool gate_permutes(const GateArg &g)
+{
+    if (g.kind == kX || g.kind == kSwap)
+        return true;
+    if (g.kind != kCU)
+        return false;
+    static const double x[8] = {0.0, 0.0, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0};
+    return memcmp(g.u, x, sizeof x) == 0;
+}
+
 PassArgs make_args(const sim *S, int in, int out, const GateArg &g)
 {
     PassArgs a{};
@@ -335,6 +480,9 @@ PassArgs make_args(const sim *S, int in, int out, const GateArg &g)
     a.segsum = S->segsum;
     a.blksum = S->blksum;
     a.dev = S->dev;
+    a.sc_skip = (S->shortcut & SIM_SC_SKIP) && gate_may_keep(g, S->b) ? 1 : 0;
+    a.sc_perm = (S->shortcut & SIM_SC_PERMUTE) && gate_permutes(g) ? 1 : 0;
+    a.sc_scaled = S->scaled ? 1 : 0;
     return a;
 }
 
@@ -419,6 +567,7 @@ int run_basis(sim *S, uint64_t x)
         return rc;
     GateArg none{};
     none.kind = kNone;
+    S->scaled = false;  // every block of a basis state has scale 1
     PassArgs a = make_args(S, 1, 0, none);
     a.src_basis = 1;
     a.basis = x;
@@ -432,9 +581,11 @@ int run_basis(sim *S, uint64_t x)
     return SIM_OK;
 }
 
-sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream)
+sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream,
+            sim_ctx *ctx = nullptr)
 {
     g_err.clear();
+    g_code = SIM_OK;
     const bool compressed = !(eb < 0.0);
     if (std::isnan(eb)) {
         fail(SIM_EINVAL, "error_bound is NaN");
@@ -454,11 +605,18 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
         return nullptr;
     }
     S->n = n;
+    S->ctx = ctx;
     S->compressed = compressed;
     S->b = block_log2 > n ? n : block_log2;
     S->s = S->b < kMaxS ? S->b : kMaxS;
     if (hipGetDevice(&S->device) != hipSuccess) {
         fail(SIM_EDEVICE, "hipGetDevice failed");
+        delete S;
+        return nullptr;
+    }
+    if (ctx && ctx->device != S->device) {
+        fail(SIM_EINVAL, "the context's buffer is on device %d, device %d is current",
+             ctx->device, S->device);
         delete S;
         return nullptr;
     }
@@ -521,6 +679,8 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
                 rc = dmalloc(S, (void **)&S->desc[k].plane_off, 8 * 2 * ns);
             if (!rc)
                 rc = dmalloc(S, (void **)&S->desc[k].segnorm, 8 * ns);
+            if (!rc)
+                rc = dmalloc(S, (void **)&S->desc[k].bscale, 8 * nb);
             if (!rc && hipMemset(S->arena[k], 0, kArenaBase) != hipSuccess)
                 rc = fail(SIM_EDEVICE, "arena initialisation failed");
         }
@@ -555,6 +715,8 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
         g_err = keep;
         return nullptr;
     }
+    if (ctx)
+        ctx->nsims++;
     return S;
 }
 
@@ -573,6 +735,77 @@ sim_t *sim_create_ex(int n_qubits, int block_log2, double error_bound,
     return create(n_qubits, block_log2, error_bound, arena_bytes, hip_stream);
 }
 
+int sim_context_create(void *dev_buf, size_t bytes, void *hip_stream, sim_ctx_t **ctx)
+{
+    g_code = SIM_OK;
+    if (!ctx)
+        return fail(SIM_EINVAL, "ctx is NULL");
+    *ctx = nullptr;
+    if (!dev_buf || bytes < 4096)
+        return fail(SIM_EINVAL, "a context needs a device buffer of at least 4096 bytes");
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, dev_buf) != hipSuccess ||
+        at.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(SIM_EINVAL, "dev_buf is not device memory");
+    }
+    sim_ctx *C = new (std::nothrow) sim_ctx();
+    if (!C)
+        return fail(SIM_ENOMEM, "host allocation failed");
+    // 256-byte aligned start; the tail that is not a multiple of 256 is unused
+    const uint64_t a0 = ((uint64_t)(uintptr_t)dev_buf + 255) & ~255ull;
+    const uint64_t skip = a0 - (uint64_t)(uintptr_t)dev_buf;
+    C->base = (uint8_t *)(uintptr_t)a0;
+    C->cap = bytes > skip ? ((bytes - skip) & ~255ull) : 0;
+    C->stream = (hipStream_t)hip_stream;
+    C->device = at.device;
+    if (C->cap)
+        C->free_[0] = C->cap;
+    *ctx = C;
+    return SIM_OK;
+}
+
+int sim_context_destroy(sim_ctx_t *C)
+{
+    if (!C)
+        return fail(SIM_EINVAL, "ctx is NULL");
+    if (C->nsims)
+        return fail(SIM_EINVAL, "%d sims created in the context are still alive", C->nsims);
+    delete C;
+    return SIM_OK;
+}
+
+int sim_context_info(const sim_ctx_t *C, uint64_t *capacity, uint64_t *used, uint64_t *peak,
+                     uint64_t *largest_free)
+{
+    if (!C)
+        return fail(SIM_EINVAL, "ctx is NULL");
+    if (capacity)
+        *capacity = C->cap;
+    if (used)
+        *used = C->used;
+    if (peak)
+        *peak = C->peak;
+    if (largest_free)
+        *largest_free = C->largest_free();
+    return SIM_OK;
+}
+
+int sim_create_in(sim_ctx_t *ctx, int n_qubits, int block_log2, double error_bound,
+                  uint64_t arena_bytes, sim_t **out)
+{
+    if (!out)
+        return fail(SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx)
+        return fail(SIM_EINVAL, "ctx is NULL");
+    sim *S = create(n_qubits, block_log2, error_bound, arena_bytes, ctx->stream, ctx);
+    if (!S)
+        return g_code ? g_code : SIM_EDEVICE;
+    *out = S;
+    return SIM_OK;
+}
+
 void sim_destroy(sim_t *S)
 {
     if (!S)
@@ -580,6 +813,8 @@ void sim_destroy(sim_t *S)
     (void)hipStreamSynchronize(S->stream);
     delete S->prof;
     free_all(S);
+    if (S->ctx)
+        S->ctx->nsims--;
     if (S->own_stream)
         (void)hipStreamDestroy(S->stream);
     delete S;
@@ -608,6 +843,8 @@ int sim_apply_gate(sim_t *S, const sim_gate_t *gate)
         launch_mean(a, ldexp(1.0, 1 - S->n), &S->dev->tdiff[0], S->stream, S->prof);
     launch_pass(a, S->grid_cap, S->stream, S->prof);
     HIPCHK(hipGetLastError());
+    if (a.sc_skip)
+        S->scaled = true;
     S->cur = out;
     S->passes++;
     return SIM_OK;
@@ -652,6 +889,18 @@ int sim_set_aalc(sim_t *S, const double *ladder, int L, double theta)
     return SIM_OK;
 }
 
+int sim_set_shortcut(sim_t *S, int flags)
+{
+    if (!S)
+        return fail(SIM_EINVAL, "sim is NULL");
+    if (flags & ~(SIM_SC_PERMUTE | SIM_SC_SKIP))
+        return fail(SIM_EINVAL, "unknown shortcut flags %d", flags);
+    if (!S->compressed)
+        return fail(SIM_EUNSUPPORTED, "the uncompressed path has no shortcuts");
+    S->shortcut = flags;
+    return SIM_OK;
+}
+
 int sim_set_normalize(sim_t *S, int on)
 {
     if (!S)
@@ -690,9 +939,12 @@ int sim_get_amplitudes(sim_t *S, uint64_t first, uint64_t count, double *out)
     if (rc && rc != SIM_ECOLLAPSED)
         return rc;
     const uint64_t step = 1ull << 24;
-    double *buf = nullptr;
     const uint64_t bcount = count < step ? count : step;
-    HIPCHK(hipMalloc((void **)&buf, 16 * bcount));
+    Tmp tb(S);
+    int ra = tb.get(16 * bcount);
+    if (ra)
+        return ra;
+    double *buf = (double *)tb.p;
     PassArgs a = make_args(S, S->cur, 1 - S->cur, GateArg{});
     for (uint64_t off = 0; off < count; off += step) {
         const uint64_t c = count - off < step ? count - off : step;
@@ -701,12 +953,9 @@ int sim_get_amplitudes(sim_t *S, uint64_t first, uint64_t count, double *out)
                                       S->stream);
         if (e == hipSuccess)
             e = hipStreamSynchronize(S->stream);
-        if (e != hipSuccess) {
-            (void)hipFree(buf);
+        if (e != hipSuccess)
             return fail(SIM_EDEVICE, "decode range: %s", hipGetErrorString(e));
-        }
     }
-    HIPCHK(hipFree(buf));
     return rc;
 }
 
@@ -729,15 +978,17 @@ int sim_export_block(sim_t *S, uint64_t j, void *buf, size_t cap, size_t *len)
     *len = l;
     if (cap < l || !buf)
         return fail(SIM_ENOMEM, "buffer of %zu bytes too small for %u", cap, l);
-    uint8_t *stage = nullptr;
-    HIPCHK(hipMalloc((void **)&stage, l));
+    Tmp ts(S);
+    int ra = ts.get(l);
+    if (ra)
+        return ra;
+    uint8_t *stage = (uint8_t *)ts.p;
     launch_export(make_args(S, S->cur, 1 - S->cur, GateArg{}), j, stage, S->stream);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
         e = hipMemcpyAsync(buf, stage, l, hipMemcpyDeviceToHost, S->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(S->stream);
-    (void)hipFree(stage);
     if (e != hipSuccess)
         return fail(SIM_EDEVICE, "export: %s", hipGetErrorString(e));
     return rc;
@@ -798,8 +1049,11 @@ int sim_export_headers(sim_t *S, uint64_t first, uint64_t count, void *buf, size
     int rc = sync_state(S);
     if (rc && rc != SIM_ECOLLAPSED)
         return rc;
-    uint8_t *stage = nullptr;
-    HIPCHK(hipMalloc((void **)&stage, 32 * count));
+    Tmp ts(S);
+    int ra = ts.get(32 * count);
+    if (ra)
+        return ra;
+    uint8_t *stage = (uint8_t *)ts.p;
     launch_export_headers(make_args(S, S->cur, 1 - S->cur, GateArg{}), first, count, stage,
                           S->stream);
     hipError_t e = hipGetLastError();
@@ -807,7 +1061,6 @@ int sim_export_headers(sim_t *S, uint64_t first, uint64_t count, void *buf, size
         e = hipMemcpyAsync(buf, stage, 32 * count, hipMemcpyDeviceToHost, S->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(S->stream);
-    (void)hipFree(stage);
     if (e != hipSuccess)
         return fail(SIM_EDEVICE, "export headers: %s", hipGetErrorString(e));
     return rc;
@@ -879,6 +1132,7 @@ int sim_import_state(sim_t *S, const void *buf, size_t len)
     const uint8_t *p = (const uint8_t *)buf;
     std::vector<uint64_t> boff(nb);
     uint64_t pos = 0;
+    bool scaled_any = false;
     for (uint64_t j = 0; j < nb; ++j) {
         if (len - pos < kHdrBytes)
             return fail(SIM_EINVAL, "stream of block %llu truncated", (unsigned long long)j);
@@ -889,9 +1143,21 @@ int sim_import_state(sim_t *S, const void *buf, size_t len)
         memcpy(&total, h + 12, 4);
         memcpy(&delta, h + 16, 8);
         const int level = h[4];
-        if (magic != kMagic || h[5] != 0 || h[6] != S->s || h[7] != S->b)
-            return fail(SIM_EINVAL, "block %llu: bad magic or geometry (s %d, b %d expected)",
-                        (unsigned long long)j, S->s, S->b);
+        if (magic != kMagic || (h[5] & ~kHdrScaled) != 0 || h[6] != S->s || h[7] != S->b)
+            return fail(SIM_EINVAL, "block %llu: bad magic, flags or geometry (s %d, b %d "
+                        "expected)", (unsigned long long)j, S->s, S->b);
+        if (h[5] & kHdrScaled) {
+            // a deferred scale c after the header: finite, > 0 and not 1
+            double c = 0.0;
+            if (total < kHdrBytes + kScaleBytes || total > len - pos)
+                return fail(SIM_EINVAL, "block %llu: stream length %u invalid",
+                            (unsigned long long)j, total);
+            memcpy(&c, h + kHdrBytes, 8);
+            if (!std::isfinite(c) || !(c > 0.0) || c == 1.0)
+                return fail(SIM_EINVAL, "block %llu: invalid deferred scale %.17g",
+                            (unsigned long long)j, c);
+            scaled_any = true;
+        }
         if (level >= S->lad.L || memcmp(&delta, &S->lad.delta[level], 8) != 0)
             return fail(SIM_EINVAL, "block %llu: level %d with bound %.17g is not a level of "
                         "this sim's ladder", (unsigned long long)j, level, delta);
@@ -948,6 +1214,7 @@ int sim_import_state(sim_t *S, const void *buf, size_t len)
     S->par = out;
     S->passes = 0;
     S->valid = true;
+    S->scaled = scaled_any;
     return sync_check(S);
 }
 
@@ -1075,17 +1342,14 @@ int sim_measure_probs(sim_t *S, const int *qubits, int nq, double *probs)
     rc = S->compressed ? sync_state(S) : SIM_OK;
     if (rc && rc != SIM_ECOLLAPSED)
         return rc;
-    int *dq = nullptr;
-    double *dp = nullptr;
     const size_t nb = (size_t)1 << nq;
-    HIPCHK(hipMalloc((void **)&dq, sizeof(int) * nq));
-    if (hipMalloc((void **)&dp, 8 * nb) != hipSuccess) {
-        (void)hipFree(dq);
-        return fail(SIM_ENOMEM, "probability buffer");
-    }
+    Tmp tp(S);
+    int ra = tp.get(8 * nb + 256);
+    if (ra)
+        return ra;
+    double *dp = (double *)tp.p;
+    int *dq = (int *)((uint8_t *)tp.p + 8 * nb);
     hipError_t e = probs_into(S, dq, dp, qubits, nq, probs);
-    (void)hipFree(dq);
-    (void)hipFree(dp);
     if (e != hipSuccess)
         return fail(SIM_EDEVICE, "measure: %s", hipGetErrorString(e));
     return rc;
@@ -1136,8 +1400,11 @@ int sim_fidelity(sim_t *A, sim_t *B, double *F)
     const int n = A->n;
     const int S = n < kMaxS ? n : kMaxS;
     const uint64_t nr = 1ull << (n - S);
-    double *part = nullptr;
-    HIPCHK(hipMalloc((void **)&part, 8 * (4 * nr + 8)));
+    Tmp tp(A);
+    int rt = tp.get(8 * (4 * nr + 8));
+    if (rt)
+        return rt;
+    double *part = (double *)tp.p;
     PassArgs pa = A->compressed ? make_args(A, A->cur, 1 - A->cur, GateArg{}) : PassArgs{};
     PassArgs pb = B->compressed ? make_args(B, B->cur, 1 - B->cur, GateArg{}) : PassArgs{};
     pa.geo.n = n;
@@ -1149,7 +1416,6 @@ int sim_fidelity(sim_t *A, sim_t *B, double *F)
         e = hipMemcpyAsync(res, part + 4 * nr, sizeof res, hipMemcpyDeviceToHost, A->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(A->stream);
-    (void)hipFree(part);
     if (e != hipSuccess)
         return fail(SIM_EDEVICE, "fidelity: %s", hipGetErrorString(e));
     *F = res[0];
@@ -1169,8 +1435,11 @@ int sim_fourier_overlap(sim_t *S, uint64_t x, double *out)
     const int n = S->n;
     const int Sg = n < kMaxS ? n : kMaxS;
     const uint64_t nr = 1ull << (n - Sg);
-    double *part = nullptr;
-    HIPCHK(hipMalloc((void **)&part, 8 * (3 * nr + 4)));
+    Tmp tp(S);
+    int rt = tp.get(8 * (3 * nr + 4));
+    if (rt)
+        return rt;
+    double *part = (double *)tp.p;
     PassArgs pa = S->compressed ? make_args(S, S->cur, 1 - S->cur, GateArg{}) : PassArgs{};
     pa.geo.n = n;
     launch_fourier(pa, S->compressed ? nullptr : S->amp, x, part, part + 3 * nr, S->stream);
@@ -1180,7 +1449,6 @@ int sim_fourier_overlap(sim_t *S, uint64_t x, double *out)
                            S->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(S->stream);
-    (void)hipFree(part);
     if (e != hipSuccess)
         return fail(SIM_EDEVICE, "fourier overlap: %s", hipGetErrorString(e));
     return rc;
@@ -1334,7 +1602,7 @@ void destroy_graph(sim_batch::Graph &G)
 }
 
 BatchLaunch slot_launch(const sim_batch *B, int p, uint32_t nst, unsigned gu, unsigned gb,
-                        bool mean, bool ladder)
+                        bool mean, bool ladder, bool sc)
 {
     const uint8_t *base = B->dslots + (size_t)p * B->slot_bytes;
     const uint64_t *pre = (const uint64_t *)(base + slot_prefix_off(B->max_states));
@@ -1350,6 +1618,7 @@ BatchLaunch slot_launch(const sim_batch *B, int p, uint32_t nst, unsigned gu, un
     L.grid_blocks = gb;
     L.any_mean = mean;
     L.any_ladder = ladder;
+    L.any_sc = sc;
     return L;
 }
 
@@ -1437,7 +1706,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
                     count, passes, B->max_states, B->max_passes);
     // validate everything before queuing anything
     uint64_t units = 0, blocks = 0;
-    bool ladder = false;
+    bool ladder = false, sc = false;
     for (int k = 0; k < count; ++k) {
         sim *S = sims[k];
         if (!S)
@@ -1452,6 +1721,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
         units += S->geo.nunits;
         blocks += S->geo.nblocks;
         ladder = ladder || S->lad.L > 1;
+        sc = sc || S->scaled || (S->shortcut & SIM_SC_SKIP);
         for (int p = 0; p < passes; ++p) {
             const sim_gate_t *g = &gates[(size_t)p * count + k];
             if (g->kind == 0 && g->pad == 0)
@@ -1461,7 +1731,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
                 return fail(rc, "pass %d, sims[%d]: %s", p, k, std::string(g_err).c_str());
         }
     }
-    const unsigned gu = (unsigned)(units < kMaxBatchGrid ? units : kMaxBatchGrid);
+    const unsigned gu = unit_grid_for(units, kMaxBatchGrid);
     const unsigned gb = (unsigned)(blocks < (1u << 20) ? blocks : (1u << 20));
     // the host mirror may still be the source of the previous upload
     HIPCHK(hipEventSynchronize(B->uploaded));
@@ -1476,7 +1746,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
     put((uint64_t)count);
     put((uint64_t)passes);
     put((uint64_t)gu | ((uint64_t)gb << 32));
-    put((uint64_t)ladder);
+    put((uint64_t)ladder | ((uint64_t)sc << 1));
     std::vector<uint8_t> mean_of(passes, 0);
     for (int p = 0; p < passes; ++p) {
         uint8_t *slot = B->hslots + (size_t)p * B->slot_bytes;
@@ -1494,6 +1764,8 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
                 args[k] = make_args(S, S->cur, 1 - S->cur, to_arg(g));
                 S->cur = 1 - S->cur;
                 S->passes++;
+                if (args[k].sc_skip)
+                    S->scaled = true;
             } else {
                 GateArg none{};
                 args[k] = make_args(S, S->cur, 1 - S->cur, none);
@@ -1543,7 +1815,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
             HIPCHK(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
             for (int p = 0; p < passes; ++p)
                 launch_batch_pass(slot_launch(B, p, (uint32_t)count, gu, gb, mean_of[p] != 0,
-                                              ladder),
+                                              ladder, sc),
                                   B->stream, nullptr);
             hipError_t e = hipStreamEndCapture(B->stream, &fresh.g);
             if (e == hipSuccess)
@@ -1561,7 +1833,7 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
     } else {
         for (int p = 0; p < passes; ++p)
             launch_batch_pass(slot_launch(B, p, (uint32_t)count, gu, gb, mean_of[p] != 0,
-                                          ladder),
+                                          ladder, sc),
                               B->stream, B->prof);
         HIPCHK(hipGetLastError());
     }

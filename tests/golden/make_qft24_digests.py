@@ -1,8 +1,9 @@
 """Write tests/golden/qft24_digests.json from the CPU oracle alone.
 
 For the 24-qubit QFT workload (blocks of 2^16, seeded random basis state),
-for each listed (error bound, theta) with the default ladder, the oracle runs
-Alg. 2 gate by gate; after the basis encode and after every gate it records
+for each listed (error bound, theta, shortcut flags) with the default ladder,
+the oracle runs Alg. 2 gate by gate (with the Sec. V shortcuts when the flags
+say so); after the basis encode and after every gate it records
 the SHA-256 of the whole state (every block stream, block 0 first), N^2 and
 the level histogram.  The GPU parity test compares its own streams with these
 digests after every gate.  Only oracle/ and the seeded input generator are
@@ -22,15 +23,16 @@ sys.path.insert(0, ROOT)
 from oracle import oracle as orc  # noqa: E402
 from paper_1811_05140_amd import inputs as I  # noqa: E402
 
-CONFIGS = [(1e-4, 4.0), (1e-3, 16.0), (1e-5, 16.0)]
+CONFIGS = [(1e-4, 4.0, 0), (1e-3, 16.0, 0), (1e-5, 16.0, 0), (1e-4, 4.0, 3)]
 OUT = os.path.join(HERE, "qft24_digests.json")
 
 
-def run(delta, theta):
+def run(delta, theta, shortcut):
     w = I.qft24_workload()
     n, b = w["n"], w["b"]
     lad = I.default_ladder(delta)
     sim = orc.OracleSim(n, b, lad, theta)
+    sim.set_shortcut(shortcut)
     sim.set_basis(w["basis"])
     digests, normsq, hist = [], [], []
 
@@ -47,7 +49,7 @@ def run(delta, theta):
             raise RuntimeError("oracle rc %d" % rc)
         record()
     return {"n": n, "b": b, "basis": w["basis"], "delta": delta, "theta": theta,
-            "ladder": lad, "gates": len(w["gates"]),
+            "shortcut": shortcut, "ladder": lad, "gates": len(w["gates"]),
             "sha256_after_gate": digests, "normsq_after_gate": normsq,
             "level_hist_after_gate": hist}
 
@@ -58,10 +60,11 @@ def main():
                    "QFT workload after the basis encode (entry 0) and after "
                    "each gate (entry k), from the CPU oracle",
            "configs": []}
-    for delta, theta in CONFIGS:
+    for delta, theta, shortcut in CONFIGS:
         t0 = time.time()
-        out["configs"].append(run(delta, theta))
-        print("delta %g theta %g: %.1f s" % (delta, theta, time.time() - t0), flush=True)
+        out["configs"].append(run(delta, theta, shortcut))
+        print("delta %g theta %g shortcut %d: %.1f s" % (delta, theta, shortcut,
+                                                       time.time() - t0), flush=True)
     with open(OUT, "w") as f:
         json.dump(out, f, indent=0)
         f.write("\n")

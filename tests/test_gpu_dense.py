@@ -5,7 +5,7 @@
   equals the oracle's, stored in tests/golden/qft24_digests.json by
   tests/golden/make_qft24_digests.py (oracle only), together with N^2 and the
   level histogram, for the default ladder at (1e-4, theta 4), (1e-3, 16) and
-  (1e-5, 16).
+  (1e-5, 16), and at (1e-4, 4) with both Sec. V shortcuts.
 * Blocks of 2^17 and 2^18 amplitudes (128 and 256 segments per block, the
   block-wide decision instance for large blocks) in dense random states,
   every gate kind, theta 4 and 16 so that replays and escalations occur:
@@ -13,6 +13,8 @@
   sim_apply_gate and through sim_batch_apply.
 * Marginal probabilities of a dense random state (not uniform) under a
   non-monotone qubit list, against the oracle.
+* Planes with whole steps of +0, -0 and values below some ladder bounds
+  (what the codec skips), every gate.
 """
 import hashlib
 import json
@@ -53,7 +55,7 @@ def _digests():
 
 
 def _cfg_id(c):
-    return "eb%g-theta%g" % (c["delta"], c["theta"])
+    return "eb%g-theta%g-sc%d" % (c["delta"], c["theta"], c.get("shortcut", 0))
 
 
 @pytest.mark.parametrize("cfg", _digests(), ids=_cfg_id)
@@ -67,6 +69,7 @@ def test_qft24_every_gate_digests(A, cfg):
     L = len(lad)
     say("qft24 every gate, delta", cfg["delta"], "theta", cfg["theta"])
     g = A.Sim(n, b, cfg["delta"], ladder=lad, theta=cfg["theta"])
+    g.set_shortcut(cfg.get("shortcut", 0))
     g.set_basis(w["basis"])
 
     def check(k, where):
@@ -206,3 +209,31 @@ def test_probs_of_a_dense_random_state(A):
         po = o.measure_probs(qs)
         assert np.max(np.abs(po - np.full_like(po, po.mean()))) > 1e-4  # not uniform
         assert np.max(np.abs(pg - po)) < 1e-12, qs
+
+
+@pytest.mark.parametrize("theta", [4.0, 32.0])
+def test_steps_of_zeros_and_small_values(A, theta):
+    """Planes whose 256-scalar steps are all +0, all -0 or hold values below
+    some ladder bounds but not others (the codec's step skips): a superposition
+    over qubits 0..7 only, then small rotations that move a little amplitude
+    (1e-9 .. 1e-3 of it) into the empty steps, diagonal gates that turn +0
+    into -0, and the reverse; streams after every gate equal the oracle's."""
+    n, b = 12, 10
+    gates = [I.h(q) for q in range(8)]
+    for k, eps in enumerate([1e-9, 3e-7, 2e-6, 5e-5, 1e-3]):
+        c, s_ = math.cos(eps), math.sin(eps)
+        gates.append(I.u_gate(8 + (k % 2), (c, 0.0, -s_, 0.0, s_, 0.0, c, 0.0)))
+        gates.append(I.diag1(10 + (k % 2), -1.0, 0.0))       # +0 -> -0 where the bit is 1
+        gates.append(I.cphase(k % 8, 9, math.pi * (k + 1) / 7))
+        gates.append(I.u_gate(11, (0.0, 0.0, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0)))
+    gates.append(I.h(9))
+    say("step skips", n, b, theta, len(gates))
+    for lad in (I.default_ladder(1e-4), I.default_ladder(1e-3), [0.0]):
+        g = A.Sim(n, b, lad[-1], ladder=lad, theta=theta)
+        o = orc.OracleSim(n, b, lad, theta)
+        for k, gate in enumerate(gates):
+            g.apply(gate)
+            o.apply(gate)
+            assert g.export_state() == o.export_state(), (lad, k, gate[:3])
+        assert g.stats()["level_hist"] == o.stats()["level_hist"]
+        g.close()
