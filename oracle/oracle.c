@@ -123,6 +123,147 @@ static uint64_t zigzag(uint64_t c)
 }
 static uint64_t unzigzag(uint64_t z) { return (z >> 1) ^ (0 - (z & 1)); }
 
+/* ---- pointwise-relative levels (the log transform of Sec. III's [xin2018]
+ * reference, SZ's relative mode): a ladder entry delta < 0 is the relative
+ * bound eps = -delta; a value x != 0 is coded through log2|x| quantised with
+ * an absolute bound dL in the log domain, its sign in the code's low bit.
+ * With dL = fl(1.4 eps) < log2(1 + eps) (for eps <= 0.05), a log-domain error
+ * within dL keeps |x - xhat| below eps |x|; the check below is what bounds
+ * every stored value, a value that fails it is an outlier.
+ *
+ * clog2 / cexp2 are this codec's logarithm and power of two, built from
+ * IEEE additions, multiplications and one division, each one rounding, in
+ * a fixed order (the GPU evaluates the same operations): accurate to a few
+ * ulps, which only decides how rarely the check fails. */
+#define REL_QOFF 268435456.0   /* 2^28: offset of log codes, so codes are >= 1 */
+#define REL_QRANGE 268435455.0 /* |y| < 2^28 - 1: codes 2 (q + 2^28) + sign <= 2^30 - 1 */
+
+/* log2 a for finite a > 0: a = m 2^k with m in [sqrt(1/2), sqrt(2)),
+ * ln m = 2 atanh(t), t = (m - 1)/(m + 1), by its odd series to t^15. */
+static double clog2(double a)
+{
+    uint64_t bits = dbits(a);
+    int e = (int)((bits >> 52) & 0x7FF);
+    if (e == 0) { /* subnormal: scale by 2^54 first (exact) */
+        bits = dbits(a * 0x1p54);
+        e = (int)((bits >> 52) & 0x7FF) - 54;
+    }
+    double m = bitsd((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull);
+    int k = e - 1023;
+    if (m > 0x1.6a09e667f3bcdp+0) { /* m > sqrt 2 */
+        m = m * 0.5;
+        k = k + 1;
+    }
+    double t = (m - 1.0) / (m + 1.0);
+    double t2 = t * t;
+    double p = 0x1.1111111111111p-4; /* 1/15 */
+    p = p * t2 + 0x1.3b13b13b13b14p-4;   /* 1/13 */
+    p = p * t2 + 0x1.745d1745d1746p-4;   /* 1/11 */
+    p = p * t2 + 0x1.c71c71c71c71cp-4;   /* 1/9 */
+    p = p * t2 + 0x1.2492492492492p-3;   /* 1/7 */
+    p = p * t2 + 0x1.999999999999ap-3;   /* 1/5 */
+    p = p * t2 + 0x1.5555555555555p-2;   /* 1/3 */
+    p = p * t2 + 1.0;
+    double lnm = (2.0 * t) * p;
+    return (double)k + lnm * 0x1.71547652b82fep+0; /* 1/ln 2 */
+}
+
+/* 2^y for finite y: y = k + f, f in [-1/2, 1/2], 2^f = e^(f ln 2) by its
+ * Taylor series to the 13th power, then scaled by 2^k (exactly, or with one
+ * rounding into the subnormals). */
+static double cexp2(double y)
+{
+    double k = floor(y);
+    double f = y - k;
+    if (f > 0.5) {
+        f = f - 1.0;
+        k = k + 1.0;
+    }
+    double z = f * 0x1.62e42fefa39efp-1; /* ln 2 */
+    double p = 0x1.6124613a86d09p-33; /* 1/13! */
+    p = p * z + 0x1.1eed8eff8d898p-29; /* 1/12! */
+    p = p * z + 0x1.ae64567f544e4p-26; /* 1/11! */
+    p = p * z + 0x1.27e4fb7789f5cp-22; /* 1/10! */
+    p = p * z + 0x1.71de3a556c734p-19; /* 1/9! */
+    p = p * z + 0x1.a01a01a01a01ap-16; /* 1/8! */
+    p = p * z + 0x1.a01a01a01a01ap-13; /* 1/7! */
+    p = p * z + 0x1.6c16c16c16c17p-10; /* 1/6! */
+    p = p * z + 0x1.1111111111111p-7;  /* 1/5! */
+    p = p * z + 0x1.5555555555555p-5;  /* 1/4! */
+    p = p * z + 0x1.5555555555555p-3;  /* 1/3! */
+    p = p * z + 0.5;
+    p = p * z + 1.0;
+    p = p * z + 1.0;
+    if (k > 1023.0)
+        return INFINITY;
+    if (k < -1022.0) { /* two steps: the second rounds into the subnormals */
+        if (k < -1100.0)
+            return 0.0;
+        double two = bitsd((uint64_t)((int)k + 600 + 1023) << 52);
+        return (p * two) * 0x1p-600;
+    }
+    return p * bitsd((uint64_t)((int)k + 1023) << 52);
+}
+
+double or_codec_log2(double a) { return clog2(a); }
+double or_codec_exp2(double y) { return cexp2(y); }
+
+/* Log-domain step of the relative bound eps: eL = 2 fl(1.4 eps). */
+static double rel_step(double eps)
+{
+    double dl = 1.4 * eps;
+    return 2.0 * dl;
+}
+
+/* Value of relative-level code c (c = 0: +0; else sign in bit 0, log code
+ * (c >> 1) - 2^28 in steps of eL). */
+static double rel_value(int64_t c, double eL)
+{
+    if (c == 0)
+        return 0.0;
+    double qv = (double)((c >> 1) - (int64_t)REL_QOFF);
+    double mag = cexp2(qv * eL);
+    return (c & 1) ? -mag : mag;
+}
+
+/* Code, outlier flag and decoded value of x at relative bound eps. */
+static void rel_quantize(double x, double eps, double eL, double rL, int64_t *code,
+                         uint8_t *out)
+{
+    if (x == 0.0) { /* +0 and -0: code 0, decoded +0, error 0 */
+        *code = 0;
+        *out = 0;
+        return;
+    }
+    if (!isfinite(x)) {
+        *code = 0;
+        *out = 1;
+        return;
+    }
+    double a = fabs(x);
+    double y = clog2(a) * rL;
+    if (!(fabs(y) < REL_QRANGE)) {
+        *code = 0;
+        *out = 1;
+        return;
+    }
+    double qr = nearbyint(y);
+    int64_t c = 2 * ((int64_t)qr + (int64_t)REL_QOFF) + (x < 0.0 ? 1 : 0);
+    double xh = rel_value(c, eL);
+    *code = c;
+    *out = !(fabs(x - xh) < eps * a);
+}
+
+/* A stream's error bound: 0 (lossless), an absolute bound > 0, or a
+ * relative one -eps with eps in [2^-19, 0.05] (from 2^-19 on, the log codes
+ * cover every finite nonzero double: 2^28 fl(2 fl(1.4 eps)) > 1075). */
+static int delta_valid(double delta)
+{
+    if (delta >= 0.0)
+        return isfinite(delta);
+    return delta >= -0.05 && delta <= -0x1p-19;
+}
+
 /* Quantise one plane of m scalars at error bound delta.
  * Lossy (delta > 0), reading of Sec. III's bound D_i - delta <= D'_i <=
  * D_i + delta, applied per real component:
@@ -135,6 +276,17 @@ static uint64_t unzigzag(uint64_t z) { return (z >> 1) ^ (0 - (z & 1)); }
 static void quantize_plane(const double *v, size_t m, double delta,
                            uint64_t *q, uint8_t *outl)
 {
+    if (delta < 0.0) { /* relative bound eps = -delta */
+        double eps = -delta;
+        double eL = rel_step(eps);
+        double rL = 1.0 / eL;
+        for (size_t i = 0; i < m; i++) {
+            int64_t c;
+            rel_quantize(v[i], eps, eL, rL, &c, &outl[i]);
+            q[i] = (uint64_t)c;
+        }
+        return;
+    }
     if (delta == 0.0) {
         for (size_t i = 0; i < m; i++) {
             q[i] = dbits(v[i]);
@@ -300,6 +452,8 @@ static size_t decode_plane(const uint8_t *p, const uint8_t *end, size_t m,
             qprev = q;
             if (delta == 0.0)
                 v[i * stride] = bitsd(q);
+            else if (delta < 0.0)
+                v[i * stride] = rel_value((int64_t)q, rel_step(-delta));
             else
                 v[i * stride] = (double)(int64_t)q * (2.0 * delta);
         }
@@ -348,7 +502,7 @@ int or_decode_block(const uint8_t *stream, size_t len, double *x)
     if (rd_u32(stream + 12) != len)
         return OR_EINVAL;
     double delta = rd_f64(stream + 16);
-    if (!(delta >= 0.0))
+    if (!delta_valid(delta))
         return OR_EINVAL;
     if ((stream[5] & ~OR_HDR_SCALED) || stream_scale(stream, len) == 0.0)
         return OR_EINVAL;
@@ -448,7 +602,7 @@ static int encode_block_obuf(obuf *o, const double *x, int b, int s,
 int or_encode_block(const double *x, int b, int s, double delta, int level,
                     uint8_t *out, size_t cap, size_t *len)
 {
-    if (s < 6 || b < s || b > 30 || !(delta >= 0.0) || level < 0 || level > 255)
+    if (s < 6 || b < s || b > 30 || !delta_valid(delta) || level < 0 || level > 255)
         return OR_EINVAL;
     obuf o = {0};
     int rc = encode_block_obuf(&o, x, b, s, delta, level);
@@ -497,19 +651,31 @@ static int aalc_encode_obuf(obuf *out, const double *x, int b, int s,
     return OR_EINVAL;
 }
 
+/* A ladder: optionally lossless first (0), then lossy levels of one kind,
+ * absolute bounds (> 0, >= 2^-30) strictly increasing, or relative bounds
+ * (entries -eps with eps in [2^-19, 0.05]) with eps strictly increasing. */
 static int ladder_ok(const double *ladder, int L, double theta)
 {
     if (L < 1 || L > 8 || !(theta >= 1.0) || !isfinite(theta))
         return 0;
+    int kind = 0; /* 1 absolute, -1 relative */
     for (int k = 0; k < L; k++) {
         double d = ladder[k];
-        if (!isfinite(d) || d < 0.0)
+        if (!isfinite(d))
             return 0;
-        if (d == 0.0 && k != 0)
+        if (d == 0.0) {
+            if (k != 0)
+                return 0;
+            continue;
+        }
+        int kk = d > 0.0 ? 1 : -1;
+        if (kind && kk != kind)
             return 0;
-        if (d > 0.0 && d < 0x1p-30)
+        kind = kk;
+        double mag = fabs(d);
+        if (mag < (kk < 0 ? 0x1p-19 : 0x1p-30) || (kk < 0 && mag > 0.05))
             return 0;
-        if (k > 0 && !(d > ladder[k - 1]))
+        if (k > 0 && ladder[k - 1] != 0.0 && !(mag > fabs(ladder[k - 1])))
             return 0;
     }
     return 1;

@@ -166,6 +166,11 @@ int or_set_shortcut(or_sim *sim, int flags);
  * effect (1 when built without OpenMP).  Results do not depend on it. */
 int or_set_threads(int nthreads);
 
+/* The codec's log2 (finite a > 0) and power of two, used by the
+ * pointwise-relative levels (ladder entries -eps): exposed for the tests. */
+double or_codec_log2(double a);
+double or_codec_exp2(double y);
+
 /* Fidelity |<a|b>|^2 / (<a|a><b|b>) of two 2^n complex arrays. */
 double or_fidelity(const double *a, const double *b, int n);
 

@@ -92,8 +92,22 @@ def lib():
         L.or_amplitude_sum.argtypes = [ctypes.c_void_p, dp]
         L.or_import_state.argtypes = [ctypes.c_void_p, u8p, ctypes.c_size_t]
         L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_codec_log2.argtypes = [ctypes.c_double]
+        L.or_codec_log2.restype = ctypes.c_double
+        L.or_codec_exp2.argtypes = [ctypes.c_double]
+        L.or_codec_exp2.restype = ctypes.c_double
         L.or_set_shortcut.argtypes = [ctypes.c_void_p, ctypes.c_int]
     return _lib
+
+
+def codec_log2(a):
+    """The relative levels' log2 of a finite a > 0."""
+    return lib().or_codec_log2(float(a))
+
+
+def codec_exp2(y):
+    """The relative levels' power of two."""
+    return lib().or_codec_exp2(float(y))
 
 
 def set_threads(nthreads):
