@@ -149,6 +149,65 @@ def cpu_baseline(A, orc, inputs, w, eb, budget_s, name):
     }
 
 
+def cpu_baseline_gates(A, orc, inputs, w, eb, stride, shortcut, name):
+    """The CPU oracle on whole gates of the same workload, on all host
+    cores: every `stride`-th gate (from the middle of each run of `stride`)
+    is applied by the oracle to the whole state -- imported from the GPU run
+    just before that gate, which equals the oracle's own state bit for bit --
+    with its block groups spread over the host's threads by OpenMP; each
+    timed gate stands for the `stride` gates around it.  The oracle's output
+    streams are checked against the GPU's after the gate."""
+    import hashlib as hl
+    n, b = w["n"], w["b"]
+    lad = inputs.default_ladder(eb)
+    threads = orc.set_threads(min(os.cpu_count() or 1, 16))
+    sim = A.Sim(n, b, eb)
+    sim.set_shortcut(shortcut)
+    sim.set_basis(w["basis"])
+    osim = orc.OracleSim(n, b, lad, 4.0)
+    osim.set_shortcut(shortcut)
+    gates = w["gates"]
+    times = []
+    same = True
+    for k, gate in enumerate(gates):
+        if k % stride == stride // 2:
+            osim.import_state(sim.export_state())
+            t0 = time.perf_counter()
+            osim.apply(gate)
+            times.append(time.perf_counter() - t0)
+            sim.apply(gate)
+            same = same and (hl.sha256(osim.export_state()).digest() ==
+                             hl.sha256(sim.export_state()).digest())
+        else:
+            sim.apply(gate)
+    sim.close()
+    est = sum(times) * stride * len(gates) / (stride * len(times))
+    return {
+        "value": len(gates) / est,
+        "unit": "gates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": ("%d of the %d %s gates (every %dth), each applied by the oracle to the "
+                   "whole state on %d threads (OpenMP over block groups), the state "
+                   "imported from the GPU run before the gate; timed %.1f s, scaled by %d; "
+                   "oracle streams %s the GPU's after every timed gate" %
+                   (len(times), len(gates), name, stride, threads, sum(times), stride,
+                    "equal to" if same else "DIFFERENT FROM")),
+        "host_cpus": os.cpu_count(),
+        "host_cpu_model": cpu_model(),
+    }
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def calibrate_copy(torch, nbytes, reps):
     """A plain device copy of known size, for scaling HBM counters."""
     x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -248,6 +307,7 @@ def bench_batch64(args, A, inputs, stream):
         # previous level can take up to the raw size before a replay
         sm = A.Sim(inst["n"], b, eb, stream=stream)
         sm.set_grid(grid)
+        sm.set_shortcut(args.shortcut)
         sims.append(sm)
     depth = len(insts[0]["layers"])
     layer_passes = []
@@ -306,14 +366,27 @@ def bench_batch64(args, A, inputs, stream):
     roofline = None
     if "pass" in prof:
         cnt, tot, mn, mx = prof["pass"]
-        # logical bytes of every pass of the step over the k_bpass time
-        achieved = amp_bytes / (tot / 1000.0) / 1e9
+        # algorithmic bytes of every batched pass of the step (each state's
+        # compressed streams in and out plus its per-plane metadata, from an
+        # untimed replay of every instance alone, which gives the same
+        # streams) over the k_bpass time
+        alg = 0
+        for k, inst in enumerate(insts):
+            flat = [g for layer in inst["layers"] for g in layer]
+            alg += pass_stream_bytes(sims[k], 0, flat, inst["n"], conf[k][0],
+                                     count_basis=False)
+        achieved = alg / (tot / 1000.0) / 1e9
+        logical = amp_bytes / (tot / 1000.0) / 1e9
         roofline = {
             "bound": "hbm", "kernel": "pass (batched)", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic("batch64", "bpass"),
             "avg_launch_ms": round(tot / cnt, 4), "launches": cnt,
-            "algorithmic_bytes_per_launch": amp_bytes // cnt,
+            "algorithmic_bytes_per_launch": alg // cnt,
+            "algorithmic_bytes": "compressed streams in + out and per-plane metadata of "
+                                 "every state in the pass, averaged over the step's launches",
+            "logical_gbs": round(logical, 1),
+            "logical_frac": round(logical / HBM_PEAK_GBS, 4),
             "kernels_ms_one_step": {k: round(v[1], 3) for k, v in sorted(prof.items())},
         }
     # fidelity of every instance against its uncompressed run
@@ -327,7 +400,7 @@ def bench_batch64(args, A, inputs, stream):
         ref.close()
     Fs_sorted = sorted(Fs)
     cpu = None
-    if args.cpu_budget > 0:
+    if args.cpu_budget > 0 and not args.shortcut:
         from oracle import oracle as orc
         cpu = cpu_baseline_batch(A, orc, inputs, insts, conf, eb, args.cpu_budget)
     for sm in sims:
@@ -348,9 +421,15 @@ def bench_batch64(args, A, inputs, stream):
                    "n_qubits": [i["n"] for i in insts], "depth": depth,
                    "error_bound": eb, "ladder": lad, "theta": 4.0,
                    "gates_per_step": total_gates, "block_log2_and_grid_by_n": b_by_n,
-                   "autotuned": tuned, "graph_launch_per_layer": True},
+                   "autotuned": tuned, "graph_launch_per_layer": True,
+                   "shortcut": args.shortcut},
+        # the metric's logical amplitude traffic (32 B per amplitude per gate,
+        # what an uncompressed simulator moves) and its fraction of the HBM
+        # peak; the HBM fraction of the bytes the pass really moves is
+        # hbm_frac (the roofline's algorithmic bytes)
         "amplitude_gbs": round(amp_gbs, 1),
-        "hbm_frac": round(amp_gbs / HBM_PEAK_GBS, 4),
+        "logical_frac": round(amp_gbs / HBM_PEAK_GBS, 4),
+        "hbm_frac": roofline["frac"] if roofline else None,
         "one_at_a_time_gates_per_s": round(total_gates / alone_s, 2),
         "batch_speedup": round((total_gates * args.steps / elapsed) / (total_gates / alone_s), 3),
         "alone_equals_batch": same,
@@ -711,7 +790,8 @@ def bench_qft24_sweep(args, A, inputs, stream):
     """QFT-24 over the error bounds {1e-3, 1e-4, 1e-5}: the default ladder at
     ratio thresholds 4, 8, 16 and 32 (the paper's AALC runs vary the
     threshold), and the fixed bound alone (one lossy level, the paper's
-    fixed-bound SZ runs).  Per point: gates/s, amplitude-GB/s and its HBM
+    fixed-bound SZ runs); for 1e-3 and 1e-4 also the pointwise-relative
+    ladder at thresholds 4, 16, 32 and the fixed relative bound.  Per point: gates/s, amplitude-GB/s and its HBM
     fraction, minimum / last compression ratio, peak resident bytes, level
     histogram, replays, and the fidelity against one uncompressed FP64 run."""
     import torch
@@ -724,6 +804,10 @@ def bench_qft24_sweep(args, A, inputs, stream):
     for eb in (1e-3, 1e-4, 1e-5):
         confs = [("aalc", inputs.default_ladder(eb), th) for th in (4.0, 8.0, 16.0, 32.0)]
         confs.append(("fixed", [eb], 4.0))
+        if eb >= 1e-4:
+            # the pointwise-relative bound of the same size (entries -eps)
+            confs += [("relative", inputs.relative_ladder(eb), th) for th in (4.0, 16.0, 32.0)]
+            confs.append(("fixed-relative", [-eb], 4.0))
         for mode, lad, th in confs:
             sim = A.Sim(n, b, eb, stream=stream, ladder=lad, theta=th)
 
@@ -744,9 +828,10 @@ def bench_qft24_sweep(args, A, inputs, stream):
             gbs = gps * LOGICAL_BYTES_PER_AMP * (1 << n) / 1e9
             st = sim.stats()
             F = sim.fidelity(ref)
-            pt = {"error_bound": eb, "mode": mode, "theta": th if mode == "aalc" else None,
+            pt = {"error_bound": eb, "mode": mode, "ladder": lad,
+                  "theta": th if mode in ("aalc", "relative") else None,
                   "gates_per_s": round(gps, 1), "amplitude_gbs": round(gbs, 1),
-                  "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                  "logical_frac": round(gbs / HBM_PEAK_GBS, 4),
                   "min_ratio": round(st["min_ratio"], 3), "last_ratio": round(st["last_ratio"], 3),
                   "peak_resident_bytes": st["peak_resident"], "fidelity": F,
                   "fidelity_ok": bool(F >= 0.999), "collapsed": st["collapsed"],
@@ -771,7 +856,7 @@ def bench_qft24_sweep(args, A, inputs, stream):
     }
 
 
-def pass_stream_bytes(sim, x, gates, n, b):
+def pass_stream_bytes(sim, x, gates, n, b, count_basis=True):
     """Algorithmic HBM bytes of one step's pass launches (the roofline's
     per-launch figure is this over the launches): each pass reads its input
     state's compressed streams and writes its output's, and per plane reads
@@ -783,7 +868,7 @@ def pass_stream_bytes(sim, x, gates, n, b):
     meta = 20 * planes + 8 * (planes // 2)
     sim.set_basis(x)
     prev = sim.stats()["resident_bytes"]
-    total = prev + meta
+    total = prev + meta if count_basis else 0
     for g in gates:
         sim.apply(g)
         cur = sim.stats()["resident_bytes"]
@@ -830,6 +915,11 @@ def main():
                     help="time without per-kernel events (no roofline entry)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a device copy of this many bytes (counters)")
+    ap.add_argument("--shortcut", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="Sec. V shortcuts for qft24 / grover36: 1 permutation "
+                         "levels, 2 skip unchanged blocks, 3 both (default 0: Alg. 2)")
+    ap.add_argument("--cpu-stride", type=int, default=16,
+                    help="qft24 CPU baseline: time every n-th gate on the whole state")
     args = ap.parse_args()
     grover = args.workload == "grover36"
     if args.steps is None:
@@ -872,6 +962,7 @@ def main():
     w = inputs.grover36_workload() if grover else inputs.qft24_workload()
     n, b, x, gates = w["n"], w["b"], w["basis"], w["gates"]
     sim = A.Sim(n, b, eb, stream=stream)
+    sim.set_shortcut(args.shortcut)
 
     def step():
         sim.set_basis(x)
@@ -951,14 +1042,17 @@ def main():
     cpu = None
     if args.cpu_budget > 0:
         from oracle import oracle as orc
-        cpu = cpu_baseline(A, orc, inputs, w, eb, args.cpu_budget,
-                           "Grover-36" if grover else "QFT-24")
+        if grover:
+            cpu = cpu_baseline(A, orc, inputs, w, eb, args.cpu_budget, "Grover-36")
+        else:
+            cpu = cpu_baseline_gates(A, orc, inputs, w, eb, args.cpu_stride, args.shortcut,
+                                     "QFT-24")
 
     config = {
         "workload": args.workload, "n_qubits": n, "block_log2": b,
         "segment_log2": min(b, 10), "error_bound": eb,
         "ladder": inputs.default_ladder(eb), "theta": 4.0,
-        "gates_per_step": len(gates),
+        "gates_per_step": len(gates), "shortcut": args.shortcut,
     }
     if grover:
         config.update({"marked": w["marked"], "iterations": k})
@@ -978,8 +1072,13 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded basis state, generated circuit)",
         "config": config,
+        # the metric's logical amplitude traffic (32 B per amplitude per gate,
+        # what an uncompressed simulator moves) and its fraction of the HBM
+        # peak; the HBM fraction of the bytes the pass really moves is
+        # hbm_frac (the roofline's algorithmic bytes)
         "amplitude_gbs": round(amp_gbs, 1),
-        "hbm_frac": round(amp_gbs / HBM_PEAK_GBS, 4),
+        "logical_frac": round(amp_gbs / HBM_PEAK_GBS, 4),
+        "hbm_frac": roofline["frac"] if roofline else None,
         "fidelity": F,
         "fidelity_ok": bool(F >= 0.999),
         "min_ratio": st["min_ratio"],

@@ -207,10 +207,15 @@ int sim_fidelity(sim_t *a, sim_t *b, double *F);
 /* Replace the state by the basis state |x> (x < 2^n); resets stats. */
 int sim_set_basis(sim_t *sim, uint64_t x);
 
-/* Set the AALC ladder: L (1..8) strictly increasing error bounds, ladder[0]
- * may be 0 (lossless), every lossy bound >= 2^-30, theta >= 1.  Takes effect
- * for the next pass.  SIM_EINVAL otherwise, SIM_EUNSUPPORTED on the
- * uncompressed path. */
+/* Set the AALC ladder: L (1..8) levels, ladder[0] may be 0 (lossless), the
+ * lossy levels all of one kind and growing: absolute bounds delta >= 2^-30
+ * (|x - xhat| < delta per real component, Sec. III), or pointwise-relative
+ * bounds given as -eps with eps in [2^-19, 0.05] and growing eps (|x - xhat|
+ * < eps |x|, zeros kept exactly: log2|x| is quantised in steps of
+ * 2 fl(1.4 eps) with the sign in the code's low bit, after the log transform
+ * of the relative-bound reference the paper builds on; values that miss the
+ * bound are stored exactly).  theta >= 1.  Takes effect for the next pass.
+ * SIM_EINVAL otherwise, SIM_EUNSUPPORTED on the uncompressed path. */
 int sim_set_aalc(sim_t *sim, const double *ladder, int L, double theta);
 
 /* Turn the normalisation before each gate (Sec. III) on (default) or off. */

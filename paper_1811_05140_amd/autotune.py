@@ -94,11 +94,13 @@ def gpu_measure(A, n, ladder, theta, layers=2, reps=2):
     return measure
 
 
-def tune(n, ladder, theta, measure, b_range=B_RANGE, grids=GRIDS):
+def tune(n, ladder, theta, measure, b_range=B_RANGE, grids=GRIDS, progress=None):
     results = []
     for b, g in candidates(n, b_range, grids):
         gps, res = measure(b, g)
         results.append({"b": b, "grid": g, "gates_per_s": gps, "resident_bytes": res})
+        if progress:
+            progress("n=%d b=%d grid=%d: %.1f gates/s" % (n, b, g, gps))
     best = pick(results)
     return {"b": best["b"], "grid": best["grid"], "gates_per_s": best["gates_per_s"],
             "candidates": results}
@@ -146,7 +148,8 @@ def main():
     entries = load_table(args.out)
     for n in ns:
         m = gpu_measure(A, n, ladder, args.theta, layers=args.layers)
-        e = tune(n, ladder, args.theta, m)
+        e = tune(n, ladder, args.theta, m,
+                 progress=lambda t: print(t, file=sys.stderr, flush=True))
         m.close()
         entries[key(n, ladder, args.theta)] = e
         print("n=%d: b=%d grid=%d %.1f gates/s" % (n, e["b"], e["grid"], e["gates_per_s"]),

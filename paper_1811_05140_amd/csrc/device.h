@@ -146,7 +146,7 @@ struct PassArgs {
     // some block of the input may carry a deferred scale (c_j != 1): the
     // unit kernels then read each block's scale (instances with SC = true)
     int32_t sc_scaled;
-    int32_t sc_pad;
+    int32_t sc_rel;      // the ladder has pointwise-relative levels
     uint32_t *psz;       // [L][2*nseg]: payload words | n_outliers << 16
     uint8_t *scratch;    // [scratch_wgs * 4][kScratchWave] staging, by workgroup and wave
     uint64_t scratch_wgs;  // workgroups the staging covers (grids must not exceed it)

@@ -283,6 +283,109 @@ __device__ __forceinline__ uint64_t field64(const uint32_t *P, uint32_t b, uint3
     return w >= 64u ? v : (v & ((1ull << w) - 1ull));
 }
 
+// ---- pointwise-relative levels: a ladder entry delta < 0 is the relative
+// bound eps = -delta.  A value x != 0 is coded through log2|x| quantised in
+// steps eL = 2 fl(1.4 eps) (a log-domain error below fl(1.4 eps) keeps the
+// relative error below eps), code c = 2 (q + 2^28) + sign; c = 0 is +0.
+// Every stored value is checked, |x - xhat| < eps |x|, else an outlier.  The
+// log and the power of two are this codec's own, from IEEE additions,
+// multiplications and one division in a fixed order, so that every device
+// and the CPU reference give the same bits.
+constexpr double kRelOff = 268435456.0;    // 2^28
+constexpr double kRelRange = 268435455.0;  // |y| < 2^28 - 1: codes <= 2^30 - 1
+
+// log2 a for finite a > 0: a = m 2^k with m in [sqrt(1/2), sqrt(2)), then
+// ln m = 2 atanh t, t = (m - 1)/(m + 1), by its odd series up to t^15.
+__device__ double codec_log2(double a)
+{
+    uint64_t bits = (uint64_t)__double_as_longlong(a);
+    int e = (int)((bits >> 52) & 0x7FFu);
+    if (e == 0) {  // subnormal: scale by 2^54 first (exact)
+        bits = (uint64_t)__double_as_longlong(a * 0x1p54);
+        e = (int)((bits >> 52) & 0x7FFu) - 54;
+    }
+    double m = __longlong_as_double(
+        (long long)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+    int k = e - 1023;
+    if (m > 0x1.6a09e667f3bcdp+0) {  // sqrt 2
+        m = m * 0.5;
+        k = k + 1;
+    }
+    const double t = (m - 1.0) / (m + 1.0);
+    const double t2 = t * t;
+    double p = 0x1.1111111111111p-4;  // 1/15
+    p = p * t2 + 0x1.3b13b13b13b14p-4;  // 1/13
+    p = p * t2 + 0x1.745d1745d1746p-4;  // 1/11
+    p = p * t2 + 0x1.c71c71c71c71cp-4;  // 1/9
+    p = p * t2 + 0x1.2492492492492p-3;  // 1/7
+    p = p * t2 + 0x1.999999999999ap-3;  // 1/5
+    p = p * t2 + 0x1.5555555555555p-2;  // 1/3
+    p = p * t2 + 1.0;
+    const double lnm = (2.0 * t) * p;
+    return (double)k + lnm * 0x1.71547652b82fep+0;  // 1/ln 2
+}
+
+// 2^y for finite y: y = k + f with f in [-1/2, 1/2]; 2^f = e^(f ln 2) by its
+// Taylor series up to the 13th power; then times 2^k (exact, or one rounding
+// into the subnormals).
+__device__ double codec_exp2(double y)
+{
+    double k = __builtin_floor(y);
+    double f = y - k;
+    if (f > 0.5) {
+        f = f - 1.0;
+        k = k + 1.0;
+    }
+    const double z = f * 0x1.62e42fefa39efp-1;  // ln 2
+    double p = 0x1.6124613a86d09p-33;          // 1/13!
+    p = p * z + 0x1.1eed8eff8d898p-29;         // 1/12!
+    p = p * z + 0x1.ae64567f544e4p-26;         // 1/11!
+    p = p * z + 0x1.27e4fb7789f5cp-22;         // 1/10!
+    p = p * z + 0x1.71de3a556c734p-19;         // 1/9!
+    p = p * z + 0x1.a01a01a01a01ap-16;         // 1/8!
+    p = p * z + 0x1.a01a01a01a01ap-13;         // 1/7!
+    p = p * z + 0x1.6c16c16c16c17p-10;         // 1/6!
+    p = p * z + 0x1.1111111111111p-7;          // 1/5!
+    p = p * z + 0x1.5555555555555p-5;          // 1/4!
+    p = p * z + 0x1.5555555555555p-3;          // 1/3!
+    p = p * z + 0.5;
+    p = p * z + 1.0;
+    p = p * z + 1.0;
+    if (k > 1023.0)
+        return __longlong_as_double(0x7FF0000000000000ll);  // +inf
+    if (k < -1022.0) {
+        if (k < -1100.0)
+            return 0.0;
+        const double two = __longlong_as_double((long long)((uint64_t)((int)k + 600 + 1023) << 52));
+        return (p * two) * 0x1p-600;
+    }
+    return p * __longlong_as_double((long long)((uint64_t)((int)k + 1023) << 52));
+}
+
+// Step between consecutive codes of a lossy level: 2 delta (absolute), or
+// eL = 2 fl(1.4 eps) in the log domain (relative, delta = -eps).
+__device__ __forceinline__ double level_step(double delta)
+{
+    if (delta > 0.0)
+        return 2.0 * delta;
+    const double dl = 1.4 * -delta;
+    return 2.0 * dl;
+}
+
+// Value of relative-level code c with log step eL.
+__device__ __forceinline__ double rel_value(int32_t c, double eL)
+{
+    const double qv = (double)((c >> 1) - (int32_t)kRelOff);
+    const double mag = codec_exp2(qv * eL);
+    return c == 0 ? 0.0 : ((c & 1) ? -mag : mag);
+}
+
+// Value of code c at a lossy level (e = level_step(delta)).
+__device__ __forceinline__ double dequant(int32_t c, double delta, double e)
+{
+    return delta > 0.0 ? (double)c * e : rel_value(c, e);
+}
+
 // Decode one plane record into dst[0 .. 2^s) (one wavefront; dst is the
 // wave's own LDS plane region), scaling each value by `scale` when do_scale
 // (normalisation before the gate).  Lossy planes run the prefix sums in 32
@@ -293,6 +396,9 @@ __device__ __forceinline__ uint64_t field64(const uint32_t *P, uint32_t b, uint3
 // outliers; the fields are then read from LDS.  A chunk's payload is at most
 // 64 words and its decoded values exactly 64, so the values written in steps
 // 0..t end below the payload of every chunk of a later step.
+// REL: the instance that also decodes relative levels (the pass kernels
+// without it are kept free of that code's registers).
+template <bool REL = true>
 __device__ uint32_t decode_plane(const uint8_t *rec, int s, double delta,
                                  double scale, bool do_scale, double *dst)
 {
@@ -356,7 +462,7 @@ __device__ uint32_t decode_plane(const uint8_t *rec, int s, double delta,
     // offsets); lanes 0..15 of row 0 hold chunks 0..15
     const uint32_t wl = wraw;
     const uint32_t ol = row_scan32(wl) - wl;
-    const double e = 2.0 * delta;
+    const double e = delta != 0.0 ? level_step(delta) : 0.0;
     uint64_t carry = anchor;
     for (int t = 0; t < steps; ++t) {
         const int c = 4 * t + r;
@@ -405,10 +511,19 @@ __device__ uint32_t decode_plane(const uint8_t *rec, int s, double delta,
             const uint32_t incl = wave_scan32(s3);
             const uint32_t ex = incl - s3;
             const int32_t c32 = (int32_t)(uint32_t)carry;
-            x[0] = (double)(c32 + (int32_t)(ex + d[0])) * e;
-            x[1] = (double)(c32 + (int32_t)(ex + s1)) * e;
-            x[2] = (double)(c32 + (int32_t)(ex + s2)) * e;
-            x[3] = (double)(c32 + (int32_t)(ex + s3)) * e;
+            const int32_t q0 = c32 + (int32_t)(ex + d[0]), q1 = c32 + (int32_t)(ex + s1);
+            const int32_t q2 = c32 + (int32_t)(ex + s2), q3 = c32 + (int32_t)(ex + s3);
+            if (!REL || delta > 0.0) {
+                x[0] = (double)q0 * e;
+                x[1] = (double)q1 * e;
+                x[2] = (double)q2 * e;
+                x[3] = (double)q3 * e;
+            } else {
+                x[0] = rel_value(q0, e);
+                x[1] = rel_value(q1, e);
+                x[2] = rel_value(q2, e);
+                x[3] = rel_value(q3, e);
+            }
             carry = (uint64_t)(int64_t)(c32 + (int32_t)__builtin_amdgcn_readlane((int)incl, 63));
         }
         if (active) {
@@ -525,9 +640,35 @@ __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
 
 // Lossy code of one scalar at one level: q the int32 code, `out` the outlier
 // flag, xh the value a decoder reconstructs (the scalar itself for outliers).
+// Code of x at a relative level (delta = -eps, eL = e, rL = r): code 0 for
+// +-0 (decoded +0, never an outlier); non-finite values and log codes out of
+// range become code 0 and outliers; otherwise an outlier iff the decoded
+// value misses |x - xhat| < eps |x| (q is kept in the predictor).
+__device__ __forceinline__ void rel_code(double x, double eps, double eL, double rL,
+                                         int32_t &q, bool &out, double &xh)
+{
+    const double a = fabs(x);
+    const bool zero = a == 0.0;
+    const bool fin = a < __longlong_as_double(0x7FF0000000000000ll);  // false for inf, NaN
+    const double y = codec_log2(fin && !zero ? a : 1.0) * rL;
+    const bool in = fin && !zero && fabs(y) < kRelRange;
+    const double qr = in ? __builtin_rint(y) : 0.0;
+    const int32_t c = in ? 2 * ((int32_t)qr + (int32_t)kRelOff) + (x < 0.0 ? 1 : 0) : 0;
+    const double mag = codec_exp2(in ? qr * eL : 0.0);
+    const double v = in ? (x < 0.0 ? -mag : mag) : 0.0;
+    out = !zero && (!in || !(fabs(x - v) < eps * a));
+    q = c;
+    xh = out ? x : v;
+}
+
+template <bool REL = true>
 __device__ __forceinline__ void lossy_code(double x, double delta, double e, double r,
                                            int32_t &q, bool &out, double &xh)
 {
+    if (REL && delta < 0.0) {
+        rel_code(x, -delta, e, r, q, out, xh);
+        return;
+    }
     // branch-free: a code out of range (or NaN) becomes 0 and an outlier
     const double y = x * r;
     const bool in = fabs(y) < kQMax;
@@ -627,6 +768,9 @@ __device__ __forceinline__ uint32_t size_skip_mask(const StepSum &q, double delt
 {
     if (delta == 0.0)
         return q.zpos;
+    if (delta < 0.0)  // relative: only +-0 has code 0
+        return (q.k0 == 0u ? 1u : 0u) | (q.k1 == 0u ? 2u : 0u) | (q.k2 == 0u ? 4u : 0u) |
+               (q.k3 == 0u ? 8u : 0u);
     const double d = delta;
     return (__hiloint2double((int)q.k0, 0) < d ? 1u : 0u) |
            (__hiloint2double((int)q.k1, 0) < d ? 2u : 0u) |
@@ -649,6 +793,7 @@ __device__ __forceinline__ uint32_t pack_skip_mask(const StepSum &q, double delt
 // so that only one level's state is live).  Returns the (payload words,
 // outliers) word of level `want` when it lies in the range; lane c (< 16)
 // of `wl` then holds that level's width of chunk c.
+template <bool REL>
 __device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k0, int k1,
                                 int want, uint32_t *psz, uint64_t plane, uint64_t nplanes,
                                 uint32_t &wl, const StepSum &sum)
@@ -711,7 +856,7 @@ __device__ uint32_t size_levels(const double *x, int s, const Ladder &lad, int k
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     double xh;
-                    lossy_code(xs[i], delta, e, rr, q[i], out[i], xh);
+                    lossy_code<REL>(xs[i], delta, e, rr, q[i], out[i], xh);
                 }
                 const int32_t prev = (int32_t)dpp32<kWaveShr1>(
                     (uint32_t)(t == 0 ? q[0] : carry), (uint32_t)q[3]);
@@ -769,6 +914,7 @@ __device__ __forceinline__ void or_bits32(uint32_t *pb, uint32_t b, uint32_t v)
 // the first kScratchOutl outliers into the staging list, and x-hat written
 // back over x.  Returns payload words | outliers << 16 (also stored to
 // *psz_slot); wl = width of chunk `lane`; anchor = the plane's first code.
+template <bool REL>
 __device__ uint32_t size_pack_level(double *x, int s, double delta, double e, double r,
                                     uint32_t *psz_slot, uint8_t *stage, uint32_t *pb,
                                     uint32_t &wl, uint64_t &anchor, const StepSum &sum)
@@ -863,7 +1009,7 @@ __device__ uint32_t size_pack_level(double *x, int s, double delta, double e, do
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                lossy_code(xs[i], delta, e, r, q[i], out[i], xh[i]);
+                lossy_code<REL>(xs[i], delta, e, r, q[i], out[i], xh[i]);
             const int32_t prev =
                 (int32_t)dpp32<kWaveShr1>((uint32_t)(t == 0 ? q[0] : (int32_t)carry),
                                           (uint32_t)q[3]);
@@ -968,6 +1114,7 @@ __device__ void emit_record(uint8_t *rec, int s, uint32_t pszv, uint32_t wl, uin
     }
 }
 
+template <bool REL>
 __device__ void encode_plane(double *x, int s, double delta, double e, double r,
                              uint32_t pszv, uint32_t wreg, uint8_t *rec,
                              uint32_t *pb, uint32_t *err)
@@ -1045,7 +1192,7 @@ __device__ void encode_plane(double *x, int s, double delta, double e, double r,
             double xh[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                lossy_code(xs[i], delta, e, r, q[i], out[i], xh[i]);
+                lossy_code<REL>(xs[i], delta, e, r, q[i], out[i], xh[i]);
             const int32_t prev =
                 (int32_t)dpp32<kWaveShr1>((uint32_t)(t == 0 ? q[0] : (int32_t)carry),
                                           (uint32_t)q[3]);
@@ -1415,9 +1562,10 @@ __device__ void zero_unit(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     }
 }
 
-// SC: the instance for passes with the skip shortcut or states that may hold
-// blocks with a deferred scale (reads each block's scale, keeps untouched
-// blocks); the other instance has none of that code.
+// SC: the general instance, for passes with the skip shortcut, states that
+// may hold blocks with a deferred scale (reads each block's scale, keeps
+// untouched blocks) and ladders with relative levels; the other instance has
+// none of that code.
 template <int MODE, bool SC>
 __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, PassLds &S,
                           double scale, const double *tdiff, bool zp,
@@ -1518,7 +1666,7 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         } else {
             // normalisation with the block's deferred scale: fl(c_j s)
             const double fac = SC ? cin * scale : scale;
-            flat = decode_plane(a.arena_in + poff, s, pdelta, fac, fac != 1.0, dst);
+            flat = decode_plane<SC>(a.arena_in + poff, s, pdelta, fac, fac != 1.0, dst);
         }
     }
     if (lane == 0)
@@ -1542,7 +1690,7 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
                                    : StepSum{0x7FF00000u, 0x7FF00000u, 0x7FF00000u,
                                              0x7FF00000u, 0u};
         if (MODE == kEsc) {
-            size_levels(&X[us][p][0], s, a.lad, h + 1, L - 1, -1, a.psz, plane, nplanes, wreg,
+            size_levels<SC>(&X[us][p][0], s, a.lad, h + 1, L - 1, -1, a.psz, plane, nplanes, wreg,
                         sum);
         } else {
             // kFused: levels below the speculated one are only sized; the
@@ -1550,9 +1698,9 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
             lev = h;
             // (permutation shortcut: the previous level only, no other sized)
             if (MODE == kFused && h > 0 && !a.sc_perm)
-                size_levels(&X[us][p][0], s, a.lad, 0, h - 1, -1, a.psz, plane, nplanes,
+                size_levels<SC>(&X[us][p][0], s, a.lad, 0, h - 1, -1, a.psz, plane, nplanes,
                             wreg, sum);
-            pszv = size_pack_level(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev],
+            pszv = size_pack_level<SC>(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev],
                                    a.lad.r[lev], a.psz + (uint64_t)lev * nplanes + plane, stage,
                                    &S.pack[wave][0], wreg, anchor, sum);
         }
@@ -1585,7 +1733,7 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         if ((pszv >> 16) <= kScratchOutl)
             emit_record(a.arena_out + off, s, pszv, wreg, anchor, stage);
         else  // more outliers than staged: encode again from x-hat (same codes)
-            encode_plane(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev], a.lad.r[lev],
+            encode_plane<SC>(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev], a.lad.r[lev],
                          pszv, wreg, a.arena_out + off, &S.pack[wave][0], &a.dev->err);
     }
     __syncthreads();
@@ -1752,7 +1900,8 @@ __device__ __forceinline__ double const_plane_value(const PassArgs &a, uint64_t 
                                                     double td)
 {
     double x = delta_in == 0.0 ? __longlong_as_double((long long)anchor)
-                               : (double)(int32_t)(uint32_t)anchor * (2.0 * delta_in);
+                               : dequant((int32_t)(uint32_t)anchor, delta_in,
+                                         level_step(delta_in));
     if (scale != 1.0)
         x = x * scale;
     (void)comp;
@@ -2193,9 +2342,9 @@ __device__ void mean_unit(const PassArgs &a, uint64_t u, Planes &X, double *red,
                 const uint64_t anc = *(const uint64_t *)(a.arena_in + o);
                 const uint64_t j = g >> (a.geo.b - s);
                 const double delta = *(const double *)(a.din.hdr + 32 * j + 16);
-                const double e = 2.0 * delta;
+                const double e = delta == 0.0 ? 0.0 : level_step(delta);
                 double v = delta == 0.0 ? __longlong_as_double((long long)anc)
-                                        : (double)(int32_t)(uint32_t)anc * e;
+                                        : dequant((int32_t)(uint32_t)anc, delta, e);
                 const double fac = a.din.bscale[j] * scale;
                 if (fac != 1.0)
                     v = v * fac;
@@ -2239,9 +2388,9 @@ __device__ bool bulk_mean_unit(const PassArgs &a, uint64_t u, double scale)
         const uint64_t anc = *(const uint64_t *)(a.arena_in + o[i]);
         const uint64_t j = g >> (a.geo.b - s);
         const double delta = *(const double *)(a.din.hdr + 32 * j + 16);
-        const double e = 2.0 * delta;
+        const double e = delta == 0.0 ? 0.0 : level_step(delta);
         double v = delta == 0.0 ? __longlong_as_double((long long)anc)
-                                : (double)(int32_t)(uint32_t)anc * e;
+                                : dequant((int32_t)(uint32_t)anc, delta, e);
         const double fac = a.din.bscale[j] * scale;
         if (fac != 1.0)
             v = v * fac;
@@ -3301,14 +3450,14 @@ __global__ __launch_bounds__(kWG) void k_import_norm(PassArgs a, uint32_t batch)
                 for (int k = 0; k < uc.nsu; ++k) {
                     const uint64_t g = uc.seg(k);
                     const double delta = *(const double *)(a.din.hdr + 32 * (g >> bs) + 16);
-                    const double e = 2.0 * delta;
+                    const double e = delta == 0.0 ? 0.0 : level_step(delta);
                     double v[2];
 #pragma unroll
                     for (int p = 0; p < 2; ++p) {
                         const uint64_t off = a.din.plane_off[2 * g + p];
                         const uint64_t anc = *(const uint64_t *)(a.arena_in + off);
                         v[p] = delta == 0.0 ? __longlong_as_double((long long)anc)
-                                            : (double)(int32_t)(uint32_t)anc * e;
+                                            : dequant((int32_t)(uint32_t)anc, delta, e);
                     }
                     const double rr = v[0] * v[0];
                     const double ii = v[1] * v[1];
@@ -3658,7 +3807,7 @@ void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *pr
     // for DIFFUSE and PHASE_FLIP
     // the instances with the shortcut code only when this pass keeps blocks
     // or the state may hold scaled blocks
-    const bool sc = a.sc_skip || a.sc_scaled;
+    const bool sc = a.sc_skip || a.sc_scaled || a.sc_rel;
     if (a.unit_batch > 1) {
         if (sc)
             TIMED(prof, kIdPassBulk, st,

@@ -290,33 +290,55 @@ struct Tmp {
     ~Tmp() { raw_free(S, p, bytes); }
 };
 
+// A ladder: optionally lossless first (0), then lossy levels of one kind --
+// absolute bounds (>= 2^-30) strictly increasing, or pointwise-relative
+// bounds (entries -eps, eps in [2^-19, 0.05]) with eps strictly increasing.
 bool ladder_ok(const double *ladder, int L, double theta)
 {
     if (!ladder || L < 1 || L > kMaxL || !(theta >= 1.0) || !std::isfinite(theta))
         return false;
+    int kind = 0;  // 1 absolute, -1 relative
     for (int k = 0; k < L; ++k) {
         const double d = ladder[k];
-        if (!std::isfinite(d) || d < 0.0)
+        if (!std::isfinite(d))
             return false;
-        if (d == 0.0 && k != 0)
+        if (d == 0.0) {
+            if (k != 0)
+                return false;
+            continue;
+        }
+        const int kk = d > 0.0 ? 1 : -1;
+        if (kind && kk != kind)
             return false;
-        if (d > 0.0 && d < 0x1p-30)
+        kind = kk;
+        const double mag = std::fabs(d);
+        if (mag < (kk < 0 ? 0x1p-19 : 0x1p-30) || (kk < 0 && mag > 0.05))
             return false;
-        if (k > 0 && !(d > ladder[k - 1]))
+        if (k > 0 && ladder[k - 1] != 0.0 && !(mag > std::fabs(ladder[k - 1])))
             return false;
     }
     return true;
 }
 
+// Per level: the bound, the step between codes e (2 delta; for a relative
+// level -eps the log-domain step 2 fl(1.4 eps)) and r = fl(1/e).
 void set_ladder(Ladder &lad, const double *ladder, int L, double theta)
 {
     lad = Ladder{};
     lad.L = L;
     lad.theta = theta;
     for (int k = 0; k < L; ++k) {
-        lad.delta[k] = ladder[k];
-        lad.e[k] = 2.0 * ladder[k];
-        lad.r[k] = ladder[k] > 0.0 ? 1.0 / lad.e[k] : 0.0;
+        const double d = ladder[k];
+        lad.delta[k] = d;
+        if (d > 0.0) {
+            lad.e[k] = 2.0 * d;
+        } else if (d < 0.0) {
+            const double dl = 1.4 * -d;
+            lad.e[k] = 2.0 * dl;
+        } else {
+            lad.e[k] = 0.0;
+        }
+        lad.r[k] = d != 0.0 ? 1.0 / lad.e[k] : 0.0;
     }
 }
 
@@ -483,6 +505,9 @@ PassArgs make_args(const sim *S, int in, int out, const GateArg &g)
     a.sc_skip = (S->shortcut & SIM_SC_SKIP) && gate_may_keep(g, S->b) ? 1 : 0;
     a.sc_perm = (S->shortcut & SIM_SC_PERMUTE) && gate_permutes(g) ? 1 : 0;
     a.sc_scaled = S->scaled ? 1 : 0;
+    a.sc_rel = 0;
+    for (int k = 0; k < S->lad.L; ++k)
+        a.sc_rel |= S->lad.delta[k] < 0.0 ? 1 : 0;
     return a;
 }
 
@@ -1722,6 +1747,8 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
         blocks += S->geo.nblocks;
         ladder = ladder || S->lad.L > 1;
         sc = sc || S->scaled || (S->shortcut & SIM_SC_SKIP);
+        for (int k = 0; k < S->lad.L; ++k)
+            sc = sc || S->lad.delta[k] < 0.0;
         for (int p = 0; p < passes; ++p) {
             const sim_gate_t *g = &gates[(size_t)p * count + k];
             if (g->kind == 0 && g->pad == 0)

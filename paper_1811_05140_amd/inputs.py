@@ -180,6 +180,18 @@ def default_ladder(delta):
     return [0.0, delta / 1000.0, delta / 100.0, delta / 10.0, delta]
 
 
+def relative_ladder(eps):
+    """Pointwise-relative AALC ladder: lossless first, then the relative
+    bounds eps/100, eps/10, eps (entries -bound), leaving out those below the
+    smallest relative bound 2^-19."""
+    lad = [0.0]
+    for j in (100.0, 10.0, 1.0):
+        v = eps / j
+        if v >= 2.0 ** -19:
+            lad.append(-v)
+    return lad
+
+
 # ---- the workloads -------------------------------------------------------
 
 def qft12_workload():

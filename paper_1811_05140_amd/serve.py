@@ -200,9 +200,14 @@ class GpuExecutor:
     the GPU busy by itself)."""
 
     def __init__(self, A, max_slots, gates_per_step=1, sequential=False, tune=None,
-                 probs_qubits=4, large_units=8192, arena_scale=1.0):
+                 probs_qubits=4, large_units=8192, arena_scale=0.3):
         self.A = A
-        self.arena_scale = arena_scale  # first arena relative to the default
+        # First arena relative to 1.3 x the raw state: 0.3 gives 0.39 x raw
+        # per arena, room for the compressed streams of a pass (ratio >= 4 at
+        # theta 4 when a level meets it) plus speculation; a state that still
+        # outgrows it is evicted and resumed with twice the arena, so the
+        # budget admits by compressed size instead of by raw size.
+        self.arena_scale = arena_scale
         self.sequential = sequential
         self.batch = None if sequential else A.Batch(max_slots, gates_per_step)
         self.tune = tune or {}
