@@ -71,7 +71,10 @@ def gpu_measure(A, n, ladder, theta, layers=2, reps=2):
             for old in cache.values():
                 old.close()
             cache.clear()
-            sim = A.Sim(n, b, ladder[-1], ladder=list(ladder), theta=theta)
+            # arenas of 1.3 x the raw state (the default caps at 8 GiB, which
+            # a dense state of 29 or more qubits can outgrow)
+            sim = A.Sim(n, b, ladder[-1], ladder=list(ladder), theta=theta,
+                        arena_bytes=int(1.3 * (16 << n)) + (1 << 20))
             cache[b] = sim
         sim.set_grid(grid)
         best = None
