@@ -1607,3 +1607,538 @@ double or_fidelity(const double *a, const double *b, int n)
     free(nb);
     return F;
 }
+
+/* ------------------------------------------------------------------------ */
+/* entropy stage: block entropy stream v1                                   */
+/* ------------------------------------------------------------------------ */
+/* SZ follows its predictor and quantiser with an entropy coder and a
+ * dictionary coder (Sec. III names SZ's pipeline).  This stage re-codes a
+ * block stream v1 losslessly, at two levels:
+ *
+ *  * plane runs: a plane record equal byte for byte to the record two planes
+ *    before it (the same component of the previous segment) is a repeat;
+ *    each maximal run of consecutive repeats is one item with no body;
+ *  * chunk codes: the 64 zigzagged residuals z_l of a chunk of width w > 0
+ *    are written in the shortest of three codes -- fixed width w (as in
+ *    v1), cost 64 w bits; Golomb-Rice with parameter k < w (q = z >> k
+ *    one-bits, a zero bit, then the k low bits of z, least significant
+ *    first), cost 64 (k + 1) + sum_l (z_l >> k), the smallest k of least
+ *    cost taken; sparse, cost 64 + nnz w: a 64-bit mask whose bit l says
+ *    z_l != 0, then each nonzero z_l (l ascending) in w bits.  Ties go to
+ *    fixed width, then Rice, then sparse.  For geometrically distributed
+ *    residuals the Golomb codes are the optimal prefix codes (Gallager and
+ *    van Voorhis, 1975), i.e. the Huffman code; the sparse code is the
+ *    zero-run coder of chunks that hold a few nonzero residuals.
+ *
+ * Layout (little-endian):
+ *   header (32 B): the v1 header with magic 0x31454141 ("AAE1") and
+ *                  total_bytes = the length of this stream
+ *   u32 v1_bytes (length of the v1 stream) | u32 n_items
+ *   [f64 scale]    iff header flag bit 0, as in v1
+ *   n_items u32 tags, zero-padded to a multiple of 8 bytes
+ *   item bodies in item order
+ * A tag with bit 31 set is a run of (tag & 0x7FFFFFFF) >= 1 repeat planes
+ * (never one of the first two planes); otherwise it is one literal plane:
+ * with bit 30 set its body is the v1 record itself, of (tag & 0x3FFFFFFF)
+ * bytes (taken when the coded body would not be shorter); else the tag is
+ * the byte count of its coded body:
+ *   i64 anchor | u32 payload_words (pw, v1's) | u32 n_outliers
+ *   if pw > 0:
+ *     u32 coded_words | u32 0
+ *     C mode bytes, zero-padded to a multiple of 8
+ *     u16 coded bit length of each chunk that is not fixed-width, in chunk
+ *       order, zero-padded to a multiple of 8 bytes
+ *     coded_words u64 words: the chunks' codes back to back in chunk order
+ *       in one little-endian bit stream, zero-padded to a whole word
+ *   outliers as in v1
+ * Mode byte m: 128 + w (0 <= w <= 64) fixed width w; k < 64 Rice with
+ * parameter k (the chunk's v1 width is the bit length of its largest z);
+ * 63 + w (1 <= w <= 64) sparse with width w.  A chunk of width 0 is fixed
+ * width 0 (no bits). */
+
+#define OR_EMAGIC 0x31454141u /* "AAE1" little-endian */
+#define E_RUN 0x80000000u
+#define E_VERBATIM 0x40000000u
+#define M_FIXED 128
+#define M_SPARSE 63 /* sparse width w: mode M_SPARSE + w, 64 .. 127 */
+
+typedef struct {
+    const uint8_t *p;
+    size_t len;
+} or_rec;
+
+typedef struct {
+    uint64_t *w;
+    size_t nbits, cap; /* cap in words */
+} bitw;
+
+static int bw_put(bitw *b, int bit)
+{
+    if ((b->nbits >> 6) >= b->cap) {
+        size_t nc = b->cap ? 2 * b->cap : 64;
+        uint64_t *nw = (uint64_t *)realloc(b->w, nc * 8);
+        if (!nw)
+            return OR_ENOMEM;
+        memset(nw + b->cap, 0, (nc - b->cap) * 8);
+        b->w = nw;
+        b->cap = nc;
+    }
+    if (bit)
+        setbit(b->w, b->nbits);
+    b->nbits++;
+    return OR_OK;
+}
+
+static int bw_bits(bitw *b, uint64_t v, int n)
+{
+    for (int i = 0; i < n; i++)
+        if (bw_put(b, (int)((v >> i) & 1)))
+            return OR_ENOMEM;
+    return OR_OK;
+}
+
+static size_t pad8z(size_t n) { return (n + 7) / 8 * 8; }
+
+/* The plane records of a v1 stream in order (lengths from their fields). */
+static int v1_records(const uint8_t *v1, size_t len, size_t nplanes, size_t nch, or_rec *rec)
+{
+    const uint8_t *p = v1 + HDR_BYTES + ((v1[5] & OR_HDR_SCALED) ? 8 : 0);
+    const uint8_t *end = v1 + len;
+    for (size_t k = 0; k < nplanes; k++) {
+        if (p > end || (size_t)(end - p) < PLANE_HDR_BYTES)
+            return OR_EINVAL;
+        const uint32_t pw = rd_u32(p + 8), no = rd_u32(p + 12);
+        const size_t r = PLANE_HDR_BYTES + (pw ? pad8z(nch) : 0) + 8 * (size_t)pw +
+                         OUTLIER_BYTES * (size_t)no;
+        if ((size_t)(end - p) < r)
+            return OR_EINVAL;
+        rec[k].p = p;
+        rec[k].len = r;
+        p += r;
+    }
+    return p == end ? OR_OK : OR_EINVAL;
+}
+
+/* Mode byte and coded bits of a chunk of width w holding z[0..63]. */
+static int chunk_mode(const uint64_t *z, int w, uint64_t *bits)
+{
+    *bits = 0;
+    if (w == 0)
+        return M_FIXED;
+    const uint64_t fixed = 64u * (uint64_t)w;
+    uint64_t rice = UINT64_MAX, nnz = 0;
+    int kbest = 0;
+    for (int k = 0; k < w; k++) {
+        /* terms saturate at 2^20: a saturated sum exceeds every fixed-width
+         * cost (at most 64 * 64), so it never wins; sums that can win are
+         * exact */
+        uint64_t cost = 64u * (uint64_t)(k + 1);
+        for (int l = 0; l < (int)CHUNK; l++) {
+            const uint64_t q = z[l] >> k;
+            cost += q > (1u << 20) ? (1u << 20) : q;
+        }
+        if (cost < rice) {
+            rice = cost;
+            kbest = k;
+        }
+    }
+    for (int l = 0; l < (int)CHUNK; l++)
+        nnz += z[l] != 0;
+    const uint64_t sparse = 64u + nnz * (uint64_t)w;
+    if (fixed <= rice && fixed <= sparse) {
+        *bits = fixed;
+        return M_FIXED + w;
+    }
+    if (rice <= sparse) {
+        *bits = rice;
+        return kbest;
+    }
+    *bits = sparse;
+    return M_SPARSE + w;
+}
+
+/* Literal body of one v1 plane record. */
+static int encode_literal(obuf *o, const uint8_t *rec, size_t nch)
+{
+    const uint32_t pw = rd_u32(rec + 8), nout = rd_u32(rec + 12);
+    const uint8_t *wid = rec + PLANE_HDR_BYTES;
+    const uint8_t *payload = wid + (pw ? pad8z(nch) : 0);
+    if (ob_put(o, rec, PLANE_HDR_BYTES))
+        return OR_ENOMEM;
+    if (pw == 0)
+        return ob_put(o, payload, OUTLIER_BYTES * (size_t)nout) ? OR_ENOMEM : OR_OK;
+    uint8_t mode[CHUNK * 4];
+    uint16_t lens[CHUNK * 4];
+    size_t nlen = 0;
+    bitw bw = {0};
+    int rc = OR_OK;
+    if (nch > sizeof mode)
+        return OR_EINVAL;
+    size_t woff = 0;
+    for (size_t c = 0; c < nch && rc == OR_OK; c++) {
+        const int w = wid[c];
+        uint64_t words[64], z[CHUNK], bits;
+        memcpy(words, payload + 8 * woff, 8 * (size_t)w);
+        for (size_t l = 0; l < CHUNK; l++) {
+            z[l] = 0;
+            for (int bit = 0; bit < w; bit++)
+                if (getbit(words, (uint64_t)l * (uint64_t)w + (uint64_t)bit))
+                    z[l] |= (uint64_t)1 << bit;
+        }
+        const int m = chunk_mode(z, w, &bits);
+        const size_t start = bw.nbits;
+        mode[c] = (uint8_t)m;
+        if (m >= M_FIXED) {
+            for (size_t l = 0; l < CHUNK && rc == OR_OK; l++)
+                rc = bw_bits(&bw, z[l], w);
+        } else if (m > M_SPARSE) {
+            uint64_t mask = 0;
+            for (size_t l = 0; l < CHUNK; l++)
+                if (z[l])
+                    mask |= (uint64_t)1 << l;
+            rc = bw_bits(&bw, mask, 64);
+            for (size_t l = 0; l < CHUNK && rc == OR_OK; l++)
+                if (z[l])
+                    rc = bw_bits(&bw, z[l], w);
+        } else {
+            for (size_t l = 0; l < CHUNK && rc == OR_OK; l++) {
+                for (uint64_t q = z[l] >> m; q > 0 && rc == OR_OK; q--)
+                    rc = bw_put(&bw, 1);
+                if (rc == OR_OK)
+                    rc = bw_put(&bw, 0);
+                if (rc == OR_OK)
+                    rc = bw_bits(&bw, z[l], m);
+            }
+        }
+        if (rc == OR_OK && bw.nbits - start != bits)
+            rc = OR_EINVAL; /* cannot happen: the cost is the code's length */
+        if (m < M_FIXED)
+            lens[nlen++] = (uint16_t)bits;
+        woff += (size_t)w;
+    }
+    const uint32_t cw = (uint32_t)((bw.nbits + 63) / 64);
+    if (rc == OR_OK &&
+        (ob_u32(o, cw) || ob_u32(o, 0) || ob_put(o, mode, nch) || ob_zero(o, pad8z(nch) - nch) ||
+         (nlen && ob_put(o, lens, 2 * nlen)) || ob_zero(o, pad8z(2 * nlen) - 2 * nlen) ||
+         (cw && ob_put(o, bw.w, 8 * (size_t)cw)) ||
+         ob_put(o, payload + 8 * (size_t)pw, OUTLIER_BYTES * (size_t)nout)))
+        rc = OR_ENOMEM;
+    free(bw.w);
+    return rc;
+}
+
+int or_entropy_encode(const uint8_t *v1, size_t len, uint8_t *out, size_t cap,
+                      size_t *olen)
+{
+    if (!v1 || !olen || len < HDR_BYTES || rd_u32(v1) != OR_MAGIC || rd_u32(v1 + 12) != len)
+        return OR_EINVAL;
+    const int s = v1[6], b = v1[7];
+    if (s < 6 || s > 14 || b < s || b > 40 || (v1[5] & ~OR_HDR_SCALED))
+        return OR_EINVAL;
+    const size_t nch = (size_t)1 << (s - 6);
+    const size_t np = (size_t)2 << (b - s);
+    const size_t scaled = (v1[5] & OR_HDR_SCALED) ? 8 : 0;
+    or_rec *rec = (or_rec *)malloc(np * sizeof(or_rec));
+    uint32_t *tags = (uint32_t *)malloc(np * 4);
+    obuf body = {0}, o = {0};
+    int rc = OR_ENOMEM;
+    if (!rec || !tags)
+        goto done;
+    rc = v1_records(v1, len, np, nch, rec);
+    if (rc)
+        goto done;
+    size_t ni = 0;
+    int prev_rep = 0;
+    for (size_t k = 0; k < np; k++) {
+        const int rep = k >= 2 && rec[k].len == rec[k - 2].len &&
+                        memcmp(rec[k].p, rec[k - 2].p, rec[k].len) == 0;
+        if (rep && prev_rep) {
+            tags[ni - 1]++; /* extends the run of the previous plane */
+        } else if (rep) {
+            tags[ni++] = E_RUN | 1u;
+        } else {
+            const size_t before = body.len;
+            rc = encode_literal(&body, rec[k].p, nch);
+            if (rc)
+                goto done;
+            if (body.len - before >= rec[k].len) {
+                body.len = before;
+                rc = ob_put(&body, rec[k].p, rec[k].len) ? OR_ENOMEM : OR_OK;
+                if (rc)
+                    goto done;
+                tags[ni++] = E_VERBATIM | (uint32_t)rec[k].len;
+            } else {
+                tags[ni++] = (uint32_t)(body.len - before);
+            }
+        }
+        prev_rep = rep;
+    }
+    rc = OR_ENOMEM;
+    if (ob_put(&o, v1, HDR_BYTES) || ob_u32(&o, (uint32_t)len) || ob_u32(&o, (uint32_t)ni) ||
+        (scaled && ob_put(&o, v1 + HDR_BYTES, 8)) || ob_put(&o, tags, 4 * ni) ||
+        ob_zero(&o, pad8z(4 * ni) - 4 * ni) || (body.len && ob_put(&o, body.p, body.len)))
+        goto done;
+    {
+        const uint32_t magic = OR_EMAGIC, total = (uint32_t)o.len;
+        memcpy(o.p, &magic, 4);
+        memcpy(o.p + 12, &total, 4);
+    }
+    *olen = o.len;
+    rc = OR_OK;
+    if (!out || cap < o.len)
+        rc = OR_ENOMEM;
+    else
+        memcpy(out, o.p, o.len);
+done:
+    free(o.p);
+    free(body.p);
+    free(tags);
+    free(rec);
+    return rc;
+}
+
+/* n bits (n <= 64) at *pos of a bit stream of nbits bits; -1 past its end. */
+static int br_get(const uint8_t *bytes, size_t nbits, size_t *pos, int n, uint64_t *v)
+{
+    if (*pos + (size_t)n > nbits)
+        return -1;
+    uint64_t r = 0;
+    for (int i = 0; i < n; i++) {
+        const size_t p = *pos + (size_t)i;
+        if ((bytes[p >> 3] >> (p & 7)) & 1)
+            r |= (uint64_t)1 << i;
+    }
+    *pos += (size_t)n;
+    *v = r;
+    return 0;
+}
+
+/* The 64 fields of one chunk coded in mode m in bits [*pos, end) of code;
+ * its v1 width into *w.  0, or -1 when malformed. */
+static int decode_chunk(const uint8_t *code, size_t end, size_t *pos, int m, uint64_t *z, int *w)
+{
+    if (m >= M_FIXED && m <= M_FIXED + 64) {
+        *w = m - M_FIXED;
+        for (size_t l = 0; l < CHUNK; l++)
+            if (br_get(code, end, pos, *w, &z[l]))
+                return -1;
+        return 0;
+    }
+    if (m > M_SPARSE && m < M_FIXED) {
+        uint64_t mask;
+        *w = m - M_SPARSE;
+        if (br_get(code, end, pos, 64, &mask))
+            return -1;
+        for (size_t l = 0; l < CHUNK; l++) {
+            z[l] = 0;
+            if ((mask >> l) & 1) {
+                if (br_get(code, end, pos, *w, &z[l]) || z[l] == 0)
+                    return -1;
+            }
+        }
+        return 0;
+    }
+    if (m <= M_SPARSE) {
+        uint64_t zmax = 0;
+        for (size_t l = 0; l < CHUNK; l++) {
+            uint64_t q = 0, bit = 1, low = 0;
+            for (;;) {
+                if (br_get(code, end, pos, 1, &bit))
+                    return -1;
+                if (!bit)
+                    break;
+                q++;
+            }
+            if (m > 0 && (q >> (64 - m)) != 0)
+                return -1;
+            if (br_get(code, end, pos, m, &low))
+                return -1;
+            z[l] = (q << m) | low;
+            if (z[l] > zmax)
+                zmax = z[l];
+        }
+        *w = bitlen64(zmax);
+        return 0;
+    }
+    return -1;
+}
+
+/* One literal body (tag bytes at p) appended to o as a v1 plane record. */
+static int decode_literal(obuf *o, const uint8_t *p, size_t tag, size_t nch)
+{
+    if (tag < PLANE_HDR_BYTES)
+        return OR_EINVAL;
+    const uint32_t pw = rd_u32(p + 8), nout = rd_u32(p + 12);
+    if (pw == 0) {
+        if (tag != PLANE_HDR_BYTES + OUTLIER_BYTES * (size_t)nout)
+            return OR_EINVAL;
+        return ob_put(o, p, tag) ? OR_ENOMEM : OR_OK;
+    }
+    if (tag < PLANE_HDR_BYTES + 8 + pad8z(nch))
+        return OR_EINVAL;
+    const uint32_t cw = rd_u32(p + 16);
+    if (rd_u32(p + 20) != 0)
+        return OR_EINVAL;
+    const uint8_t *mode = p + PLANE_HDR_BYTES + 8;
+    size_t nlen = 0;
+    for (size_t c = 0; c < nch; c++)
+        nlen += mode[c] < M_FIXED;
+    for (size_t c = nch; c < pad8z(nch); c++)
+        if (mode[c])
+            return OR_EINVAL;
+    const size_t need = PLANE_HDR_BYTES + 8 + pad8z(nch) + pad8z(2 * nlen) + 8 * (size_t)cw +
+                        OUTLIER_BYTES * (size_t)nout;
+    if (need != tag)
+        return OR_EINVAL;
+    const uint8_t *lens = mode + pad8z(nch);
+    for (size_t i = 2 * nlen; i < pad8z(2 * nlen); i++)
+        if (lens[i])
+            return OR_EINVAL;
+    const uint8_t *code = lens + pad8z(2 * nlen);
+    const size_t nbits = 64 * (size_t)cw;
+    uint64_t(*zz)[CHUNK] = (uint64_t(*)[CHUNK])malloc(nch * sizeof *zz);
+    uint8_t wid[CHUNK * 4];
+    if (!zz)
+        return OR_ENOMEM;
+    int rc = OR_EINVAL;
+    size_t pos = 0, li = 0;
+    uint32_t sum = 0;
+    for (size_t c = 0; c < nch; c++) {
+        const int m = mode[c];
+        size_t end = nbits;
+        if (m < M_FIXED) {
+            /* a coded length given for the chunk must be what it decodes to */
+            end = pos + (size_t)(lens[2 * li] | (lens[2 * li + 1] << 8));
+            if (end > nbits)
+                goto done;
+        }
+        int w = 0;
+        if (decode_chunk(code, end, &pos, m, zz[c], &w))
+            goto done;
+        if (m < M_FIXED && pos != end)
+            goto done;
+        li += m < M_FIXED;
+        wid[c] = (uint8_t)w;
+        sum += (uint32_t)w;
+    }
+    /* the codes end in the last word; its padding bits are zero */
+    if ((pos + 63) / 64 != cw || sum != pw)
+        goto done;
+    for (size_t q = pos; q < nbits; q++)
+        if ((code[q >> 3] >> (q & 7)) & 1)
+            goto done;
+    rc = OR_ENOMEM;
+    if (ob_put(o, p, PLANE_HDR_BYTES) || ob_put(o, wid, nch) || ob_zero(o, pad8z(nch) - nch))
+        goto done;
+    for (size_t c = 0; c < nch; c++) {
+        const int w = wid[c];
+        uint64_t words[64];
+        memset(words, 0, sizeof words);
+        for (size_t l = 0; l < CHUNK; l++)
+            for (int bit = 0; bit < w; bit++)
+                if ((zz[c][l] >> bit) & 1)
+                    setbit(words, (uint64_t)l * (uint64_t)w + (uint64_t)bit);
+        if (ob_put(o, words, 8 * (size_t)w))
+            goto done;
+    }
+    if (ob_put(o, code + 8 * (size_t)cw, OUTLIER_BYTES * (size_t)nout))
+        goto done;
+    rc = OR_OK;
+done:
+    free(zz);
+    return rc;
+}
+
+int or_entropy_decode(const uint8_t *e, size_t len, uint8_t *out, size_t cap, size_t *olen)
+{
+    if (!e || !olen || len < HDR_BYTES + 8 || rd_u32(e) != OR_EMAGIC ||
+        rd_u32(e + 12) != len || len % 8)
+        return OR_EINVAL;
+    const int s = e[6], b = e[7];
+    if (s < 6 || s > 14 || b < s || b > 40 || (e[5] & ~OR_HDR_SCALED))
+        return OR_EINVAL;
+    const uint32_t v1len = rd_u32(e + HDR_BYTES), ni = rd_u32(e + HDR_BYTES + 4);
+    const size_t scaled = (e[5] & OR_HDR_SCALED) ? 8 : 0;
+    const size_t nch = (size_t)1 << (s - 6);
+    const size_t np = (size_t)2 << (b - s);
+    /* every v1 plane record takes at least 16 bytes */
+    if ((uint64_t)v1len < HDR_BYTES + scaled + (uint64_t)PLANE_HDR_BYTES * np || v1len % 8 ||
+        ni == 0 || ni > np)
+        return OR_EINVAL;
+    *olen = v1len;
+    const size_t tpos = HDR_BYTES + 8 + scaled;
+    if (len < tpos + pad8z(4 * (size_t)ni))
+        return OR_EINVAL;
+    const uint8_t *tags = e + tpos;
+    for (size_t i = 4 * (size_t)ni; i < pad8z(4 * (size_t)ni); i++)
+        if (tags[i])
+            return OR_EINVAL;
+    size_t bpos = tpos + pad8z(4 * (size_t)ni);
+    size_t *roff = (size_t *)malloc(np * sizeof(size_t));
+    size_t *rlen = (size_t *)malloc(np * sizeof(size_t));
+    obuf o = {0};
+    int rc = OR_ENOMEM;
+    if (!roff || !rlen)
+        goto done;
+    if (ob_put(&o, e, HDR_BYTES) || (scaled && ob_put(&o, e + HDR_BYTES + 8, 8)))
+        goto done;
+    size_t k = 0;
+    for (uint32_t i = 0; i < ni; i++) {
+        const uint32_t t = rd_u32(tags + 4 * (size_t)i);
+        rc = OR_EINVAL;
+        if (t & E_RUN) {
+            const uint32_t R = t & ~E_RUN;
+            if (R == 0 || k < 2 || R > np - k)
+                goto done;
+            for (uint32_t r = 0; r < R; r++, k++) {
+                roff[k] = o.len;
+                rlen[k] = rlen[k - 2];
+                rc = OR_ENOMEM;
+                if (ob_zero(&o, rlen[k]))
+                    goto done;
+                memcpy(o.p + roff[k], o.p + roff[k - 2], rlen[k]);
+            }
+        } else {
+            const size_t tb = t & ~E_VERBATIM;
+            if (k >= np || tb % 8 || tb > len - bpos)
+                goto done;
+            roff[k] = o.len;
+            if (t & E_VERBATIM) {
+                /* a v1 record, its length from its own fields */
+                rc = OR_EINVAL;
+                if (tb < PLANE_HDR_BYTES)
+                    goto done;
+                const uint32_t pw = rd_u32(e + bpos + 8), no = rd_u32(e + bpos + 12);
+                if (tb != PLANE_HDR_BYTES + (pw ? pad8z(nch) : 0) + 8 * (size_t)pw +
+                              OUTLIER_BYTES * (size_t)no)
+                    goto done;
+                rc = ob_put(&o, e + bpos, tb) ? OR_ENOMEM : OR_OK;
+            } else {
+                rc = decode_literal(&o, e + bpos, tb, nch);
+            }
+            if (rc)
+                goto done;
+            rlen[k] = o.len - roff[k];
+            bpos += tb;
+            k++;
+        }
+    }
+    rc = OR_EINVAL;
+    if (k != np || bpos != len || o.len != v1len)
+        goto done;
+    {
+        const uint32_t magic = OR_MAGIC;
+        memcpy(o.p, &magic, 4);
+        memcpy(o.p + 12, &v1len, 4);
+    }
+    rc = OR_OK;
+    if (!out || cap < o.len)
+        rc = OR_ENOMEM;
+    else
+        memcpy(out, o.p, o.len);
+done:
+    free(o.p);
+    free(rlen);
+    free(roff);
+    return rc;
+}

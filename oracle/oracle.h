@@ -112,6 +112,17 @@ int or_export_block(const or_sim *sim, uint64_t j, uint8_t *buf, size_t cap,
  * finite. */
 int or_import_state(or_sim *sim, const uint8_t *buf, size_t len);
 
+/* Entropy stage (block entropy stream v1, defined in oracle.c): lossless
+ * re-coding of one block stream v1 (runs of plane records equal to the
+ * record two planes before, Golomb-Rice or fixed-width chunk codes).  Both
+ * set *olen to the output length (also when out is NULL or cap too small:
+ * OR_ENOMEM).  The decoder returns OR_EINVAL for a malformed stream; what
+ * it returns is a v1 stream whose own checks are or_decode_block's. */
+int or_entropy_encode(const uint8_t *v1, size_t len, uint8_t *out, size_t cap,
+                      size_t *olen);
+int or_entropy_decode(const uint8_t *e, size_t len, uint8_t *out, size_t cap,
+                      size_t *olen);
+
 typedef struct {
     double normsq;           /* N^2 of the stored state after the last pass */
     double scale;            /* s applied at the next decode */

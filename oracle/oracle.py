@@ -97,6 +97,8 @@ def lib():
         L.or_codec_exp2.argtypes = [ctypes.c_double]
         L.or_codec_exp2.restype = ctypes.c_double
         L.or_set_shortcut.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.or_entropy_encode.argtypes = [u8p, ctypes.c_size_t, u8p, ctypes.c_size_t, szp]
+        L.or_entropy_decode.argtypes = [u8p, ctypes.c_size_t, u8p, ctypes.c_size_t, szp]
     return _lib
 
 
@@ -181,6 +183,56 @@ def decode_block_interleaved(stream):
     if rc:
         raise ValueError("or_decode_block rc=%d" % rc)
     return x
+
+
+def _coder(fn, data):
+    src = np.frombuffer(bytes(data), dtype=np.uint8).copy()
+    n = ctypes.c_size_t(0)
+    rc = fn(_u8p(src), src.size, None, 0, ctypes.byref(n))
+    if rc not in (0, -2):
+        raise ValueError("entropy coder rc=%d" % rc)
+    out = np.zeros(max(n.value, 1), dtype=np.uint8)
+    rc = fn(_u8p(src), src.size, _u8p(out), out.size, ctypes.byref(n))
+    if rc:
+        raise ValueError("entropy coder rc=%d" % rc)
+    return bytes(out[:n.value])
+
+
+def entropy_encode(stream):
+    """Block entropy stream of one block stream v1 (oracle.c defines it)."""
+    return _coder(lib().or_entropy_encode, stream)
+
+
+def entropy_decode(estream):
+    """The block stream v1 that a block entropy stream encodes."""
+    return _coder(lib().or_entropy_decode, estream)
+
+
+E_MAGIC = 0x31454141
+
+
+def split_streams(data):
+    """The block streams (v1 or entropy) of a concatenation, in order."""
+    data = bytes(data)
+    out, pos = [], 0
+    while pos < len(data):
+        total = int.from_bytes(data[pos + 12:pos + 16], "little")
+        if total < 32 or pos + total > len(data):
+            raise ValueError("truncated stream at byte %d" % pos)
+        out.append(data[pos:pos + total])
+        pos += total
+    return out
+
+
+def entropy_state(data):
+    """Every v1 block stream of a checkpoint through the entropy stage."""
+    return b"".join(entropy_encode(x) for x in split_streams(data))
+
+
+def plain_state(data):
+    """A checkpoint with every entropy-coded block stream decoded to v1."""
+    return b"".join(entropy_decode(x) if int.from_bytes(x[:4], "little") == E_MAGIC else x
+                    for x in split_streams(data))
 
 
 def aalc_encode(x, b, s, ladder, theta):
@@ -305,16 +357,23 @@ class OracleSim:
             raise ValueError("or_export_block rc=%d" % rc)
         return bytes(out[:n.value])
 
-    def export_state(self):
-        """Every block's stream, block 0 first (the checkpoint of the state)."""
-        return b"".join(self.export_block(j)
+    def export_state(self, entropy=False):
+        """Every block's stream, block 0 first (the checkpoint of the state);
+        with entropy, each through the entropy stage."""
+        data = b"".join(self.export_block(j)
                         for j in range(1 << (self.n - self.b)))
+        return entropy_state(data) if entropy else data
 
     def import_state(self, data):
         """Replace the state by concatenated block streams; returns the code
         (0, or -5 when N^2 of the imported state is 0 or not finite) and
         raises ValueError when a stream is rejected."""
-        buf = np.frombuffer(bytes(data), dtype=np.uint8).copy()
+        data = bytes(data)
+        try:
+            data = plain_state(data)
+        except ValueError:
+            pass  # or_import_state rejects what cannot be split or decoded
+        buf = np.frombuffer(data, dtype=np.uint8).copy()
         rc = lib().or_import_state(self.h, _u8p(buf), buf.size)
         if rc not in (0, -5):
             raise ValueError("or_import_state rc=%d" % rc)
