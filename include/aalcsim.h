@@ -242,9 +242,44 @@ int sim_export_block(sim_t *sim, uint64_t j, void *buf, size_t cap,
  * SIM_EUNSUPPORTED on the uncompressed path. */
 int sim_export_state(sim_t *sim, void *buf, size_t cap, size_t *len);
 
+/* Checkpoint through the entropy stage: as sim_export_state, but each
+ * block's stream re-coded losslessly as a block entropy stream v1.  SZ, the
+ * compressor of Sec. III, ends in entropy and dictionary coding; the
+ * resident streams keep the fixed-width packer that the per-gate kernels
+ * decode, and this stage is applied where streams leave the GPU.  Layout
+ * (little-endian):
+ *   header (32 B): the v1 header with magic 0x31454141 ("AAE1") and
+ *                  total_bytes = the length of this stream
+ *   u32 v1_bytes (length of the v1 stream) | u32 n_items
+ *   [f64 scale]  iff header flag bit 0, as in v1
+ *   n_items u32 tags, zero-padded to a multiple of 8 bytes; item bodies
+ * Tag bit 31: a run of (tag & 0x7FFFFFFF) >= 1 planes, each plane's v1
+ * record equal to the record two planes before it (never planes 0, 1), no
+ * body.  Else one literal plane: bit 30 set: the body is the v1 record
+ * itself, (tag & 0x3FFFFFFF) bytes; bit 30 clear: a coded body of tag bytes:
+ *   i64 anchor | u32 payload_words (pw) | u32 n_outliers
+ *   if pw > 0: u32 coded_words | u32 0 | C mode bytes (padded to 8) |
+ *     u16 coded bit length of each chunk that is not fixed width (padded to
+ *     8) | coded_words u64 words of chunk codes back to back (LSB first,
+ *     zero-padded)
+ *   outliers as in v1
+ * Mode m: 128 + w fixed width w (0..64); 63 + w sparse of width w (1..64):
+ * a 64-bit mask of the nonzero residuals, then those in w bits; k < 64
+ * Golomb-Rice with parameter k: per residual z, z >> k one-bits, a zero bit,
+ * the k low bits (the chunk's v1 width is the bit length of its largest z).
+ * The encoder takes, per chunk of width w > 0, the shortest of fixed (64 w
+ * bits), Rice (64 (k + 1) + sum (z >> k), the smallest best k) and sparse
+ * (64 + nnz w), ties in that order; a literal whose coded body would not be
+ * shorter than its record is stored verbatim.  Every block size the library
+ * takes qualifies (at most 2^(20-10+1) planes).  *len and SIM_ENOMEM as for
+ * sim_export_state; the streams are staged in the idle arena.  Synchronises. */
+int sim_export_state_entropy(sim_t *sim, void *buf, size_t cap, size_t *len);
+
 /* Resume from a checkpoint: replace the state by the concatenated block
- * streams in host memory buf[0..len) as sim_export_state writes them (or any
- * producer of block stream v1).  Every stream must have this sim's segment
+ * streams in host memory buf[0..len) as sim_export_state or
+ * sim_export_state_entropy write them (or any producer of block stream v1 or
+ * block entropy stream v1, mixed freely; entropy streams are decoded on the
+ * GPU, above the room their v1 streams take in the idle arena).  Every stream must have this sim's segment
  * and block sizes and a level of this sim's ladder whose bound equals its
  * delta bit for bit (set the ladder first with sim_set_aalc), its records
  * must be well formed (sizes, chunk widths, first residual 0, lossy anchors

@@ -28,6 +28,7 @@ EXPORTS = [
     "sim_batch_create", "sim_batch_destroy", "sim_batch_apply", "sim_batch_sync",
     "sim_batch_info", "sim_set_grid", "sim_batch_profile", "sim_batch_profile_read",
     "sim_fourier_overlap", "sim_export_state", "sim_import_state",
+    "sim_export_state_entropy",
     "sim_measure_probs_noalloc",
     "sim_context_create", "sim_context_destroy", "sim_context_info", "sim_create_in",
     "sim_set_shortcut",
@@ -112,6 +113,7 @@ def _load():
     L.sim_amplitude_sum.argtypes = [vp, dp]
     L.sim_export_state.argtypes = [vp, vp, ctypes.c_size_t, P(ctypes.c_size_t)]
     L.sim_import_state.argtypes = [vp, vp, ctypes.c_size_t]
+    L.sim_export_state_entropy.argtypes = [vp, vp, ctypes.c_size_t, P(ctypes.c_size_t)]
     L.sim_set_grid.argtypes = [vp, ctypes.c_int]
     L.sim_fourier_overlap.argtypes = [vp, ctypes.c_uint64, dp]
     L.sim_stats.argtypes = [vp, P(Stats)]
@@ -314,12 +316,14 @@ class Sim:
         check(lib.sim_export_block(self.h, j, buf, ln.value, ctypes.byref(ln)), True)
         return buf.raw[:ln.value]
 
-    def export_state(self, out=None):
+    def export_state(self, out=None, entropy=False):
         """Checkpoint: every block's stream, block 0 first, as bytes (or into
         `out`, a writable buffer such as a pinned uint8 tensor's numpy view,
-        when given; then the byte count is returned)."""
+        when given; then the byte count is returned).  entropy: each stream
+        through the entropy stage (sim_export_state_entropy)."""
+        fn = lib.sim_export_state_entropy if entropy else lib.sim_export_state
         ln = ctypes.c_size_t(0)
-        rc = lib.sim_export_state(self.h, None, 0, ctypes.byref(ln))
+        rc = fn(self.h, None, 0, ctypes.byref(ln))
         if rc not in (SIM_OK, SIM_ENOMEM, SIM_ECOLLAPSED):
             check(rc)
         if out is not None:
@@ -327,11 +331,10 @@ class Sim:
             if arr.size < ln.value:
                 raise SimError(SIM_ENOMEM, "buffer of %d bytes too small for %d"
                                % (arr.size, ln.value))
-            check(lib.sim_export_state(self.h, arr.ctypes.data, arr.size,
-                                       ctypes.byref(ln)), True)
+            check(fn(self.h, arr.ctypes.data, arr.size, ctypes.byref(ln)), True)
             return ln.value
         buf = ctypes.create_string_buffer(max(ln.value, 1))
-        check(lib.sim_export_state(self.h, buf, ln.value, ctypes.byref(ln)), True)
+        check(fn(self.h, buf, ln.value, ctypes.byref(ln)), True)
         return buf.raw[:ln.value]
 
     def import_state(self, data, nbytes=None):

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaalcsim.so")
 ROOT = os.path.dirname(HERE)
-SOURCES = ["kernels.hip", "sv.hip", "sim.cpp"]
+SOURCES = ["kernels.hip", "sv.hip", "entropy.hip", "sim.cpp"]
 HEADERS = ["device.h", "gates.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

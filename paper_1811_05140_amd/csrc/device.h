@@ -203,6 +203,21 @@ void launch_export_headers(const PassArgs &a, uint64_t first, uint64_t count, ui
 // out + offs[k] (device pointers).
 void launch_export_range(const PassArgs &a, uint64_t first, uint64_t count,
                          const uint64_t *offs, uint8_t *out, hipStream_t st, Prof *prof);
+// Entropy stage of checkpoints (entropy.hip), blocks of at most
+// kEntropyMaxPlanes planes: entropy stream bytes of blocks [first, first +
+// count) of the set a.din into elen[k]; the streams themselves into out +
+// eoff[k]; and the v1 streams of count given streams (v1 ones copied,
+// entropy ones decoded) from src + soff[k] into dst + doff[k] (soff and doff
+// with count + 1 entries), errors in kErrImport.
+constexpr uint32_t kEntropyMagic = 0x31454141u;  // "AAE1"
+constexpr uint64_t kEntropyMaxPlanes = 4096;
+void launch_entropy_size(const PassArgs &a, uint64_t first, uint64_t count, uint32_t *elen,
+                         hipStream_t st);
+void launch_entropy_write(const PassArgs &a, uint64_t first, uint64_t count,
+                          const uint64_t *eoff, uint8_t *out, hipStream_t st);
+void launch_entropy_expand(const PassArgs &a, uint64_t count, const uint8_t *src,
+                           const uint64_t *soff, uint8_t *dst, const uint64_t *doff,
+                           hipStream_t st);
 // Checkpoint import: streams already copied to a.arena_out + kArenaBase + boff[j]
 // become descriptor set a.dout; then N^2 and s as after a pass (a.src_basis
 // set: no pass is counted).  Errors set kErrImport / kErrImportNorm.

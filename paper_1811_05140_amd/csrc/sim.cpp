@@ -1147,6 +1147,67 @@ int sim_export_state(sim_t *S, void *buf, size_t cap, size_t *len)
     return rc;
 }
 
+int sim_export_state_entropy(sim_t *S, void *buf, size_t cap, size_t *len)
+{
+    if (!S || !len)
+        return fail(SIM_EINVAL, "NULL argument");
+    if (!S->compressed)
+        return fail(SIM_EUNSUPPORTED, "the uncompressed path has no block streams");
+    if ((2ull << (S->b - S->s)) > kEntropyMaxPlanes)
+        return fail(SIM_EUNSUPPORTED, "the entropy stage takes blocks of at most %llu planes "
+                    "(b - s <= 11)", (unsigned long long)kEntropyMaxPlanes);
+    int rc = sync_state(S);
+    if (rc && rc != SIM_ECOLLAPSED)
+        return rc;
+    const uint64_t nb = S->geo.nblocks;
+    if (!S->xoff) {
+        int r2 = dmalloc(S, (void **)&S->xoff, 8 * nb);
+        if (r2)
+            return r2;
+    }
+    // entropy stream lengths (4 bytes per block, in the offsets array's room)
+    const PassArgs a = make_args(S, S->cur, 1 - S->cur, GateArg{});
+    uint32_t *elen_dev = (uint32_t *)S->xoff;
+    launch_entropy_size(a, 0, nb, elen_dev, S->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<uint32_t> el(nb);
+    HIPCHK(hipMemcpyAsync(el.data(), elen_dev, 4 * nb, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(hipStreamSynchronize(S->stream));
+    const uint64_t room = S->arena_cap - kArenaBase;
+    uint64_t total = 0;
+    for (uint64_t j = 0; j < nb; ++j) {
+        if (el[j] < kHdrBytes + 8 || el[j] > room)
+            return fail(SIM_EDEVICE, "block %llu has an implausible entropy stream length %u",
+                        (unsigned long long)j, el[j]);
+        total += el[j];
+    }
+    *len = (size_t)total;
+    if (!buf || cap < total)
+        return fail(SIM_ENOMEM, "buffer of %zu bytes too small for %llu", cap,
+                    (unsigned long long)total);
+    uint8_t *stage = S->arena[1 - S->cur] + kArenaBase;
+    std::vector<uint64_t> offs(nb);
+    uint64_t done = 0;
+    for (uint64_t j0 = 0; j0 < nb;) {
+        uint64_t j1 = j0, bytes = 0;
+        while (j1 < nb && bytes + el[j1] <= room) {
+            offs[j1 - j0] = bytes;
+            bytes += el[j1];
+            ++j1;
+        }
+        HIPCHK(hipMemcpyAsync(S->xoff, offs.data(), 8 * (j1 - j0), hipMemcpyHostToDevice,
+                              S->stream));
+        launch_entropy_write(a, j0, j1 - j0, S->xoff, stage, S->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync((uint8_t *)buf + done, stage, bytes, hipMemcpyDeviceToHost,
+                              S->stream));
+        HIPCHK(hipStreamSynchronize(S->stream));
+        done += bytes;
+        j0 = j1;
+    }
+    return rc;
+}
+
 int sim_import_state(sim_t *S, const void *buf, size_t len)
 {
     if (!S || (!buf && len))
@@ -1155,9 +1216,12 @@ int sim_import_state(sim_t *S, const void *buf, size_t len)
         return fail(SIM_EUNSUPPORTED, "the uncompressed path has no block streams");
     const uint64_t nb = S->geo.nblocks;
     const uint8_t *p = (const uint8_t *)buf;
-    std::vector<uint64_t> boff(nb);
-    uint64_t pos = 0;
-    bool scaled_any = false;
+    // per block: where its stream starts in buf (soff) and where its v1
+    // stream goes in the arena (boff); entropy streams are expanded there
+    std::vector<uint64_t> boff(nb + 1), soff(nb + 1);
+    uint64_t pos = 0, vpos = 0;
+    bool scaled_any = false, any_entropy = false;
+    const uint64_t planes = 2ull << (S->b - S->s);
     for (uint64_t j = 0; j < nb; ++j) {
         if (len - pos < kHdrBytes)
             return fail(SIM_EINVAL, "stream of block %llu truncated", (unsigned long long)j);
@@ -1168,16 +1232,37 @@ int sim_import_state(sim_t *S, const void *buf, size_t len)
         memcpy(&total, h + 12, 4);
         memcpy(&delta, h + 16, 8);
         const int level = h[4];
-        if (magic != kMagic || (h[5] & ~kHdrScaled) != 0 || h[6] != S->s || h[7] != S->b)
+        const bool ent = magic == kEntropyMagic;
+        if ((magic != kMagic && !ent) || (h[5] & ~kHdrScaled) != 0 || h[6] != S->s ||
+            h[7] != S->b)
             return fail(SIM_EINVAL, "block %llu: bad magic, flags or geometry (s %d, b %d "
                         "expected)", (unsigned long long)j, S->s, S->b);
+        if (ent && planes > kEntropyMaxPlanes)
+            return fail(SIM_EUNSUPPORTED, "block %llu: entropy streams take blocks of at most "
+                        "%llu planes", (unsigned long long)j,
+                        (unsigned long long)kEntropyMaxPlanes);
+        // an entropy stream has its v1 length and item count after the header
+        const uint32_t extra = ent ? 8u : 0u;
+        uint32_t vlen = total;
+        if (ent) {
+            if (total < kHdrBytes + extra || total > len - pos)
+                return fail(SIM_EINVAL, "block %llu: stream length %u invalid",
+                            (unsigned long long)j, total);
+            memcpy(&vlen, h + kHdrBytes, 4);
+            const uint64_t vmin = kHdrBytes + ((h[5] & kHdrScaled) ? kScaleBytes : 0u) +
+                                  (uint64_t)kPlaneHdrBytes * planes;
+            if (vlen < vmin || vlen % 8 != 0)
+                return fail(SIM_EINVAL, "block %llu: v1 length %u of an entropy stream invalid",
+                            (unsigned long long)j, vlen);
+            any_entropy = true;
+        }
         if (h[5] & kHdrScaled) {
             // a deferred scale c after the header: finite, > 0 and not 1
             double c = 0.0;
-            if (total < kHdrBytes + kScaleBytes || total > len - pos)
+            if (total < kHdrBytes + extra + kScaleBytes || total > len - pos)
                 return fail(SIM_EINVAL, "block %llu: stream length %u invalid",
                             (unsigned long long)j, total);
-            memcpy(&c, h + kHdrBytes, 8);
+            memcpy(&c, h + kHdrBytes + extra, 8);
             if (!std::isfinite(c) || !(c > 0.0) || c == 1.0)
                 return fail(SIM_EINVAL, "block %llu: invalid deferred scale %.17g",
                             (unsigned long long)j, c);
@@ -1189,15 +1274,28 @@ int sim_import_state(sim_t *S, const void *buf, size_t len)
         if (total < kHdrBytes || total % 8 != 0 || total > len - pos)
             return fail(SIM_EINVAL, "block %llu: stream length %u invalid",
                         (unsigned long long)j, total);
-        boff[j] = pos;
+        soff[j] = pos;
+        boff[j] = vpos;
         pos += total;
+        vpos += vlen;
     }
+    soff[nb] = pos;
+    boff[nb] = vpos;
     if (pos != len)
         return fail(SIM_EINVAL, "%llu bytes after the last block stream",
                     (unsigned long long)(len - pos));
-    if (len > S->arena_cap - kArenaBase)
-        return fail(SIM_ENOMEM, "%zu bytes of streams exceed the arena (%llu bytes)", len,
-                    (unsigned long long)S->arena_cap);
+    // entropy streams sit above the room of the v1 streams they expand to
+    const uint64_t vroom = (vpos + 255) & ~255ull;
+    const uint64_t need = any_entropy ? vroom + len : len;
+    if (need > S->arena_cap - kArenaBase)
+        return fail(SIM_ENOMEM, "%llu bytes of streams exceed the arena (%llu bytes)",
+                    (unsigned long long)need, (unsigned long long)S->arena_cap);
+    Tmp offs_dev(S);
+    if (any_entropy) {
+        int r2 = offs_dev.get(16 * (nb + 1));
+        if (r2)
+            return r2;
+    }
     if (!S->xoff) {
         int r2 = dmalloc(S, (void **)&S->xoff, 8 * nb);
         if (r2)
@@ -1213,12 +1311,23 @@ int sim_import_state(sim_t *S, const void *buf, size_t len)
     d.scale = 1.0;
     d.normalize = S->normalize;
     d.arena_used[0] = d.arena_used[1] = kArenaBase;
-    d.arena_used[out] = kArenaBase + ((len + 255) & ~255ull);
+    d.arena_used[out] = kArenaBase + vroom;
     HIPCHK(hipMemcpyAsync(S->dev, &d, sizeof d, hipMemcpyHostToDevice, S->stream));
-    HIPCHK(hipMemcpyAsync(S->arena[out] + kArenaBase, buf, len, hipMemcpyHostToDevice,
+    uint8_t *varea = S->arena[out] + kArenaBase;
+    HIPCHK(hipMemcpyAsync(any_entropy ? varea + vroom : varea, buf, len, hipMemcpyHostToDevice,
                           S->stream));
     HIPCHK(hipMemcpyAsync(S->xoff, boff.data(), 8 * nb, hipMemcpyHostToDevice, S->stream));
     PassArgs a = make_args(S, out, out, GateArg{});
+    if (any_entropy) {
+        // v1 streams copied, entropy streams decoded, into their v1 places
+        uint64_t *so = (uint64_t *)offs_dev.p, *vo = so + (nb + 1);
+        HIPCHK(hipMemcpyAsync(so, soff.data(), 8 * (nb + 1), hipMemcpyHostToDevice,
+                              S->stream));
+        HIPCHK(hipMemcpyAsync(vo, boff.data(), 8 * (nb + 1), hipMemcpyHostToDevice,
+                              S->stream));
+        launch_entropy_expand(a, nb, varea + vroom, so, varea, vo, S->stream);
+        HIPCHK(hipGetLastError());
+    }
     a.in_arena = 1 - out;  // the reduction frees the previous state's arena
     a.pass = kBasisPass;
     launch_import(a, S->xoff, S->stream, S->prof);
