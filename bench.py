@@ -622,6 +622,40 @@ def bench_checkpoint(args, A, inputs, stream):
         same = same and a.export_state() == r.export_state()
         a.close()
         r.close()
+    # the entropy stage (block entropy streams) on this state and, for
+    # QFT-24, on the state after 200 gates, where most chunks still hold a
+    # few nonzero residuals: sizes, both legs through pinned memory, and the
+    # resumed state's v1 streams
+    def entropy_leg(sim, label):
+        v1 = sim.export_state()
+        e = sim.export_state(entropy=True)
+        ebuf = torch.empty(len(e) + 4096, dtype=torch.uint8, pin_memory=True)
+        ev = ebuf.numpy()
+        r = A.Sim(n, b, eb, stream=stream)
+        r.import_state(ev, sim.export_state(out=ev, entropy=True))
+        c0 = time.perf_counter()
+        for _ in range(args.steps):
+            ne = sim.export_state(out=ev, entropy=True)
+        c1 = time.perf_counter()
+        for _ in range(args.steps):
+            r.import_state(ev, ne)
+        c2 = time.perf_counter()
+        ok = r.export_state() == v1 and bytes(ev[:ne]) == e
+        r.close()
+        return {"state": label, "v1_bytes": len(v1), "entropy_bytes": len(e),
+                "v1_over_entropy": round(len(v1) / len(e), 3),
+                "logical_ratio": round((16 << n) / len(e), 1),
+                "export_ms": round(1000.0 * (c1 - c0) / args.steps, 3),
+                "import_ms": round(1000.0 * (c2 - c1) / args.steps, 3),
+                "resume_identical": bool(ok)}
+
+    entropy = [entropy_leg(src, "final")]
+    if not grover:
+        m = A.Sim(n, b, eb, stream=stream)
+        m.set_basis(w["basis"])
+        m.run(w["gates"][:200])
+        entropy.append(entropy_leg(m, "after 200 gates"))
+        m.close()
     spb = 1 << (b - min(b, 10))
     nblocks = 1 << (n - b)
     nseg = nblocks * spb
@@ -690,6 +724,7 @@ def bench_checkpoint(args, A, inputs, stream):
         "import_ms": round(1000.0 * (te2 - te1) / args.steps, 3),
         "import_pageable_ms": round(1000.0 * (tp1 - tp0) / args.steps, 3),
         "resume_identical": bool(same),
+        "entropy_stage": entropy,
         "roofline": roofline, "cpu_baseline": cpu,
     }
 
@@ -948,8 +983,14 @@ def main():
         print(json.dumps(bench_batch64(args, A, inputs, stream)), flush=True)
         return
     if args.workload == "serve512":
-        print(json.dumps(bench_serve(args, A, inputs, stream)), flush=True)
-        return
+        # The 512-request serving run took a GPU memory fault (an address
+        # outside every allocation, reported at the first retirement's
+        # probability query, so raised by an earlier batched pass or basis
+        # encode) with the current kernels, arenas of 0.39 x the raw state and
+        # the extended tune table.  Until its cause is found the workload does
+        # not run.
+        sys.exit("bench.py: the serve512 workload is disabled until the cause of its GPU "
+                 "memory fault is found")
     if args.workload == "qft12":
         print(json.dumps(bench_qft12(args, A, inputs, stream)), flush=True)
         return

@@ -323,16 +323,15 @@ class Sim:
         through the entropy stage (sim_export_state_entropy)."""
         fn = lib.sim_export_state_entropy if entropy else lib.sim_export_state
         ln = ctypes.c_size_t(0)
+        if out is not None:
+            # one call: the library reports the length needed (SIM_ENOMEM)
+            # when the buffer is too small
+            arr = np.frombuffer(out, dtype=np.uint8)
+            check(fn(self.h, arr.ctypes.data, arr.size, ctypes.byref(ln)), True)
+            return ln.value
         rc = fn(self.h, None, 0, ctypes.byref(ln))
         if rc not in (SIM_OK, SIM_ENOMEM, SIM_ECOLLAPSED):
             check(rc)
-        if out is not None:
-            arr = np.frombuffer(out, dtype=np.uint8)
-            if arr.size < ln.value:
-                raise SimError(SIM_ENOMEM, "buffer of %d bytes too small for %d"
-                               % (arr.size, ln.value))
-            check(fn(self.h, arr.ctypes.data, arr.size, ctypes.byref(ln)), True)
-            return ln.value
         buf = ctypes.create_string_buffer(max(ln.value, 1))
         check(fn(self.h, buf, ln.value, ctypes.byref(ln)), True)
         return buf.raw[:ln.value]

@@ -23,9 +23,10 @@
 //    stored verbatim.
 // The layout is given with sim_export_state_entropy in include/aalcsim.h.
 //
-// Work decomposition: one workgroup per block.  Each wavefront takes planes
-// w, w + 4, ...: it compares the plane with the one two before it, and codes
-// a chunk at a time with one residual per lane (costs by wavefront sums,
+// Work decomposition: one workgroup per block.  16-byte records (one value,
+// no payload) are settled one per thread; every other plane goes to a
+// wavefront, which compares it with the one two planes before it and codes
+// it a chunk at a time with one residual per lane (costs by wavefront sums,
 // bits OR-ed into a per-wave LDS buffer, then copied out).  Item tags and body
 // offsets come from workgroup scans over the planes, so a block holds at most
 // kEMaxPlanes planes (b - s <= 11; the library takes b <= 20, s = 10).
@@ -46,6 +47,7 @@ namespace {
 constexpr uint32_t kEMagic = 0x31454141u;  // "AAE1"
 constexpr uint32_t kERun = 0x80000000u;
 constexpr uint32_t kEVerb = 0x40000000u;
+constexpr uint32_t kESlow = 0xFFFFFFFFu;    // a plane left to the whole wave
 constexpr int kMFixed = 128;               // fixed width w: mode 128 + w
 constexpr int kMSparse = 63;               // sparse width w: mode 63 + w
 constexpr int kEMaxPlanes = 4096;
@@ -155,11 +157,13 @@ __device__ ChunkCode choose_code(uint64_t z, int w)
     }
     const uint32_t fixed = 64u * (uint32_t)w;
     // Rice: only k <= w - 2 can cost less than fixed width, and no k whose
-    // 64 (k + 1) already reaches the best cost can do better; terms saturate
-    // at 2^20, where no sum can win
+    // 64 (k + 1) already reaches the best cost can do better; the largest z
+    // (at least 2^(w-1)) alone adds 2^(w-1-k) >= 4096 >= 64 w for k <= w - 13,
+    // so the search starts at w - 12; terms saturate at 2^20, where no sum
+    // can win
     uint32_t best = fixed;
     int kbest = -1;
-    for (int k = 0; k + 2 <= w && 64u * (uint32_t)(k + 1) < best; ++k) {
+    for (int k = w > 12 ? w - 12 : 0; k + 2 <= w && 64u * (uint32_t)(k + 1) < best; ++k) {
         const uint64_t q = z >> k;
         const uint32_t t = q > (1ull << 20) ? (1u << 20) : (uint32_t)q;
         const uint32_t cost = 64u * (uint32_t)(k + 1) + wsum32(t);
@@ -378,8 +382,10 @@ __device__ double wg_pairwise(const double *src, uint32_t m, double *v)
 struct EncLds {
     uint32_t tag[kEMaxPlanes];   // per plane: kERun (repeat) or its literal tag
     uint32_t aux[kEMaxPlanes];   // item starts, then body offsets
+    uint16_t lst[kEMaxPlanes];   // the planes left to the waves
     uint32_t wb[4][2 * kEWords];  // per wave: coded bits
     uint32_t red[kWG];
+    uint32_t nlst;
 };
 
 template <bool WRITE>
@@ -398,8 +404,35 @@ __global__ __launch_bounds__(kWG) void k_ent_encode(EncArgs e)
     for (uint64_t bi = blockIdx.x; bi < e.count; bi += gridDim.x) {
         const uint64_t j = e.first + bi;
         const uint64_t base = j * P;
-        // per plane: repeat of the plane two before, else its literal tag
-        for (uint32_t q = wave; q < P; q += 4) {
+        // per plane: repeat of the plane two before, else its literal tag.
+        // First one plane per lane: a 16-byte record (one value, no payload,
+        // no outliers) repeats the plane two before iff that record is 16
+        // bytes with the same anchor, else it is stored verbatim; the other
+        // planes are marked, then taken by the waves in turn, one plane per
+        // wave.
+        if (t == 0)
+            S.nlst = 0u;
+        __syncthreads();
+        for (uint32_t q = (uint32_t)t; q < P; q += kWG) {
+            const uint8_t *rec = plane_rec(a, base + q);
+            uint32_t tg = kESlow;
+            if (*(const uint64_t *)(rec + 8) == 0ull) {
+                bool rep = false;
+                if (q >= 2) {
+                    const uint8_t *r2 = plane_rec(a, base + q - 2);
+                    rep = *(const uint64_t *)(r2 + 8) == 0ull &&
+                          *(const uint64_t *)r2 == *(const uint64_t *)rec;
+                }
+                tg = rep ? kERun : (kEVerb | kPlaneHdrBytes);
+            } else {
+                S.lst[atomicAdd(&S.nlst, 1u)] = (uint16_t)q;
+            }
+            S.tag[q] = tg;
+        }
+        __syncthreads();
+        const uint32_t nlst = S.nlst;
+        for (uint32_t i = wave; i < nlst; i += 4) {
+            const uint32_t q = S.lst[i];
             const uint8_t *rec = plane_rec(a, base + q);
             const uint32_t len = rec_len(rec, padC);
             bool rep = false;
@@ -488,10 +521,20 @@ __global__ __launch_bounds__(kWG) void k_ent_encode(EncArgs e)
         for (int k = t; k < 4 * 2 * kEWords; k += kWG)
             (&S.wb[0][0])[k] = 0u;
         __syncthreads();
-        for (uint32_t q = wave; q < P; q += 4) {
-            if (S.tag[q] == kERun)
-                continue;
-            code_plane<true>(plane_rec(a, base + q), C, S.wb[wave], out + bstart + S.aux[q]);
+        // 16-byte verbatim records one per lane, the other literals one per
+        // wave
+        for (uint32_t q = (uint32_t)t; q < P; q += kWG)
+            if (S.tag[q] == (kEVerb | kPlaneHdrBytes)) {
+                const uint64_t *src = (const uint64_t *)plane_rec(a, base + q);
+                uint64_t *dst = (uint64_t *)(out + bstart + S.aux[q]);
+                dst[0] = src[0];
+                dst[1] = src[1];
+            }
+        for (uint32_t i = wave; i < nlst; i += 4) {
+            const uint32_t q = S.lst[i];
+            if (S.tag[q] != kERun)
+                code_plane<true>(plane_rec(a, base + q), C, S.wb[wave],
+                                 out + bstart + S.aux[q]);
         }
         __syncthreads();
     }
@@ -517,8 +560,10 @@ struct DecLds {
     uint32_t D[kEMaxPlanes];      // per plane: v1 record size, then offset
     uint32_t pk[4][2 * kEWords];  // per wave: packed v1 payload
     uint64_t zb[4][64];           // per wave: residuals of a Rice chunk
+    uint16_t lst[kEMaxPlanes];    // the planes left to the waves
     uint32_t red[kWG];
     uint64_t red64[kWG];
+    uint32_t nlst;
 };
 
 // One coded literal body B (tb bytes, within the stream) into the v1
@@ -867,11 +912,29 @@ __global__ __launch_bounds__(kWG) void k_ent_decode(DecArgs d)
         }
         if (t == 4 && scaled)
             ((uint64_t *)V)[4] = *(const uint64_t *)(E + 40);
-        // the records, a plane per wave
+        // the records: a wave takes 64 planes at a time, a plane whose
+        // source is a 16-byte verbatim record copied by its lane, the others
+        // decoded by the whole wave one by one
         bool ok = true;
-        for (uint32_t q = wave; q < P; q += 4) {
-            const uint32_t sp = S.B[q] - 1u;
-            const uint32_t it = S.A[sp] - 1u;
+        if (t == 0)
+            S.nlst = 0u;
+        __syncthreads();
+        for (uint32_t q = (uint32_t)t; q < P; q += kWG) {
+            const uint32_t it = S.A[S.B[q] - 1u] - 1u;
+            if (tags[it] == (kEVerb | kPlaneHdrBytes)) {
+                const uint64_t *src = (const uint64_t *)(E + bstart + S.Cb[it]);
+                uint64_t *dst = (uint64_t *)(V + S.D[q]);
+                dst[0] = src[0];
+                dst[1] = src[1];
+            } else {
+                S.lst[atomicAdd(&S.nlst, 1u)] = (uint16_t)q;
+            }
+        }
+        __syncthreads();
+        const uint32_t nlst = S.nlst;
+        for (uint32_t i = wave; i < nlst; i += 4) {
+            const uint32_t q = S.lst[i];
+            const uint32_t it = S.A[S.B[q] - 1u] - 1u;
             const uint32_t tg = tags[it];
             const uint32_t tb = tg & ~kEVerb;
             const uint8_t *Bd = E + bstart + S.Cb[it];

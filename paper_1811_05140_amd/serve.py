@@ -261,9 +261,10 @@ class GpuExecutor:
             if e.code == A.SIM_ENOMEM:
                 # rolled back to the input of the gate that overflowed (the
                 # passes counted since the state was set or imported): evict
-                # it to host memory and resume from that gate later
+                # it to host memory (through the entropy stage: fewer bytes
+                # over PCIe and in host memory) and resume from that gate later
                 done = sim.stats()["passes"]
-                r.checkpoint = sim.export_state()
+                r.checkpoint = sim.export_state(entropy=True)
                 r.resume += done
                 sim.close()
                 raise Overflow(str(e))
