@@ -69,11 +69,25 @@ struct Desc {
     uint8_t *hdr;         // [nblocks][32] stream headers (block stream v1)
     uint32_t *blk_len;    // [nblocks] canonical stream bytes
     uint8_t *blk_level;   // [nblocks] ladder level of the stream
-    uint64_t *plane_off;  // [2*nseg] byte offset of each plane record
+    uint32_t *plane_off;  // [2*nseg] offset of each plane record, in 8-byte units
     double *segnorm;      // [nseg] pairwise normsq of each segment's x-hat
     double *bscale;       // [nblocks] deferred scale c_j of each block (1 unless the
                           // block was kept by the skip shortcut)
 };
+
+// Plane records are 8-byte aligned, so their offsets are stored in 8-byte
+// units: a 32-bit entry covers arenas of up to kMaxArenaBytes.
+constexpr uint64_t kMaxArenaBytes = 32ull << 30;
+
+__device__ __forceinline__ uint64_t rec_at(const Desc &d, uint64_t plane)
+{
+    return (uint64_t)d.plane_off[plane] << 3;
+}
+
+__device__ __forceinline__ void set_rec_at(const Desc &d, uint64_t plane, uint64_t off)
+{
+    d.plane_off[plane] = (uint32_t)(off >> 3);
+}
 
 // Device-resident scalars of one sim, read and written only by kernels.
 // The counters that every workgroup of a pass updates atomically sit on

@@ -204,7 +204,7 @@ struct EncArgs {
 
 __device__ __forceinline__ const uint8_t *plane_rec(const PassArgs &a, uint64_t plane)
 {
-    return a.arena_in + a.din.plane_off[plane];
+    return a.arena_in + rec_at(a.din, plane);
 }
 
 __device__ __forceinline__ uint32_t rec_len(const uint8_t *rec, uint32_t padC)

@@ -575,7 +575,7 @@ __device__ void load_unit(const PassArgs &a, const Unit &uc, Planes &X,
     const uint64_t j = g >> (a.geo.b - s);
     const double delta = *(const double *)(a.din.hdr + 32 * j + 16);
     const double fac = normalise ? a.din.bscale[j] * scale : 1.0;
-    decode_plane(a.arena_in + a.din.plane_off[2 * g + p], s, delta, fac, fac != 1.0, dst);
+    decode_plane(a.arena_in + rec_at(a.din, 2 * g + p), s, delta, fac, fac != 1.0, dst);
 }
 
 __device__ void gate_unit(const GateArg &G, const Unit &uc, int s, Planes &X,
@@ -1550,7 +1550,7 @@ __device__ void zero_unit(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         for (int k = k0; k <= k1; ++k)
             a.psz[(uint64_t)k * nplanes + plane] = 0u;
         if (MODE != kEsc) {
-            a.dout.plane_off[plane] = 0;  // the shared all-zero record
+            set_rec_at(a.dout, plane, 0);  // the shared all-zero record
         }
     }
     if (MODE == kEsc)
@@ -1609,8 +1609,8 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         if (MODE != kReplay)
             lraw = a.din.blk_level[j];
         const uint64_t g0 = uc.seg(0), g1 = uc.seg(1);
-        const uint64_t o00 = a.din.plane_off[2 * g0], o01 = a.din.plane_off[2 * g0 + 1];
-        const uint64_t o10 = a.din.plane_off[2 * g1], o11 = a.din.plane_off[2 * g1 + 1];
+        const uint64_t o00 = rec_at(a.din, 2 * g0), o01 = rec_at(a.din, 2 * g0 + 1);
+        const uint64_t o10 = rec_at(a.din, 2 * g1), o11 = rec_at(a.din, 2 * g1 + 1);
         poff = us == 0 ? (p ? o01 : o00) : (p ? o11 : o10);
         zoff = o00 | o01 | o10 | o11;
         // keeps the compiler from sinking these loads to their first uses
@@ -1629,10 +1629,10 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         if (active) {
             if (poff == 0) {
                 if (lane == 0)
-                    a.dout.plane_off[2 * g + p] = 0;
+                    set_rec_at(a.dout, 2 * g + p, 0);
             } else if (off != ~0ull) {
                 if (lane == 0)
-                    a.dout.plane_off[2 * g + p] = off;
+                    set_rec_at(a.dout, 2 * g + p, off);
                 copy_record(a.arena_in + poff, a.arena_out + off, rb);
             }
         }
@@ -1718,18 +1718,18 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     if (SC && keep_me) {
         if (poff == 0) {
             if (lane == 0)
-                a.dout.plane_off[plane] = 0;
+                set_rec_at(a.dout, plane, 0);
         } else if (off != ~0ull) {
             if (lane == 0)
-                a.dout.plane_off[plane] = off;
+                set_rec_at(a.dout, plane, off);
             copy_record(a.arena_in + poff, a.arena_out + off, kb);
         }
     } else if (mine && zrec) {
         if (lane == 0)
-            a.dout.plane_off[plane] = 0;
+            set_rec_at(a.dout, plane, 0);
     } else if (mine && off != ~0ull) {
         if (lane == 0)
-            a.dout.plane_off[plane] = off;
+            set_rec_at(a.dout, plane, off);
         if ((pszv >> 16) <= kScratchOutl)
             emit_record(a.arena_out + off, s, pszv, wreg, anchor, stage);
         else  // more outliers than staged: encode again from x-hat (same codes)
@@ -1795,7 +1795,7 @@ __device__ bool bulk_zero_unit(const PassArgs &a, const Unit &uc)
     } else {
         uint64_t o = 0;
         for (int i = 0; i < 2 * uc.nsu; ++i)
-            o |= a.din.plane_off[2 * uc.seg(i >> 1) + (i & 1)];
+            o |= rec_at(a.din, 2 * uc.seg(i >> 1) + (i & 1));
         if (o != 0)
             return false;
     }
@@ -1806,7 +1806,7 @@ __device__ bool bulk_zero_unit(const PassArgs &a, const Unit &uc)
             const uint64_t plane = 2 * g + p;
             for (int l = 0; l <= lvl; ++l)
                 a.psz[(uint64_t)l * nplanes + plane] = 0u;
-            a.dout.plane_off[plane] = 0;  // the shared all-zero record
+            set_rec_at(a.dout, plane, 0);  // the shared all-zero record
         }
         a.dout.segnorm[g] = 0.0;
     }
@@ -1860,10 +1860,10 @@ __device__ __forceinline__ void bulk_const_write(const PassArgs &a, const Unit &
             a.psz[(uint64_t)k * nplanes + plane] = v;
         }
         if (anc[i] == 0ull) {
-            a.dout.plane_off[plane] = 0;
+            set_rec_at(a.dout, plane, 0);
         } else {
             if (rec != ~0ull) {
-                a.dout.plane_off[plane] = at;
+                set_rec_at(a.dout, plane, at);
                 uint4 r;
                 r.x = (uint32_t)anc[i];
                 r.y = (uint32_t)(anc[i] >> 32);
@@ -1960,8 +1960,8 @@ __device__ __forceinline__ bool const_eval(const PassArgs &a, const Unit &uc, do
             return false;
     }
     const uint64_t g0 = uc.seg(0), g1 = uc.seg(1);
-    const uint64_t o[4] = {a.din.plane_off[2 * g0], a.din.plane_off[2 * g0 + 1],
-                           a.din.plane_off[2 * g1], a.din.plane_off[2 * g1 + 1]};
+    const uint64_t o[4] = {rec_at(a.din, 2 * g0), rec_at(a.din, 2 * g0 + 1),
+                           rec_at(a.din, 2 * g1), rec_at(a.din, 2 * g1 + 1)};
     uint64_t hv = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -2054,9 +2054,9 @@ __device__ bool const_unit(const PassArgs &a, const Unit &uc, PassLds &S, double
     const uint64_t off = alloc_records(a, S, active && !zrec, kPlaneHdrBytes);
     if (active && lane == 0) {
         if (zrec) {
-            a.dout.plane_off[plane] = 0;
+            set_rec_at(a.dout, plane, 0);
         } else if (off != ~0ull) {
-            a.dout.plane_off[plane] = off;
+            set_rec_at(a.dout, plane, off);
             uint4 r;
             r.x = (uint32_t)ai;
             r.y = (uint32_t)(ai >> 32);
@@ -2327,8 +2327,8 @@ __device__ void mean_unit(const PassArgs &a, uint64_t u, Planes &X, double *red,
     // (Grover states are almost entirely such units.)
     {
         const uint64_t g0 = uc.seg(0), g1 = uc.seg(1);
-        const uint64_t o0 = a.din.plane_off[2 * g0], o1 = a.din.plane_off[2 * g0 + 1];
-        const uint64_t o2 = a.din.plane_off[2 * g1], o3 = a.din.plane_off[2 * g1 + 1];
+        const uint64_t o0 = rec_at(a.din, 2 * g0), o1 = rec_at(a.din, 2 * g0 + 1);
+        const uint64_t o2 = rec_at(a.din, 2 * g1), o3 = rec_at(a.din, 2 * g1 + 1);
         // payload words | outliers << 32 of each record
         const uint64_t h0 = *(const uint64_t *)(a.arena_in + o0 + 8);
         const uint64_t h1 = *(const uint64_t *)(a.arena_in + o1 + 8);
@@ -2375,7 +2375,7 @@ __device__ bool bulk_mean_unit(const PassArgs &a, uint64_t u, double scale)
     uint64_t hv = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        o[i] = i < 2 * uc.nsu ? a.din.plane_off[2 * uc.seg(i >> 1) + (i & 1)] : 0ull;
+        o[i] = i < 2 * uc.nsu ? rec_at(a.din, 2 * uc.seg(i >> 1) + (i & 1)) : 0ull;
         hv |= *(const uint64_t *)(a.arena_in + o[i] + 8);
     }
     if (hv != 0)
@@ -3033,7 +3033,7 @@ __device__ void load_range(const PassArgs &a, const double *amp, uint64_t first,
         const uint64_t j = g >> (a.geo.b - s);
         const double delta = *(const double *)(a.din.hdr + 32 * j + 16);
         const double fac = a.din.bscale[j] * scale;  // fl(c_j s)
-        decode_plane(a.arena_in + a.din.plane_off[2 * g + p], s, delta, fac, fac != 1.0,
+        decode_plane(a.arena_in + rec_at(a.din, 2 * g + p), s, delta, fac, fac != 1.0,
                      dst + off);
     }
 }
@@ -3184,7 +3184,7 @@ __device__ void export_body(const PassArgs &a, uint64_t j, uint8_t *out, uint64_
     // sizes of this thread's planes, from their record headers
     uint64_t local = 0;
     for (uint64_t q = t * per; q < (t + 1) * per && q < npb; ++q) {
-        const uint64_t po = a.din.plane_off[base + q];
+        const uint64_t po = rec_at(a.din, base + q);
         const uint8_t *rec = a.arena_in + po;
         const uint32_t pw = *(const uint32_t *)(rec + 8);
         const uint32_t no = *(const uint32_t *)(rec + 12);
@@ -3349,7 +3349,7 @@ __global__ __launch_bounds__(kWG) void k_import_scan(PassArgs a, const uint64_t 
         }
         // an all-zero record (anchor 0, no payload, no outliers) decodes to
         // all +0: point it at the shared zero record, as a pass does
-        a.dout.plane_off[j * npb + q] = (anc | v) == 0 ? 0 : pos;
+        set_rec_at(a.dout, j * npb + q, (anc | v) == 0 ? 0 : pos);
         nsum += no;
         pos += sz;
     }
@@ -3373,7 +3373,7 @@ __global__ __launch_bounds__(kWG) void k_import_check(PassArgs a)
     const uint64_t nplanes = 2 * a.geo.nseg;
     for (uint64_t q = (uint64_t)blockIdx.x * kWG + threadIdx.x; q < nplanes;
          q += (uint64_t)gridDim.x * kWG) {
-        const uint64_t off = a.dout.plane_off[q];
+        const uint64_t off = rec_at(a.dout, q);
         if (off == 0)
             continue;
         const uint8_t *rec = a.arena_out + off;
@@ -3443,7 +3443,7 @@ __global__ __launch_bounds__(kWG) void k_import_norm(PassArgs a, uint32_t batch)
             const Unit uc = unit_of(u, a.geo.nseg, 0);
             uint64_t hv = 0;
             for (int i = 0; i < 2 * uc.nsu; ++i) {
-                const uint64_t off = a.din.plane_off[2 * uc.seg(i >> 1) + (i & 1)];
+                const uint64_t off = rec_at(a.din, 2 * uc.seg(i >> 1) + (i & 1));
                 hv |= *(const uint64_t *)(a.arena_in + off + 8);  // payload words | outliers
             }
             if (hv == 0) {
@@ -3454,7 +3454,7 @@ __global__ __launch_bounds__(kWG) void k_import_norm(PassArgs a, uint32_t batch)
                     double v[2];
 #pragma unroll
                     for (int p = 0; p < 2; ++p) {
-                        const uint64_t off = a.din.plane_off[2 * g + p];
+                        const uint64_t off = rec_at(a.din, 2 * g + p);
                         const uint64_t anc = *(const uint64_t *)(a.arena_in + off);
                         v[p] = delta == 0.0 ? __longlong_as_double((long long)anc)
                                             : dequant((int32_t)(uint32_t)anc, delta, e);

@@ -690,6 +690,10 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
             cap = want > (double)(8 * kGiB) ? 8 * kGiB : (uint64_t)want;
         }
         cap = (cap + 255) & ~255ull;
+        if (cap > kMaxArenaBytes)
+            rc = fail(SIM_EINVAL, "arena of %llu bytes exceeds the %llu bytes that plane "
+                      "offsets address", (unsigned long long)cap,
+                      (unsigned long long)kMaxArenaBytes);
         S->arena_cap = cap;
         const uint64_t nb = S->geo.nblocks, ns = S->geo.nseg;
         for (int k = 0; k < 2 && !rc; ++k) {
@@ -701,7 +705,7 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
             if (!rc)
                 rc = dmalloc(S, (void **)&S->desc[k].blk_level, nb);
             if (!rc)
-                rc = dmalloc(S, (void **)&S->desc[k].plane_off, 8 * 2 * ns);
+                rc = dmalloc(S, (void **)&S->desc[k].plane_off, 4 * 2 * ns);
             if (!rc)
                 rc = dmalloc(S, (void **)&S->desc[k].segnorm, 8 * ns);
             if (!rc)

@@ -178,8 +178,12 @@ def reservation_bytes(n, b, arena_factor=1.0, levels=5):
     nseg = 1 << (n - s)
     nblocks = 1 << (n - b)
     arena = arena_bytes(n, arena_factor)
-    per_seg = 2 * (16 + 8) + 8 * levels + 16
-    per_block = 2 * (32 + 4 + 1) + 4 + 4 + 8 + 16
+    # per segment, two descriptor sets of two 4-byte record offsets and an
+    # 8-byte norm, the size table (4 bytes per plane and level), the mean
+    # pre-pass sums; per block, two sets of header, length, level and scale,
+    # the replay and escalation lists, norms, sums and checkpoint offsets
+    per_seg = 2 * (8 + 8) + 8 * levels + 16
+    per_block = 2 * (32 + 4 + 1 + 8) + 4 + 4 + 8 + 16 + 8
     # staging of the pass kernels: 4 waves x (8 KiB payload + 64 outliers)
     # per workgroup, one workgroup per segment pair up to the default grid
     # of 3072
