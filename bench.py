@@ -787,6 +787,9 @@ def bench_qft12(args, A, inputs, stream):
     cpu = None
     if args.cpu_budget > 0:
         from oracle import oracle as orc
+        # the oracle's passes spread block groups over OpenMP threads: one
+        # thread here, as the sample line states
+        orc.set_threads(1)
         runs, tcpu = 0, 0.0
         while tcpu < min(args.cpu_budget, 10.0):
             o = orc.OracleSim(n, b, inputs.default_ladder(1e-4), 4.0)
@@ -895,12 +898,12 @@ def pass_stream_bytes(sim, x, gates, n, b, count_basis=True):
     """Algorithmic HBM bytes of one step's pass launches (the roofline's
     per-launch figure is this over the launches): each pass reads its input
     state's compressed streams and writes its output's, and per plane reads
-    and writes a record offset (16 B) and writes a size word (4 B), per
+    and writes a record offset (4 B each) and writes a size word (4 B), per
     segment a normsq (8 B).  Measured by replaying the step untimed with the
     resident bytes read after every gate; the basis encode reads nothing."""
     s = min(b, 10)
     planes = 2 << (n - s)
-    meta = 20 * planes + 8 * (planes // 2)
+    meta = 12 * planes + 8 * (planes // 2)
     sim.set_basis(x)
     prev = sim.stats()["resident_bytes"]
     total = prev + meta if count_basis else 0
