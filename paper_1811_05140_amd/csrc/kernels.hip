@@ -1472,7 +1472,9 @@ __device__ __forceinline__ bool zero_preserving(const GateArg &G)
 // One unit of a pass: decode + normalise + gate in LDS, then per plane
 //   kFused:  sizes at levels 0..h (h = the block's previous level), encode
 //            at h (the speculation);
-//   kEsc:    sizes at levels h+1 .. L-1 for the planes of block jsel;
+//   kEsc:    for the planes of block jsel (whose sized levels 0..h all
+//            missed theta): sizes at levels h+2 .. L-1, encode at h+1 (the
+//            likeliest choice, kept when the block's decision takes it);
 //   kReplay: encode the planes of block jsel at its chosen level;
 // records are bump-allocated per unit; per-segment normsq of what was
 // encoded.
@@ -1549,12 +1551,8 @@ __device__ void zero_unit(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
         }
         for (int k = k0; k <= k1; ++k)
             a.psz[(uint64_t)k * nplanes + plane] = 0u;
-        if (MODE != kEsc) {
-            set_rec_at(a.dout, plane, 0);  // the shared all-zero record
-        }
+        set_rec_at(a.dout, plane, 0);  // the shared all-zero record
     }
-    if (MODE == kEsc)
-        return;
     if (threadIdx.x < (unsigned)uc.nsu) {
         const uint64_t gs = uc.seg((int)threadIdx.x);
         if (MODE == kFused || (gs >> bs) == jsel)
@@ -1690,8 +1688,12 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
                                    : StepSum{0x7FF00000u, 0x7FF00000u, 0x7FF00000u,
                                              0x7FF00000u, 0u};
         if (MODE == kEsc) {
-            size_levels<SC>(&X[us][p][0], s, a.lad, h + 1, L - 1, -1, a.psz, plane, nplanes, wreg,
-                        sum);
+            // an escalated block (h < L - 1): the levels above h + 1 are only
+            // sized; h + 1 is sized and packed together
+            lev = h + 1;
+            if (lev < L - 1)
+                size_levels<SC>(&X[us][p][0], s, a.lad, lev + 1, L - 1, -1, a.psz, plane,
+                                nplanes, wreg, sum);
         } else {
             // kFused: levels below the speculated one are only sized; the
             // speculated level is sized and packed together
@@ -1700,13 +1702,11 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
             if (MODE == kFused && h > 0 && !a.sc_perm)
                 size_levels<SC>(&X[us][p][0], s, a.lad, 0, h - 1, -1, a.psz, plane, nplanes,
                             wreg, sum);
-            pszv = size_pack_level<SC>(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev],
+        }
+        pszv = size_pack_level<SC>(&X[us][p][0], s, a.lad.delta[lev], a.lad.e[lev],
                                    a.lad.r[lev], a.psz + (uint64_t)lev * nplanes + plane, stage,
                                    &S.pack[wave][0], wreg, anchor, sum);
-        }
     }
-    if (MODE == kEsc)
-        return;
     // bump-allocate this unit's records in the output arena (an all-zero
     // record is the shared one)
     const bool zrec = pszv == 0u && anchor == 0ull;
@@ -1758,7 +1758,7 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     }
 }
 
-__device__ void decide_escalated(const PassArgs &a, uint64_t j, PassLds &S);
+__device__ bool decide_escalated(const PassArgs &a, uint64_t j, PassLds &S);
 
 // ------------------------------------------------------- bulk rounds ----
 //
@@ -2250,9 +2250,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 }
 
 // Replays and escalations left by k_decide.  Items: (replayed block,
-// segment) pairs, one unit each, encoded again at the chosen level; then
-// one item per escalated block, whose workgroup sizes the remaining levels
-// over all the block's units, decides, and re-encodes the block itself.
+// segment) pairs, one unit each, encoded again at the chosen level; then one
+// item per escalated block, whose workgroup sizes the block's remaining
+// levels over all its units while encoding them at the first of those
+// (kEsc), decides, and encodes the block's units again only when the level
+// decided is a higher one.
 // Workgroup wg of nwg working on one state's replays and escalations (the
 // pack buffers of S must be zero).
 template <bool SC>
@@ -2278,15 +2280,15 @@ __device__ void fix_body(const PassArgs &a, uint64_t wg, uint64_t nwg, PassLds &
     const double scale = a.dev->scale;
     const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
     const bool zp = zero_preserving(a.gate);
-    // one call site per unit_body mode (keeps them inlined)
+    // one call site per unit_body mode (keeps them inlined once each)
     for (uint64_t it = wg; it < nitems; it += nwg) {
         const bool rep = it < nrep_items;
         const uint64_t jsel = rep ? a.replay_list[it >> bs] : a.esc_list[it - nrep_items];
         const uint64_t t0 = rep ? (it & (spb - 1)) : 0;
         const uint64_t tn = rep ? t0 + 1 : spb;
         for (int phase = rep ? 1 : 0; phase < 2; ++phase) {
-            if (phase == 1 && !rep)
-                decide_escalated(a, jsel, S);
+            if (phase == 1 && !rep && !decide_escalated(a, jsel, S))
+                break;  // the block's encoding at the first remaining level stands
             for (uint64_t t = t0; t < tn; ++t) {
                 const uint64_t g = (jsel << bs) | t;
                 const Unit uc = unit_of_seg(g, a.geo.nseg, Ms);
@@ -2810,8 +2812,11 @@ __device__ void decide_block(const PassArgs &a, uint64_t j)
 }
 
 // Choice for an escalated block over levels h+1 .. L-1 (the first whose
-// ratio reaches theta, else the last) (workgroup).
-__device__ void decide_escalated(const PassArgs &a, uint64_t j, PassLds &S)
+// ratio reaches theta, else the last), once the workgroup has sized every
+// unit of the block at those levels and encoded it at h+1.  Returns whether
+// the choice is above h+1, so that the block's units have to be encoded
+// again at the level chosen.
+__device__ bool decide_escalated(const PassArgs &a, uint64_t j, PassLds &S)
 {
     uint64_t *red = (uint64_t *)&S.X[0][0][0];
     uint64_t *tot = red + kWG;
@@ -2829,8 +2834,12 @@ __device__ void decide_escalated(const PassArgs &a, uint64_t j, PassLds &S)
             }
         finalize_block(a, j, d, tot[d], nout[d]);
         atomicAdd((unsigned long long *)&a.dev->replays, 1ull);
+        S.misc[0] = d != h + 1;
     }
     __syncthreads();
+    const bool again = S.misc[0] != 0;
+    __syncthreads();
+    return again;
 }
 
 // N^2 (pairwise over all amplitudes: block and segment sums are aligned

@@ -36,10 +36,11 @@ class FakeSim:
 
 def test_pass_stream_bytes_counts_streams_in_and_out_plus_metadata():
     # n = 12, b = 8: s = 8, 16 segments, 32 planes; metadata per pass
-    # 20 B per plane + 8 B per segment = 640 + 128 = 768 B
+    # 12 B per plane (two 4-byte record offsets, one size word) + 8 B per
+    # segment = 384 + 128 = 512 B
     n, b = 12, 8
     res = [1000, 3000, 2000]  # after the basis encode, gate 1, gate 2
     total = bench.pass_stream_bytes(FakeSim(res), 0, ["g1", "g2"], n, b)
-    meta = 20 * 32 + 8 * 16
+    meta = 12 * 32 + 8 * 16
     want = (1000 + meta) + (1000 + 3000 + meta) + (3000 + 2000 + meta)
     assert total == want
