@@ -2265,10 +2265,9 @@ __device__ void fix_body(const PassArgs &a, uint64_t wg, uint64_t nwg, PassLds &
             atomicOr(&a.dev->err, kErrSize);
         return;
     }
-    if (a.dev->err)
-        return;
-    const uint32_t nrep = a.dev->n_replay, nesc = a.dev->n_esc;
-    if (nrep + nesc == 0)
+    // the error word and the list lengths in one round trip
+    const uint32_t err = a.dev->err, nrep = a.dev->n_replay, nesc = a.dev->n_esc;
+    if ((err != 0) | (nrep + nesc == 0))
         return;
     if (threadIdx.x == 0)
         S.chunk[0] = S.chunk[1] = 0;
@@ -2700,8 +2699,9 @@ __device__ void keep_block(const PassArgs &a, uint64_t j)
 // reaches theta.  When that is the speculated level h the block is done;
 // another level sends the block to the replay list; when none qualifies and
 // levels above h remain, the block joins the escalation list.
+// h: the block's previous level (hint_level).
 template <int VEC>
-__device__ void decide_block(const PassArgs &a, uint64_t j);
+__device__ void decide_block(const PassArgs &a, uint64_t j, int h);
 
 // One wavefront per block.
 // VEC: 1 = blocks of 256 planes or more (vector loads), 0 = smaller blocks,
@@ -2709,16 +2709,20 @@ __device__ void decide_block(const PassArgs &a, uint64_t j);
 template <int VEC>
 __global__ __launch_bounds__(kWG) void k_decide(PassArgs a)
 {
-    if (a.dev->err)
-        return;
     const uint64_t nw = (uint64_t)gridDim.x * (kWG / 64);
-    for (uint64_t j = (uint64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
-         j < a.geo.nblocks; j += nw)
-        decide_block<VEC>(a, j);
+    const uint64_t j0 = (uint64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
+    // the error word and the first block's previous level in one round trip
+    const uint32_t err = a.dev->err;
+    const int h0 = j0 < a.geo.nblocks ? hint_level(a, j0) : 0;
+    asm volatile("" ::"v"(err), "v"(h0));
+    if (err)
+        return;
+    for (uint64_t j = j0; j < a.geo.nblocks; j += nw)
+        decide_block<VEC>(a, j, j == j0 ? h0 : hint_level(a, j));
 }
 
 template <int VEC>
-__device__ void decide_block(const PassArgs &a, uint64_t j)
+__device__ void decide_block(const PassArgs &a, uint64_t j, int h)
 {
     if (block_kept(a, j)) {
         keep_block(a, j);
@@ -2728,7 +2732,6 @@ __device__ void decide_block(const PassArgs &a, uint64_t j)
     // (permutation shortcut: level h only, taken without the theta test)
     const int lane = lane_id();
     const int L = a.lad.L;
-    const int h = hint_level(a, j);
     const int k0 = a.sc_perm ? h : 0;
     const uint64_t npb = 2ull << (a.geo.b - a.geo.s);
     const uint64_t nplanes = 2 * a.geo.nseg;
@@ -2845,23 +2848,29 @@ __device__ bool decide_escalated(const PassArgs &a, uint64_t j, PassLds &S)
 // N^2 (pairwise over all amplitudes: block and segment sums are aligned
 // subtrees, so the tree runs over segment sums, or over block sums when
 // k_segtree has formed them), s, statistics; frees the input arena.
-__device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures);
+// nrep, nesc: the replay and escalation list lengths.
+__device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures, uint32_t nrep,
+                            uint32_t nesc);
 
 __global__ __launch_bounds__(kWG) void k_reduce(PassArgs a)
 {
-    if (a.dev->err)
+    // the error word and the list lengths in one round trip
+    const uint32_t err = a.dev->err, nrep = a.dev->n_replay, nesc = a.dev->n_esc;
+    asm volatile("" ::"v"(err), "v"(nrep), "v"(nesc));
+    if (err)
         return;
     __shared__ double lds[kWG];
     __shared__ uint64_t ures[kWG];
-    reduce_body(a, lds, ures);
+    reduce_body(a, lds, ures, nrep, nesc);
 }
 
-__device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures)
+__device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures, uint32_t nrep,
+                            uint32_t nesc)
 {
     const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
     // normsq of the blocks that were re-encoded after k_decide
     const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
-    const uint32_t nrep = a.dev->n_replay, nfix = nrep + a.dev->n_esc;
+    const uint32_t nfix = nrep + nesc;
     for (uint32_t k = (uint32_t)wave; k < nfix; k += kWG / 64) {
         const uint64_t j = k < nrep ? a.replay_list[k] : a.esc_list[k - nrep];
         const double v = wave_pairwise(a.dout.segnorm + j * spb, spb);
@@ -3619,7 +3628,7 @@ __global__ __launch_bounds__(kWG) void k_bdecide(const PassArgs *__restrict__ ar
         const PassArgs &a = args[st];
         if (a.dev->err)
             continue;
-        decide_block<-1>(a, it - bpre[st]);
+        decide_block<-1>(a, it - bpre[st], hint_level(a, it - bpre[st]));
     }
 }
 
@@ -3657,9 +3666,14 @@ __global__ __launch_bounds__(kWG) void k_breduce(const PassArgs *__restrict__ ar
     __shared__ double lds[kWG];
     __shared__ uint64_t ures[kWG];
     const uint32_t st = blockIdx.x;
-    if (upre[st + 1] == upre[st] || args[st].dev->err)
+    if (upre[st + 1] == upre[st])
         return;
-    reduce_body(args[st], lds, ures);
+    const DevState *d = args[st].dev;
+    const uint32_t err = d->err, nrep = d->n_replay, nesc = d->n_esc;
+    asm volatile("" ::"v"(err), "v"(nrep), "v"(nesc));
+    if (err)
+        return;
+    reduce_body(args[st], lds, ures, nrep, nesc);
 }
 
 // DIFFUSE pre-pass of the states whose gate is DIFFUSE (items: units).
