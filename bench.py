@@ -389,13 +389,19 @@ def bench_batch64(args, A, inputs, stream):
             "logical_frac": round(logical / HBM_PEAK_GBS, 4),
             "kernels_ms_one_step": {k: round(v[1], 3) for k, v in sorted(prof.items())},
         }
-    # fidelity of every instance against its uncompressed run
+    # fidelity of every instance against its uncompressed run (the runs,
+    # one instance at a time, also give the uncompressed path's rate)
     Fs = []
+    sv_s = 0.0
     for k, inst in enumerate(insts):
         ref = A.Sim(inst["n"], conf[k][0], -1.0, stream=stream)
+        ref.sync()
+        t0 = time.perf_counter()
         ref.set_basis(0)
         for layer in inst["layers"]:
             ref.run(layer)
+        ref.sync()
+        sv_s += time.perf_counter() - t0
         Fs.append(sims[k].fidelity(ref))
         ref.close()
     Fs_sorted = sorted(Fs)
@@ -432,6 +438,9 @@ def bench_batch64(args, A, inputs, stream):
         "hbm_frac": roofline["frac"] if roofline else None,
         "one_at_a_time_gates_per_s": round(total_gates / alone_s, 2),
         "batch_speedup": round((total_gates * args.steps / elapsed) / (total_gates / alone_s), 3),
+        "uncompressed_gates_per_s": round(total_gates / sv_s, 2),
+        "compressed_over_uncompressed": round((total_gates * args.steps / elapsed) /
+                                              (total_gates / sv_s), 3),
         "alone_equals_batch": same,
         "fidelity": Fs_sorted[0], "fidelity_median": Fs_sorted[len(Fs) // 2],
         "fidelity_ok_count": sum(1 for f in Fs if f >= 0.999),
@@ -1048,13 +1057,23 @@ def main():
         extra = {"p_marked": P, "p_marked_closed_form": P_closed,
                  "fidelity_reference": "closed-form Grover state"}
     else:
-        # fidelity against the uncompressed FP64 run of the same circuit
+        # fidelity against the uncompressed FP64 run of the same circuit,
+        # whose second run (untimed for the metric) gives the uncompressed
+        # path's own rate on this circuit
         ref = A.Sim(n, b, -1.0, stream=stream)
         ref.set_basis(x)
         ref.run(gates)
+        ref.sync()
+        t0 = time.perf_counter()
+        ref.set_basis(x)
+        ref.run(gates)
+        ref.sync()
+        sv_gps = len(gates) / (time.perf_counter() - t0)
         F = sim.fidelity(ref)
         ref.close()
-        extra = {"fidelity_reference": "uncompressed FP64 GPU run"}
+        extra = {"fidelity_reference": "uncompressed FP64 GPU run",
+                 "uncompressed_gates_per_s": round(sv_gps, 1),
+                 "compressed_over_uncompressed": round(gates_per_s / sv_gps, 3)}
 
     roofline = None
     if prof:
