@@ -115,6 +115,8 @@ struct DevState {
     uint64_t replays;       // cumulative count of replayed blocks
     uint64_t escalations;   // cumulative count of escalated blocks
     uint64_t level_hist[kMaxL];
+    uint32_t red_ticket;    // workgroups of the wide reduction done (0 between passes)
+    uint32_t pad2;
 };
 
 static_assert(offsetof(DevState, arena_used) == 128 && offsetof(DevState, n_replay) == 256,

@@ -2851,6 +2851,109 @@ __device__ bool decide_escalated(const PassArgs &a, uint64_t j, PassLds &S)
 // nrep, nesc: the replay and escalation list lengths.
 __device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures, uint32_t nrep,
                             uint32_t nesc);
+__device__ void reduce_finish(const PassArgs &a, double N2, uint64_t res, const uint32_t *hist);
+
+// Sum of v over the workgroup (integers: any order is exact).
+__device__ uint64_t wg_sum_u64(uint64_t v, uint64_t *ures)
+{
+    const int t = threadIdx.x;
+    ures[t] = v;
+    __syncthreads();
+    for (int st = kWG / 2; st > 0; st >>= 1) {
+        if (t < st)
+            ures[t] += ures[t + st];
+        __syncthreads();
+    }
+    const uint64_t r = ures[0];
+    __syncthreads();
+    return r;
+}
+
+// The reduction of a state with many blocks by gridDim.x workgroups (a power
+// of two dividing the block count): each takes an aligned run of blocks,
+// whose pairwise sum is a subtree of the tree over all blocks, after
+// recomputing the norms of the replayed blocks in its run; its partial sums
+// go to blksum (free between the DIFFUSE pre-pass and the next pass); the
+// workgroup that finishes last (a ticket taken after a device-scope release
+// fence, then an acquire fence) sums the partials by the same tree -- the
+// top of the tree over all blocks -- and finishes as k_reduce does.
+__global__ __launch_bounds__(kWG) void k_reduce_wide(PassArgs a)
+{
+    const uint32_t err = a.dev->err, nrep = a.dev->n_replay, nesc = a.dev->n_esc;
+    if (err)
+        return;
+    __shared__ double lds[kWG];
+    __shared__ uint64_t ures[kWG];
+    __shared__ uint32_t last;
+    const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
+    const uint64_t G = gridDim.x, per = a.geo.nblocks / G;
+    const uint64_t lo = (uint64_t)blockIdx.x * per, hi = lo + per;
+    const uint64_t spb = 1ull << (a.geo.b - a.geo.s);
+    for (uint32_t k = (uint32_t)wave; k < nrep + nesc; k += kWG / 64) {
+        const uint64_t j = k < nrep ? a.replay_list[k] : a.esc_list[k - nrep];
+        if (j < lo || j >= hi)
+            continue;
+        const double v = wave_pairwise(a.dout.segnorm + j * spb, spb);
+        if (lane == 0)
+            a.blknorm[j] = v;
+    }
+    __syncthreads();
+    const double part = wg_tree([&](uint64_t i) { return a.blknorm[lo + i]; }, per, lds);
+    uint64_t by = 0;
+    uint32_t hist[kMaxL];
+#pragma unroll
+    for (int k = 0; k < kMaxL; ++k)
+        hist[k] = 0;
+    for (uint64_t j = lo + t; j < hi; j += kWG) {
+        by += a.dout.blk_len[j];
+        const int lv = a.dout.blk_level[j];
+#pragma unroll
+        for (int k = 0; k < kMaxL; ++k)
+            hist[k] += lv == k;
+    }
+    by = wg_sum_u64(by, ures);
+#pragma unroll
+    for (int k = 0; k < kMaxL; ++k)
+        hist[k] = (uint32_t)wg_sum_u64(hist[k], ures);
+    // partials: G norms, G byte counts, G x kMaxL level counts
+    double *pn = a.blksum;
+    uint64_t *pb = (uint64_t *)(pn + G);
+    uint32_t *ph = (uint32_t *)(pb + G);
+    if (t == 0) {
+        pn[blockIdx.x] = part;
+        pb[blockIdx.x] = by;
+        for (int k = 0; k < kMaxL; ++k)
+            ph[blockIdx.x * kMaxL + k] = hist[k];
+        __threadfence();
+        const uint32_t before = atomicAdd(&a.dev->red_ticket, 1u);
+        last = before == (uint32_t)(G - 1);
+        if (last) {
+            __threadfence();
+            a.dev->red_ticket = 0u;
+        }
+    }
+    __syncthreads();
+    if (!last)
+        return;
+    const double N2 = wg_tree([&](uint64_t i) { return pn[i]; }, G, lds);
+    uint64_t res = 0;
+    uint32_t htot[kMaxL];
+#pragma unroll
+    for (int k = 0; k < kMaxL; ++k)
+        htot[k] = 0;
+    for (uint64_t g = t; g < G; g += kWG) {
+        res += pb[g];
+#pragma unroll
+        for (int k = 0; k < kMaxL; ++k)
+            htot[k] += ph[g * kMaxL + k];
+    }
+    res = wg_sum_u64(res, ures);
+#pragma unroll
+    for (int k = 0; k < kMaxL; ++k)
+        htot[k] = (uint32_t)wg_sum_u64(htot[k], ures);
+    if (t == 0)
+        reduce_finish(a, N2, res, htot);
+}
 
 __global__ __launch_bounds__(kWG) void k_reduce(PassArgs a)
 {
@@ -2936,7 +3039,15 @@ __device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures, uint
             __syncthreads();
         }
     }
-    if (t == 0) {
+    if (t == 0)
+        reduce_finish(a, N2, res, hist);
+}
+
+// N^2 and the pass's statistics into the sim's device state; frees the
+// input arena and clears the replay lists (one thread).
+__device__ void reduce_finish(const PassArgs &a, double N2, uint64_t res, const uint32_t *hist)
+{
+    {
         DevState *d = a.dev;
         d->normsq = N2;
         if (N2 > 0.0 && __builtin_isfinite(N2)) {
@@ -3814,6 +3925,21 @@ unsigned unit_grid_for(uint64_t units, unsigned cap)
     return grid_for(cap > 1 ? ((cap - 1) | 1u) : 1u);
 }
 
+// The pass's reduction: one workgroup, or for more than 4096 blocks one
+// workgroup per run of 1024 blocks (at most 256 workgroups, a power of two
+// dividing the block count).
+void launch_reduce(const PassArgs &a, hipStream_t st, Prof *prof)
+{
+    const uint64_t nb = a.geo.nblocks;
+    if (nb <= 4096) {
+        TIMED(prof, kIdReduce, st, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, a));
+        return;
+    }
+    const uint64_t g = nb / 1024 < 256 ? nb / 1024 : 256;
+    TIMED(prof, kIdReduce, st,
+          hipLaunchKernelGGL(k_reduce_wide, dim3((unsigned)g), dim3(kWG), 0, st, a));
+}
+
 void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *prof)
 {
     const unsigned gu = unit_grid_for(a0.geo.nunits, grid_cap);
@@ -3867,7 +3993,7 @@ void launch_pass(const PassArgs &a0, unsigned grid_cap, hipStream_t st, Prof *pr
             TIMED(prof, kIdReplay, st,
                   hipLaunchKernelGGL(k_fix<false>, dim3(gfix), dim3(kWG), 0, st, a));
     }
-    TIMED(prof, kIdReduce, st, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, a));
+    launch_reduce(a, st, prof);
 }
 
 void launch_batch_pass(const BatchLaunch &b, hipStream_t st, Prof *prof)
@@ -4015,7 +4141,7 @@ void launch_import(const PassArgs &a0, const uint64_t *boff, hipStream_t st, Pro
           hipLaunchKernelGGL(k_import_blocks,
                              dim3(grid_for(a.geo.nblocks < 4096 ? a.geo.nblocks : 4096)),
                              dim3(kWG), 0, st, a));
-    TIMED(prof, kIdReduce, st, hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, r));
+    launch_reduce(r, st, prof);
 }
 
 void launch_export_headers(const PassArgs &a, uint64_t first, uint64_t count, uint8_t *out,

@@ -504,3 +504,33 @@ def test_qft24_sampled_parity_and_fidelity(A):
     st = g.stats()
     say("qft24 fidelity", F, "min ratio", st["min_ratio"], "levels", st["level_hist"])
     assert F > 0.99
+
+
+def test_wide_reduction_many_blocks(A):
+    """A state of more than 4096 blocks (n = 19, b = 6: 8192 blocks) takes
+    the reduction over several workgroups (runs of 1024 blocks combined by
+    the last one): N^2, s, resident bytes, ratios, the level histogram and
+    every stream equal the oracle's after each gate, through replays, a
+    DIFFUSE (whose pre-pass uses the same scratch) and a PHASE_FLIP."""
+    n, b = 19, 6
+    rng = np.random.default_rng(19)
+    gates = [I.h(q) for q in range(0, n, 3)]
+    for _ in range(10):
+        a_, c_ = (int(v) for v in rng.choice(n, 2, replace=False))
+        gates += [I.cphase(a_, c_, float(rng.uniform(0, 6.3))), I.h(int(rng.integers(0, n)))]
+    gates += [I.phase_flip(0x2B5A3), I.diffuse(), I.swap(2, 17), I.t_gate(18)]
+    say("wide reduction n=19 b=6", len(gates), "gates")
+    g = A.Sim(n, b, 1e-4)
+    g.set_basis(0x1D2F3)
+    o = orc.OracleSim(n, b, I.default_ladder(1e-4), 4.0)
+    o.set_basis(0x1D2F3)
+    for k, gate in enumerate(gates):
+        g.apply(gate)
+        o.apply(gate)
+        sg, so = g.stats(), o.stats()
+        for key in ("normsq", "scale", "resident_bytes", "min_ratio", "level_hist"):
+            assert sg[key] == so[key], (k, key, sg[key], so[key])
+        if k % 5 == 4 or k == len(gates) - 1:
+            assert g.export_state() == o.export_state(), k
+    assert g.stats()["replays"] > 0
+    g.close()
