@@ -23,6 +23,8 @@ constexpr int kWG = 256;       // threads per workgroup: four wavefronts
 constexpr int kMaxL = 8;       // ladder levels
 constexpr int kMinS = 6;       // segment log2 range supported by the kernels
 constexpr int kMaxS = 10;
+// Blocks are at most 2^kMaxB amplitudes (sim_create refuses larger).
+constexpr int kMaxB = 20;
 // Largest |y| (exclusive) that quantises to a code: 2^30 - 1, so codes lie
 // in [-(2^30 - 1), 2^30 - 1] and the Lorenzo residual of two codes always
 // fits 32 signed bits (the format defines it in 64-bit arithmetic).

@@ -620,7 +620,7 @@ sim *create(int n, int block_log2, double eb, uint64_t arena_bytes, void *stream
         fail(SIM_EINVAL, "n_qubits %d out of range", n);
         return nullptr;
     }
-    if (block_log2 < 6 || block_log2 > 20) {
+    if (block_log2 < 6 || block_log2 > kMaxB) {
         fail(SIM_EINVAL, "block_log2 %d outside [6, 20]", block_log2);
         return nullptr;
     }
