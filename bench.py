@@ -962,6 +962,10 @@ def main():
                     help="time without per-kernel events (no roofline entry)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a device copy of this many bytes (counters)")
+    ap.add_argument("--grid", type=int, default=0,
+                    help="qft24 / grover36: workgroups of the per-gate unit kernels (0: the "
+                         "fastest of 1024, 2048, 3072 and 4096 on one untimed step each, "
+                         "before the warmup; -1: the library's default)")
     ap.add_argument("--shortcut", type=int, default=0, choices=(0, 1, 2, 3),
                     help="Sec. V shortcuts for qft24 / grover36: 1 permutation "
                          "levels, 2 skip unchanged blocks, 3 both (default 0: Alg. 2)")
@@ -1020,6 +1024,30 @@ def main():
     def step():
         sim.set_basis(x)
         sim.run(gates)
+
+    # the unit kernels' grid (a launch parameter: results are the same at
+    # every grid): by default the fastest candidate on one untimed step of
+    # this circuit each, after one untimed step at it, with the pass timers
+    # of the timed region on
+    grid_trials = None
+    if args.grid == 0:
+        grid_trials = {}
+        if not args.no_profile:
+            sim.profile(True, pass_only=True)
+        for g in (1024, 2048, 3072, 4096):
+            sim.set_grid(g)
+            step()
+            sim.sync()
+            t0 = time.perf_counter()
+            step()
+            sim.sync()
+            grid_trials[g] = round(1000.0 * (time.perf_counter() - t0), 3)
+        sim.profile(False)
+        sim.set_grid(min(grid_trials, key=grid_trials.get))
+    elif args.grid > 0:
+        sim.set_grid(args.grid)
+    grid_used = (min(grid_trials, key=grid_trials.get) if grid_trials
+                 else (args.grid if args.grid > 0 else "library default"))
 
     for _ in range(args.warmup):
         step()
@@ -1116,6 +1144,7 @@ def main():
         "segment_log2": min(b, 10), "error_bound": eb,
         "ladder": inputs.default_ladder(eb), "theta": 4.0,
         "gates_per_step": len(gates), "shortcut": args.shortcut,
+        "grid": grid_used, "grid_trial_ms": grid_trials,
     }
     if grover:
         config.update({"marked": w["marked"], "iterations": k})
