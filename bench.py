@@ -66,20 +66,24 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, kernel):
-    """HBM bytes per launch from the committed PMC summary of this workload,
-    if it was taken on the current kernel source (else None)."""
+def measured_counters(workload, kernel):
+    """The committed PMC summary of this workload's kernel, if it was taken
+    on the current kernel source (else {})."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
-        return None
+        return {}
     try:
         d = json.load(open(path))
     except ValueError:
-        return None
+        return {}
     if d.get("kernel_source_sha") != kernel_source_hash():
-        return None
-    k = d.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+        return {}
+    return d.get("kernels", {}).get(kernel) or {}
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed PMC summary (or None)."""
+    return measured_counters(workload, kernel).get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(A, orc, inputs, w, eb, budget_s, name):
@@ -1118,6 +1122,10 @@ def main():
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.workload, name),
+            # share of the VALU issue capacity the pass used, from the
+            # committed SQ counters (SQ_INSTS_VALU x 4 cycles over 1024
+            # SIMDs x 2.4 GHz x the traced launch time), or None
+            "valu_busy": measured_counters(args.workload, name).get("valu_busy"),
             "avg_launch_ms": round(tot / cnt, 4), "launches": cnt,
             "algorithmic_bytes_per_launch": int(alg_bytes),
             "algorithmic_bytes": "compressed streams in + out and per-plane metadata, "
