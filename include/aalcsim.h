@@ -89,7 +89,9 @@ typedef struct {
     uint64_t passes;           /* gates applied since the last set_basis */
     uint64_t level_hist[8];    /* blocks encoded at each ladder level */
     uint64_t arena_bytes;      /* capacity of each of the two arenas */
-    uint64_t device_bytes;     /* all device memory held by the sim */
+    uint64_t device_bytes;     /* all device memory held by the sim (not the
+                                  pass kernels' staging of a sim outside a
+                                  context: one buffer per GPU, shared) */
     uint64_t replays;          /* blocks re-encoded because the level chosen
                                   differed from the one speculated */
     uint64_t escalations;      /* blocks whose first sized levels all missed
@@ -107,7 +109,11 @@ typedef struct {
  *                     "no compression" comparator of Sec. IV.
  * Two arenas of compressed streams are allocated (ping-pong between
  * passes); their size is min(2.1 * 16 * 2^n + 1 MiB, 8 GiB) each unless
- * sim_create_ex gives one.  Returns NULL on failure (sim_last_error()). */
+ * sim_create_ex gives one.  The first compressed sim (or batch) on a GPU
+ * also allocates the pass kernels' staging for that GPU (1.2 GB, indexed by
+ * hardware wave slot and shared by every sim and batch of the process on
+ * that GPU; held until the process ends).  Returns NULL on failure
+ * (sim_last_error()). */
 sim_t *sim_create(int n_qubits, int block_log2, double error_bound);
 
 /* As sim_create, with an explicit capacity per arena (0 = default) and a

@@ -39,6 +39,16 @@ constexpr uint32_t kScratchOutl = 64;
 constexpr uint64_t kArenaBase = 256;
 constexpr uint64_t kScratchPayload = 16 * 64 * 8;
 constexpr uint64_t kScratchWave = kScratchPayload + kScratchOutl * 16;
+// The staging can be indexed by the hardware slot its wave occupies (XCC,
+// shader engine and array, CU, SIMD, wave buffer slot: 17 bits of the
+// HW_ID and XCC_ID registers), which no two resident waves share.  One
+// device-wide buffer then serves every unit kernel on the GPU, and only the
+// waves resident at once touch it, so it stays in the L2 caches.
+constexpr uint32_t kHwSlotBits = 17;
+constexpr uint64_t kHwSlots = 1ull << kHwSlotBits;
+// The device-wide slot-indexed staging of the current GPU (allocated at the
+// first call for that GPU, held until the process ends).
+hipError_t slot_staging(int device, uint8_t **ptr);
 
 // Gate kinds (numbering of the public header).
 enum : uint32_t {
@@ -165,8 +175,11 @@ struct PassArgs {
     // unit kernels then read each block's scale (instances with SC = true)
     int32_t sc_scaled;
     int32_t sc_rel;      // the ladder has pointwise-relative levels
+    int32_t stage_by_slot;  // scratch is the slot-indexed staging (else by workgroup)
     uint32_t *psz;       // [L][2*nseg]: payload words | n_outliers << 16
-    uint8_t *scratch;    // [scratch_wgs * 4][kScratchWave] staging, by workgroup and wave
+    uint8_t *scratch;    // staging: [kHwSlots][kScratchWave] by hardware wave slot
+                         // (stage_by_slot), else [scratch_wgs * 4][kScratchWave]
+                         // by workgroup and wave
     uint64_t scratch_wgs;  // workgroups the staging covers (grids must not exceed it)
     uint32_t *replay_list;  // [nblocks]
     uint32_t *esc_list;     // [nblocks]

@@ -1433,6 +1433,16 @@ struct PassLds {
     uint64_t chunk[2]; // this workgroup's current arena chunk [cur, end)
 };
 
+// The hardware slot of the calling wave, < kHwSlots: HW_ID's wave slot
+// [3:0], SIMD [5:4], CU [11:8], shader array [12] and engine [14:13], and
+// XCC_ID [3:0].
+__device__ __forceinline__ uint64_t hw_wave_slot()
+{
+    const uint32_t hw = __builtin_amdgcn_s_getreg((31 << 11) | (0 << 6) | 4);
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
+    return (uint64_t)((hw & 0x3Fu) | (((hw >> 8) & 0x7Fu) << 6) | ((xcc & 0xFu) << 13));
+}
+
 // Whether the gate maps amplitudes that are +0 in both components to +0 in
 // both, for every amplitude index, as evaluated by the gate code itself (a
 // product with a negative matrix entry or a negation yields -0, whose
@@ -1681,7 +1691,10 @@ __device__ void unit_body(const PassArgs &a, const Unit &uc, uint64_t jsel, Pass
     int lev = 0;
     uint32_t pszv = 0, wreg = 0;
     uint64_t anchor = 0;
-    uint8_t *stage = a.scratch + ((uint64_t)blockIdx.x * 4 + (uint64_t)wave) * kScratchWave;
+    uint8_t *stage =
+        a.scratch +
+        (a.stage_by_slot ? hw_wave_slot() : ((uint64_t)blockIdx.x * 4 + (uint64_t)wave)) *
+            kScratchWave;
     if (mine) {
         const int h = lvl;
         const StepSum sum = sparse ? step_summary(&X[us][p][0], s)
@@ -4168,6 +4181,26 @@ constexpr int kNoAllocDevices = 64;
 std::mutex g_noalloc_mu;
 void *g_noalloc_ptr[kNoAllocDevices] = {};
 }  // namespace
+
+std::mutex g_stage_mu;
+uint8_t *g_stage_ptr[kNoAllocDevices] = {};
+
+hipError_t slot_staging(int device, uint8_t **ptr)
+{
+    *ptr = nullptr;
+    if (device < 0 || device >= kNoAllocDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    if (!g_stage_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipMalloc(&p, kHwSlots * kScratchWave);
+        if (e != hipSuccess)
+            return e;
+        g_stage_ptr[device] = (uint8_t *)p;
+    }
+    *ptr = g_stage_ptr[device];
+    return hipSuccess;
+}
 
 hipError_t noalloc_scratch(int device, void **ptr)
 {

@@ -186,6 +186,7 @@ struct sim {
     int psz_levels = 0;
     uint8_t *scratch = nullptr;  // per-wave staging for the unit kernels
     uint64_t scratch_wgs = 0;
+    bool stage_slot = false;  // scratch is the device-wide slot-indexed staging
     uint32_t *replay_list = nullptr, *esc_list = nullptr;
     double *blknorm = nullptr, *segsum = nullptr, *blksum = nullptr;
     DevState *dev = nullptr;
@@ -358,9 +359,24 @@ int ensure_psz(sim *S, int L)
     return SIM_OK;
 }
 
-// Staging for `wgs` workgroups of the unit kernels (grown on demand).
+// Staging for `wgs` workgroups of the unit kernels (grown on demand).  A
+// sim that allocates its own memory uses the device-wide staging indexed by
+// hardware wave slot, which serves any grid; a sim in a caller's context
+// takes workgroup-indexed staging from the context.
 int ensure_scratch(sim *S, uint64_t wgs)
 {
+    if (!S->ctx) {
+        if (!S->stage_slot) {
+            const hipError_t e = slot_staging(S->device, &S->scratch);
+            if (e != hipSuccess)
+                return fail(SIM_ENOMEM, "slot staging of %llu bytes: %s",
+                            (unsigned long long)(kHwSlots * kScratchWave),
+                            hipGetErrorString(e));
+            S->stage_slot = true;
+            S->scratch_wgs = 0xFFFFFFFFull;
+        }
+        return SIM_OK;
+    }
     if (S->scratch_wgs >= wgs)
         return SIM_OK;
     if (S->scratch) {
@@ -496,6 +512,7 @@ PassArgs make_args(const sim *S, int in, int out, const GateArg &g)
     a.psz = S->psz;
     a.scratch = S->scratch;
     a.scratch_wgs = S->scratch_wgs;
+    a.stage_by_slot = S->stage_slot ? 1 : 0;
     a.replay_list = S->replay_list;
     a.esc_list = S->esc_list;
     a.blknorm = S->blknorm;
@@ -1704,7 +1721,7 @@ struct sim_batch {
     int max_states = 0, max_passes = 0;
     size_t slot_bytes = 0;     // one pass: PassArgs[max_states] + 4 prefixes
     uint8_t *dslots = nullptr; // device [max_passes] slots
-    uint8_t *scratch = nullptr; // staging for kMaxBatchGrid workgroups of the unit kernels
+    uint8_t *scratch = nullptr; // the device-wide slot-indexed staging (not owned)
     uint8_t *hslots = nullptr; // pinned host mirror
     hipEvent_t uploaded = nullptr;  // the last upload from hslots has finished
     hipEvent_t joined = nullptr;
@@ -1774,8 +1791,6 @@ void batch_free(sim_batch *B)
         (void)hipEventDestroy(B->joined);
     if (B->dslots)
         (void)hipFree(B->dslots);
-    if (B->scratch)
-        (void)hipFree(B->scratch);
     if (B->hslots)
         (void)hipHostFree(B->hslots);
     delete B->prof;
@@ -1814,8 +1829,9 @@ sim_batch_t *sim_batch_create(int max_states, int max_passes, void *hip_stream)
         B->own_stream = ok;
     }
     ok = ok && hipMalloc((void **)&B->dslots, total) == hipSuccess;
-    ok = ok && hipMalloc((void **)&B->scratch, (size_t)kMaxBatchGrid * 4 * kScratchWave) ==
-                   hipSuccess;
+    int dev = 0;
+    ok = ok && hipGetDevice(&dev) == hipSuccess;
+    ok = ok && slot_staging(dev, &B->scratch) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&B->hslots, total, hipHostMallocDefault) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&B->uploaded, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&B->joined, hipEventDisableTiming) == hipSuccess;
@@ -1912,7 +1928,8 @@ int sim_batch_apply(sim_batch_t *B, sim_t *const *sims, int count, const sim_gat
             }
             args[k].chunk_bytes = batch_chunk_bytes(S->arena_cap, gu);
             args[k].scratch = B->scratch;
-            args[k].scratch_wgs = kMaxBatchGrid;
+            args[k].scratch_wgs = 0xFFFFFFFFull;
+            args[k].stage_by_slot = 1;
             upre[k + 1] = upre[k] + (on ? S->geo.nunits : 0);
             bpre[k + 1] = bpre[k] + (on ? S->geo.nblocks : 0);
             mpre[k + 1] = mpre[k] + (mean ? S->geo.nunits : 0);

@@ -172,8 +172,7 @@ def reservation_bytes(n, b, arena_factor=1.0, levels=5):
     """Device bytes a state of n qubits holds: two arenas of
     ceil(1.3 * factor * 16 * 2^n) + 1 MiB (the pass's speculative encode at
     the previous level can take up to the raw size before a replay, on top of
-    the kept streams), plus descriptors, size tables, reduction scratch and
-    the pass kernels' per-wave staging."""
+    the kept streams), plus descriptors, size tables and reduction scratch."""
     s = min(b, 10)
     nseg = 1 << (n - s)
     nblocks = 1 << (n - b)
@@ -184,12 +183,9 @@ def reservation_bytes(n, b, arena_factor=1.0, levels=5):
     # the replay and escalation lists, norms, sums and checkpoint offsets
     per_seg = 2 * (8 + 8) + 8 * levels + 16
     per_block = 2 * (32 + 4 + 1 + 8) + 4 + 4 + 8 + 16 + 8
-    # staging of the pass kernels: 4 waves x (8 KiB payload + 64 outliers)
-    # per workgroup, one workgroup per segment pair up to the default grid
-    # of 3072
-    nunits = 1 if nseg == 1 else nseg // 2
-    staging = min(nunits, 3072) * 4 * (16 * 64 * 8 + 64 * 16)
-    return 2 * arena + per_seg * nseg + per_block * nblocks + staging + 4096
+    # (the pass kernels' staging is one device-wide buffer, indexed by
+    # hardware wave slot, shared by every sim: not part of a request)
+    return 2 * arena + per_seg * nseg + per_block * nblocks + 4096
 
 
 def arena_bytes(n, arena_factor=1.0):
