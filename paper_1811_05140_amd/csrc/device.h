@@ -37,6 +37,15 @@ constexpr uint32_t kScratchOutl = 64;
 // [0, 16) holds the one all-zero plane record that every all-+0 plane of a
 // pass points to.
 constexpr uint64_t kArenaBase = 256;
+// Where an arena's bump pointer starts after a reset: [kArenaBase, start)
+// is reserved for the first chunk of each workgroup of a pass (workgroup i
+// takes [kArenaBase + i c, kArenaBase + (i + 1) c), c = its chunk size, at
+// most cap / (8 x grid), so all of them fit), which it uses without taking
+// it from the bump pointer.
+__host__ __device__ inline uint64_t arena_start(uint64_t cap)
+{
+    return kArenaBase + ((cap / 8) & ~255ull);
+}
 constexpr uint64_t kScratchPayload = 16 * 64 * 8;
 constexpr uint64_t kScratchWave = kScratchPayload + kScratchOutl * 16;
 // The staging can be indexed by the hardware slot its wave occupies (XCC,
@@ -207,7 +216,8 @@ struct Prof {
 };
 
 // Launchers (kernels.hip).
-void launch_init_state(DevState *dev, int normalize, hipStream_t st, Prof *prof);
+void launch_init_state(DevState *dev, int normalize, uint64_t arena_cap, hipStream_t st,
+                       Prof *prof);
 // Pairwise sums S (re, im) of the normalised amplitudes; out[c] = fl(S_c * mul)
 // (device pointer).
 void launch_mean(const PassArgs &a, double mul, double *out, hipStream_t st, Prof *prof);

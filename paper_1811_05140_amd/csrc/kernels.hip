@@ -1510,6 +1510,21 @@ __device__ __forceinline__ uint64_t take_arena(const PassArgs &a, PassLds &S, ui
     return base;
 }
 
+// This workgroup's first arena chunk of a pass, from the reservation below
+// arena_start (S.chunk, set by one thread); an empty chunk (the first
+// allocation then takes one from the bump pointer) when the grid's chunks
+// would not fit the reservation.
+__device__ __forceinline__ void first_chunk(const PassArgs &a, PassLds &S)
+{
+    const uint64_t c = a.chunk_bytes;
+    if ((uint64_t)gridDim.x * c <= arena_start(a.arena_cap) - kArenaBase) {
+        S.chunk[0] = kArenaBase + (uint64_t)blockIdx.x * c;
+        S.chunk[1] = S.chunk[0] + c;
+    } else {
+        S.chunk[0] = S.chunk[1] = 0;
+    }
+}
+
 // Bump-allocate `mine ? bytes : 0` per wave for this unit's records (all
 // threads); returns this wave's offset, or ~0 when the arena is full (the
 // error is recorded).
@@ -2122,7 +2137,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
         (&S.pack[0][0])[k] = 0u;
     if (threadIdx.x == 0)
-        S.chunk[0] = S.chunk[1] = 0;
+        first_chunk(a, S);
     const uint64_t Ms = a.gate.mask >> a.geo.s;
     // s and 2*mean are read by each unit together with its own reads
     const bool zp = zero_preserving(a.gate);
@@ -2245,7 +2260,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     for (int k = threadIdx.x; k < 4 * 4 * kPackRow; k += kWG)
         (&S.pack[0][0])[k] = 0u;
     if (threadIdx.x == 0)
-        S.chunk[0] = S.chunk[1] = 0;
+        first_chunk(a, S);
     const double scale = a.dev->scale;
     const double tdiff[2] = {a.dev->tdiff[0], a.dev->tdiff[1]};
     const bool zp = zero_preserving(a.gate);
@@ -3086,7 +3101,7 @@ __device__ void reduce_finish(const PassArgs &a, double N2, uint64_t res, const 
         }
         if (d->arena_used[a.out_arena] > d->arena_peak)
             d->arena_peak = d->arena_used[a.out_arena];
-        d->arena_used[a.in_arena] = kArenaBase;
+        d->arena_used[a.in_arena] = arena_start(a.arena_cap);
         d->n_replay = 0;
         d->n_esc = 0;
     }
@@ -3722,7 +3737,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         if (st != cur) {
             cur = st;
             if (threadIdx.x == 0)
-                S.chunk[0] = S.chunk[1] = 0;  // arena chunks belong to one state
+                first_chunk(a, S);  // arena chunks belong to one state
             if (gridDim.x > a.scratch_wgs && threadIdx.x == 0)
                 atomicOr(&a.dev->err, kErrSize);
             skip = a.dev->err != 0 || gridDim.x > a.scratch_wgs;
@@ -3883,21 +3898,23 @@ static unsigned grid_for(uint64_t items)
             (prof)->end((id), (st));                                             \
     } while (0)
 
-__global__ void k_init_state(DevState *dev, int normalize)
+__global__ void k_init_state(DevState *dev, int normalize, uint64_t arena_cap)
 {
     if (threadIdx.x == 0) {
         DevState d = {};
         d.scale = 1.0;
         d.normalize = normalize;
-        d.arena_used[0] = d.arena_used[1] = kArenaBase;
+        d.arena_used[0] = d.arena_used[1] = arena_start(arena_cap);
         *dev = d;
     }
 }
 
-void launch_init_state(DevState *dev, int normalize, hipStream_t st, Prof *prof)
+void launch_init_state(DevState *dev, int normalize, uint64_t arena_cap, hipStream_t st,
+                       Prof *prof)
 {
     TIMED(prof, kIdInitState, st,
-          hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, st, dev, normalize));
+          hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, st, dev, normalize,
+                             arena_cap));
 }
 
 void launch_mean(const PassArgs &a, double mul, double *out, hipStream_t st, Prof *prof)

@@ -530,7 +530,7 @@ PassArgs make_args(const sim *S, int in, int out, const GateArg &g)
 
 int reset_devstate(sim *S)
 {
-    launch_init_state(S->dev, S->normalize, S->stream, S->prof);
+    launch_init_state(S->dev, S->normalize, S->arena_cap, S->stream, S->prof);
     HIPCHK(hipGetLastError());
     return SIM_OK;
 }
@@ -555,7 +555,7 @@ int sync_check(sim *S)
             d.err = 0;
             d.err_pass = 0;
             d.passes = 0;
-            d.arena_used[0] = d.arena_used[1] = kArenaBase;
+            d.arena_used[0] = d.arena_used[1] = arena_start(S->arena_cap);
             d.n_replay = d.n_esc = 0;
             HIPCHK(hipMemcpy(S->dev, &d, sizeof d, hipMemcpyHostToDevice));
             return fail(bits & kErrSize ? SIM_EDEVICE : SIM_ENOMEM,
@@ -568,7 +568,7 @@ int sync_check(sim *S)
         d.err = 0;
         d.err_pass = 0;
         d.passes = pe;
-        d.arena_used[1 - S->cur] = kArenaBase;
+        d.arena_used[1 - S->cur] = arena_start(S->arena_cap);
         d.n_replay = d.n_esc = 0;
         HIPCHK(hipMemcpy(S->dev, &d, sizeof d, hipMemcpyHostToDevice));
         if (bits & kErrSize)
@@ -1331,7 +1331,7 @@ int sim_import_state(sim_t *S, const void *buf, size_t len)
     DevState d{};
     d.scale = 1.0;
     d.normalize = S->normalize;
-    d.arena_used[0] = d.arena_used[1] = kArenaBase;
+    d.arena_used[0] = d.arena_used[1] = arena_start(S->arena_cap);
     d.arena_used[out] = kArenaBase + vroom;
     HIPCHK(hipMemcpyAsync(S->dev, &d, sizeof d, hipMemcpyHostToDevice, S->stream));
     uint8_t *varea = S->arena[out] + kArenaBase;
