@@ -3731,8 +3731,14 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     double scale = 1.0, tdiff[2] = {0.0, 0.0};
     uint64_t Ms = 0;
     bool zp = false;
+    uint64_t lo = 0, hi = 0;  // item range of state cur (a search only on leaving it)
     for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
-        const uint32_t st = state_of(upre, nst, it);
+        uint32_t st = cur;
+        if (it < lo || it >= hi) {
+            st = state_of(upre, nst, it);
+            lo = upre[st];
+            hi = upre[st + 1];
+        }
         const PassArgs &a = args[st];
         if (st != cur) {
             cur = st;
@@ -3749,8 +3755,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         }
         if (skip)
             continue;
-        unit_body<kFused, SC>(a, unit_of(it - upre[st], a.geo.nseg, Ms), ~0ull, S, scale,
-                              tdiff, zp);
+        unit_body<kFused, SC>(a, unit_of(it - lo, a.geo.nseg, Ms), ~0ull, S, scale, tdiff,
+                              zp);
         __syncthreads();
     }
 }
