@@ -1800,10 +1800,13 @@ __device__ bool decide_escalated(const PassArgs &a, uint64_t j, PassLds &S);
 // units keep unit_batch 1: one unit per round, no first phase.
 
 // Units per round for a state of nunits units on a grid of at most grid
-// workgroups: the largest power of two up to one per thread that leaves
-// every workgroup at least two rounds.
+// workgroups: 1 (no bulk rounds) below 16 units per workgroup, else the
+// largest power of two up to one per thread that leaves every workgroup at
+// least two rounds.
 __host__ __device__ inline uint32_t unit_batch_for(uint64_t nunits, uint64_t grid)
 {
+    if (nunits < 16 * grid)
+        return 1;
     uint32_t b = 1;
     while (b < (uint32_t)kWG && (uint64_t)b * 4 * grid <= nunits)
         b *= 2;
