@@ -187,15 +187,18 @@ def test_bulk_rounds_grover21_small_grid(A):
     assert sg["normsq"] == so["normsq"] and sg["level_hist"] == so["level_hist"]
 
 
-def test_bulk_rounds_sparse_random_n20(A):
-    """Bulk rounds of 2 units (n = 20, grid 64) on a sparse state: a basis
-    state opened on a few high qubits, then gates of every kind; the basis
-    encode and the zero units go through the per-thread path."""
-    n, b = 20, 12
+@pytest.mark.parametrize("n", [20, 21])
+def test_bulk_rounds_sparse_random_n20(A, n):
+    """A sparse state on a grid of 64 workgroups: a basis state opened on a
+    few high qubits, then gates of every kind.  n = 20 (512 units) runs the
+    one-unit kernel looping over them on 63 workgroups; n = 21 (1024 units)
+    runs bulk rounds of 8 units, where the basis encode and the zero units go
+    through the per-thread path."""
+    b = 12
     rng = np.random.default_rng(20)
-    gates = [I.h(q) for q in (19, 16, 12, 3)] + random_gates(n, 30, rng)
+    gates = [I.h(q) for q in (n - 1, 16, 12, 3)] + random_gates(n, 30, rng)
     x = int(rng.integers(0, 1 << n))
-    say("bulk rounds: sparse random n=20 grid 64 basis", x)
+    say("sparse random n=%d grid 64 basis" % n, x)
     g = A.Sim(n, b, 1e-4)
     g.set_grid(64)
     g.set_basis(x)
@@ -210,12 +213,12 @@ def test_bulk_rounds_sparse_random_n20(A):
 
 @pytest.mark.parametrize("ladder", [None, [1e-4]])
 def test_bulk_rounds_one_value_planes_every_gate_kind(A, ladder):
-    """Bulk rounds (n = 20, grid 64: 2 units per round) over planes of one
-    value: the uniform superposition, then gates of every kind whose qubits
-    are all at or above s = 10 (one-value planes stay one-value planes and
-    are settled per thread), mixed with gates on low qubits (full path).
-    Streams after every gate equal the oracle's."""
-    n, b = 20, 12
+    """Bulk rounds (n = 21, grid 64: 1024 units, 8 per round) over planes of
+    one value: the uniform superposition, then gates of every kind whose
+    qubits are all at or above s = 10 (one-value planes stay one-value
+    planes and are settled per thread), mixed with gates on low qubits (full
+    path).  Streams after every gate equal the oracle's."""
+    n, b = 21, 12
     rng = np.random.default_rng(33)
     hi = lambda: int(rng.integers(10, n))
     gates = [I.h(q) for q in range(n)]

@@ -142,8 +142,9 @@ def test_shortcuts_batched_with_graphs(A):
 
 def test_grover_phase_flip_skips_and_bulk_rounds(A):
     """Grover with the skip shortcut: PHASE_FLIP keeps every block but one
-    (the one-value pass kernel, and the bulk-round kernel at a small grid)."""
-    for n, b, grid in ((14, 8, 0), (18, 12, 64)):
+    (the one-value pass kernel; at grid 64 the same kernel looping over 128
+    units, and the bulk-round kernel over 1024 units)."""
+    for n, b, grid in ((14, 8, 0), (18, 12, 64), (21, 13, 64)):
         m = (0x2D5B7 * 7) & ((1 << n) - 1)
         gates = I.grover(n, m, 3)
         say("grover skip", n, b, grid)
