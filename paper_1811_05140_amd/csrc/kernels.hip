@@ -3078,36 +3078,47 @@ __device__ void reduce_body(const PassArgs &a, double *lds, uint64_t *ures, uint
 // input arena and clears the replay lists (one thread).
 __device__ void reduce_finish(const PassArgs &a, double N2, uint64_t res, const uint32_t *hist)
 {
-    {
-        DevState *d = a.dev;
-        d->normsq = N2;
-        if (N2 > 0.0 && __builtin_isfinite(N2)) {
-            if (d->normalize)
-                d->scale = inv_sqrt_exact(N2);
-        } else {
-            d->collapsed = 1;
-            d->scale = 1.0;
-        }
-        d->resident = res;
-        if (res > d->peak_resident)
-            d->peak_resident = res;
-        const double ratio = (double)(16ull << a.geo.n) / (double)res;
-        d->last_ratio = ratio;
-        if (a.src_basis) {
-            d->min_ratio = ratio;
-        } else {
-            d->passes += 1;
-            if (ratio < d->min_ratio)
-                d->min_ratio = ratio;
-            for (int k = 0; k < kMaxL; ++k)
-                d->level_hist[k] += hist[k];
-        }
-        if (d->arena_used[a.out_arena] > d->arena_peak)
-            d->arena_peak = d->arena_used[a.out_arena];
-        d->arena_used[a.in_arena] = arena_start(a.arena_cap);
-        d->n_replay = 0;
-        d->n_esc = 0;
+    DevState *d = a.dev;
+    // every field this update reads, loaded before any store: one memory
+    // round trip instead of one per read-modify-write
+    const int32_t normalize = d->normalize;
+    const uint64_t peak = d->peak_resident;
+    const double minr = d->min_ratio;
+    const uint64_t passes = d->passes;
+    const uint64_t used_out = d->arena_used[a.out_arena];
+    const uint64_t apeak = d->arena_peak;
+    uint64_t lh[kMaxL];
+#pragma unroll
+    for (int k = 0; k < kMaxL; ++k)
+        lh[k] = d->level_hist[k];
+    d->normsq = N2;
+    if (N2 > 0.0 && __builtin_isfinite(N2)) {
+        if (normalize)
+            d->scale = inv_sqrt_exact(N2);
+    } else {
+        d->collapsed = 1;
+        d->scale = 1.0;
     }
+    d->resident = res;
+    if (res > peak)
+        d->peak_resident = res;
+    const double ratio = (double)(16ull << a.geo.n) / (double)res;
+    d->last_ratio = ratio;
+    if (a.src_basis) {
+        d->min_ratio = ratio;
+    } else {
+        d->passes = passes + 1;
+        if (ratio < minr)
+            d->min_ratio = ratio;
+#pragma unroll
+        for (int k = 0; k < kMaxL; ++k)
+            d->level_hist[k] = lh[k] + hist[k];
+    }
+    if (used_out > apeak)
+        d->arena_peak = used_out;
+    d->arena_used[a.in_arena] = arena_start(a.arena_cap);
+    d->n_replay = 0;
+    d->n_esc = 0;
 }
 
 // ---------------------------------------------------- queries -------------
